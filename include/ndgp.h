@@ -1,0 +1,196 @@
+/*
+ * ndgp.h -- C ABI of the MI355X (gfx950) solver for the nDGP scalar field.
+ *
+ * The equation is the quasi-static scalar-field equation of the normal-branch
+ * DGP model, Sec. II Eq. (eomvarphi) of Barreira, Bose & Li, arXiv:1511.08200:
+ *
+ *     lap(phi) + r_c^2 / (3 beta a^2) [ (lap phi)^2 - (d_i d_j phi)^2 ]
+ *         = 8 pi G a^2 delta rho_m / (3 beta),
+ *
+ * written with H0 = c = 1 (lengths in units of c/H0, phi in units of c^2) as
+ *
+ *     lap(phi) + alpha [ ... ] = S,   alpha = r_c^2/(3 beta a^2),
+ *                                     S = Omega_m (delta - mean delta)/(a beta).
+ *
+ * It is solved on a periodic domain grid and on up to two static nested
+ * refinement patches (Sec. III.A: domain level first, then refinements with
+ * boundary values and initial guess interpolated from the coarser level).
+ * In NDGP_MODE_INTERPOLATED the refinements keep the interpolated guess as
+ * their answer: the paper's speed-up, Sec. III.B.  The fifth force is
+ * -grad(phi)/2 (Eq. modpoisson) by central differences (Sec. III.B).
+ *
+ * Discretisation (the paper defers it to another work): cell-centred fields;
+ * second differences D_aa on the diagonal; each mixed derivative squared is
+ * the mean over the four corners of its plane of the one-sided mixed
+ * difference squared.  This 19-point form is conservative: the nonlinear term
+ * sums to zero over a periodic grid, as it must for a zero-mean source.
+ *
+ * Conventions for every entry point
+ *  - Grid arrays are float64 in natural layout [z][y][x], x fastest.  Domain
+ *    arrays have n^3 cells.  Patch SOLUTION arrays are "padded":
+ *    (m+2)^3 cells, the m^3 interior plus a one-cell ghost shell, cell (i,j,k)
+ *    with i,j,k in [-1, m] at ((k+1)(m+2) + (j+1))(m+2) + (i+1).  Patch
+ *    DENSITY arrays have m^3 cells (no shell).
+ *  - Array and workspace pointers are DEVICE pointers; the caller owns them
+ *    and keeps them alive until the work enqueued on `stream` has finished.
+ *    ndgp_grid, ndgp_params and ndgp_report are HOST structs.
+ *  - The library never allocates device memory: all scratch space is carved
+ *    from the caller's workspace (size from ndgp_workspace_bytes, 256-byte
+ *    aligned start).
+ *  - Work is enqueued on `stream` (0 = the null stream).  Nothing throws
+ *    across the ABI; every call returns an ndgp_status and, on failure,
+ *    leaves a message for ndgp_last_error() in the calling thread.
+ *  - Results are deterministic: the same inputs give the same bits, whatever
+ *    else runs on the GPU (all reductions have a fixed order, no atomics
+ *    touch results).
+ */
+#ifndef NDGP_H
+#define NDGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NDGP_ABI_VERSION 1
+#define NDGP_MAX_PATCHES 2
+#define NDGP_HIST_LEN 64
+
+typedef enum {
+    NDGP_OK = 0,
+    NDGP_EINVAL = -1,  /* bad argument: sizes, parameters, pointers, non-finite delta */
+    NDGP_ENOMEM = -2,  /* workspace smaller than ndgp_workspace_bytes()             */
+    NDGP_ENOCONV = -3, /* tolerance not reached in max_cycles, or divergence:
+                          phi holds the last iterate                                 */
+    NDGP_EDEVICE = -4  /* a HIP call failed                                          */
+} ndgp_status;
+
+typedef enum {
+    NDGP_MODE_FULL = 0,        /* refinements relaxed to convergence (Sec. III.A)     */
+    NDGP_MODE_INTERPOLATED = 1 /* refinements = interpolated coarse field (Sec. III.B) */
+} ndgp_mode;
+
+typedef enum {
+    NDGP_PREC_FP64 = 0, /* every kernel in FP64                                       */
+    NDGP_PREC_MIXED = 1 /* FP32 relaxation inside an FP64 defect-correction loop      */
+} ndgp_precision;
+
+/* flags */
+#define NDGP_WARM_START 1u /* phi[0] holds the initial guess of the domain level
+                              (the paper allows the previous time step's field);
+                              otherwise the guess comes from nested iteration */
+
+typedef struct {
+    int32_t n;             /* domain cells per side: power of two, 8..1024              */
+    double h;              /* domain cell size in c/H0 (> 0)                            */
+    int32_t n_patch;       /* number of nested refinement levels, 0..2                 */
+    int32_t patch_n[NDGP_MAX_PATCHES];       /* cells per side, power of two, 8..512   */
+    int32_t patch_origin[NDGP_MAX_PATCHES][3]; /* lower corner (x,y,z) in PARENT cells;
+                                                  patch 1 may wrap around the periodic
+                                                  domain; patch 2 must lie inside patch 1
+                                                  with room for the interpolation
+                                                  stencils of all its multigrid levels */
+} ndgp_grid;
+
+typedef struct {
+    double rc;         /* r_c H0 (>= 0; 0 gives the linear Poisson equation)          */
+    double beta;       /* beta(a) of Eq. (beta) (> 0); see ndgp_beta_lcdm              */
+    double a;          /* scale factor (> 0)                                           */
+    double omega_m;    /* Omega_m0 (> 0)                                               */
+    double tol;        /* stop when ||S - L phi||_2 / ||S||_2 <= tol on every relaxed
+                          level (>= 0; 0 = run max_cycles)                              */
+    int32_t max_cycles; /* V-cycles per level (1..1000; 0 = 50)                         */
+    int32_t nu1, nu2;  /* pre/post red-black sweeps per level (0 = 2; at most 16)       */
+    int32_t n_levels;  /* multigrid levels of the domain grid (0 = down to 8^3)         */
+    int32_t mode;      /* ndgp_mode                                                    */
+    int32_t precision; /* ndgp_precision                                               */
+    uint32_t flags;    /* NDGP_WARM_START                                              */
+} ndgp_params;
+
+typedef struct {
+    int32_t cycles[1 + NDGP_MAX_PATCHES];  /* V-cycles (or outer iterations) per level  */
+    double rel_res[1 + NDGP_MAX_PATCHES];  /* final relative residual per level
+                                              (-1 for a level filled by interpolation) */
+    double removed_mean;   /* mean of delta projected out of the domain source         */
+    double phi_mean;       /* mean of the domain phi removed at the end (gauge)        */
+    int32_t fallbacks;     /* relaxation visits where the cell quadratic had no real
+                              root (moved to the vertex instead)                        */
+    int32_t hist_len;      /* entries of res_hist used                                 */
+    double res_hist[NDGP_HIST_LEN]; /* relative residual of the domain level per cycle */
+    double t_total_ms;     /* wall time of the call                                    */
+} ndgp_report;
+
+/* Library ABI version (NDGP_ABI_VERSION of the build). */
+int32_t ndgp_version(void);
+
+/* Message of the last failure in the calling thread ("" if none).  The string
+   stays valid until the next failing call in that thread. */
+const char *ndgp_last_error(void);
+
+/* beta(a) of Eq. (beta), 1 + 2 H r_c (1 + Hdot/(3 H^2)), for the normal branch
+   whose expansion is tuned to LCDM (Sec. II): H^2 = Omega_m a^-3 + 1 - Omega_m,
+   H0 = 1.  Host function. */
+double ndgp_beta_lcdm(double a, double omega_m, double rc);
+
+/* Bytes of device workspace that ndgp_solve / ndgp_residual need for this
+   grid and these parameters (0 if the arguments are invalid). */
+size_t ndgp_workspace_bytes(const ndgp_grid *grid, const ndgp_params *params);
+
+/*
+ * Solve Eq. (eomvarphi) on the domain grid and every patch (Sec. III.A), or
+ * fill the patches by interpolation (Sec. III.B, NDGP_MODE_INTERPOLATED).
+ *   delta[0]      domain density contrast, n^3 (its mean is projected out)
+ *   delta[1..2]   patch density contrasts, patch_n^3, measured against the
+ *                 same mean density as the domain (unused in interpolated mode,
+ *                 may be NULL there)
+ *   phi[0]        out: domain phi, n^3, zero mean (in: initial guess with
+ *                 NDGP_WARM_START)
+ *   phi[1..2]     out: patch phi, padded (patch_n+2)^3 with its ghost shell
+ *                 (the fixed boundary values interpolated from the parent)
+ *   report        optional (NULL allowed)
+ * Blocks until the domain level converged (one 8-byte device-to-host read of
+ * the residual norm per V-cycle), then until the whole call completed.
+ * Returns NDGP_ENOCONV if a relaxed level did not reach tol; phi then holds
+ * the last iterate.
+ */
+ndgp_status ndgp_solve(const ndgp_grid *grid, const ndgp_params *params,
+                       const double *const delta[1 + NDGP_MAX_PATCHES],
+                       double *const phi[1 + NDGP_MAX_PATCHES], void *workspace,
+                       size_t workspace_bytes, hipStream_t stream, ndgp_report *report);
+
+/*
+ * Discrete residual of Eq. (eomgen-disc) on one level, r = S - L_h[phi], and its
+ * relative 2-norm ||r|| / ||S||.
+ *   level         0 = domain (phi n^3 natural); 1..n_patch = patch (phi padded,
+ *                 its ghost shell used as boundary values)
+ *   delta         delta[0] is always needed (its mean defines S on every level);
+ *                 delta[level] is the level's density
+ *   r_out         optional device array, n^3 / patch_n^3 natural, physical units
+ *   rel_norm_out  optional host double
+ * Blocks until rel_norm_out is written.
+ */
+ndgp_status ndgp_residual(const ndgp_grid *grid, const ndgp_params *params, int32_t level,
+                          const double *const delta[1 + NDGP_MAX_PATCHES], const double *phi,
+                          double *r_out, double *rel_norm_out, void *workspace,
+                          size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Fifth force F = -grad(phi)/2 by central differences on every level
+ * (Sec. III.B), patches using their ghost shells.
+ *   phi[l]        as produced by ndgp_solve
+ *   force[l]      out: 3 * cells(l) doubles, x then y then z components, each
+ *                 natural (n^3 or patch_n^3)
+ * Enqueues only; does not block.
+ */
+ndgp_status ndgp_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_MAX_PATCHES],
+                       double *const force[1 + NDGP_MAX_PATCHES], hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NDGP_H */

@@ -1,0 +1,89 @@
+// ndgp_internal.h -- types and kernel launchers shared by the library's two
+// translation units (kernels, host driver).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ndgp {
+
+constexpr int kMaxLevels = 12;
+constexpr int kBlock = 256;        // threads per block of the streaming kernels
+constexpr int kReduceBlocks = 512; // fixed partial count of the deterministic reductions
+constexpr int kCoarsestMax = 8;    // the single-workgroup coarsest solve holds <= 8^3 cells
+constexpr int kCoarsestSweeps = 48;
+
+// One grid of a multigrid hierarchy.
+//  periodic: phi/alt/hat are natural n^3 with periodic wrap-around;
+//  else    : phi/alt/hat are padded (n+2)^3 with a fixed ghost shell.
+// s (the source) is always natural n^3.  Everything is in cell units: the
+// level's spacing is 1, alpha is alpha_phys / h_l^2 and s is h_l^2 S_phys.
+struct Level {
+    int n = 0;
+    int lg = 0;            // log2(n)
+    bool periodic = true;
+    double alpha = 0.0;    // cell-unit coefficient of the nonlinear term
+    double *phi = nullptr; // current iterate
+    double *alt = nullptr; // ping-pong partner of phi (same layout, same ghosts)
+    double *s = nullptr;   // source, natural n^3
+    double *hat = nullptr; // restriction of the finer iterate (levels >= 1)
+
+    size_t cells() const { return (size_t)n * n * n; }
+    size_t slots() const {
+        return periodic ? cells() : (size_t)(n + 2) * (n + 2) * (n + 2);
+    }
+};
+
+// Where a child box sits in its parent: lower corner in parent cells and a
+// cell size of 2^m / 2 parent cells.
+struct ChildBox {
+    int origin[3];
+    int m;
+    int nc;
+};
+
+// ---- kernel launchers (ndgp_kernels.hip); all enqueue on `st` ------------
+
+// Red-black half sweep: cells of colour `colour` ((i+j+k) & 1) get the root
+// of their own discrete quadratic from pin; the other colour is copied.
+void launch_smooth_half(const Level &L, const double *pin, double *pout, int colour,
+                        unsigned *fallbacks, hipStream_t st);
+// Per-block partial sums of r^2, r = s - L[phi]; optionally r_out = r * scale.
+void launch_residual_sumsq(const Level &L, double *partials, double *r_out, double r_scale,
+                           hipStream_t st);
+// Per-block partial sums of a[i]^2 (squares != 0) or a[i] over count values.
+void launch_partial_sums(const double *a, size_t count, bool squares, double *partials,
+                         hipStream_t st);
+// out[0] = sum of the kReduceBlocks partials, in a fixed order.
+void launch_reduce_final(const double *partials, double *out, hipStream_t st);
+// FAS restriction: C.hat = mean of children of F.phi; C.s = 4 * mean of children residuals.
+void launch_restrict_residual(const Level &F, const Level &C, hipStream_t st);
+// FAS coarse source C.s = L_C[C.hat] + C.s; C.phi = C.hat (interior).
+void launch_coarse_source(const Level &C, hipStream_t st);
+// F.phi += trilinear(C.phi - C.hat)
+void launch_prolong_correct(const Level &F, const Level &C, hipStream_t st);
+// F.phi = trilinear(C.phi)    (periodic levels; nested-iteration start)
+void launch_prolong_full(const Level &F, const Level &C, hipStream_t st);
+// C.s = 4 * mean of children of F.s
+void launch_restrict_source(const Level &F, const Level &C, hipStream_t st);
+// Many red-black sweeps of a <= 8^3 level in one workgroup (LDS resident).
+void launch_coarsest(const Level &L, int sweeps, unsigned *fallbacks, hipStream_t st);
+// s = f * (delta - sum[0] * inv_count_mean)     (sum: device scalar)
+void launch_source(const double *delta, size_t count, const double *sum, double inv_count_mean,
+                   double f, double *s, hipStream_t st);
+// a[i] -= sum[0] / count        (sum: device scalar; removes the mean)
+void launch_shift_by_mean(double *a, size_t count, const double *sum, hipStream_t st);
+// a[i] = v
+void launch_fill(double *a, size_t count, double v, hipStream_t st);
+// Cell-centred trilinear interpolation of a parent level into a padded child
+// (interior and ghost shell, or ghost shell only).
+void launch_interpolate(const double *parent, int np, bool parent_periodic, const ChildBox &b,
+                        double *child_pad, bool ghosts_only, hipStream_t st);
+// F = -grad(phi)/2 by central differences; f has 3 * n^3 values (x, y, z).
+void launch_force(const double *phi, int n, bool periodic, double h, double *f, hipStream_t st);
+// dst[i] = src[i]
+void launch_copy(const double *src, double *dst, size_t count, hipStream_t st);
+
+} // namespace ndgp

@@ -1,0 +1,642 @@
+// ndgp_solver.hip -- host side of the library: argument checks, workspace
+// carve-up, the FAS multigrid driver and the C ABI declared in ndgp.h.
+//
+// Order of work (arXiv:1511.08200, Sec. III.A): the periodic domain level is
+// solved first; each refinement then takes its boundary values (a ghost shell)
+// and its initial guess by interpolation from the level above and is relaxed
+// with its own multigrid hierarchy, or, in the truncated mode of Sec. III.B,
+// keeps the interpolated field.  Relaxation is red-black with the per-cell
+// root of the cell's own quadratic; multigrid is a full-approximation-storage
+// V(nu1, nu2) cycle (the coarse levels see the nonlinear operator itself).
+
+#include "ndgp.h"
+#include "ndgp_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace ndgp;
+
+namespace {
+
+thread_local std::string g_err;
+
+ndgp_status fail(ndgp_status st, std::string msg) {
+    g_err = std::move(msg);
+    return st;
+}
+
+struct HipFailure {
+    hipError_t err;
+    const char *what;
+};
+
+#define HIP_TRY(x)                                                                           \
+    do {                                                                                     \
+        hipError_t e_ = (x);                                                                 \
+        if (e_ != hipSuccess) throw HipFailure{e_, #x};                                      \
+    } while (0)
+
+// ------------------------------------------------------------------------
+// pinned 8-byte mailboxes for the per-cycle residual norm (allocated once,
+// reused across calls; each call holds its own while it runs)
+
+class PinnedSlots {
+  public:
+    double *acquire() {
+        std::lock_guard<std::mutex> g(mu_);
+        if (!free_.empty()) {
+            double *p = free_.back();
+            free_.pop_back();
+            return p;
+        }
+        void *p = nullptr;
+        HIP_TRY(hipHostMalloc(&p, 64 * sizeof(double), hipHostMallocDefault));
+        return static_cast<double *>(p);
+    }
+    void release(double *p) {
+        std::lock_guard<std::mutex> g(mu_);
+        free_.push_back(p);
+    }
+
+  private:
+    std::mutex mu_;
+    std::vector<double *> free_;
+};
+
+PinnedSlots &pinned_slots() {
+    static PinnedSlots s;
+    return s;
+}
+
+struct SlotGuard {
+    double *p;
+    SlotGuard() : p(pinned_slots().acquire()) {}
+    ~SlotGuard() { pinned_slots().release(p); }
+    SlotGuard(const SlotGuard &) = delete;
+    SlotGuard &operator=(const SlotGuard &) = delete;
+};
+
+// ------------------------------------------------------------------------
+// configuration
+
+int ilog2(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+struct Cfg {
+    int n = 0, lgn = 0, nl = 0;
+    double h = 0.0;
+    int np = 0;
+    int pn[NDGP_MAX_PATCHES] = {0, 0};
+    int po[NDGP_MAX_PATCHES][3] = {{0, 0, 0}, {0, 0, 0}};
+    int pnl[NDGP_MAX_PATCHES] = {0, 0};
+    double alpha = 0.0; // r_c^2 / (3 beta a^2), physical
+    double fsrc = 0.0;  // Omega_m / (a beta)
+    double tol = 0.0;
+    int maxc = 50, nu1 = 2, nu2 = 2;
+    int mode = NDGP_MODE_FULL, prec = NDGP_PREC_FP64;
+    unsigned flags = 0;
+
+    double hl(int level) const { return h / (double)(1 << level); } // patch p is level p+1
+    int nlev(int level) const { return level == 0 ? n : pn[level - 1]; }
+};
+
+// levels of a hierarchy that coarsens by 2 down to <= 8 cells per side
+int default_levels(int n) {
+    int l = 1;
+    while ((n >> (l - 1)) > kCoarsestMax) ++l;
+    return l;
+}
+
+// Can every multigrid level of a Dirichlet child interpolate its ghost shell
+// (and, for m = 0, its interior) from a padded parent of np cells?
+bool child_fits(int np, const int origin[3], int nc, int nlev) {
+    for (int m = 0; m < nlev; ++m) {
+        const int nm = nc >> m;
+        const double q = std::ldexp(1.0, m - 1);
+        for (int a = 0; a < 3; ++a) {
+            const double xmin = origin[a] + (-1 + 0.5) * q - 0.5;
+            const double xmax = origin[a] + (nm + 0.5) * q - 0.5;
+            if (std::floor(xmin) < -1.0 || std::floor(xmax) + 1.0 > (double)np) return false;
+        }
+    }
+    return true;
+}
+
+bool resolve(const ndgp_grid *g, const ndgp_params *p, Cfg &c, std::string &why) {
+    if (!g || !p) {
+        why = "grid and params must not be NULL";
+        return false;
+    }
+    if (!pow2(g->n) || g->n < 8 || g->n > 1024) {
+        why = "n must be a power of two in [8, 1024]";
+        return false;
+    }
+    if (!finite_pos(g->h)) {
+        why = "h must be finite and > 0";
+        return false;
+    }
+    if (!(std::isfinite(p->rc) && p->rc >= 0.0) || !finite_pos(p->beta) || !finite_pos(p->a) ||
+        !finite_pos(p->omega_m)) {
+        why = "need rc >= 0 and beta, a, omega_m > 0, all finite";
+        return false;
+    }
+    if (!(std::isfinite(p->tol) && p->tol >= 0.0)) {
+        why = "tol must be finite and >= 0";
+        return false;
+    }
+    c.n = g->n;
+    c.lgn = ilog2(g->n);
+    c.h = g->h;
+    c.maxc = p->max_cycles ? p->max_cycles : 50;
+    c.nu1 = p->nu1 ? p->nu1 : 2;
+    c.nu2 = p->nu2 ? p->nu2 : 2;
+    if (c.maxc < 1 || c.maxc > 1000 || c.nu1 < 1 || c.nu1 > 16 || c.nu2 < 1 || c.nu2 > 16) {
+        why = "max_cycles must be in [1, 1000] and nu1, nu2 in [1, 16] (0 = default)";
+        return false;
+    }
+    c.nl = p->n_levels ? p->n_levels : default_levels(c.n);
+    if (c.nl < 1 || c.nl > c.lgn || (c.n >> (c.nl - 1)) > kCoarsestMax) {
+        why = "n_levels must coarsen the domain grid to at most 8 and at least 2 cells per side";
+        return false;
+    }
+    if (p->mode != NDGP_MODE_FULL && p->mode != NDGP_MODE_INTERPOLATED) {
+        why = "unknown mode";
+        return false;
+    }
+    if (p->precision != NDGP_PREC_FP64) {
+        why = "precision must be NDGP_PREC_FP64 in this build";
+        return false;
+    }
+    if (p->flags & ~NDGP_WARM_START) {
+        why = "unknown flag bits";
+        return false;
+    }
+    c.mode = p->mode;
+    c.prec = p->precision;
+    c.flags = p->flags;
+    c.tol = p->tol;
+    c.alpha = p->rc * p->rc / (3.0 * p->beta * p->a * p->a);
+    c.fsrc = p->omega_m / (p->a * p->beta);
+    if (g->n_patch < 0 || g->n_patch > NDGP_MAX_PATCHES) {
+        why = "n_patch must be 0, 1 or 2";
+        return false;
+    }
+    c.np = g->n_patch;
+    for (int q = 0; q < c.np; ++q) {
+        const int m = g->patch_n[q];
+        const int parent_n = q == 0 ? c.n : c.pn[0];
+        if (!pow2(m) || m < 8 || m > 512 || m > 2 * parent_n) {
+            why = "patch_n must be a power of two in [8, 512] covering at most its parent";
+            return false;
+        }
+        c.pn[q] = m;
+        c.pnl[q] = default_levels(m);
+        for (int a = 0; a < 3; ++a) {
+            const int o = g->patch_origin[q][a];
+            if (o < -4 * c.n || o > 4 * c.n) {
+                why = "patch origin out of range";
+                return false;
+            }
+            c.po[q][a] = o;
+        }
+        if (q == 1) {
+            const int need = c.mode == NDGP_MODE_FULL ? c.pnl[1] : 1;
+            if (!child_fits(c.pn[0], c.po[1], m, need)) {
+                why = "patch 2 must lie inside patch 1 with room for the interpolation stencils "
+                      "of its multigrid levels";
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------------
+// workspace
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct Plan {
+    Cfg c;
+    Level base[kMaxLevels];
+    Level patch[NDGP_MAX_PATCHES][kMaxLevels];
+    double *partials = nullptr;
+    double *scal = nullptr; // [0] sum delta, [1] sum s^2, [2] sum r^2, [3] sum phi
+    unsigned *fallbacks = nullptr;
+};
+
+// Lays out every array in `base` (or only counts bytes when base == nullptr).
+size_t carve(Plan &P, char *base) {
+    Carver cv{base};
+    const Cfg &c = P.c;
+    for (int l = 0; l < c.nl; ++l) {
+        Level &L = P.base[l];
+        L.n = c.n >> l;
+        L.lg = c.lgn - l;
+        L.periodic = true;
+        const double hl = c.h * (double)(1 << l);
+        L.alpha = c.alpha / (hl * hl);
+        L.phi = l ? cv.take<double>(L.slots()) : nullptr;
+        L.alt = cv.take<double>(L.slots());
+        L.s = cv.take<double>(L.cells());
+        L.hat = l ? cv.take<double>(L.slots()) : nullptr;
+    }
+    if (c.mode == NDGP_MODE_FULL) {
+        for (int q = 0; q < c.np; ++q) {
+            const double hp = c.hl(q + 1);
+            for (int m = 0; m < c.pnl[q]; ++m) {
+                Level &L = P.patch[q][m];
+                L.n = c.pn[q] >> m;
+                L.lg = ilog2(L.n);
+                L.periodic = false;
+                const double hm = hp * (double)(1 << m);
+                L.alpha = c.alpha / (hm * hm);
+                L.phi = m ? cv.take<double>(L.slots()) : nullptr;
+                L.alt = cv.take<double>(L.slots());
+                L.s = cv.take<double>(L.cells());
+                L.hat = m ? cv.take<double>(L.slots()) : nullptr;
+            }
+        }
+    }
+    P.partials = cv.take<double>(kReduceBlocks);
+    P.scal = cv.take<double>(16);
+    P.fallbacks = cv.take<unsigned>(16);
+    return cv.off;
+}
+
+// workspace of ndgp_residual on the largest level
+size_t residual_bytes(const Cfg &c) {
+    size_t cells = (size_t)c.n * c.n * c.n;
+    for (int q = 0; q < c.np; ++q) cells = std::max(cells, (size_t)c.pn[q] * c.pn[q] * c.pn[q]);
+    Carver cv{nullptr};
+    cv.take<double>(cells);
+    cv.take<double>(kReduceBlocks);
+    cv.take<double>(16);
+    return cv.off;
+}
+
+size_t total_bytes(const Cfg &c) {
+    Plan P;
+    P.c = c;
+    return std::max(carve(P, nullptr), residual_bytes(c)) + 256;
+}
+
+char *aligned_base(void *ws) {
+    const uintptr_t u = reinterpret_cast<uintptr_t>(ws);
+    return reinterpret_cast<char *>((u + 255) & ~(uintptr_t)255);
+}
+
+// ------------------------------------------------------------------------
+// the multigrid driver
+
+struct Runner {
+    Plan &P;
+    hipStream_t st;
+    double *host;
+
+    double read_scalar(const double *dev) {
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return host[0];
+    }
+
+    double sum(const double *a, size_t count, bool squares, int slot) {
+        launch_partial_sums(a, count, squares, P.partials, st);
+        launch_reduce_final(P.partials, P.scal + slot, st);
+        return read_scalar(P.scal + slot);
+    }
+
+    double residual_sumsq(const Level &L) {
+        launch_residual_sumsq(L, P.partials, nullptr, 0.0, st);
+        launch_reduce_final(P.partials, P.scal + 2, st);
+        return read_scalar(P.scal + 2);
+    }
+
+    void smooth(Level &L, int sweeps) {
+        for (int s = 0; s < sweeps; ++s)
+            for (int col = 0; col < 2; ++col) {
+                launch_smooth_half(L, L.phi, L.alt, col, P.fallbacks, st);
+                std::swap(L.phi, L.alt);
+            }
+    }
+
+    void vcycle(Level *H, int nl, int l) {
+        Level &L = H[l];
+        if (l == nl - 1) {
+            launch_coarsest(L, kCoarsestSweeps, P.fallbacks, st);
+            return;
+        }
+        smooth(L, P.c.nu1);
+        Level &C = H[l + 1];
+        launch_restrict_residual(L, C, st);
+        launch_coarse_source(C, st);
+        vcycle(H, nl, l + 1);
+        launch_prolong_correct(L, C, st);
+        smooth(L, P.c.nu2);
+    }
+
+    // Initial guess by nested iteration: average the source down, solve the
+    // coarsest level, then interpolate each solution up and improve it by one
+    // V-cycle (the way the paper starts a refinement from its coarser level,
+    // applied to the multigrid levels; a zero guess can diverge for strongly
+    // screened sources).
+    void nested_start(Level *H, int nl) {
+        for (int l = 1; l < nl; ++l) launch_restrict_source(H[l - 1], H[l], st);
+        launch_fill(H[nl - 1].phi, H[nl - 1].slots(), 0.0, st);
+        launch_coarsest(H[nl - 1], kCoarsestSweeps, P.fallbacks, st);
+        for (int l = nl - 2; l >= 0; --l) {
+            launch_prolong_full(H[l], H[l + 1], st);
+            if (l > 0) vcycle(H, nl, l);
+        }
+    }
+
+    // V-cycles on H[0] until ||r|| <= tol ||s|| (tol > 0) or until the
+    // residual stops falling (tol == 0).
+    ndgp_status drive(Level *H, int nl, double snorm2, int &cycles, double &rel, double *hist,
+                      int *hist_len) {
+        const Cfg &c = P.c;
+        rel = std::sqrt(residual_sumsq(H[0]) / snorm2);
+        const double rel0 = rel;
+        double prev = rel;
+        int slow = 0;
+        cycles = 0;
+        while (cycles < c.maxc) {
+            if (c.tol > 0.0 && rel <= c.tol) break;
+            vcycle(H, nl, 0);
+            ++cycles;
+            rel = std::sqrt(residual_sumsq(H[0]) / snorm2);
+            if (hist && cycles - 1 < NDGP_HIST_LEN) {
+                hist[cycles - 1] = rel;
+                *hist_len = cycles;
+            }
+            if (!std::isfinite(rel) || rel > 1e6 * std::max(rel0, 1.0))
+                return fail(NDGP_ENOCONV, "multigrid diverged");
+            if (c.tol == 0.0) {
+                slow = rel > 0.7 * prev ? slow + 1 : 0;
+                if (slow >= 2) break;
+            }
+            prev = rel;
+        }
+        if (c.tol > 0.0 && rel > c.tol)
+            return fail(NDGP_ENOCONV, "tolerance not reached within max_cycles");
+        if (c.tol == 0.0 && rel > 1e-11)
+            return fail(NDGP_ENOCONV, "stagnated above rounding level");
+        return NDGP_OK;
+    }
+};
+
+ndgp_status check_arrays(const Cfg &c, const double *const *delta, double *const *phi,
+                         bool need_patch_delta) {
+    if (!delta || !phi || !delta[0] || !phi[0])
+        return fail(NDGP_EINVAL, "delta[0] and phi[0] must not be NULL");
+    for (int q = 0; q < c.np; ++q) {
+        if (!phi[q + 1]) return fail(NDGP_EINVAL, "phi of every patch must not be NULL");
+        if (need_patch_delta && !delta[q + 1])
+            return fail(NDGP_EINVAL, "delta of every patch must not be NULL in full mode");
+    }
+    return NDGP_OK;
+}
+
+ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
+                       const double *const delta[], double *const phi[], void *ws,
+                       size_t ws_bytes, hipStream_t st, ndgp_report *rep) {
+    const auto t0 = std::chrono::steady_clock::now();
+    Plan P;
+    std::string why;
+    if (!resolve(grid, params, P.c, why)) return fail(NDGP_EINVAL, why);
+    const Cfg &c = P.c;
+    ndgp_status s = check_arrays(c, delta, phi, c.mode == NDGP_MODE_FULL);
+    if (s != NDGP_OK) return s;
+    const size_t need = total_bytes(c);
+    if (!ws || ws_bytes < need)
+        return fail(NDGP_ENOMEM, "workspace smaller than ndgp_workspace_bytes() = " +
+                                     std::to_string(need));
+    carve(P, aligned_base(ws));
+    P.base[0].phi = phi[0];
+
+    ndgp_report R;
+    std::memset(&R, 0, sizeof(R));
+    for (int l = 0; l <= NDGP_MAX_PATCHES; ++l) R.rel_res[l] = -1.0;
+    SlotGuard slot;
+    Runner run{P, st, slot.p};
+    HIP_TRY(hipMemsetAsync(P.fallbacks, 0, sizeof(unsigned), st));
+
+    // domain source: S = Omega_m (delta - mean) / (a beta), in cell units (x h^2)
+    const size_t cells0 = (size_t)c.n * c.n * c.n;
+    const double dsum = run.sum(delta[0], cells0, false, 0);
+    if (!std::isfinite(dsum)) return fail(NDGP_EINVAL, "delta[0] has non-finite values");
+    R.removed_mean = dsum / (double)cells0;
+    launch_source(delta[0], cells0, P.scal + 0, 1.0 / (double)cells0, c.fsrc * c.h * c.h,
+                  P.base[0].s, st);
+    const double snorm2 = run.sum(P.base[0].s, cells0, true, 1);
+
+    ndgp_status status = NDGP_OK;
+    if (snorm2 == 0.0) {
+        launch_fill(phi[0], cells0, 0.0, st); // no source: phi = 0
+        R.rel_res[0] = 0.0;
+    } else {
+        if (!(c.flags & NDGP_WARM_START)) run.nested_start(P.base, c.nl);
+        double rel = 0.0;
+        status = run.drive(P.base, c.nl, snorm2, R.cycles[0], rel, R.res_hist, &R.hist_len);
+        R.rel_res[0] = rel;
+        if (status != NDGP_OK && !std::isfinite(rel)) {
+            if (rep) *rep = R;
+            return status;
+        }
+    }
+    // gauge: only derivatives of phi enter, report the zero-mean field
+    const double psum = run.sum(phi[0], cells0, false, 3);
+    R.phi_mean = psum / (double)cells0;
+    launch_shift_by_mean(phi[0], cells0, P.scal + 3, st);
+
+    for (int q = 0; q < c.np; ++q) {
+        const bool parent_periodic = q == 0;
+        const double *parent = phi[q];
+        const int npar = q == 0 ? c.n : c.pn[0];
+        ChildBox b0{{c.po[q][0], c.po[q][1], c.po[q][2]}, 0, c.pn[q]};
+        launch_interpolate(parent, npar, parent_periodic, b0, phi[q + 1], false, st);
+        if (c.mode == NDGP_MODE_INTERPOLATED) continue; // Sec. III.B: keep the guess
+        Level *H = P.patch[q];
+        H[0].phi = phi[q + 1];
+        launch_interpolate(parent, npar, parent_periodic, b0, H[0].alt, true, st);
+        for (int m = 1; m < c.pnl[q]; ++m) {
+            ChildBox bm{{c.po[q][0], c.po[q][1], c.po[q][2]}, m, c.pn[q] >> m};
+            launch_interpolate(parent, npar, parent_periodic, bm, H[m].phi, true, st);
+            launch_interpolate(parent, npar, parent_periodic, bm, H[m].alt, true, st);
+            launch_interpolate(parent, npar, parent_periodic, bm, H[m].hat, true, st);
+        }
+        const size_t cq = (size_t)c.pn[q] * c.pn[q] * c.pn[q];
+        const double hq = c.hl(q + 1);
+        launch_source(delta[q + 1], cq, P.scal + 0, 1.0 / (double)cells0, c.fsrc * hq * hq,
+                      H[0].s, st);
+        double sn2 = run.sum(H[0].s, cq, true, 1);
+        if (sn2 == 0.0) sn2 = std::max(run.residual_sumsq(H[0]), 1e-300);
+        double rel = 0.0;
+        const ndgp_status sq = run.drive(H, c.pnl[q], sn2, R.cycles[q + 1], rel, nullptr, nullptr);
+        R.rel_res[q + 1] = rel;
+        if (sq != NDGP_OK && status == NDGP_OK) status = sq;
+    }
+    unsigned fb = 0;
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(slot.p, P.fallbacks, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::memcpy(&fb, slot.p, sizeof(unsigned));
+    R.fallbacks = (int32_t)fb;
+    R.t_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = R;
+    return status;
+}
+
+ndgp_status residual_impl(const ndgp_grid *grid, const ndgp_params *params, int32_t level,
+                          const double *const delta[], const double *phi, double *r_out,
+                          double *rel_out, void *ws, size_t ws_bytes, hipStream_t st) {
+    Cfg c;
+    std::string why;
+    if (!resolve(grid, params, c, why)) return fail(NDGP_EINVAL, why);
+    if (level < 0 || level > c.np) return fail(NDGP_EINVAL, "level out of range");
+    if (!delta || !delta[0] || !delta[level] || !phi)
+        return fail(NDGP_EINVAL, "delta[0], delta[level] and phi must not be NULL");
+    const size_t need = total_bytes(c);
+    if (!ws || ws_bytes < need)
+        return fail(NDGP_ENOMEM, "workspace smaller than ndgp_workspace_bytes() = " +
+                                     std::to_string(need));
+    Plan P;
+    P.c = c;
+    Carver cv{aligned_base(ws)};
+    const int nlv = c.nlev(level);
+    Level L;
+    L.n = nlv;
+    L.lg = ilog2(nlv);
+    L.periodic = level == 0;
+    const double hl = c.hl(level);
+    L.alpha = c.alpha / (hl * hl);
+    L.phi = const_cast<double *>(phi);
+    L.s = cv.take<double>(L.cells());
+    P.partials = cv.take<double>(kReduceBlocks);
+    P.scal = cv.take<double>(16);
+    SlotGuard slot;
+    Runner run{P, st, slot.p};
+    const size_t cells0 = (size_t)c.n * c.n * c.n;
+    const double dsum = run.sum(delta[0], cells0, false, 0);
+    if (!std::isfinite(dsum)) return fail(NDGP_EINVAL, "delta[0] has non-finite values");
+    launch_source(delta[level], L.cells(), P.scal + 0, 1.0 / (double)cells0, c.fsrc * hl * hl,
+                  L.s, st);
+    const double sn2 = run.sum(L.s, L.cells(), true, 1);
+    launch_residual_sumsq(L, P.partials, r_out, 1.0 / (hl * hl), st);
+    launch_reduce_final(P.partials, P.scal + 2, st);
+    const double rr = run.read_scalar(P.scal + 2);
+    if (rel_out) *rel_out = sn2 > 0.0 ? std::sqrt(rr / sn2) : std::sqrt(rr);
+    return NDGP_OK;
+}
+
+ndgp_status force_impl(const ndgp_grid *grid, const double *const phi[], double *const force[],
+                       hipStream_t st) {
+    if (!grid) return fail(NDGP_EINVAL, "grid must not be NULL");
+    ndgp_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.beta = 1.0;
+    p.a = 1.0;
+    p.omega_m = 1.0;
+    p.mode = NDGP_MODE_INTERPOLATED; // geometry checks only need level 0 of patch 2
+    Cfg c;
+    std::string why;
+    if (!resolve(grid, &p, c, why)) return fail(NDGP_EINVAL, why);
+    if (!phi || !force) return fail(NDGP_EINVAL, "phi and force must not be NULL");
+    for (int l = 0; l <= c.np; ++l)
+        if (!phi[l] || !force[l]) return fail(NDGP_EINVAL, "phi/force of every level must not be NULL");
+    for (int l = 0; l <= c.np; ++l) launch_force(phi[l], c.nlev(l), l == 0, c.hl(l), force[l], st);
+    HIP_TRY(hipGetLastError());
+    return NDGP_OK;
+}
+
+template <class F>
+ndgp_status guarded(F &&f) {
+    try {
+        return f();
+    } catch (const HipFailure &e) {
+        return fail(NDGP_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
+    } catch (const std::exception &e) {
+        return fail(NDGP_EDEVICE, e.what());
+    } catch (...) {
+        return fail(NDGP_EDEVICE, "unknown failure");
+    }
+}
+
+} // namespace
+
+// ------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+int32_t ndgp_version(void) { return NDGP_ABI_VERSION; }
+
+const char *ndgp_last_error(void) { return g_err.c_str(); }
+
+double ndgp_beta_lcdm(double a, double omega_m, double rc) {
+    // E^2 = Om a^-3 + 1 - Om; Hdot / (3 H^2) = -Om(a) / 2 with Om(a) = Om a^-3 / E^2
+    const double E2 = omega_m / (a * a * a) + 1.0 - omega_m;
+    const double om_a = omega_m / (a * a * a) / E2;
+    return 1.0 + 2.0 * std::sqrt(E2) * rc * (1.0 - 0.5 * om_a);
+}
+
+size_t ndgp_workspace_bytes(const ndgp_grid *grid, const ndgp_params *params) {
+    Cfg c;
+    std::string why;
+    if (!resolve(grid, params, c, why)) {
+        g_err = why;
+        return 0;
+    }
+    return total_bytes(c);
+}
+
+ndgp_status ndgp_solve(const ndgp_grid *grid, const ndgp_params *params,
+                       const double *const delta[1 + NDGP_MAX_PATCHES],
+                       double *const phi[1 + NDGP_MAX_PATCHES], void *workspace,
+                       size_t workspace_bytes, hipStream_t stream, ndgp_report *report) {
+    return guarded([&] {
+        return solve_impl(grid, params, delta, phi, workspace, workspace_bytes, stream, report);
+    });
+}
+
+ndgp_status ndgp_residual(const ndgp_grid *grid, const ndgp_params *params, int32_t level,
+                          const double *const delta[1 + NDGP_MAX_PATCHES], const double *phi,
+                          double *r_out, double *rel_norm_out, void *workspace,
+                          size_t workspace_bytes, hipStream_t stream) {
+    return guarded([&] {
+        return residual_impl(grid, params, level, delta, phi, r_out, rel_norm_out, workspace,
+                             workspace_bytes, stream);
+    });
+}
+
+ndgp_status ndgp_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_MAX_PATCHES],
+                       double *const force[1 + NDGP_MAX_PATCHES], hipStream_t stream) {
+    return guarded([&] { return force_impl(grid, phi, force, stream); });
+}
+
+} // extern "C"

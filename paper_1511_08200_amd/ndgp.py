@@ -1,0 +1,299 @@
+"""Python binding of libndgp.so (the C ABI of include/ndgp.h).
+
+Argument marshalling only: torch supplies device memory and the stream, every
+step of the solve runs in the library's HIP kernels.  There is no CPU path: if
+the library is not built, or no GPU is present, the calls raise.
+
+Units: lengths in c/H0 (``cell_size`` converts from Mpc/h), phi in c^2.
+Arrays: float64, natural layout [z][y][x]; patch solutions are padded with a
+one-cell ghost shell, shape (m+2, m+2, m+2).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libndgp.so")
+C_OVER_H0_MPC_H = 2997.92458  # c / H0 in Mpc/h
+
+NDGP_OK, NDGP_EINVAL, NDGP_ENOMEM, NDGP_ENOCONV, NDGP_EDEVICE = 0, -1, -2, -3, -4
+MODE_FULL, MODE_INTERPOLATED = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+WARM_START = 1
+MAX_PATCHES = 2
+HIST_LEN = 64
+
+_STATUS = {NDGP_EINVAL: "EINVAL", NDGP_ENOMEM: "ENOMEM", NDGP_ENOCONV: "ENOCONV",
+           NDGP_EDEVICE: "EDEVICE"}
+
+
+class NdgpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ndgp {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("h", ctypes.c_double), ("n_patch", ctypes.c_int32),
+                ("patch_n", ctypes.c_int32 * MAX_PATCHES),
+                ("patch_origin", (ctypes.c_int32 * 3) * MAX_PATCHES)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("rc", ctypes.c_double), ("beta", ctypes.c_double), ("a", ctypes.c_double),
+                ("omega_m", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_cycles", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int32 * (1 + MAX_PATCHES)),
+                ("rel_res", ctypes.c_double * (1 + MAX_PATCHES)),
+                ("removed_mean", ctypes.c_double), ("phi_mean", ctypes.c_double),
+                ("fallbacks", ctypes.c_int32), ("hist_len", ctypes.c_int32),
+                ("res_hist", ctypes.c_double * HIST_LEN), ("t_total_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libndgp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run python -m paper_1511_08200_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.ndgp_version.restype = ctypes.c_int32
+        L.ndgp_last_error.restype = ctypes.c_char_p
+        L.ndgp_beta_lcdm.restype = ctypes.c_double
+        L.ndgp_beta_lcdm.argtypes = [ctypes.c_double] * 3
+        L.ndgp_workspace_bytes.restype = ctypes.c_size_t
+        L.ndgp_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params)]
+        arr3 = vp * (1 + MAX_PATCHES)
+        L.ndgp_solve.restype = ctypes.c_int
+        L.ndgp_solve.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), arr3, arr3, vp,
+                                 ctypes.c_size_t, vp, ctypes.POINTER(_Report)]
+        L.ndgp_residual.restype = ctypes.c_int
+        L.ndgp_residual.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int32,
+                                    arr3, vp, vp, ctypes.POINTER(ctypes.c_double), vp,
+                                    ctypes.c_size_t, vp]
+        L.ndgp_force.restype = ctypes.c_int
+        L.ndgp_force.argtypes = [ctypes.POINTER(_Grid), arr3, arr3, vp]
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != NDGP_OK:
+        raise NdgpError(status, lib().ndgp_last_error().decode())
+
+
+# --------------------------------------------------------------------------
+# parameters
+
+def cell_size(box_mpc_h: float, n: int) -> float:
+    """Cell size in c/H0 of n cells across a box of box_mpc_h Mpc/h."""
+    return box_mpc_h / n / C_OVER_H0_MPC_H
+
+
+def beta_lcdm(a: float, omega_m: float, rc: float) -> float:
+    """beta(a) of Eq. (beta) for an LCDM expansion history (library routine)."""
+    return float(lib().ndgp_beta_lcdm(a, omega_m, rc))
+
+
+@dataclasses.dataclass
+class Patch:
+    n: int                 # cells per side
+    origin: tuple          # lower corner (x, y, z) in parent cells
+
+
+@dataclasses.dataclass
+class Grid:
+    n: int
+    h: float
+    patches: list = dataclasses.field(default_factory=list)
+
+    def _c(self) -> _Grid:
+        g = _Grid()
+        g.n, g.h, g.n_patch = self.n, self.h, len(self.patches)
+        for q, p in enumerate(self.patches):
+            g.patch_n[q] = p.n
+            for a in range(3):
+                g.patch_origin[q][a] = int(p.origin[a])
+        return g
+
+    def level_n(self, level: int) -> int:
+        return self.n if level == 0 else self.patches[level - 1].n
+
+    def level_h(self, level: int) -> float:
+        return self.h / (1 << level)
+
+
+@dataclasses.dataclass
+class Params:
+    rc: float = 1.0
+    beta: Optional[float] = None  # None: beta_lcdm(a, omega_m, rc)
+    a: float = 1.0
+    omega_m: float = 0.3
+    tol: float = 1e-10
+    max_cycles: int = 50
+    nu1: int = 2
+    nu2: int = 2
+    n_levels: int = 0
+    mode: int = MODE_FULL
+    precision: int = PREC_FP64
+    warm_start: bool = False
+
+    def _c(self) -> _Params:
+        p = _Params()
+        p.rc, p.a, p.omega_m, p.tol = self.rc, self.a, self.omega_m, self.tol
+        p.beta = self.beta if self.beta is not None else beta_lcdm(self.a, self.omega_m, self.rc)
+        p.max_cycles, p.nu1, p.nu2, p.n_levels = self.max_cycles, self.nu1, self.nu2, self.n_levels
+        p.mode, p.precision = self.mode, self.precision
+        p.flags = WARM_START if self.warm_start else 0
+        return p
+
+
+@dataclasses.dataclass
+class Report:
+    cycles: list
+    rel_res: list
+    removed_mean: float
+    phi_mean: float
+    fallbacks: int
+    history: list
+    t_total_ms: float
+    status: int = NDGP_OK
+
+
+def _report(r: _Report, status: int) -> Report:
+    return Report(cycles=list(r.cycles), rel_res=list(r.rel_res), removed_mean=r.removed_mean,
+                  phi_mean=r.phi_mean, fallbacks=r.fallbacks,
+                  history=[r.res_hist[i] for i in range(r.hist_len)], t_total_ms=r.t_total_ms,
+                  status=status)
+
+
+# --------------------------------------------------------------------------
+# device buffers
+
+def _dev(t: torch.Tensor, shape=None, name="array") -> int:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA/HIP tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+_ws_cache: dict = {}
+
+
+def workspace_bytes(grid: Grid, params: Params) -> int:
+    g, p = grid._c(), params._c()
+    nb = lib().ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p))
+    if nb == 0:
+        raise NdgpError(NDGP_EINVAL, lib().ndgp_last_error().decode())
+    return int(nb)
+
+
+def workspace(nbytes: int, device=None) -> torch.Tensor:
+    """A cached uint8 workspace of at least nbytes on the device."""
+    dev = torch.device(device if device is not None else "cuda")
+    key = (dev.type, dev.index if dev.index is not None else torch.cuda.current_device())
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        _ws_cache[key] = ws
+    return ws
+
+
+def _arr3(ptrs):
+    a = (ctypes.c_void_p * (1 + MAX_PATCHES))()
+    for i, p in enumerate(ptrs):
+        a[i] = p
+    return a
+
+
+def alloc_phi(grid: Grid, device="cuda") -> list:
+    out = [torch.zeros((grid.n,) * 3, dtype=torch.float64, device=device)]
+    for p in grid.patches:
+        out.append(torch.zeros((p.n + 2,) * 3, dtype=torch.float64, device=device))
+    return out
+
+
+def solve(grid: Grid, params: Params, delta: Sequence[torch.Tensor], phi=None, ws=None,
+          stream=None, check: bool = True):
+    """Run ndgp_solve.  ``delta``: [domain (n^3), patch1 (m^3), ...] device
+    float64; returns (phi list, Report).  With check=False a non-OK status is
+    reported in Report.status instead of raised."""
+    g, p = grid._c(), params._c()
+    if phi is None:
+        phi = alloc_phi(grid, device=delta[0].device)
+    dptr = [_dev(delta[0], (grid.n,) * 3, "delta[0]")]
+    for q, pt in enumerate(grid.patches):
+        if q + 1 < len(delta) and delta[q + 1] is not None:
+            dptr.append(_dev(delta[q + 1], (pt.n,) * 3, f"delta[{q + 1}]"))
+        else:
+            dptr.append(None)
+    pptr = [_dev(phi[0], (grid.n,) * 3, "phi[0]")]
+    for q, pt in enumerate(grid.patches):
+        pptr.append(_dev(phi[q + 1], (pt.n + 2,) * 3, f"phi[{q + 1}]"))
+    nb = workspace_bytes(grid, params)
+    if ws is None:
+        ws = workspace(nb, delta[0].device)
+    rep = _Report()
+    st = lib().ndgp_solve(ctypes.byref(g), ctypes.byref(p), _arr3(dptr), _arr3(pptr),
+                          ws.data_ptr(), ws.numel(), _stream(stream), ctypes.byref(rep))
+    if check:
+        _check(st)
+    elif st != NDGP_OK and st != NDGP_ENOCONV:
+        _check(st)
+    return phi, _report(rep, st)
+
+
+def residual(grid: Grid, params: Params, delta: Sequence[torch.Tensor], phi: torch.Tensor,
+             level: int = 0, want_r: bool = True, ws=None, stream=None):
+    """r = S - L_h[phi] (physical units) on one level, and ||r|| / ||S||."""
+    g, p = grid._c(), params._c()
+    n = grid.level_n(level)
+    shape = (n,) * 3 if level == 0 else (n + 2,) * 3
+    dptr = [_dev(delta[0], (grid.n,) * 3, "delta[0]")] + [None] * MAX_PATCHES
+    if level:
+        dptr[level] = _dev(delta[level], (n,) * 3, f"delta[{level}]")
+    r = torch.empty((n,) * 3, dtype=torch.float64, device=phi.device) if want_r else None
+    nb = workspace_bytes(grid, params)
+    if ws is None:
+        ws = workspace(nb, phi.device)
+    rel = ctypes.c_double()
+    _check(lib().ndgp_residual(ctypes.byref(g), ctypes.byref(p), level, _arr3(dptr),
+                               _dev(phi, shape, "phi"), r.data_ptr() if r is not None else None,
+                               ctypes.byref(rel), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return r, rel.value
+
+
+def force(grid: Grid, phi: Sequence[torch.Tensor], stream=None) -> list:
+    """F = -grad(phi)/2 on every level: list of (3, m, m, m) tensors."""
+    g = grid._c()
+    out, pptr = [], []
+    for lvl in range(1 + len(grid.patches)):
+        n = grid.level_n(lvl)
+        shape = (n,) * 3 if lvl == 0 else (n + 2,) * 3
+        pptr.append(_dev(phi[lvl], shape, f"phi[{lvl}]"))
+        out.append(torch.empty((3, n, n, n), dtype=torch.float64, device=phi[lvl].device))
+    _check(lib().ndgp_force(ctypes.byref(g), _arr3(pptr), _arr3([o.data_ptr() for o in out]),
+                            _stream(stream)))
+    return out

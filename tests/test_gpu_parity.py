@@ -1,0 +1,288 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: FP64 solutions agree to a relative L2 error <= 1e-11 when both sides are
+run to rounding-level stagnation (the tolerance the FP64 path is built for);
+residuals, interpolation and forces agree element by element to rounding.
+At the full 256^3 / 512^3 sizes, where the oracle cannot afford a solve, the
+oracle evaluates the residual of the GPU answer (everywhere, and at sampled
+cells against the GPU's own residual).
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1511_08200_amd import ndgp, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+PHI_TOL = 1e-11
+
+
+def say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ndgp.lib()  # fails loudly if the HIP library is missing
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def oracle_periodic(delta, h, rc, omega_m=0.3, a=1.0):
+    beta = O.beta_lcdm(a, omega_m, rc)
+    S, _ = O.source(delta, omega_m, a, beta)
+    phi, info = O.solve_periodic(S, h, O.alpha(rc, beta, a))
+    assert info.status == 0, info
+    return phi, S
+
+
+def gpu_solve(delta_list, grid, **kw):
+    params = ndgp.Params(**kw)
+    phi, rep = ndgp.solve(grid, params, [dev(d) if d is not None else None for d in delta_list])
+    torch.cuda.synchronize()
+    return [p.cpu().numpy() for p in phi], rep
+
+
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,box,sigma,tophats,rc,seed", [
+    (32, 64.0, 1.0, 0, 1.0, 1512),     # the 32^3 plain FP64 configuration
+    (32, 64.0, 2.0, 4, 5.0, 7),
+    (64, 64.0, 2.0, 20, 1.0, 8),       # lognormal + top-hats, several tiles
+    (64, 128.0, 2.5, 0, 5.0, 9),       # strongest screening of the 512^3 set
+    (16, 16.0, 1.0, 1, 0.5, 3),
+])
+def test_periodic_solution_matches_oracle(n, box, sigma, tophats, rc, seed):
+    say(f"periodic n={n} sigma={sigma} tophats={tophats} rc={rc}")
+    f = synth.make_field(n, sigma, seed, n_tophats=tophats)
+    h = ndgp.cell_size(box, n)
+    phio, S = oracle_periodic(f.delta, h, rc)
+    (phig,), rep = gpu_solve([f.delta], ndgp.Grid(n=n, h=h), rc=rc, tol=0.0, max_cycles=200)
+    say(f"  cycles={rep.cycles[0]} rel_res={rep.rel_res[0]:.2e} fallbacks={rep.fallbacks}")
+    assert rep.status == 0
+    assert abs(phig.mean()) < 1e-15 * np.abs(phig).max()
+    assert rel(phig, phio) <= PHI_TOL
+
+
+def test_tolerance_stop_and_history():
+    n = 32
+    f = synth.make_field(n, 1.0, 1512)
+    h = ndgp.cell_size(64.0, n)
+    (phig,), rep = gpu_solve([f.delta], ndgp.Grid(n=n, h=h), rc=1.0, tol=1e-10)
+    say(f"tol stop: cycles={rep.cycles[0]} hist={rep.history}")
+    assert rep.status == 0 and rep.rel_res[0] <= 1e-10
+    assert rep.cycles[0] <= 25
+    assert len(rep.history) == rep.cycles[0]
+    assert all(b < a for a, b in zip(rep.history, rep.history[1:]))
+    # the oracle's residual of the GPU answer says the same
+    beta = O.beta_lcdm(1.0, 0.3, 1.0)
+    S, _ = O.source(f.delta, 0.3, 1.0, beta)
+    r = S - O.operator(phig, h, O.alpha(1.0, beta, 1.0))
+    assert np.linalg.norm(r) / np.linalg.norm(S) == pytest.approx(rep.rel_res[0], rel=1e-3)
+
+
+@pytest.mark.parametrize("n,level_shape", [(32, None), (64, None)])
+def test_residual_elementwise(n, level_shape):
+    say(f"residual n={n}")
+    rng = np.random.default_rng(n)
+    f = synth.make_field(n, 2.0, 21, n_tophats=3)
+    h = ndgp.cell_size(n * 1.0, n)
+    rc = 2.0
+    beta = O.beta_lcdm(1.0, 0.3, rc)
+    S, _ = O.source(f.delta, 0.3, 1.0, beta)
+    phi = rng.standard_normal((n, n, n)) * 1e-6
+    ro = S - O.operator(phi, h, O.alpha(rc, beta, 1.0))
+    grid = ndgp.Grid(n=n, h=h)
+    r, relg = ndgp.residual(grid, ndgp.Params(rc=rc), [dev(f.delta)], dev(phi))
+    rg = r.cpu().numpy()
+    scale = np.abs(ro).max()
+    assert np.abs(rg - ro).max() <= 1e-12 * scale
+    assert relg == pytest.approx(np.linalg.norm(ro) / np.linalg.norm(S), rel=1e-12)
+
+
+def test_zero_source_and_one_dimensional_source():
+    n = 32
+    h = ndgp.cell_size(64.0, n)
+    say("zero source")
+    (phig,), rep = gpu_solve([np.zeros((n, n, n))], ndgp.Grid(n=n, h=h), rc=1.0)
+    assert rep.cycles[0] == 0 and np.all(phig == 0.0)
+    say("1D source")
+    rng = np.random.default_rng(12)
+    rho = np.exp(2.0 * rng.standard_normal(n))
+    prof = rho / rho.mean() - 1.0
+    delta = np.broadcast_to(prof.reshape(1, 1, n), (n, n, n)).copy()
+    (phig,), rep = gpu_solve([delta], ndgp.Grid(n=n, h=h), rc=5.0, tol=0.0, max_cycles=200)
+    beta = O.beta_lcdm(1.0, 0.3, 5.0)
+    S, _ = O.source(delta, 0.3, 1.0, beta)
+    # discrete Poisson answer by FFT (the nonlinear term vanishes on 1D fields)
+    m = np.fft.fftfreq(n) * n
+    lam = -(4.0 / h**2) * np.sin(np.pi * m / n) ** 2
+    lam[0] = 1.0
+    pk = np.fft.fft(S[0, 0, :]) / lam
+    pk[0] = 0.0
+    ref = np.real(np.fft.ifft(pk))
+    assert rel(phig[0, 0, :], ref) <= PHI_TOL
+    assert np.abs(phig - phig[:1, :1, :]).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_scale_law_bitwise_and_determinism():
+    """h -> 2h with the same density gives exactly 4 phi (the kernels work in
+    cell units and every step is homogeneous); a rerun gives the same bits."""
+    n = 32
+    f = synth.make_field(n, 2.0, 5, n_tophats=2)
+    h = ndgp.cell_size(64.0, n)
+    say("scale law")
+    (p1,), r1 = gpu_solve([f.delta], ndgp.Grid(n=n, h=h), rc=1.0, tol=1e-12, max_cycles=100)
+    (p2,), r2 = gpu_solve([f.delta], ndgp.Grid(n=n, h=2 * h), rc=1.0, tol=1e-12, max_cycles=100)
+    (p3,), r3 = gpu_solve([f.delta], ndgp.Grid(n=n, h=h), rc=1.0, tol=1e-12, max_cycles=100)
+    assert r1.cycles == r2.cycles
+    assert np.array_equal(p2, 4 * p1)
+    assert np.array_equal(p3, p1)
+
+
+def test_warm_start_and_errors():
+    n = 32
+    f = synth.make_field(n, 1.0, 1512)
+    h = ndgp.cell_size(64.0, n)
+    grid = ndgp.Grid(n=n, h=h)
+    say("warm start")
+    phi, rep = ndgp.solve(grid, ndgp.Params(rc=1.0, tol=1e-10), [dev(f.delta)])
+    phi2, rep2 = ndgp.solve(grid, ndgp.Params(rc=1.0, tol=1e-10, warm_start=True), [dev(f.delta)],
+                            phi=[phi[0].clone()])
+    assert rep2.cycles[0] == 0
+    say("no convergence")
+    _, rep3 = ndgp.solve(grid, ndgp.Params(rc=1.0, tol=1e-14, max_cycles=2), [dev(f.delta)],
+                         check=False)
+    assert rep3.status == ndgp.NDGP_ENOCONV and rep3.cycles[0] == 2
+    say("non-finite delta")
+    bad = f.delta.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(ndgp.NdgpError) as e:
+        ndgp.solve(grid, ndgp.Params(rc=1.0), [dev(bad)])
+    assert e.value.status == ndgp.NDGP_EINVAL
+    say("workspace too small")
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ndgp.NdgpError) as e:
+        ndgp.solve(grid, ndgp.Params(rc=1.0), [dev(f.delta)], ws=small)
+    assert e.value.status == ndgp.NDGP_ENOMEM
+
+
+# --------------------------------------------------------------------------
+# refined patches (Sec. III.A) and the interpolated mode (Sec. III.B)
+
+def patch_problem(n=64, pn=(64, 64), seed=11, wrap=False):
+    f = synth.make_field(n, 2.0, seed, n_tophats=10)
+    c = synth.densest_tophat_centre(f)
+    o1 = synth.patch_origin_centred(c, pn[0] // 2)
+    if wrap:
+        o1 = (-pn[0] // 8, o1[1], o1[2])  # patch 1 straddles the periodic boundary
+    c1 = tuple((c[a] - o1[a]) * 2 for a in range(3))
+    o2 = synth.patch_origin_centred(c1, pn[1] // 2)
+    o2 = tuple(min(max(v, 8), pn[0] - pn[1] // 2 - 8) for v in o2)
+    d1 = synth.patch_delta(f, n, [o1], pn[0])
+    d2 = synth.patch_delta(f, n, [o1, o2], pn[1])
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n),
+                     patches=[ndgp.Patch(pn[0], o1), ndgp.Patch(pn[1], o2)])
+    return f, [f.delta, d1, d2], grid
+
+
+@pytest.mark.parametrize("interpolated", [False, True])
+@pytest.mark.parametrize("wrap", [False, True])
+def test_patches_match_oracle(interpolated, wrap):
+    say(f"patches interpolated={interpolated} wrap={wrap}")
+    rc = 1.0
+    f, deltas, grid = patch_problem(wrap=wrap)
+    beta = O.beta_lcdm(1.0, 0.3, rc)
+    prob = O.Problem(delta=deltas, h=grid.h, rc=rc, beta=beta,
+                     origins=tuple(p.origin for p in grid.patches))
+    phio, infos = O.solve_problem(prob, interpolated=interpolated)
+    for inf in infos[: (1 if interpolated else 3)]:
+        assert inf.status == 0
+    mode = ndgp.MODE_INTERPOLATED if interpolated else ndgp.MODE_FULL
+    phig, rep = gpu_solve(deltas, grid, rc=rc, tol=0.0, max_cycles=200, mode=mode)
+    say(f"  cycles={rep.cycles} rel_res={rep.rel_res}")
+    assert rep.status == 0
+    for lvl in range(3):
+        e = rel(phig[lvl], phio[lvl])
+        say(f"  level {lvl}: rel err {e:.2e}")
+        assert e <= PHI_TOL
+    # forces from the same fields agree to rounding; end to end within the bar
+    fg = [x.cpu().numpy() for x in ndgp.force(grid, [dev(p) for p in phig])]
+    for lvl in range(3):
+        fo = O.force(phig[lvl], grid.level_h(lvl), periodic=(lvl == 0))
+        assert np.abs(fg[lvl] - fo).max() <= 1e-13 * np.abs(fo).max()
+        fo_or = O.force(phio[lvl], grid.level_h(lvl), periodic=(lvl == 0))
+        assert rel(fg[lvl], fo_or) <= 1e-10
+
+
+def test_patch_residual_level():
+    """ndgp_residual on a patch level uses the ghost shell as boundary."""
+    f, deltas, grid = patch_problem()
+    phig, rep = gpu_solve(deltas, grid, rc=1.0, tol=1e-10)
+    beta = O.beta_lcdm(1.0, 0.3, 1.0)
+    al = O.alpha(1.0, beta, 1.0)
+    _, mean = O.source(deltas[0], 0.3, 1.0, beta)
+    for lvl in (1, 2):
+        say(f"patch residual level {lvl}")
+        S = O.source_shift(deltas[lvl], mean, 0.3, 1.0, beta)
+        ro = S - O.operator_padded(phig[lvl], grid.level_h(lvl), al)
+        r, relg = ndgp.residual(grid, ndgp.Params(rc=1.0), [dev(d) for d in deltas],
+                                dev(phig[lvl]), level=lvl)
+        assert np.abs(r.cpu().numpy() - ro).max() <= 1e-12 * np.abs(S).max()
+        assert relg <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# full sizes, in the launch configuration the benchmark times
+
+@pytest.mark.parametrize("n,box,sigma,tophats,rc,seed", [
+    (256, 256.0, 2.0, 50, 1.0, 1513),   # 256^3 lognormal + 50 top-hats
+    (512, 512.0, 2.5, 0, 1.0, 1515),    # 512^3 lognormal, sigma 2.5
+])
+def test_full_size_residual_by_oracle(n, box, sigma, tophats, rc, seed):
+    say(f"full size n={n}: generating")
+    f = synth.make_field(n, sigma, seed, n_tophats=tophats)
+    h = ndgp.cell_size(box, n)
+    grid = ndgp.Grid(n=n, h=h)
+    params = ndgp.Params(rc=rc, tol=1e-10)
+    d = dev(f.delta)
+    say(f"full size n={n}: solving")
+    phi, rep = ndgp.solve(grid, params, [d])
+    r, relg = ndgp.residual(grid, params, [d], phi[0])
+    torch.cuda.synchronize()
+    say(f"  cycles={rep.cycles[0]} rel_res={rep.rel_res[0]:.3e} t={rep.t_total_ms:.1f} ms")
+    assert rep.status == 0 and rep.rel_res[0] <= 1e-10
+    phig = phi[0].cpu().numpy()
+    rg = r.cpu().numpy()
+    del phi, r, d
+    beta = O.beta_lcdm(1.0, 0.3, rc)
+    al = O.alpha(rc, beta, 1.0)
+    S, _ = O.source(f.delta, 0.3, 1.0, beta)
+    rng = np.random.default_rng(0)
+    cells = rng.integers(0, n, size=(4096, 3))
+    cells[:8] = [[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 0], [n - 1, 0, n - 1],
+                 [n // 2, 0, n - 1], [1, 1, 1], [n - 2, n - 1, 0], [0, 0, n - 1]]
+    ro = S[cells[:, 2], cells[:, 1], cells[:, 0]] - O.operator_at(phig, h, al, cells)
+    scale = np.abs(S).max()
+    assert np.abs(rg[cells[:, 2], cells[:, 1], cells[:, 0]] - ro).max() <= 1e-12 * scale
+    say(f"full size n={n}: oracle residual over the whole grid")
+    del rg
+    ro_all = S - O.operator(phig, h, al)
+    assert np.linalg.norm(ro_all) / np.linalg.norm(S) == pytest.approx(relg, rel=1e-6)
+    assert relg <= 1e-10
