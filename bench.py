@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the nDGP scalar-field multigrid solve on one MI355X.
+
+One step = one whole solve of the domain grid to ||S - L phi|| / ||S|| <= 1e-10
+(source preparation, nested start, FAS V-cycles, norms, gauge) followed by the
+fifth force, on a 256^3 periodic grid (box 256 Mpc/h, r_c H0 = 1, Omega_m = 0.3,
+lognormal delta with sigma_ln = 2 and P(k) ~ k^-2 plus 50 top-hats of
+delta = 200, radius 2-8 cells; seeded synthetic input resident in HBM).
+
+value = cell-updates/s = n^3 (nu1 + nu2) cycles / wall time per step.
+
+The JSON line also carries:
+  roofline      the red-black relaxation kernel, timed with HIP events on its
+                launch stream during the timed steps; algorithmic bytes per
+                cell update = 24 (read phi and S, write phi; FP64);
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload;
+  extra         the 256^3 + two 128^3 patch workload in both modes (time to
+                tolerance, force difference of the interpolated mode) and
+                512^3 solves at three r_c, with the relaxation roofline there.
+
+    python bench.py [--steps K] [--warmup W] [--no-extra] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "nDGP MG cell-updates/s + HBM GB/s vs peak; served solves/s, p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE_FP64 = 24.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("ndgp_kernels.hip", "ndgp_internal.h"):
+        with open(os.path.join(ROOT, "paper_1511_08200_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(n: int):
+    """Measured HBM bytes per relaxation launch (rocprofv3 FETCH_SIZE +
+    WRITE_SIZE, calibrated by a copy kernel), if taken on the current kernels."""
+    path = os.path.join(ROOT, "profiles", "smoother_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch", {}).get(str(n))
+
+
+def make_domain(n, box, sigma, tophats, seed):
+    from paper_1511_08200_amd import synth
+    return synth.make_field(n, sigma, seed, n_tophats=tophats)
+
+
+def solve_steps(ndgp, torch, grid, params, deltas, steps, warmup, with_force=True):
+    dd = [torch.from_numpy(d).to("cuda") if d is not None else None for d in deltas]
+    phi = ndgp.alloc_phi(grid)
+    ws = ndgp.workspace(ndgp.workspace_bytes(grid, params))
+    reps = []
+    for _ in range(warmup):
+        ndgp.solve(grid, params, dd, phi=phi, ws=ws)
+        if with_force:
+            ndgp.force(grid, phi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, rep = ndgp.solve(grid, params, dd, phi=phi, ws=ws)
+        if with_force:
+            ndgp.force(grid, phi)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    return dt, reps, phi, dd
+
+
+def roofline(reps, n):
+    launches = sum(r.smooth_launches for r in reps)
+    t_ms = sum(r.t_smooth_ms for r in reps)
+    if not launches or t_ms <= 0:
+        return None
+    cells = reps[0].smooth_cells_per_launch
+    avg_s = t_ms / 1e3 / launches
+    alg_bytes = BYTES_PER_UPDATE_FP64 * cells
+    achieved = alg_bytes / avg_s / 1e9
+    tr = traffic_from_profiles(n)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": tr, "kernel": "k_smooth_half (red-black half sweep, FP64)",
+            "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+            "cells_per_launch": cells, "alg_bytes_per_launch": alg_bytes,
+            "cell_updates_per_s": cells / avg_s}
+
+
+def cpu_baseline(delta, h, rc, cycles):
+    from oracle import oracle as O
+    beta = O.beta_lcdm(1.0, 0.3, rc)
+    S, _ = O.source(delta, 0.3, 1.0, beta)
+    n = delta.shape[0]
+    t0 = time.perf_counter()
+    _, info = O.solve_periodic(S, h, O.alpha(rc, beta, 1.0), max_cycles=cycles, tol=1e-300)
+    dt = time.perf_counter() - t0
+    return {"value": n**3 * 4 * info.cycles / dt, "unit": "cell-updates/s",
+            "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{n}^3 same input: nested start + {info.cycles} V(2,2) cycles "
+                      f"(rel. residual {info.rel_res:.2e}) in {dt:.1f} s"}
+
+
+def patch_workload(ndgp, torch, steps):
+    """256^3 domain + 128^3 patches at 2x and 4x resolution centred on the
+    largest top-hat; full and interpolated modes; force difference."""
+    from paper_1511_08200_amd import synth
+    n, box, rc = 256, 256.0, 1.0
+    f = make_domain(n, box, 2.0, 50, 1513)
+    c = synth.densest_tophat_centre(f)
+    o1 = synth.patch_origin_centred(c, 64)
+    c1 = tuple((c[a] - o1[a]) * 2 for a in range(3))
+    o2 = synth.patch_origin_centred(c1, 64)
+    o2 = tuple(min(max(v, 8), 128 - 64 - 8) for v in o2)
+    deltas = [f.delta, synth.patch_delta(f, n, [o1], 128), synth.patch_delta(f, n, [o1, o2], 128)]
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n),
+                     patches=[ndgp.Patch(128, o1), ndgp.Patch(128, o2)])
+    out = {"workload": "256^3 + 2 nested 128^3 patches (2x, 4x), FP64, r_cH0=1",
+           "origins": [list(o1), list(o2)]}
+    res = {}
+    for name, mode in (("full", ndgp.MODE_FULL), ("interpolated", ndgp.MODE_INTERPOLATED)):
+        params = ndgp.Params(rc=rc, tol=1e-10, mode=mode)
+        dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, deltas, steps, 1)
+        res[name] = (phi, reps[-1])
+        out[name] = {"ms_to_tol": round(dt * 1e3, 2), "cycles": reps[-1].cycles,
+                     "rel_res": reps[-1].rel_res}
+    out["speedup_interpolated_vs_full"] = round(out["full"]["ms_to_tol"]
+                                                / out["interpolated"]["ms_to_tol"], 2)
+    # force of the truncated run against the fully relaxed one (Eqs. errors,
+    # errors2): relative to the full fifth force and to the GR force, whose
+    # potential solves lap Psi = (3 beta / 2) S, i.e. 3 beta / 2 times the r_c = 0 field
+    beta = ndgp.beta_lcdm(1.0, 0.3, rc)
+    phi_gr, _ = ndgp.solve(grid, ndgp.Params(rc=0.0, beta=beta, tol=1e-10),
+                           [torch.from_numpy(d).to("cuda") for d in deltas])
+    F_full = ndgp.force(grid, res["full"][0])
+    F_int = ndgp.force(grid, res["interpolated"][0])
+    F_lin = ndgp.force(grid, phi_gr)
+    diffs = []
+    for lvl in (1, 2):
+        dd2, ff2, _ = ndgp.diff_norms(F_int[lvl], F_full[lvl])
+        _, gr2, _ = ndgp.diff_norms(F_lin[lvl])
+        gr2 *= (3 * beta) ** 2
+        diffs.append({"level": lvl, "rel_to_F5_full": float(np.sqrt(dd2 / ff2)),
+                      "rel_to_F_GR": float(np.sqrt(dd2 / gr2)),
+                      "F5_over_FGR": float(np.sqrt(ff2 / gr2))})
+    out["force_difference"] = diffs
+    return out
+
+
+def large_workload(ndgp, torch, steps):
+    """512^3 periodic, sigma_ln = 2.5, FP64, r_c H0 in {0.5, 1, 5}."""
+    n, box = 512, 512.0
+    log("generating 512^3 input")
+    f = make_domain(n, box, 2.5, 0, 1515)
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
+    out = {"workload": "512^3 periodic, lognormal sigma 2.5, FP64, tol 1e-10"}
+    for rc in (0.5, 1.0, 5.0):
+        params = ndgp.Params(rc=rc, tol=1e-10, profile=True)
+        dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, [f.delta], steps, 1,
+                                        with_force=False)
+        cyc = reps[-1].cycles[0]
+        out[f"rc{rc:g}"] = {"ms_to_tol": round(dt * 1e3, 1), "cycles": cyc,
+                            "cell_updates_per_s": n**3 * 4 * cyc / dt,
+                            "roofline": roofline(reps, n)}
+        del phi, dd
+        torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-cycles", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this solver runs on a single MI355X "
+              "(multi-GPU domain decomposition is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1511_08200_amd import ndgp
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    ndgp.lib()
+
+    n, box, rc = 256, 256.0, 1.0
+    log("generating 256^3 input")
+    f = make_domain(n, box, 2.0, 50, 1513)
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
+    params = ndgp.Params(rc=rc, tol=1e-10, profile=True)
+    log("timing")
+    dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, [f.delta], args.steps,
+                                    args.warmup)
+    cycles = reps[-1].cycles[0]
+    assert all(r.cycles[0] == cycles for r in reps)
+    value = n**3 * 4 * cycles / dt
+    line = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "ndgp-256^3-fp64-lognormal-sigma2+50tophats, box 256 Mpc/h, "
+                               "r_cH0=1, tol 1e-10, V(2,2) 6 levels, + force",
+                   "n": n, "cycles": cycles, "rel_res": reps[-1].rel_res[0],
+                   "solves_per_s": 1.0 / dt},
+        "roofline": roofline(reps, n),
+    }
+    del phi, dd
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(f.delta, grid.h, rc, args.cpu_cycles)
+    if not args.no_extra:
+        log("patch workload")
+        line.setdefault("extra", {})["patches"] = patch_workload(ndgp, torch, 3)
+        log("512^3 workload")
+        line["extra"]["large"] = large_workload(ndgp, torch, 3)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -83,6 +83,8 @@ typedef enum {
 #define NDGP_WARM_START 1u /* phi[0] holds the initial guess of the domain level
                               (the paper allows the previous time step's field);
                               otherwise the guess comes from nested iteration */
+#define NDGP_PROFILE 2u    /* time the domain level's relaxation sweeps with HIP
+                              events on `stream` (ndgp_report.t_smooth_ms) */
 
 typedef struct {
     int32_t n;             /* domain cells per side: power of two, 8..1024              */
@@ -108,7 +110,7 @@ typedef struct {
     int32_t n_levels;  /* multigrid levels of the domain grid (0 = down to 8^3)         */
     int32_t mode;      /* ndgp_mode                                                    */
     int32_t precision; /* ndgp_precision                                               */
-    uint32_t flags;    /* NDGP_WARM_START                                              */
+    uint32_t flags;    /* NDGP_WARM_START | NDGP_PROFILE                               */
 } ndgp_params;
 
 typedef struct {
@@ -122,6 +124,10 @@ typedef struct {
     int32_t hist_len;      /* entries of res_hist used                                 */
     double res_hist[NDGP_HIST_LEN]; /* relative residual of the domain level per cycle */
     double t_total_ms;     /* wall time of the call                                    */
+    double t_smooth_ms;    /* NDGP_PROFILE: GPU time of the domain level's relaxation
+                              kernels (V-cycles after the start; events on `stream`)    */
+    int32_t smooth_launches; /* relaxation kernel launches inside t_smooth_ms           */
+    int32_t smooth_cells_per_launch; /* cells one such launch updates                   */
 } ndgp_report;
 
 /* Library ABI version (NDGP_ABI_VERSION of the build). */
@@ -188,6 +194,18 @@ ndgp_status ndgp_residual(const ndgp_grid *grid, const ndgp_params *params, int3
  */
 ndgp_status ndgp_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_MAX_PATCHES],
                        double *const force[1 + NDGP_MAX_PATCHES], hipStream_t stream);
+
+/*
+ * Norms for comparing two fields, e.g. the force of the interpolated mode with
+ * the fully relaxed one (the error of Sec. III.B, Eqs. errors-errors2):
+ *   out[0] = sum (a - b)^2,  out[1] = sum a^2,  out[2] = sum b^2
+ * over `count` doubles (b may be NULL: then it counts as zero).  out is a HOST
+ * array; the workspace needs NDGP_DIFF_NORMS_WORKSPACE bytes.  Deterministic;
+ * blocks until out is written.
+ */
+#define NDGP_DIFF_NORMS_WORKSPACE 65536
+ndgp_status ndgp_diff_norms(const double *a, const double *b, size_t count, double out[3],
+                            void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

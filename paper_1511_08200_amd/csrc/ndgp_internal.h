@@ -83,6 +83,10 @@ void launch_interpolate(const double *parent, int np, bool parent_periodic, cons
                         double *child_pad, bool ghosts_only, hipStream_t st);
 // F = -grad(phi)/2 by central differences; f has 3 * n^3 values (x, y, z).
 void launch_force(const double *phi, int n, bool periodic, double h, double *f, hipStream_t st);
+// partials[0..B) = per-block sum (a-b)^2, [B..2B) sum a^2, [2B..3B) sum b^2
+// (B = kReduceBlocks; b may be null)
+void launch_diff_partials(const double *a, const double *b, size_t count, double *partials,
+                          hipStream_t st);
 // dst[i] = src[i]
 void launch_copy(const double *src, double *dst, size_t count, hipStream_t st);
 

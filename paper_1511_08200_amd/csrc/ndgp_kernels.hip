@@ -217,6 +217,30 @@ k_partial_sums(const double *__restrict__ a, size_t count, int squares,
 }
 
 __global__ void __launch_bounds__(kBlock)
+k_diff_partials(const double *__restrict__ a, const double *__restrict__ b, size_t count,
+                double *__restrict__ partials) {
+    double dd = 0.0, aa = 0.0, bb = 0.0;
+    for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < count;
+         c += (size_t)gridDim.x * kBlock) {
+        const double x = a[c];
+        const double y = b ? b[c] : 0.0;
+        dd = fma(x - y, x - y, dd);
+        aa = fma(x, x, aa);
+        bb = fma(y, y, bb);
+    }
+    const double s0 = block_sum(dd);
+    __syncthreads();
+    const double s1 = block_sum(aa);
+    __syncthreads();
+    const double s2 = block_sum(bb);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = s0;
+        partials[kReduceBlocks + blockIdx.x] = s1;
+        partials[2 * kReduceBlocks + blockIdx.x] = s2;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
 k_reduce_final(const double *__restrict__ partials, double *__restrict__ out) {
     double acc = 0.0;
     for (int q = threadIdx.x; q < kReduceBlocks; q += kBlock) acc += partials[q];
@@ -504,6 +528,11 @@ void launch_residual_sumsq(const Level &L, double *partials, double *r_out, doub
 void launch_partial_sums(const double *a, size_t count, bool squares, double *partials,
                          hipStream_t st) {
     k_partial_sums<<<kReduceBlocks, kBlock, 0, st>>>(a, count, squares ? 1 : 0, partials);
+}
+
+void launch_diff_partials(const double *a, const double *b, size_t count, double *partials,
+                          hipStream_t st) {
+    k_diff_partials<<<kReduceBlocks, kBlock, 0, st>>>(a, b, count, partials);
 }
 
 void launch_reduce_final(const double *partials, double *out, hipStream_t st) {

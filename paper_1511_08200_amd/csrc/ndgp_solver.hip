@@ -180,7 +180,7 @@ bool resolve(const ndgp_grid *g, const ndgp_params *p, Cfg &c, std::string &why)
         why = "precision must be NDGP_PREC_FP64 in this build";
         return false;
     }
-    if (p->flags & ~NDGP_WARM_START) {
+    if (p->flags & ~(NDGP_WARM_START | NDGP_PROFILE)) {
         why = "unknown flag bits";
         return false;
     }
@@ -312,10 +312,38 @@ char *aligned_base(void *ws) {
 // ------------------------------------------------------------------------
 // the multigrid driver
 
+// HIP events around the domain level's relaxation phases (NDGP_PROFILE)
+struct SmoothTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev; // start/stop pairs
+    int launches = 0;
+    ~SmoothTimer() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    void mark(hipStream_t st) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        ev.push_back(e);
+        HIP_TRY(hipEventRecord(e, st));
+    }
+    double total_ms() {
+        double t = 0.0;
+        for (size_t q = 0; q + 1 < ev.size(); q += 2) {
+            HIP_TRY(hipEventSynchronize(ev[q + 1]));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[q], ev[q + 1]));
+            t += ms;
+        }
+        return t;
+    }
+};
+
 struct Runner {
     Plan &P;
     hipStream_t st;
     double *host;
+    SmoothTimer *timer = nullptr; // times smooth() calls on this level's arrays
+    const double *timed_s = nullptr;
 
     double read_scalar(const double *dev) {
         HIP_TRY(hipGetLastError());
@@ -337,11 +365,17 @@ struct Runner {
     }
 
     void smooth(Level &L, int sweeps) {
+        const bool timed = timer && timer->on && L.s == timed_s;
+        if (timed) timer->mark(st);
         for (int s = 0; s < sweeps; ++s)
             for (int col = 0; col < 2; ++col) {
                 launch_smooth_half(L, L.phi, L.alt, col, P.fallbacks, st);
                 std::swap(L.phi, L.alt);
             }
+        if (timed) {
+            timer->mark(st);
+            timer->launches += 2 * sweeps;
+        }
     }
 
     void vcycle(Level *H, int nl, int l) {
@@ -409,6 +443,9 @@ struct Runner {
     }
 };
 
+// cells one red-black half sweep updates
+size_t cells_half(int n) { return (size_t)n * n * n / 2; }
+
 ndgp_status check_arrays(const Cfg &c, const double *const *delta, double *const *phi,
                          bool need_patch_delta) {
     if (!delta || !phi || !delta[0] || !phi[0])
@@ -442,7 +479,10 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     std::memset(&R, 0, sizeof(R));
     for (int l = 0; l <= NDGP_MAX_PATCHES; ++l) R.rel_res[l] = -1.0;
     SlotGuard slot;
+    SmoothTimer timer;
     Runner run{P, st, slot.p};
+    run.timer = &timer;
+    run.timed_s = P.base[0].s;
     HIP_TRY(hipMemsetAsync(P.fallbacks, 0, sizeof(unsigned), st));
 
     // domain source: S = Omega_m (delta - mean) / (a beta), in cell units (x h^2)
@@ -460,9 +500,16 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         R.rel_res[0] = 0.0;
     } else {
         if (!(c.flags & NDGP_WARM_START)) run.nested_start(P.base, c.nl);
+        timer.on = (c.flags & NDGP_PROFILE) != 0; // the V-cycles only, not the start
         double rel = 0.0;
         status = run.drive(P.base, c.nl, snorm2, R.cycles[0], rel, R.res_hist, &R.hist_len);
         R.rel_res[0] = rel;
+        timer.on = false;
+        if (timer.launches) {
+            R.t_smooth_ms = timer.total_ms();
+            R.smooth_launches = timer.launches;
+            R.smooth_cells_per_launch = (int32_t)(cells_half(c.n));
+        }
         if (status != NDGP_OK && !std::isfinite(rel)) {
             if (rep) *rep = R;
             return status;
@@ -574,6 +621,24 @@ ndgp_status force_impl(const ndgp_grid *grid, const double *const phi[], double 
     return NDGP_OK;
 }
 
+ndgp_status diff_norms_impl(const double *a, const double *b, size_t count, double out[3],
+                            void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!a || !out) return fail(NDGP_EINVAL, "a and out must not be NULL");
+    if (!ws || ws_bytes < NDGP_DIFF_NORMS_WORKSPACE)
+        return fail(NDGP_ENOMEM, "workspace smaller than NDGP_DIFF_NORMS_WORKSPACE");
+    Carver cv{aligned_base(ws)};
+    double *partials = cv.take<double>(3 * kReduceBlocks);
+    double *sums = cv.take<double>(3);
+    SlotGuard slot;
+    launch_diff_partials(a, b, count, partials, st);
+    for (int q = 0; q < 3; ++q) launch_reduce_final(partials + q * kReduceBlocks, sums + q, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(slot.p, sums, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int q = 0; q < 3; ++q) out[q] = slot.p[q];
+    return NDGP_OK;
+}
+
 template <class F>
 ndgp_status guarded(F &&f) {
     try {
@@ -637,6 +702,12 @@ ndgp_status ndgp_residual(const ndgp_grid *grid, const ndgp_params *params, int3
 ndgp_status ndgp_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_MAX_PATCHES],
                        double *const force[1 + NDGP_MAX_PATCHES], hipStream_t stream) {
     return guarded([&] { return force_impl(grid, phi, force, stream); });
+}
+
+ndgp_status ndgp_diff_norms(const double *a, const double *b, size_t count, double out[3],
+                            void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    return guarded(
+        [&] { return diff_norms_impl(a, b, count, out, workspace, workspace_bytes, stream); });
 }
 
 } // extern "C"

@@ -25,6 +25,7 @@ NDGP_OK, NDGP_EINVAL, NDGP_ENOMEM, NDGP_ENOCONV, NDGP_EDEVICE = 0, -1, -2, -3, -
 MODE_FULL, MODE_INTERPOLATED = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 WARM_START = 1
+PROFILE = 2
 MAX_PATCHES = 2
 HIST_LEN = 64
 
@@ -57,7 +58,9 @@ class _Report(ctypes.Structure):
                 ("rel_res", ctypes.c_double * (1 + MAX_PATCHES)),
                 ("removed_mean", ctypes.c_double), ("phi_mean", ctypes.c_double),
                 ("fallbacks", ctypes.c_int32), ("hist_len", ctypes.c_int32),
-                ("res_hist", ctypes.c_double * HIST_LEN), ("t_total_ms", ctypes.c_double)]
+                ("res_hist", ctypes.c_double * HIST_LEN), ("t_total_ms", ctypes.c_double),
+                ("t_smooth_ms", ctypes.c_double), ("smooth_launches", ctypes.c_int32),
+                ("smooth_cells_per_launch", ctypes.c_int32)]
 
 
 _lib = None
@@ -87,6 +90,9 @@ def lib():
                                     ctypes.c_size_t, vp]
         L.ndgp_force.restype = ctypes.c_int
         L.ndgp_force.argtypes = [ctypes.POINTER(_Grid), arr3, arr3, vp]
+        L.ndgp_diff_norms.restype = ctypes.c_int
+        L.ndgp_diff_norms.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
+                                      vp, ctypes.c_size_t, vp]
         _lib = L
     return _lib
 
@@ -151,6 +157,7 @@ class Params:
     mode: int = MODE_FULL
     precision: int = PREC_FP64
     warm_start: bool = False
+    profile: bool = False
 
     def _c(self) -> _Params:
         p = _Params()
@@ -158,7 +165,7 @@ class Params:
         p.beta = self.beta if self.beta is not None else beta_lcdm(self.a, self.omega_m, self.rc)
         p.max_cycles, p.nu1, p.nu2, p.n_levels = self.max_cycles, self.nu1, self.nu2, self.n_levels
         p.mode, p.precision = self.mode, self.precision
-        p.flags = WARM_START if self.warm_start else 0
+        p.flags = (WARM_START if self.warm_start else 0) | (PROFILE if self.profile else 0)
         return p
 
 
@@ -171,6 +178,9 @@ class Report:
     fallbacks: int
     history: list
     t_total_ms: float
+    t_smooth_ms: float = 0.0
+    smooth_launches: int = 0
+    smooth_cells_per_launch: int = 0
     status: int = NDGP_OK
 
 
@@ -178,7 +188,8 @@ def _report(r: _Report, status: int) -> Report:
     return Report(cycles=list(r.cycles), rel_res=list(r.rel_res), removed_mean=r.removed_mean,
                   phi_mean=r.phi_mean, fallbacks=r.fallbacks,
                   history=[r.res_hist[i] for i in range(r.hist_len)], t_total_ms=r.t_total_ms,
-                  status=status)
+                  t_smooth_ms=r.t_smooth_ms, smooth_launches=r.smooth_launches,
+                  smooth_cells_per_launch=r.smooth_cells_per_launch, status=status)
 
 
 # --------------------------------------------------------------------------
@@ -297,3 +308,18 @@ def force(grid: Grid, phi: Sequence[torch.Tensor], stream=None) -> list:
     _check(lib().ndgp_force(ctypes.byref(g), _arr3(pptr), _arr3([o.data_ptr() for o in out]),
                             _stream(stream)))
     return out
+
+
+DIFF_NORMS_WORKSPACE = 65536
+
+
+def diff_norms(a: torch.Tensor, b: Optional[torch.Tensor] = None, stream=None):
+    """(sum (a-b)^2, sum a^2, sum b^2) over all elements, in the library's
+    deterministic reduction kernels."""
+    if b is not None and b.shape != a.shape:
+        raise ValueError("a and b differ in shape")
+    out = (ctypes.c_double * 3)()
+    ws = workspace(DIFF_NORMS_WORKSPACE, a.device)
+    _check(lib().ndgp_diff_norms(_dev(a, None, "a"), _dev(b, None, "b") if b is not None else None,
+                                 a.numel(), out, ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out[0], out[1], out[2]
