@@ -91,6 +91,12 @@ def solve_steps(ndgp, torch, grid, params, deltas, steps, warmup, with_force=Tru
     return dt, reps, phi, dd
 
 
+def kernel_name(cells, n):
+    if cells == n**3:
+        return "k_sweep_fused (one red-black sweep per launch, LDS-streamed, FP64)"
+    return "k_smooth_half (one colour per launch, FP64)"
+
+
 def roofline(reps, n):
     launches = sum(r.smooth_launches for r in reps)
     t_ms = sum(r.t_smooth_ms for r in reps)
@@ -103,7 +109,7 @@ def roofline(reps, n):
     tr = traffic_from_profiles(n)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": tr, "kernel": "k_smooth_half (red-black half sweep, FP64)",
+            "traffic": tr, "kernel": kernel_name(cells, n),
             "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
             "cells_per_launch": cells, "alg_bytes_per_launch": alg_bytes,
             "cell_updates_per_s": cells / avg_s}

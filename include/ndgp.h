@@ -85,6 +85,9 @@ typedef enum {
                               otherwise the guess comes from nested iteration */
 #define NDGP_PROFILE 2u    /* time the domain level's relaxation sweeps with HIP
                               events on `stream` (ndgp_report.t_smooth_ms) */
+#define NDGP_TWO_PASS 4u   /* relax every level with two launches per red-black
+                              sweep (one per colour) instead of the fused
+                              one-launch sweep; same results, bit for bit */
 
 typedef struct {
     int32_t n;             /* domain cells per side: power of two, 8..1024              */
@@ -110,7 +113,7 @@ typedef struct {
     int32_t n_levels;  /* multigrid levels of the domain grid (0 = down to 8^3)         */
     int32_t mode;      /* ndgp_mode                                                    */
     int32_t precision; /* ndgp_precision                                               */
-    uint32_t flags;    /* NDGP_WARM_START | NDGP_PROFILE                               */
+    uint32_t flags;    /* NDGP_WARM_START | NDGP_PROFILE | NDGP_TWO_PASS               */
 } ndgp_params;
 
 typedef struct {

@@ -269,13 +269,33 @@ static int hier_alloc(hier_t *H, int n, double h, int periodic, double alpha)
     return 0;
 }
 
-/* Put the level's boundary into a padded array: periodic copy, or the fixed
-   Dirichlet values held in L->ghost. */
+/* Put the level's boundary into a padded array: periodic copy, or the
+   Dirichlet values held in L->ghost.
+   On the coarse levels of a refinement's hierarchy the iterate differs from
+   the restricted fine field R phi by a correction that must vanish where the
+   fine boundary values sit, half a fine cell outside the patch, while the
+   coarse ghost centres lie a fine cell and a half outside.  Extrapolating the
+   correction linearly through zero at the fine ghost position gives the
+   coarse ghost -1/3 of the correction of the interior cell next to it (a
+   factor -1/3 per axis along which the ghost lies outside).  This only
+   changes how fast the cycles converge, not the solution on the patch. */
 static void apply_bc(const hier_t *H, const level_t *L, double *a)
 {
     const int n = L->n;
     if (H->periodic) {
         fill_periodic(n, a);
+        return;
+    }
+    if (L->phihat && a == L->phi) {
+        FOR_SHELL(n, {
+            const int ci = i < 0 ? 0 : (i >= n ? n - 1 : i);
+            const int cj = j < 0 ? 0 : (j >= n ? n - 1 : j);
+            const int ck = k < 0 ? 0 : (k >= n ? n - 1 : k);
+            const int d = (ci != i) + (cj != j) + (ck != k);
+            const double f = d == 1 ? -1.0 / 3.0 : (d == 2 ? 1.0 / 9.0 : -1.0 / 27.0);
+            const int64_t q = pidx(n, ci, cj, ck);
+            a[pidx(n, i, j, k)] = L->ghost[pidx(n, i, j, k)] + f * (a[q] - L->phihat[q]);
+        })
         return;
     }
     FOR_SHELL(n, a[pidx(n, i, j, k)] = L->ghost[pidx(n, i, j, k)])

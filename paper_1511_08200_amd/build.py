@@ -31,6 +31,9 @@ def build(verbose: bool = False) -> str:
     cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
            # packed FP32 instructions are kept out of every kernel
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # no implicit fused multiply-adds: the same expression rounds the same
+           # way in every kernel it is inlined into (fma() is written out)
+           "-ffp-contract=off",
            "-Wall", "-Wno-unused-function",
            "-I", INCLUDE, "-I", CSRC, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:

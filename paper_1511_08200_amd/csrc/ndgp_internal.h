@@ -29,6 +29,11 @@ struct Level {
     double *alt = nullptr; // ping-pong partner of phi (same layout, same ghosts)
     double *s = nullptr;   // source, natural n^3
     double *hat = nullptr; // restriction of the finer iterate (levels >= 1)
+    // Coarse level of a refinement's hierarchy: the ghost shell follows the
+    // interior (ghost = hat + (-1/3)^d (phi - hat) of the adjacent interior
+    // cell, d = number of axes along which the ghost lies outside), so that
+    // the coarse correction vanishes where the fine boundary values sit.
+    bool dyn_bc = false;
 
     size_t cells() const { return (size_t)n * n * n; }
     size_t slots() const {
@@ -50,6 +55,12 @@ struct ChildBox {
 // of their own discrete quadratic from pin; the other colour is copied.
 void launch_smooth_half(const Level &L, const double *pin, double *pout, int colour,
                         unsigned *fallbacks, hipStream_t st);
+// One full red-black sweep (both colours) in one launch through LDS tiles;
+// identical results to two launch_smooth_half calls.  Periodic levels with
+// n >= 128 only (fused_sweep_ok).
+bool fused_sweep_ok(const Level &L);
+void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
+                        hipStream_t st);
 // Per-block partial sums of r^2, r = s - L[phi]; optionally r_out = r * scale.
 void launch_residual_sumsq(const Level &L, double *partials, double *r_out, double r_scale,
                            hipStream_t st);

@@ -127,6 +127,22 @@ __device__ __forceinline__ double apply_L(const Terms &t, double al) {
 // and the root is dt = 2 r / (B + sqrt(B^2 - 18 alpha r)) (no cancellation).
 // B <= 0: the linearised operator is not elliptic at this cell; it waits for
 // its neighbours.  No real root: move to the vertex dt = B / (9 alpha).
+// Reciprocal and square root from the hardware estimates plus one Newton
+// step each (relative error near 1e-16).  The relaxation only needs them to
+// pick its step: the fixed point L[phi] = s does not depend on how they round.
+__device__ __forceinline__ double fast_rcp(double q) {
+    const double y = __builtin_amdgcn_rcp(q);
+    return fma(y, fma(-q, y, 1.0), y);
+}
+
+__device__ __forceinline__ double fast_sqrt(double d) {
+    const double rs = __builtin_amdgcn_rsq(d);
+    const double s0 = d * rs;
+    const double e = fma(-s0, 0.5 * rs, 0.5);
+    const double s1 = fma(s0, e, s0);
+    return d > 0.0 ? s1 : 0.0;
+}
+
 __device__ __forceinline__ double relax_cell(const double v[19], double s, double al,
                                              unsigned &fallbacks) {
     const Terms t = stencil_terms(v);
@@ -138,7 +154,39 @@ __device__ __forceinline__ double relax_cell(const double v[19], double s, doubl
         ++fallbacks;
         return v[0] + B / (18.0 * al);
     }
-    return v[0] + r / (B + sqrt(D));
+    return fma(r, fast_rcp(B + fast_sqrt(D)), v[0]);
+}
+
+// Coarse levels of a refinement: write the ghosts whose correction is taken
+// from interior cell (i,j,k), now holding `val`.  The correction phi - hat is
+// extrapolated linearly through zero at the fine boundary position (half a
+// fine cell outside), which puts -1/3 of it on the coarse ghost per axis
+// along which the ghost lies outside.  Every ghost has exactly one such
+// interior cell, so each is written by one thread.
+template <bool PER>
+__device__ __forceinline__ void write_owned_ghosts(double *__restrict__ out,
+                                                   const double *__restrict__ hat,
+                                                   const Ix<PER> &ix, int i, int j, int k,
+                                                   double val) {
+    if constexpr (!PER) {
+        const int n = ix.n;
+        const bool bx = i == 0 || i == n - 1, by = j == 0 || j == n - 1, bz = k == 0 || k == n - 1;
+        if (!(bx || by || bz)) return;
+        const int gx = i == 0 ? -1 : n, gy = j == 0 ? -1 : n, gz = k == 0 ? -1 : n;
+        const double e = val - hat[ix(i, j, k)];
+#pragma unroll
+        for (int mz = 0; mz < 2; ++mz)
+#pragma unroll
+            for (int my = 0; my < 2; ++my)
+#pragma unroll
+                for (int mx = 0; mx < 2; ++mx) {
+                    if ((mx && !bx) || (my && !by) || (mz && !bz) || (mx + my + mz) == 0) continue;
+                    const int d = mx + my + mz;
+                    const double f = d == 1 ? -1.0 / 3.0 : (d == 2 ? 1.0 / 9.0 : -1.0 / 27.0);
+                    const int q = ix(mx ? gx : i, my ? gy : j, mz ? gz : k);
+                    out[q] = hat[q] + f * e;
+                }
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -162,7 +210,7 @@ template <bool PER>
 __global__ void __launch_bounds__(kBlock)
 k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
               const double *__restrict__ s, Ix<PER> ix, double al, int colour,
-              unsigned *__restrict__ fallbacks) {
+              unsigned *__restrict__ fallbacks, const double *__restrict__ hat, int dyn_bc) {
     const int n = ix.n, lg = ix.lg;
     const int half = n >> 1;
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -178,8 +226,155 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
     gather(pin, ix, iu, j, k, v);
     unsigned fb = 0;
     const double un = relax_cell(v, s[((k << lg) + j) * n + iu], al, fb);
+    const double uc = pin[ix(ic, j, k)];
     pout[ix(iu, j, k)] = un;
-    pout[ix(ic, j, k)] = pin[ix(ic, j, k)];
+    pout[ix(ic, j, k)] = uc;
+    if (!PER && dyn_bc) {
+        write_owned_ghosts(pout, hat, ix, iu, j, k, un);
+        write_owned_ghosts(pout, hat, ix, ic, j, k, uc);
+    }
+    if (fb) atomicAdd(fallbacks, fb);
+}
+
+// One full red-black sweep of a periodic level in one launch, with the same
+// semantics as two k_smooth_half launches (colour 0 from pin, then colour 1
+// from that result; same-colour neighbours always at their pass-start
+// values), bit for bit.
+//
+// A workgroup owns a TX x TY column of the x-y plane over TZ planes and
+// streams along z.  Per output plane k it keeps in LDS
+//   P: the old field on planes k..k+2, TX+4 x TY+4 (halo 2),
+//   R: planes k-1..k+1 after the red pass, TX+2 x TY+2 (halo 1): red cells
+//      relaxed, black cells old,
+// relaxes the red cells of plane k+1 over the tile plus halo 1 (the black
+// pass of the tile's edge cells needs them), then the black cells of plane k
+// over the tile, and writes plane k.  Plane k+3 is read into registers
+// while plane k is relaxed.  HBM sees each old value and each source value
+// once and each new value once: 24 bytes per cell and sweep, plus the halo
+// re-reads, which neighbouring workgroups mostly find in L2.
+template <int TX, int TY, int TZ, int NT>
+__global__ void __launch_bounds__(NT)
+k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
+              const double *__restrict__ s, int lg, double al, unsigned *__restrict__ fallbacks) {
+    constexpr int PX = TX + 4, PY = TY + 4, RX = TX + 2, RY = TY + 2;
+    constexpr int PLANE = PX * PY;
+    constexpr int PRE = (PLANE + NT - 1) / NT; // prefetched values per thread
+    constexpr int RED_ROW = RX / 2;            // red (or black) cells per region row
+    constexpr int RED_CELLS = RED_ROW * RY;
+    constexpr int SEGS = TX * TY / 2;          // 2-cell (one red, one black) output segments
+    static_assert(TX % 2 == 0 && TY % 2 == 0 && SEGS == NT, "one output segment per thread");
+    __shared__ double P[3][PLANE];
+    __shared__ double R[3][RY][RX];
+
+    const int n = 1 << lg, m = n - 1;
+    const int ntx = n / TX;
+    const int x0 = (blockIdx.x % ntx) * TX;
+    const int y0 = (blockIdx.x / ntx) * TY;
+    const int z0 = blockIdx.y * TZ;
+    const int tid = threadIdx.x;
+    unsigned fb = 0;
+
+    auto gidx = [&](int x, int y, int z) {
+        return ((((z & m) << lg) | (y & m)) << lg) | (x & m);
+    };
+    auto slot = [](int z) { return (z + 3 * 4096) % 3; };
+
+    double pre[PRE];
+    auto fetch = [&](int z) {
+#pragma unroll
+        for (int e = 0; e < PRE; ++e) {
+            const int q = tid + e * NT;
+            if (q < PLANE) {
+                const int yy = q / PX, xx = q - yy * PX;
+                pre[e] = pin[gidx(x0 - 2 + xx, y0 - 2 + yy, z)];
+            }
+        }
+    };
+    auto commit = [&](int z) {
+        double *dst = P[slot(z)];
+#pragma unroll
+        for (int e = 0; e < PRE; ++e) {
+            const int q = tid + e * NT;
+            if (q < PLANE) dst[q] = pre[e];
+        }
+    };
+
+    // R plane z: black cells copied, red cells relaxed from P planes z-1..z+1
+    auto red_plane = [&](int z) {
+        const double(*pm)[PX] = reinterpret_cast<const double(*)[PX]>(P[slot(z - 1)]);
+        const double(*p0)[PX] = reinterpret_cast<const double(*)[PX]>(P[slot(z)]);
+        const double(*pp)[PX] = reinterpret_cast<const double(*)[PX]>(P[slot(z + 1)]);
+        double(*r)[RX] = R[slot(z)];
+        for (int q = tid; q < RED_CELLS; q += NT) {
+            const int yr = q / RED_ROW, c2 = q - yr * RED_ROW;
+            const int y = y0 - 1 + yr;
+            // region column xr <-> global x = x0 - 1 + xr; red: (x + y + z) even
+            const int xr_red = 2 * c2 + ((1 + y + z) & 1);
+            const int xr_blk = 2 * c2 + ((y + z) & 1);
+            const double sv = s[gidx(x0 - 1 + xr_red, y, z)];
+            r[yr][xr_blk] = p0[yr + 1][xr_blk + 1];
+            const int c = xr_red + 1, rr = yr + 1;
+            const double v[19] = {
+                p0[rr][c], p0[rr][c + 1], p0[rr][c - 1], p0[rr + 1][c], p0[rr - 1][c],
+                pp[rr][c], pm[rr][c],
+                p0[rr + 1][c + 1], p0[rr - 1][c + 1], p0[rr + 1][c - 1], p0[rr - 1][c - 1],
+                pp[rr][c + 1], pm[rr][c + 1], pp[rr][c - 1], pm[rr][c - 1],
+                pp[rr + 1][c], pm[rr + 1][c], pp[rr - 1][c], pm[rr - 1][c]};
+            r[yr][xr_red] = relax_cell(v, sv, al, fb);
+        }
+    };
+
+    // black cell of plane k in this thread's segment, then write the segment
+    const int yt = tid / (TX / 2), xs = (tid - yt * (TX / 2)) * 2;
+    auto black_and_store = [&](int k, double sv) {
+        const double(*rm)[RX] = R[slot(k - 1)];
+        const double(*r0)[RX] = R[slot(k)];
+        const double(*rp)[RX] = R[slot(k + 1)];
+        const int y = y0 + yt;
+        const int b = (1 + y + k + x0 + xs) & 1; // black cell's offset in the segment
+        const int c = xs + b + 1, rr = yt + 1;
+        const double v[19] = {
+            r0[rr][c], r0[rr][c + 1], r0[rr][c - 1], r0[rr + 1][c], r0[rr - 1][c],
+            rp[rr][c], rm[rr][c],
+            r0[rr + 1][c + 1], r0[rr - 1][c + 1], r0[rr + 1][c - 1], r0[rr - 1][c - 1],
+            rp[rr][c + 1], rm[rr][c + 1], rp[rr][c - 1], rm[rr][c - 1],
+            rp[rr + 1][c], rm[rr + 1][c], rp[rr - 1][c], rm[rr - 1][c]};
+        const double vb = relax_cell(v, sv, al, fb);
+        const double vr = r0[rr][xs + (1 - b) + 1];
+        double *dst = pout + gidx(x0 + xs, y, k);
+        dst[0] = b ? vr : vb;
+        dst[1] = b ? vb : vr;
+    };
+    auto black_source = [&](int k) {
+        const int y = y0 + yt;
+        const int b = (1 + y + k + x0 + xs) & 1;
+        return s[gidx(x0 + xs + b, y, k)];
+    };
+
+    fetch(z0 - 2);
+    commit(z0 - 2);
+    fetch(z0 - 1);
+    commit(z0 - 1);
+    fetch(z0);
+    commit(z0);
+    __syncthreads();
+    red_plane(z0 - 1);
+    fetch(z0 + 1);
+    __syncthreads();
+    commit(z0 + 1);
+    fetch(z0 + 2);
+    __syncthreads();
+    red_plane(z0);
+    __syncthreads();
+    for (int k = z0; k < z0 + TZ; ++k) {
+        commit(k + 2); // into the slot of plane k-1, last read by red_plane(k)
+        if (k + 3 <= z0 + TZ + 1) fetch(k + 3);
+        const double sb = black_source(k);
+        __syncthreads();
+        red_plane(k + 1);
+        __syncthreads();
+        black_and_store(k, sb);
+    }
     if (fb) atomicAdd(fallbacks, fb);
 }
 
@@ -298,7 +493,7 @@ k_restrict_residual(const double *__restrict__ phi_f, const double *__restrict__
 template <bool PER>
 __global__ void __launch_bounds__(kBlock)
 k_coarse_source(const double *__restrict__ hat, double *__restrict__ phi,
-                double *__restrict__ s, Ix<PER> ix, double al) {
+                double *__restrict__ s, Ix<PER> ix, double al, int dyn_bc) {
     const int n = ix.n, lg = ix.lg;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= (1 << (3 * lg))) return;
@@ -307,6 +502,7 @@ k_coarse_source(const double *__restrict__ hat, double *__restrict__ phi,
     gather(hat, ix, i, j, k, v);
     s[t] = apply_L(stencil_terms(v), al) + s[t];
     phi[ix(i, j, k)] = v[0];
+    if (!PER && dyn_bc) write_owned_ghosts(phi, hat, ix, i, j, k, v[0]); // zero correction
 }
 
 // Trilinear cell-centred transfer: a fine cell centre sits a quarter coarse
@@ -315,7 +511,8 @@ k_coarse_source(const double *__restrict__ hat, double *__restrict__ phi,
 template <bool PER, bool CORRECT>
 __global__ void __launch_bounds__(kBlock)
 k_prolong(double *__restrict__ phi_f, Ix<PER> ixf, const double *__restrict__ phi_c,
-          const double *__restrict__ hat_c, Ix<PER> ixc) {
+          const double *__restrict__ hat_c, Ix<PER> ixc, const double *__restrict__ hat_f,
+          int dyn_bc_f) {
     const int n = ixf.n, lg = ixf.lg;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= (1 << (3 * lg))) return;
@@ -334,10 +531,10 @@ k_prolong(double *__restrict__ phi_f, Ix<PER> ixf, const double *__restrict__ ph
                 const double val = CORRECT ? phi_c[q] - hat_c[q] : phi_c[q];
                 acc = fma(w, val, acc);
             }
-    if (CORRECT)
-        phi_f[ixf(i, j, k)] += acc;
-    else
-        phi_f[ixf(i, j, k)] = acc;
+    const int me = ixf(i, j, k);
+    const double val = CORRECT ? phi_f[me] + acc : acc;
+    phi_f[me] = val;
+    if (!PER && dyn_bc_f) write_owned_ghosts(phi_f, hat_f, ixf, i, j, k, val);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -363,7 +560,8 @@ k_restrict_source(const double *__restrict__ s_f, int nf, double *__restrict__ s
 template <bool PER>
 __global__ void __launch_bounds__(512)
 k_coarsest(double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix, double al,
-           int sweeps, unsigned *__restrict__ fallbacks) {
+           int sweeps, unsigned *__restrict__ fallbacks, const double *__restrict__ hat,
+           int dyn_bc) {
     __shared__ double A[(kCoarsestMax + 2) * (kCoarsestMax + 2) * (kCoarsestMax + 2)];
     __shared__ double B[(kCoarsestMax + 2) * (kCoarsestMax + 2) * (kCoarsestMax + 2)];
     const int n = ix.n, lg = ix.lg;
@@ -403,11 +601,12 @@ k_coarsest(double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix, d
                     val = src[me];
                 }
                 dst[me] = val;
+                if (!PER && dyn_bc) write_owned_ghosts(dst, hat, ix, i, j, k, val);
             }
             __syncthreads();
         }
     }
-    if (active) phi[ix(i, j, k)] = A[ix(i, j, k)];
+    for (int q = threadIdx.x; q < slots; q += blockDim.x) phi[q] = A[q];
     if (fb) atomicAdd(fallbacks, fb);
 }
 
@@ -509,10 +708,28 @@ void launch_smooth_half(const Level &L, const double *pin, double *pout, int col
     const unsigned nb = blocks_for(L.cells() / 2);
     if (L.periodic)
         k_smooth_half<true><<<nb, kBlock, 0, st>>>(pin, pout, L.s, make_ix<true>(L.n, L.lg),
-                                                   L.alpha, colour, fallbacks);
+                                                   L.alpha, colour, fallbacks, nullptr, 0);
     else
         k_smooth_half<false><<<nb, kBlock, 0, st>>>(pin, pout, L.s, make_ix<false>(L.n, L.lg),
-                                                    L.alpha, colour, fallbacks);
+                                                    L.alpha, colour, fallbacks, L.hat,
+                                                    L.dyn_bc ? 1 : 0);
+}
+
+bool fused_sweep_ok(const Level &L) { return L.periodic && L.n >= 128; }
+
+void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
+                        hipStream_t st) {
+    constexpr int TX = 64, TY = 16, NT = 512;
+    const int tiles = (L.n / TX) * (L.n / TY);
+    if (L.n >= 512) {
+        constexpr int TZ = 32;
+        k_sweep_fused<TX, TY, TZ, NT><<<dim3(tiles, L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
+                                                                          L.alpha, fallbacks);
+    } else {
+        constexpr int TZ = 16;
+        k_sweep_fused<TX, TY, TZ, NT><<<dim3(tiles, L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
+                                                                          L.alpha, fallbacks);
+    }
 }
 
 void launch_residual_sumsq(const Level &L, double *partials, double *r_out, double r_scale,
@@ -555,30 +772,34 @@ void launch_coarse_source(const Level &C, hipStream_t st) {
     const unsigned nb = blocks_for(C.cells());
     if (C.periodic)
         k_coarse_source<true><<<nb, kBlock, 0, st>>>(C.hat, C.phi, C.s, make_ix<true>(C.n, C.lg),
-                                                     C.alpha);
+                                                     C.alpha, 0);
     else
         k_coarse_source<false><<<nb, kBlock, 0, st>>>(C.hat, C.phi, C.s,
-                                                      make_ix<false>(C.n, C.lg), C.alpha);
+                                                      make_ix<false>(C.n, C.lg), C.alpha,
+                                                      C.dyn_bc ? 1 : 0);
 }
 
 void launch_prolong_correct(const Level &F, const Level &C, hipStream_t st) {
     const unsigned nb = blocks_for(F.cells());
     if (F.periodic)
         k_prolong<true, true><<<nb, kBlock, 0, st>>>(F.phi, make_ix<true>(F.n, F.lg), C.phi,
-                                                     C.hat, make_ix<true>(C.n, C.lg));
+                                                     C.hat, make_ix<true>(C.n, C.lg), nullptr, 0);
     else
         k_prolong<false, true><<<nb, kBlock, 0, st>>>(F.phi, make_ix<false>(F.n, F.lg), C.phi,
-                                                      C.hat, make_ix<false>(C.n, C.lg));
+                                                      C.hat, make_ix<false>(C.n, C.lg), F.hat,
+                                                      F.dyn_bc ? 1 : 0);
 }
 
 void launch_prolong_full(const Level &F, const Level &C, hipStream_t st) {
     const unsigned nb = blocks_for(F.cells());
     if (F.periodic)
         k_prolong<true, false><<<nb, kBlock, 0, st>>>(F.phi, make_ix<true>(F.n, F.lg), C.phi,
-                                                      nullptr, make_ix<true>(C.n, C.lg));
+                                                      nullptr, make_ix<true>(C.n, C.lg), nullptr,
+                                                      0);
     else
         k_prolong<false, false><<<nb, kBlock, 0, st>>>(F.phi, make_ix<false>(F.n, F.lg), C.phi,
-                                                       nullptr, make_ix<false>(C.n, C.lg));
+                                                       nullptr, make_ix<false>(C.n, C.lg), F.hat,
+                                                       F.dyn_bc ? 1 : 0);
 }
 
 void launch_restrict_source(const Level &F, const Level &C, hipStream_t st) {
@@ -589,10 +810,10 @@ void launch_coarsest(const Level &L, int sweeps, unsigned *fallbacks, hipStream_
     const int threads = L.cells() < 64 ? 64 : (int)L.cells();
     if (L.periodic)
         k_coarsest<true><<<1, threads, 0, st>>>(L.phi, L.s, make_ix<true>(L.n, L.lg), L.alpha,
-                                                sweeps, fallbacks);
+                                                sweeps, fallbacks, nullptr, 0);
     else
         k_coarsest<false><<<1, threads, 0, st>>>(L.phi, L.s, make_ix<false>(L.n, L.lg), L.alpha,
-                                                 sweeps, fallbacks);
+                                                 sweeps, fallbacks, L.hat, L.dyn_bc ? 1 : 0);
 }
 
 void launch_source(const double *delta, size_t count, const double *sum, double inv_count_mean,

@@ -180,7 +180,7 @@ bool resolve(const ndgp_grid *g, const ndgp_params *p, Cfg &c, std::string &why)
         why = "precision must be NDGP_PREC_FP64 in this build";
         return false;
     }
-    if (p->flags & ~(NDGP_WARM_START | NDGP_PROFILE)) {
+    if (p->flags & ~(NDGP_WARM_START | NDGP_PROFILE | NDGP_TWO_PASS)) {
         why = "unknown flag bits";
         return false;
     }
@@ -278,6 +278,7 @@ size_t carve(Plan &P, char *base) {
                 L.alt = cv.take<double>(L.slots());
                 L.s = cv.take<double>(L.cells());
                 L.hat = m ? cv.take<double>(L.slots()) : nullptr;
+                L.dyn_bc = m > 0;
             }
         }
     }
@@ -317,6 +318,7 @@ struct SmoothTimer {
     bool on = false;
     std::vector<hipEvent_t> ev; // start/stop pairs
     int launches = 0;
+    size_t cells_per_launch = 0;
     ~SmoothTimer() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
@@ -364,17 +366,27 @@ struct Runner {
         return read_scalar(P.scal + 2);
     }
 
+    // `sweeps` red-black sweeps; the iterate ends in the buffer it started in
+    // (the fused kernel swaps once per sweep, so an odd last sweep takes the
+    // two-launch path, which swaps twice).
     void smooth(Level &L, int sweeps) {
+        const bool fused = !(P.c.flags & NDGP_TWO_PASS) && fused_sweep_ok(L);
+        const int nf = fused ? (sweeps & ~1) : 0;
         const bool timed = timer && timer->on && L.s == timed_s;
         if (timed) timer->mark(st);
-        for (int s = 0; s < sweeps; ++s)
+        for (int s = 0; s < nf; ++s) {
+            launch_sweep_fused(L, L.phi, L.alt, P.fallbacks, st);
+            std::swap(L.phi, L.alt);
+        }
+        for (int s = nf; s < sweeps; ++s)
             for (int col = 0; col < 2; ++col) {
                 launch_smooth_half(L, L.phi, L.alt, col, P.fallbacks, st);
                 std::swap(L.phi, L.alt);
             }
         if (timed) {
             timer->mark(st);
-            timer->launches += 2 * sweeps;
+            timer->launches += nf + 2 * (sweeps - nf);
+            timer->cells_per_launch = nf ? L.cells() : L.cells() / 2;
         }
     }
 
@@ -443,9 +455,6 @@ struct Runner {
     }
 };
 
-// cells one red-black half sweep updates
-size_t cells_half(int n) { return (size_t)n * n * n / 2; }
-
 ndgp_status check_arrays(const Cfg &c, const double *const *delta, double *const *phi,
                          bool need_patch_delta) {
     if (!delta || !phi || !delta[0] || !phi[0])
@@ -508,7 +517,7 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         if (timer.launches) {
             R.t_smooth_ms = timer.total_ms();
             R.smooth_launches = timer.launches;
-            R.smooth_cells_per_launch = (int32_t)(cells_half(c.n));
+            R.smooth_cells_per_launch = (int32_t)timer.cells_per_launch;
         }
         if (status != NDGP_OK && !std::isfinite(rel)) {
             if (rep) *rep = R;

@@ -26,6 +26,7 @@ MODE_FULL, MODE_INTERPOLATED = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 WARM_START = 1
 PROFILE = 2
+TWO_PASS = 4
 MAX_PATCHES = 2
 HIST_LEN = 64
 
@@ -158,6 +159,7 @@ class Params:
     precision: int = PREC_FP64
     warm_start: bool = False
     profile: bool = False
+    two_pass: bool = False
 
     def _c(self) -> _Params:
         p = _Params()
@@ -165,7 +167,8 @@ class Params:
         p.beta = self.beta if self.beta is not None else beta_lcdm(self.a, self.omega_m, self.rc)
         p.max_cycles, p.nu1, p.nu2, p.n_levels = self.max_cycles, self.nu1, self.nu2, self.n_levels
         p.mode, p.precision = self.mode, self.precision
-        p.flags = (WARM_START if self.warm_start else 0) | (PROFILE if self.profile else 0)
+        p.flags = ((WARM_START if self.warm_start else 0) | (PROFILE if self.profile else 0)
+                   | (TWO_PASS if self.two_pass else 0))
         return p
 
 

@@ -67,6 +67,7 @@ def gpu_solve(delta_list, grid, **kw):
     (64, 64.0, 2.0, 20, 1.0, 8),       # lognormal + top-hats, several tiles
     (64, 128.0, 2.5, 0, 5.0, 9),       # strongest screening of the 512^3 set
     (16, 16.0, 1.0, 1, 0.5, 3),
+    (128, 128.0, 2.0, 30, 1.0, 10),    # large enough for the fused LDS sweep
 ])
 def test_periodic_solution_matches_oracle(n, box, sigma, tophats, rc, seed):
     say(f"periodic n={n} sigma={sigma} tophats={tophats} rc={rc}")
@@ -154,6 +155,21 @@ def test_scale_law_bitwise_and_determinism():
     assert r1.cycles == r2.cycles
     assert np.array_equal(p2, 4 * p1)
     assert np.array_equal(p3, p1)
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_fused_sweep_bitwise_equals_two_pass(n):
+    """The one-launch LDS sweep and the one-colour-per-launch kernels give the
+    same bits for the whole solve."""
+    say(f"fused vs two-pass n={n}")
+    f = synth.make_field(n, 2.0, 31, n_tophats=10)
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n))
+    d = dev(f.delta)
+    a, ra = ndgp.solve(grid, ndgp.Params(rc=1.0, tol=1e-10), [d])
+    b, rb = ndgp.solve(grid, ndgp.Params(rc=1.0, tol=1e-10, two_pass=True), [d])
+    torch.cuda.synchronize()
+    assert ra.cycles == rb.cycles and ra.history == rb.history
+    assert torch.equal(a[0], b[0])
 
 
 def test_warm_start_and_errors():
