@@ -203,6 +203,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=4)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 128 MiB device-to-device copy three times "
+                         "(the reference kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this solver runs on a single MI355X "
@@ -239,6 +242,14 @@ def main():
     }
     del phi, dd
     torch.cuda.empty_cache()
+    if args.calibrate_copy:
+        a = torch.ones(n**3, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = {"read": a.numel() * 8, "write": b.numel() * 8}
+        del a, b
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(f.delta, grid.h, rc, args.cpu_cycles)

@@ -76,7 +76,12 @@ typedef enum {
 
 typedef enum {
     NDGP_PREC_FP64 = 0, /* every kernel in FP64                                       */
-    NDGP_PREC_MIXED = 1 /* FP32 relaxation inside an FP64 defect-correction loop      */
+    NDGP_PREC_MIXED = 1 /* domain level: FP32 multigrid on the correction e of
+                           L[phi + e] - L[phi] = s - L[phi] inside an FP64
+                           defect-correction loop (FP64 residual, update and
+                           quadratic discriminant); ndgp_report.cycles[0] counts
+                           the outer iterations (2 FP32 V-cycles each).  Patches
+                           relax in FP64. */
 } ndgp_precision;
 
 /* flags */

@@ -102,3 +102,48 @@ void launch_diff_partials(const double *a, const double *b, size_t count, double
 void launch_copy(const double *src, double *dst, size_t count, hipStream_t st);
 
 } // namespace ndgp
+
+namespace ndgp {
+
+// FP32 side of the mixed-precision solve: per periodic level the FP32 copy
+// of the current FP64 field (`phi`, the base of the correction), the
+// correction e and its ping-pong partner, the correction equation's source
+// r and, on coarse levels, the restriction of the finer correction.  Cell
+// units as in Level.
+struct Level32 {
+    int n = 0, lg = 0;
+    double alpha = 0.0;
+    float *phi = nullptr;
+    float *e = nullptr;
+    float *ealt = nullptr;
+    float *r = nullptr;
+    float *ehat = nullptr;
+    size_t cells() const { return (size_t)n * n * n; }
+};
+
+// ---- mixed-precision launchers (ndgp_mixed.hip) ---------------------------
+
+// r32 = float(s - L[phi]) with FP64 arithmetic, and per-block partials of
+// (s - L[phi])^2.
+void launch_residual_to32(const Level &L, float *r32, double *partials, hipStream_t st);
+// phi32 = float(phi64)
+void launch_to32(const double *a, float *b, size_t count, hipStream_t st);
+// coarse = mean of the 8 children (FP32 field)
+void launch_avg32(const Level32 &F, const Level32 &C, hipStream_t st);
+// phi64 += double(e32)
+void launch_add32(double *phi, const float *e, size_t count, hipStream_t st);
+void launch_fill32(float *a, size_t count, float v, hipStream_t st);
+// one colour of a red-black sweep of the correction equation
+// L[phi + e] - L[phi] = r on a periodic level
+void launch_corr_half(const Level32 &L, const float *ein, float *eout, int colour,
+                      unsigned *fallbacks, hipStream_t st);
+// C.ehat = mean children of F.e; C.r = 4 mean children of (r - A(e))
+void launch_corr_restrict(const Level32 &F, const Level32 &C, hipStream_t st);
+// C.r = A_C(C.ehat) + C.r; C.e = C.ehat
+void launch_corr_coarse_source(const Level32 &C, hipStream_t st);
+// F.e += trilinear(C.e - C.ehat)
+void launch_corr_prolong(const Level32 &F, const Level32 &C, hipStream_t st);
+// many sweeps of the correction equation on a <= 8^3 level in one workgroup
+void launch_corr_coarsest(const Level32 &L, int sweeps, unsigned *fallbacks, hipStream_t st);
+
+} // namespace ndgp

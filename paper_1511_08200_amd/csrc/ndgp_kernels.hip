@@ -12,196 +12,12 @@
 // kReduceBlocks blocks, a fixed per-thread order, in-wave xor-shuffle trees
 // and a fixed combination across waves.
 
-#include "ndgp_internal.h"
+#include "ndgp_device.h"
 
 namespace ndgp {
 namespace {
 
-// ------------------------------------------------------------------------
-// indexing: periodic levels are natural n^3 with wrap-around (n a power of
-// two, so wrap is a mask); Dirichlet levels are padded (n+2)^3.
-
-template <bool PER>
-struct Ix {
-    int n, lg, p;
-    __device__ __forceinline__ int operator()(int i, int j, int k) const {
-        if constexpr (PER) {
-            const int m = n - 1;
-            return ((((k & m) << lg) | (j & m)) << lg) | (i & m);
-        } else {
-            return ((k + 1) * p + (j + 1)) * p + (i + 1);
-        }
-    }
-};
-
-template <bool PER>
-inline Ix<PER> make_ix(int n, int lg) {
-    return Ix<PER>{n, lg, n + 2};
-}
-
-inline int log2i(int n) {
-    int l = 0;
-    while ((1 << l) < n) ++l;
-    return l;
-}
-
-inline unsigned blocks_for(size_t total) {
-    return (unsigned)((total + kBlock - 1) / kBlock);
-}
-
-// ------------------------------------------------------------------------
-// the 19-point stencil
-//
-// v[0] centre; v[1..6] faces x+ x- y+ y- z+ z-; v[7..18] edges, by plane and
-// corner (s,t) in the order ++ +- -+ --: xy (7-10), xz (11-14), yz (15-18).
-
-template <bool PER>
-__device__ __forceinline__ void gather(const double *__restrict__ a, const Ix<PER> &ix, int i,
-                                       int j, int k, double v[19]) {
-    v[0] = a[ix(i, j, k)];
-    v[1] = a[ix(i + 1, j, k)];
-    v[2] = a[ix(i - 1, j, k)];
-    v[3] = a[ix(i, j + 1, k)];
-    v[4] = a[ix(i, j - 1, k)];
-    v[5] = a[ix(i, j, k + 1)];
-    v[6] = a[ix(i, j, k - 1)];
-    v[7] = a[ix(i + 1, j + 1, k)];
-    v[8] = a[ix(i + 1, j - 1, k)];
-    v[9] = a[ix(i - 1, j + 1, k)];
-    v[10] = a[ix(i - 1, j - 1, k)];
-    v[11] = a[ix(i + 1, j, k + 1)];
-    v[12] = a[ix(i + 1, j, k - 1)];
-    v[13] = a[ix(i - 1, j, k + 1)];
-    v[14] = a[ix(i - 1, j, k - 1)];
-    v[15] = a[ix(i, j + 1, k + 1)];
-    v[16] = a[ix(i, j + 1, k - 1)];
-    v[17] = a[ix(i, j - 1, k + 1)];
-    v[18] = a[ix(i, j - 1, k - 1)];
-}
-
-// Pieces of the discrete operator at one cell (spacing 1):
-//   lap = D_xx + D_yy + D_zz, D_aa = second difference along a;
-//   nl  = sum_{a<b} D_aa D_bb - (1/4) sum over the 12 corner mixed
-//         differences C^2, C = phi[c+s e_a+t e_b] - phi[c+s e_a] - phi[c+t e_b] + phi[c];
-//   see = sum over the 12 edge neighbours of (phi_edge - phi[c]).
-// L[phi] = lap + 2 alpha nl.
-struct Terms {
-    double lap, nl, see;
-};
-
-__device__ __forceinline__ Terms stencil_terms(const double v[19]) {
-    const double u = v[0];
-    const double dxp = v[1] - u, dxm = v[2] - u;
-    const double dyp = v[3] - u, dym = v[4] - u;
-    const double dzp = v[5] - u, dzm = v[6] - u;
-    const double Dxx = dxp + dxm, Dyy = dyp + dym, Dzz = dzp + dzm;
-    double e, c, c2, see;
-    e = v[7] - u;  see = e;  c = e - dxp - dyp; c2 = c * c;
-    e = v[8] - u;  see += e; c = e - dxp - dym; c2 = fma(c, c, c2);
-    e = v[9] - u;  see += e; c = e - dxm - dyp; c2 = fma(c, c, c2);
-    e = v[10] - u; see += e; c = e - dxm - dym; c2 = fma(c, c, c2);
-    e = v[11] - u; see += e; c = e - dxp - dzp; c2 = fma(c, c, c2);
-    e = v[12] - u; see += e; c = e - dxp - dzm; c2 = fma(c, c, c2);
-    e = v[13] - u; see += e; c = e - dxm - dzp; c2 = fma(c, c, c2);
-    e = v[14] - u; see += e; c = e - dxm - dzm; c2 = fma(c, c, c2);
-    e = v[15] - u; see += e; c = e - dyp - dzp; c2 = fma(c, c, c2);
-    e = v[16] - u; see += e; c = e - dyp - dzm; c2 = fma(c, c, c2);
-    e = v[17] - u; see += e; c = e - dym - dzp; c2 = fma(c, c, c2);
-    e = v[18] - u; see += e; c = e - dym - dzm; c2 = fma(c, c, c2);
-    Terms t;
-    t.lap = (Dxx + Dyy) + Dzz;
-    t.nl = fma(Dxx, Dyy, fma(Dxx, Dzz, Dyy * Dzz)) - 0.25 * c2;
-    t.see = see;
-    return t;
-}
-
-__device__ __forceinline__ double apply_L(const Terms &t, double al) {
-    return fma(2.0 * al, t.nl, t.lap);
-}
-
-// New value of the centre cell: the root of its own equation T(u') = 0 that is
-// continuous with the linear case.  Moving u by du shifts every D_aa by -2 du
-// and every corner difference by +du, so with dt = 2 du
-//     T(dt) = r - B dt + (9/2) alpha dt^2,   r = L - s,
-//     B = 3 + 4 alpha lap + 2 alpha M,  M = (1/4) sum C = see/4 - lap,
-// and the root is dt = 2 r / (B + sqrt(B^2 - 18 alpha r)) (no cancellation).
-// B <= 0: the linearised operator is not elliptic at this cell; it waits for
-// its neighbours.  No real root: move to the vertex dt = B / (9 alpha).
-// Reciprocal and square root from the hardware estimates plus one Newton
-// step each (relative error near 1e-16).  The relaxation only needs them to
-// pick its step: the fixed point L[phi] = s does not depend on how they round.
-__device__ __forceinline__ double fast_rcp(double q) {
-    const double y = __builtin_amdgcn_rcp(q);
-    return fma(y, fma(-q, y, 1.0), y);
-}
-
-__device__ __forceinline__ double fast_sqrt(double d) {
-    const double rs = __builtin_amdgcn_rsq(d);
-    const double s0 = d * rs;
-    const double e = fma(-s0, 0.5 * rs, 0.5);
-    const double s1 = fma(s0, e, s0);
-    return d > 0.0 ? s1 : 0.0;
-}
-
-__device__ __forceinline__ double relax_cell(const double v[19], double s, double al,
-                                             unsigned &fallbacks) {
-    const Terms t = stencil_terms(v);
-    const double r = apply_L(t, al) - s;
-    const double B = fma(al, fma(2.0, t.lap, 0.5 * t.see), 3.0);
-    if (!(B > 0.0)) return v[0];
-    const double D = fma(B, B, -18.0 * al * r);
-    if (D < 0.0) {
-        ++fallbacks;
-        return v[0] + B / (18.0 * al);
-    }
-    return fma(r, fast_rcp(B + fast_sqrt(D)), v[0]);
-}
-
-// Coarse levels of a refinement: write the ghosts whose correction is taken
-// from interior cell (i,j,k), now holding `val`.  The correction phi - hat is
-// extrapolated linearly through zero at the fine boundary position (half a
-// fine cell outside), which puts -1/3 of it on the coarse ghost per axis
-// along which the ghost lies outside.  Every ghost has exactly one such
-// interior cell, so each is written by one thread.
-template <bool PER>
-__device__ __forceinline__ void write_owned_ghosts(double *__restrict__ out,
-                                                   const double *__restrict__ hat,
-                                                   const Ix<PER> &ix, int i, int j, int k,
-                                                   double val) {
-    if constexpr (!PER) {
-        const int n = ix.n;
-        const bool bx = i == 0 || i == n - 1, by = j == 0 || j == n - 1, bz = k == 0 || k == n - 1;
-        if (!(bx || by || bz)) return;
-        const int gx = i == 0 ? -1 : n, gy = j == 0 ? -1 : n, gz = k == 0 ? -1 : n;
-        const double e = val - hat[ix(i, j, k)];
-#pragma unroll
-        for (int mz = 0; mz < 2; ++mz)
-#pragma unroll
-            for (int my = 0; my < 2; ++my)
-#pragma unroll
-                for (int mx = 0; mx < 2; ++mx) {
-                    if ((mx && !bx) || (my && !by) || (mz && !bz) || (mx + my + mz) == 0) continue;
-                    const int d = mx + my + mz;
-                    const double f = d == 1 ? -1.0 / 3.0 : (d == 2 ? 1.0 / 9.0 : -1.0 / 27.0);
-                    const int q = ix(mx ? gx : i, my ? gy : j, mz ? gz : k);
-                    out[q] = hat[q] + f * e;
-                }
-    }
-}
-
-// ------------------------------------------------------------------------
-// deterministic block sum (kBlock = 256 threads = 4 waves of 64)
-
-__device__ __forceinline__ double block_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    __shared__ double wsum[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
-    return r;
-}
+using namespace dev;
 
 // ------------------------------------------------------------------------
 // kernels

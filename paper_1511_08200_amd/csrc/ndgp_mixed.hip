@@ -1,0 +1,331 @@
+// ndgp_mixed.hip -- FP32 kernels of the mixed-precision solve.
+//
+// The FP64 outer loop computes r = s - L[phi] and adds corrections to phi.
+// The correction e solves L[phi + e] - L[phi] = r, relaxed here in FP32 with
+// the same red-black per-cell root and full-approximation multigrid as the
+// FP64 path.  An FP32 copy of phi alone cannot carry the solution (its
+// second differences keep only a few of FP32's digits), so the operator is
+// never formed as a difference of two full evaluations: writing w = phi + e,
+//   L[w] - L[phi] = lap e + 2 alpha ( sum_{a<b} (Dw_a De_b + De_a Dphi_b)
+//                                     - 1/4 sum_corners (Cw + Cphi) Ce ),
+// every term carries a factor of e, so FP32 rounding stays relative to the
+// correction.  The phi terms only set the coefficients, where FP32's
+// accuracy is ample.  The quadratic's discriminant, the root and every
+// FP64-field update are in FP64.  Periodic levels only.
+
+#include "ndgp_device.h"
+
+namespace ndgp {
+namespace {
+
+using namespace dev;
+
+struct CorrTerms {
+    float A;    // L[phi + e] - L[phi] at the cell
+    float lapw; // lap of w = phi + e
+    float seew; // sum over edges of (w_edge - w_centre)
+};
+
+__device__ __forceinline__ CorrTerms corr_terms(const float vp[19], const float ve[19], float al) {
+    const float up = vp[0], ue = ve[0];
+    const float pxp = vp[1] - up, pxm = vp[2] - up, pyp = vp[3] - up, pym = vp[4] - up;
+    const float pzp = vp[5] - up, pzm = vp[6] - up;
+    const float exp_ = ve[1] - ue, exm = ve[2] - ue, eyp = ve[3] - ue, eym = ve[4] - ue;
+    const float ezp = ve[5] - ue, ezm = ve[6] - ue;
+    const float Dpx = pxp + pxm, Dpy = pyp + pym, Dpz = pzp + pzm;
+    const float Dex = exp_ + exm, Dey = eyp + eym, Dez = ezp + ezm;
+    const float Dwx = Dpx + Dex, Dwy = Dpy + Dey, Dwz = Dpz + Dez;
+    const float pair = fmaf(Dwx, Dey, Dex * Dpy) + fmaf(Dwx, Dez, Dex * Dpz) +
+                       fmaf(Dwy, Dez, Dey * Dpz);
+    float cs = 0.f, see = 0.f;
+    auto corner = [&](int q, float pa, float pb, float ea, float eb) {
+        const float gp = vp[q] - up, ge = ve[q] - ue;
+        see += gp + ge;
+        const float Cp = gp - pa - pb, Ce = ge - ea - eb;
+        cs = fmaf(Cp + Cp + Ce, Ce, cs);
+    };
+    corner(7, pxp, pyp, exp_, eyp);
+    corner(8, pxp, pym, exp_, eym);
+    corner(9, pxm, pyp, exm, eyp);
+    corner(10, pxm, pym, exm, eym);
+    corner(11, pxp, pzp, exp_, ezp);
+    corner(12, pxp, pzm, exp_, ezm);
+    corner(13, pxm, pzp, exm, ezp);
+    corner(14, pxm, pzm, exm, ezm);
+    corner(15, pyp, pzp, eyp, ezp);
+    corner(16, pyp, pzm, eyp, ezm);
+    corner(17, pym, pzp, eym, ezp);
+    corner(18, pym, pzm, eym, ezm);
+    CorrTerms t;
+    t.A = fmaf(2.f * al, pair - 0.25f * cs, (Dex + Dey) + Dez);
+    t.lapw = (Dwx + Dwy) + Dwz;
+    t.seew = see;
+    return t;
+}
+
+// New correction at the cell: the root of its own quadratic (same algebra as
+// relax_cell, with w = phi + e in place of phi), discriminant and root in FP64.
+__device__ __forceinline__ float relax_corr_cell(const float vp[19], const float ve[19], float r,
+                                                 float al, unsigned &fallbacks) {
+    const CorrTerms t = corr_terms(vp, ve, al);
+    const double ad = (double)al;
+    const double rT = (double)t.A - (double)r;
+    const double B = fma(ad, fma(2.0, (double)t.lapw, 0.5 * (double)t.seew), 3.0);
+    if (!(B > 0.0)) return ve[0];
+    const double D = fma(B, B, -18.0 * ad * rT);
+    if (D < 0.0) {
+        ++fallbacks;
+        return (float)((double)ve[0] + B / (18.0 * ad));
+    }
+    return (float)fma(rT, fast_rcp(B + fast_sqrt(D)), (double)ve[0]);
+}
+
+using IxP = Ix<true>;
+
+__global__ void __launch_bounds__(kBlock)
+k_residual_to32(const double *__restrict__ phi, const double *__restrict__ s, IxP ix, double al,
+                float *__restrict__ r32, double *__restrict__ partials) {
+    const int n = ix.n, lg = ix.lg;
+    const int total = 1 << (3 * lg);
+    double acc = 0.0;
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < total; c += gridDim.x * kBlock) {
+        const int i = c & (n - 1), j = (c >> lg) & (n - 1), k = c >> (2 * lg);
+        double v[19];
+        gather(phi, ix, i, j, k, v);
+        const double r = s[c] - apply_L(stencil_terms(v), al);
+        acc = fma(r, r, acc);
+        r32[c] = (float)r;
+    }
+    const double b = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_to32(const double *__restrict__ a, float *__restrict__ b, size_t count) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < count) b[t] = (float)a[t];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_add32(double *__restrict__ phi, const float *__restrict__ e, size_t count) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < count) phi[t] += (double)e[t];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_fill32(float *__restrict__ a, size_t count, float v) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < count) a[t] = v;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_avg32(const float *__restrict__ f, int nf, float *__restrict__ c, int lgc) {
+    const int nc = 1 << lgc;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (1 << (3 * lgc))) return;
+    const int I = t & (nc - 1), J = (t >> lgc) & (nc - 1), K = t >> (2 * lgc);
+    float acc = 0.f;
+#pragma unroll
+    for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+        for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+            for (int di = 0; di < 2; ++di)
+                acc += f[((size_t)(2 * K + dk) * nf + (2 * J + dj)) * nf + (2 * I + di)];
+    c[t] = acc * 0.125f;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_corr_half(const float *__restrict__ ein, float *__restrict__ eout,
+            const float *__restrict__ phi, const float *__restrict__ r, IxP ix, float al,
+            int colour, unsigned *__restrict__ fallbacks) {
+    const int n = ix.n, lg = ix.lg;
+    const int half = n >> 1;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (half << (2 * lg))) return;
+    const int m = t & (half - 1);
+    const int row = t >> (lg - 1);
+    const int j = row & (n - 1);
+    const int k = row >> lg;
+    const int off = (colour ^ j ^ k) & 1;
+    const int iu = 2 * m + off, ic = 2 * m + 1 - off;
+    float vp[19], ve[19];
+    gather(phi, ix, iu, j, k, vp);
+    gather(ein, ix, iu, j, k, ve);
+    unsigned fb = 0;
+    const int me = ix(iu, j, k);
+    eout[me] = relax_corr_cell(vp, ve, r[me], al, fb);
+    eout[ix(ic, j, k)] = ein[ix(ic, j, k)];
+    if (fb) atomicAdd(fallbacks, fb);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_corr_restrict(const float *__restrict__ e_f, const float *__restrict__ phi_f,
+                const float *__restrict__ r_f, IxP ixf, float al_f, float *__restrict__ ehat_c,
+                float *__restrict__ r_c, int lgc) {
+    const int nc = 1 << lgc;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (1 << (3 * lgc))) return;
+    const int I = t & (nc - 1), J = (t >> lgc) & (nc - 1), K = t >> (2 * lgc);
+    float se = 0.f, sr = 0.f;
+#pragma unroll
+    for (int ck = 0; ck < 2; ++ck)
+#pragma unroll
+        for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+            for (int ci = 0; ci < 2; ++ci) {
+                const int i = 2 * I + ci, j = 2 * J + cj, k = 2 * K + ck;
+                float vp[19], ve[19];
+                gather(phi_f, ixf, i, j, k, vp);
+                gather(e_f, ixf, i, j, k, ve);
+                const CorrTerms ct = corr_terms(vp, ve, al_f);
+                se += ve[0];
+                sr += r_f[ixf(i, j, k)] - ct.A;
+            }
+    ehat_c[t] = se * 0.125f;
+    r_c[t] = sr * 0.5f; // 4 * mean: the coarse cell is twice as wide
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_corr_coarse_source(const float *__restrict__ ehat, const float *__restrict__ phi,
+                     float *__restrict__ r, float *__restrict__ e, IxP ix, float al) {
+    const int n = ix.n, lg = ix.lg;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (1 << (3 * lg))) return;
+    const int i = t & (n - 1), j = (t >> lg) & (n - 1), k = t >> (2 * lg);
+    float vp[19], ve[19];
+    gather(phi, ix, i, j, k, vp);
+    gather(ehat, ix, i, j, k, ve);
+    r[t] = corr_terms(vp, ve, al).A + r[t];
+    e[t] = ve[0];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_corr_prolong(float *__restrict__ e_f, IxP ixf, const float *__restrict__ e_c,
+               const float *__restrict__ ehat_c, IxP ixc) {
+    const int n = ixf.n, lg = ixf.lg;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (1 << (3 * lg))) return;
+    const int i = t & (n - 1), j = (t >> lg) & (n - 1), k = t >> (2 * lg);
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+    float acc = 0.f;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const float w = (a ? 0.25f : 0.75f) * (b ? 0.25f : 0.75f) * (c ? 0.25f : 0.75f);
+                const int q = ixc(I + a * si, J + b * sj, K + c * sk);
+                acc = fmaf(w, e_c[q] - ehat_c[q], acc);
+            }
+    e_f[t] += acc;
+}
+
+__global__ void __launch_bounds__(512)
+k_corr_coarsest(float *__restrict__ e, const float *__restrict__ phi, const float *__restrict__ r,
+                IxP ix, float al, int sweeps, unsigned *__restrict__ fallbacks) {
+    constexpr int MAXC = kCoarsestMax * kCoarsestMax * kCoarsestMax;
+    __shared__ float A[MAXC], B[MAXC], Ph[MAXC];
+    const int n = ix.n, lg = ix.lg;
+    const int cells = 1 << (3 * lg);
+    for (int q = threadIdx.x; q < cells; q += blockDim.x) {
+        A[q] = e[q];
+        B[q] = e[q];
+        Ph[q] = phi[q];
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const bool active = t < cells;
+    int i = 0, j = 0, k = 0;
+    float rc = 0.f;
+    if (active) {
+        i = t & (n - 1);
+        j = (t >> lg) & (n - 1);
+        k = t >> (2 * lg);
+        rc = r[t];
+    }
+    float vp[19];
+    if (active) gather(Ph, ix, i, j, k, vp);
+    const int mycol = (i + j + k) & 1;
+    unsigned fb = 0;
+    for (int sw = 0; sw < sweeps; ++sw) {
+#pragma unroll
+        for (int col = 0; col < 2; ++col) {
+            const float *src = col ? B : A;
+            float *dst = col ? A : B;
+            if (active) {
+                const int me = ix(i, j, k);
+                float val;
+                if (mycol == col) {
+                    float ve[19];
+                    gather(src, ix, i, j, k, ve);
+                    val = relax_corr_cell(vp, ve, rc, al, fb);
+                } else {
+                    val = src[me];
+                }
+                dst[me] = val;
+            }
+            __syncthreads();
+        }
+    }
+    if (active) e[t] = A[t];
+    if (fb) atomicAdd(fallbacks, fb);
+}
+
+inline unsigned nblocks(size_t total) { return (unsigned)((total + kBlock - 1) / kBlock); }
+
+inline IxP ixp(int n, int lg) { return IxP{n, lg, n + 2}; }
+
+} // namespace
+
+void launch_residual_to32(const Level &L, float *r32, double *partials, hipStream_t st) {
+    k_residual_to32<<<kReduceBlocks, kBlock, 0, st>>>(L.phi, L.s, ixp(L.n, L.lg), L.alpha, r32,
+                                                      partials);
+}
+
+void launch_to32(const double *a, float *b, size_t count, hipStream_t st) {
+    k_to32<<<nblocks(count), kBlock, 0, st>>>(a, b, count);
+}
+
+void launch_avg32(const Level32 &F, const Level32 &C, hipStream_t st) {
+    k_avg32<<<nblocks(C.cells()), kBlock, 0, st>>>(F.phi, F.n, C.phi, C.lg);
+}
+
+void launch_add32(double *phi, const float *e, size_t count, hipStream_t st) {
+    k_add32<<<nblocks(count), kBlock, 0, st>>>(phi, e, count);
+}
+
+void launch_fill32(float *a, size_t count, float v, hipStream_t st) {
+    k_fill32<<<nblocks(count), kBlock, 0, st>>>(a, count, v);
+}
+
+void launch_corr_half(const Level32 &L, const float *ein, float *eout, int colour,
+                      unsigned *fallbacks, hipStream_t st) {
+    k_corr_half<<<nblocks(L.cells() / 2), kBlock, 0, st>>>(ein, eout, L.phi, L.r, ixp(L.n, L.lg),
+                                                          (float)L.alpha, colour, fallbacks);
+}
+
+void launch_corr_restrict(const Level32 &F, const Level32 &C, hipStream_t st) {
+    k_corr_restrict<<<nblocks(C.cells()), kBlock, 0, st>>>(F.e, F.phi, F.r, ixp(F.n, F.lg),
+                                                          (float)F.alpha, C.ehat, C.r, C.lg);
+}
+
+void launch_corr_coarse_source(const Level32 &C, hipStream_t st) {
+    k_corr_coarse_source<<<nblocks(C.cells()), kBlock, 0, st>>>(C.ehat, C.phi, C.r, C.e,
+                                                               ixp(C.n, C.lg), (float)C.alpha);
+}
+
+void launch_corr_prolong(const Level32 &F, const Level32 &C, hipStream_t st) {
+    k_corr_prolong<<<nblocks(F.cells()), kBlock, 0, st>>>(F.e, ixp(F.n, F.lg), C.e, C.ehat,
+                                                         ixp(C.n, C.lg));
+}
+
+void launch_corr_coarsest(const Level32 &L, int sweeps, unsigned *fallbacks, hipStream_t st) {
+    const int threads = L.cells() < 64 ? 64 : (int)L.cells();
+    k_corr_coarsest<<<1, threads, 0, st>>>(L.e, L.phi, L.r, ixp(L.n, L.lg), (float)L.alpha,
+                                           sweeps, fallbacks);
+}
+
+} // namespace ndgp

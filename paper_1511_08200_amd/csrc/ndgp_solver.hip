@@ -176,8 +176,8 @@ bool resolve(const ndgp_grid *g, const ndgp_params *p, Cfg &c, std::string &why)
         why = "unknown mode";
         return false;
     }
-    if (p->precision != NDGP_PREC_FP64) {
-        why = "precision must be NDGP_PREC_FP64 in this build";
+    if (p->precision != NDGP_PREC_FP64 && p->precision != NDGP_PREC_MIXED) {
+        why = "unknown precision";
         return false;
     }
     if (p->flags & ~(NDGP_WARM_START | NDGP_PROFILE | NDGP_TWO_PASS)) {
@@ -239,9 +239,13 @@ struct Carver {
     }
 };
 
+// FP32 V-cycles on the correction per FP64 defect-correction iteration
+constexpr int kMixedInner = 2;
+
 struct Plan {
     Cfg c;
     Level base[kMaxLevels];
+    Level32 base32[kMaxLevels]; // mixed precision only
     Level patch[NDGP_MAX_PATCHES][kMaxLevels];
     double *partials = nullptr;
     double *scal = nullptr; // [0] sum delta, [1] sum s^2, [2] sum r^2, [3] sum phi
@@ -263,6 +267,19 @@ size_t carve(Plan &P, char *base) {
         L.alt = cv.take<double>(L.slots());
         L.s = cv.take<double>(L.cells());
         L.hat = l ? cv.take<double>(L.slots()) : nullptr;
+    }
+    if (c.prec == NDGP_PREC_MIXED) {
+        for (int l = 0; l < c.nl; ++l) {
+            Level32 &L = P.base32[l];
+            L.n = c.n >> l;
+            L.lg = c.lgn - l;
+            L.alpha = P.base[l].alpha;
+            L.phi = cv.take<float>(L.cells());
+            L.e = cv.take<float>(L.cells());
+            L.ealt = cv.take<float>(L.cells());
+            L.r = cv.take<float>(L.cells());
+            L.ehat = l ? cv.take<float>(L.cells()) : nullptr;
+        }
     }
     if (c.mode == NDGP_MODE_FULL) {
         for (int q = 0; q < c.np; ++q) {
@@ -420,6 +437,77 @@ struct Runner {
         }
     }
 
+    // ---- mixed precision: FP32 FAS on the correction e of
+    //      L[phi + e] - L[phi] = r, inside an FP64 defect-correction loop
+    void corr_smooth(Level32 &L, int sweeps) {
+        for (int s = 0; s < sweeps; ++s)
+            for (int col = 0; col < 2; ++col) {
+                launch_corr_half(L, L.e, L.ealt, col, P.fallbacks, st);
+                std::swap(L.e, L.ealt);
+            }
+    }
+
+    void corr_vcycle(Level32 *H, int nl, int l) {
+        Level32 &L = H[l];
+        if (l == nl - 1) {
+            launch_corr_coarsest(L, kCoarsestSweeps, P.fallbacks, st);
+            return;
+        }
+        corr_smooth(L, P.c.nu1);
+        Level32 &C = H[l + 1];
+        launch_corr_restrict(L, C, st);
+        launch_corr_coarse_source(C, st);
+        corr_vcycle(H, nl, l + 1);
+        launch_corr_prolong(L, C, st);
+        corr_smooth(L, P.c.nu2);
+    }
+
+    double residual_to32(const Level &L, float *r32) {
+        launch_residual_to32(L, r32, P.partials, st);
+        launch_reduce_final(P.partials, P.scal + 2, st);
+        return read_scalar(P.scal + 2);
+    }
+
+    // Outer iterations: r = s - L[phi] in FP64 (also the stopping test), the
+    // FP32 copy of phi on every level, kMixedInner FP32 V-cycles on the
+    // correction from e = 0, phi += e in FP64.
+    ndgp_status drive_mixed(Level *H, Level32 *H32, int nl, double snorm2, int &outer,
+                            double &rel, double *hist, int *hist_len) {
+        const Cfg &c = P.c;
+        const size_t cells = H[0].cells();
+        rel = std::sqrt(residual_to32(H[0], H32[0].r) / snorm2);
+        const double rel0 = rel;
+        double prev = rel;
+        int slow = 0;
+        outer = 0;
+        while (outer < c.maxc) {
+            if (c.tol > 0.0 && rel <= c.tol) break;
+            launch_to32(H[0].phi, H32[0].phi, cells, st);
+            for (int l = 1; l < nl; ++l) launch_avg32(H32[l - 1], H32[l], st);
+            launch_fill32(H32[0].e, cells, 0.f, st);
+            for (int q = 0; q < kMixedInner; ++q) corr_vcycle(H32, nl, 0);
+            launch_add32(H[0].phi, H32[0].e, cells, st);
+            ++outer;
+            rel = std::sqrt(residual_to32(H[0], H32[0].r) / snorm2);
+            if (hist && outer - 1 < NDGP_HIST_LEN) {
+                hist[outer - 1] = rel;
+                *hist_len = outer;
+            }
+            if (!std::isfinite(rel) || rel > 1e6 * std::max(rel0, 1.0))
+                return fail(NDGP_ENOCONV, "mixed-precision iteration diverged");
+            if (c.tol == 0.0) {
+                slow = rel > 0.7 * prev ? slow + 1 : 0;
+                if (slow >= 2) break;
+            }
+            prev = rel;
+        }
+        if (c.tol > 0.0 && rel > c.tol)
+            return fail(NDGP_ENOCONV, "tolerance not reached within max_cycles");
+        if (c.tol == 0.0 && rel > 1e-11)
+            return fail(NDGP_ENOCONV, "stagnated above rounding level");
+        return NDGP_OK;
+    }
+
     // V-cycles on H[0] until ||r|| <= tol ||s|| (tol > 0) or until the
     // residual stops falling (tol == 0).
     ndgp_status drive(Level *H, int nl, double snorm2, int &cycles, double &rel, double *hist,
@@ -511,7 +599,11 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         if (!(c.flags & NDGP_WARM_START)) run.nested_start(P.base, c.nl);
         timer.on = (c.flags & NDGP_PROFILE) != 0; // the V-cycles only, not the start
         double rel = 0.0;
-        status = run.drive(P.base, c.nl, snorm2, R.cycles[0], rel, R.res_hist, &R.hist_len);
+        if (c.prec == NDGP_PREC_MIXED)
+            status = run.drive_mixed(P.base, P.base32, c.nl, snorm2, R.cycles[0], rel,
+                                     R.res_hist, &R.hist_len);
+        else
+            status = run.drive(P.base, c.nl, snorm2, R.cycles[0], rel, R.res_hist, &R.hist_len);
         R.rel_res[0] = rel;
         timer.on = false;
         if (timer.launches) {

@@ -172,6 +172,25 @@ def test_fused_sweep_bitwise_equals_two_pass(n):
     assert torch.equal(a[0], b[0])
 
 
+MIXED_TOL = 1e-8
+
+
+@pytest.mark.parametrize("rc", [0.5, 1.0, 5.0])
+def test_mixed_precision_matches_oracle(rc):
+    """FP32 multigrid on the correction inside the FP64 defect-correction loop
+    reaches the FP64 oracle's answer within the mixed-precision bar."""
+    n = 64
+    say(f"mixed n={n} rc={rc}")
+    f = synth.make_field(n, 2.5, 40, n_tophats=4)
+    h = ndgp.cell_size(128.0, n)
+    phio, S = oracle_periodic(f.delta, h, rc)
+    (phig,), rep = gpu_solve([f.delta], ndgp.Grid(n=n, h=h), rc=rc, tol=1e-12, max_cycles=100,
+                             precision=ndgp.PREC_MIXED)
+    say(f"  outer={rep.cycles[0]} rel_res={rep.rel_res[0]:.2e} hist={[f'{x:.1e}' for x in rep.history]}")
+    assert rep.status == 0
+    assert rel(phig, phio) <= MIXED_TOL
+
+
 def test_warm_start_and_errors():
     n = 32
     f = synth.make_field(n, 1.0, 1512)
@@ -267,16 +286,17 @@ def test_patch_residual_level():
 # --------------------------------------------------------------------------
 # full sizes, in the launch configuration the benchmark times
 
-@pytest.mark.parametrize("n,box,sigma,tophats,rc,seed", [
-    (256, 256.0, 2.0, 50, 1.0, 1513),   # 256^3 lognormal + 50 top-hats
-    (512, 512.0, 2.5, 0, 1.0, 1515),    # 512^3 lognormal, sigma 2.5
+@pytest.mark.parametrize("n,box,sigma,tophats,rc,seed,prec", [
+    (256, 256.0, 2.0, 50, 1.0, 1513, ndgp.PREC_FP64),   # 256^3 lognormal + 50 top-hats
+    (512, 512.0, 2.5, 0, 1.0, 1515, ndgp.PREC_FP64),    # 512^3 lognormal, sigma 2.5
+    (512, 512.0, 2.5, 0, 5.0, 1515, ndgp.PREC_MIXED),   # same, mixed precision, r_c = 5
 ])
-def test_full_size_residual_by_oracle(n, box, sigma, tophats, rc, seed):
-    say(f"full size n={n}: generating")
+def test_full_size_residual_by_oracle(n, box, sigma, tophats, rc, seed, prec):
+    say(f"full size n={n} precision={prec}: generating")
     f = synth.make_field(n, sigma, seed, n_tophats=tophats)
     h = ndgp.cell_size(box, n)
     grid = ndgp.Grid(n=n, h=h)
-    params = ndgp.Params(rc=rc, tol=1e-10)
+    params = ndgp.Params(rc=rc, tol=1e-10, precision=prec)
     d = dev(f.delta)
     say(f"full size n={n}: solving")
     phi, rep = ndgp.solve(grid, params, [d])
