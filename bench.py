@@ -181,17 +181,46 @@ def large_workload(ndgp, torch, steps):
     log("generating 512^3 input")
     f = make_domain(n, box, 2.5, 0, 1515)
     grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
-    out = {"workload": "512^3 periodic, lognormal sigma 2.5, FP64, tol 1e-10"}
+    out = {"workload": "512^3 periodic, lognormal sigma 2.5, tol 1e-10, FP64 and mixed"}
     for rc in (0.5, 1.0, 5.0):
         params = ndgp.Params(rc=rc, tol=1e-10, profile=True)
         dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, [f.delta], steps, 1,
                                         with_force=False)
         cyc = reps[-1].cycles[0]
-        out[f"rc{rc:g}"] = {"ms_to_tol": round(dt * 1e3, 1), "cycles": cyc,
-                            "cell_updates_per_s": n**3 * 4 * cyc / dt,
-                            "roofline": roofline(reps, n)}
-        del phi, dd
+        ent = {"fp64_ms_to_tol": round(dt * 1e3, 1), "fp64_cycles": cyc,
+               "fp64_cell_updates_per_s": n**3 * 4 * cyc / dt, "roofline": roofline(reps, n)}
+        phi64 = phi[0].clone()
+        del phi
+        pm = ndgp.Params(rc=rc, tol=1e-10, precision=ndgp.PREC_MIXED)
+        dtm, repm, phim, _ = solve_steps(ndgp, torch, grid, pm, [f.delta], steps, 1,
+                                         with_force=False)
+        dd2, aa2, _ = ndgp.diff_norms(phim[0], phi64)
+        ent.update({"mixed_ms_to_tol": round(dtm * 1e3, 1), "mixed_outer_iters": repm[-1].cycles[0],
+                    "mixed_rel_res": repm[-1].rel_res[0],
+                    "mixed_vs_fp64_rel_l2": float(np.sqrt(dd2 / aa2)),
+                    "mixed_speedup_vs_fp64": round(dt / dtm, 3)})
+        out[f"rc{rc:g}"] = ent
+        del phim, phi64, dd
         torch.cuda.empty_cache()
+    return out
+
+
+def serving_workload(ndgp, torch, count, rate, sat_count):
+    """Request stream: Poisson arrivals, n in {32, 64, 128, 256}^3, r_c H0 in
+    {0.5, 1, 2, 5}, sigma_ln in [1, 2.5], mixed precision + one interpolated
+    2x patch each, 64 GB device budget; then the same kind of requests all
+    arriving at once (throughput at saturation)."""
+    from paper_1511_08200_amd import serving
+    trace = serving.make_trace(count=count, rate=rate)
+    log(f"serving {count} requests at {rate}/s")
+    res, summ = serving.serve(trace, budget_bytes=64e9, max_active=16, log=log)
+    out = {"workload": f"{count} requests, Poisson {rate}/s, n in 32..256, r_cH0 in "
+                       "{0.5,1,2,5}, mixed + interpolated patch, 64 GB budget",
+           "poisson": summ}
+    trace2 = serving.make_trace(count=sat_count, seed=1517, all_at_once=True)
+    log(f"serving {sat_count} requests arriving at once")
+    res2, summ2 = serving.serve(trace2, budget_bytes=64e9, max_active=16, realtime=False, log=log)
+    out["saturation"] = summ2
     return out
 
 
@@ -203,6 +232,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=4)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-saturation", type=int, default=400)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 128 MiB device-to-device copy three times "
                          "(the reference kernel that scales the HBM byte counters)")
@@ -258,6 +290,9 @@ def main():
         line.setdefault("extra", {})["patches"] = patch_workload(ndgp, torch, 3)
         log("512^3 workload")
         line["extra"]["large"] = large_workload(ndgp, torch, 3)
+        if args.serve_requests > 0:
+            line["extra"]["serving"] = serving_workload(ndgp, torch, args.serve_requests,
+                                                        args.serve_rate, args.serve_saturation)
     print(json.dumps(line), flush=True)
 
 

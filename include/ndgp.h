@@ -204,6 +204,40 @@ ndgp_status ndgp_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_M
                        double *const force[1 + NDGP_MAX_PATCHES], hipStream_t stream);
 
 /*
+ * Serving: the same solve as ndgp_solve, split into non-blocking steps so that
+ * one host thread can keep many solves in flight on different streams
+ * (continuous batching).  A plan owns nothing on the device: delta, phi and
+ * the workspace stay the caller's and must stay alive until the plan is done
+ * or destroyed.  Patches are supported in NDGP_MODE_INTERPOLATED only.  The
+ * number of V-cycles a plan runs depends only on its own residual history,
+ * so its result is bit for bit the one ndgp_solve gives, whatever else runs.
+ *
+ * ndgp_plan_create  checks the arguments, enqueues the source, the initial
+ *                   guess and the first residual norm on `stream`; does not
+ *                   block.
+ * ndgp_plan_poll    never blocks: *done = 0 while work is in flight or the
+ *                   plan waits for ndgp_plan_step; *done = 1 once phi is final
+ *                   (report filled if non-NULL; the returned status is then
+ *                   the solve's: NDGP_OK, NDGP_ENOCONV or NDGP_EINVAL for a
+ *                   non-finite delta).  When a V-cycle has finished it decides
+ *                   whether to stop (then it enqueues the gauge and the patch
+ *                   interpolation).
+ * ndgp_plan_step    enqueues the next V-cycle (mixed precision: the next outer
+ *                   iteration) and its residual norm if the last poll found
+ *                   the plan waiting; otherwise does nothing.  Never blocks.
+ * ndgp_plan_destroy releases the plan's host resources; the caller must not
+ *                   free the device buffers before the plan's stream is idle.
+ */
+typedef struct ndgp_plan ndgp_plan;
+ndgp_status ndgp_plan_create(const ndgp_grid *grid, const ndgp_params *params,
+                             const double *const delta[1 + NDGP_MAX_PATCHES],
+                             double *const phi[1 + NDGP_MAX_PATCHES], void *workspace,
+                             size_t workspace_bytes, hipStream_t stream, ndgp_plan **plan);
+ndgp_status ndgp_plan_poll(ndgp_plan *plan, int32_t *done, ndgp_report *report);
+ndgp_status ndgp_plan_step(ndgp_plan *plan);
+void ndgp_plan_destroy(ndgp_plan *plan);
+
+/*
  * Norms for comparing two fields, e.g. the force of the interpolated mode with
  * the fully relaxed one (the error of Sec. III.B, Eqs. errors-errors2):
  *   out[0] = sum (a - b)^2,  out[1] = sum a^2,  out[2] = sum b^2

@@ -371,6 +371,30 @@ struct Runner {
         return host[0];
     }
 
+    // enqueue a reduction into P.scal[slot] without waiting for it
+    void enqueue_sum(const double *a, size_t count, bool squares, int slot) {
+        launch_partial_sums(a, count, squares, P.partials, st);
+        launch_reduce_final(P.partials, P.scal + slot, st);
+    }
+
+    void enqueue_residual(Level *H, Level32 *H32) {
+        if (P.c.prec == NDGP_PREC_MIXED)
+            launch_residual_to32(H[0], H32[0].r, P.partials, st);
+        else
+            launch_residual_sumsq(H[0], P.partials, nullptr, 0.0, st);
+        launch_reduce_final(P.partials, P.scal + 2, st);
+    }
+
+    // one outer iteration of the mixed-precision loop (without its residual)
+    void mixed_outer(Level *H, Level32 *H32, int nl) {
+        const size_t cells = H[0].cells();
+        launch_to32(H[0].phi, H32[0].phi, cells, st);
+        for (int l = 1; l < nl; ++l) launch_avg32(H32[l - 1], H32[l], st);
+        launch_fill32(H32[0].e, cells, 0.f, st);
+        for (int q = 0; q < kMixedInner; ++q) corr_vcycle(H32, nl, 0);
+        launch_add32(H[0].phi, H32[0].e, cells, st);
+    }
+
     double sum(const double *a, size_t count, bool squares, int slot) {
         launch_partial_sums(a, count, squares, P.partials, st);
         launch_reduce_final(P.partials, P.scal + slot, st);
@@ -474,7 +498,6 @@ struct Runner {
     ndgp_status drive_mixed(Level *H, Level32 *H32, int nl, double snorm2, int &outer,
                             double &rel, double *hist, int *hist_len) {
         const Cfg &c = P.c;
-        const size_t cells = H[0].cells();
         rel = std::sqrt(residual_to32(H[0], H32[0].r) / snorm2);
         const double rel0 = rel;
         double prev = rel;
@@ -482,11 +505,7 @@ struct Runner {
         outer = 0;
         while (outer < c.maxc) {
             if (c.tol > 0.0 && rel <= c.tol) break;
-            launch_to32(H[0].phi, H32[0].phi, cells, st);
-            for (int l = 1; l < nl; ++l) launch_avg32(H32[l - 1], H32[l], st);
-            launch_fill32(H32[0].e, cells, 0.f, st);
-            for (int q = 0; q < kMixedInner; ++q) corr_vcycle(H32, nl, 0);
-            launch_add32(H[0].phi, H32[0].e, cells, st);
+            mixed_outer(H, H32, nl);
             ++outer;
             rel = std::sqrt(residual_to32(H[0], H32[0].r) / snorm2);
             if (hist && outer - 1 < NDGP_HIST_LEN) {
@@ -722,6 +741,210 @@ ndgp_status force_impl(const ndgp_grid *grid, const double *const phi[], double 
     return NDGP_OK;
 }
 
+} // namespace
+
+// ------------------------------------------------------------------------
+// serving plans: the steps of solve_impl, each enqueued without blocking
+
+struct ndgp_plan {
+    Plan P;
+    hipStream_t st = nullptr;
+    double *slot = nullptr; // pinned: [0] sum delta, [1] sum s^2, [2] sum r^2,
+                            //         [3] sum phi, [4] fallbacks (bits)
+    hipEvent_t ev = nullptr;
+    const double *delta[1 + NDGP_MAX_PATCHES] = {nullptr, nullptr, nullptr};
+    double *phi[1 + NDGP_MAX_PATCHES] = {nullptr, nullptr, nullptr};
+    enum State { RUNNING, READY, FINISHING, DONE } state = RUNNING;
+    bool started = false;
+    double snorm2 = 0.0, rel = 0.0, rel0 = 0.0, prev = 0.0;
+    int slow = 0;
+    ndgp_status status = NDGP_OK;
+    std::string message;
+    ndgp_report R;
+    std::chrono::steady_clock::time_point t0;
+};
+
+namespace {
+
+Runner plan_runner(ndgp_plan *pl) { return Runner{pl->P, pl->st, pl->slot}; }
+
+void plan_record(ndgp_plan *pl) { HIP_TRY(hipEventRecord(pl->ev, pl->st)); }
+
+// gauge, patch interpolation, and the numbers the report needs
+void plan_enqueue_tail(ndgp_plan *pl, bool zero_field) {
+    const Cfg &c = pl->P.c;
+    Runner run = plan_runner(pl);
+    const size_t cells0 = (size_t)c.n * c.n * c.n;
+    if (zero_field) launch_fill(pl->phi[0], cells0, 0.0, pl->st);
+    run.enqueue_sum(pl->phi[0], cells0, false, 3);
+    launch_shift_by_mean(pl->phi[0], cells0, pl->P.scal + 3, pl->st);
+    for (int q = 0; q < c.np; ++q) {
+        ChildBox b0{{c.po[q][0], c.po[q][1], c.po[q][2]}, 0, c.pn[q]};
+        launch_interpolate(pl->phi[q], q == 0 ? c.n : c.pn[0], q == 0, b0, pl->phi[q + 1], false,
+                           pl->st);
+    }
+    HIP_TRY(hipMemcpyAsync(pl->slot + 3, pl->P.scal + 3, sizeof(double), hipMemcpyDeviceToHost,
+                           pl->st));
+    HIP_TRY(hipMemcpyAsync(pl->slot + 4, pl->P.fallbacks, sizeof(unsigned),
+                           hipMemcpyDeviceToHost, pl->st));
+    plan_record(pl);
+    pl->state = ndgp_plan::FINISHING;
+}
+
+ndgp_status plan_create_impl(const ndgp_grid *grid, const ndgp_params *params,
+                             const double *const delta[], double *const phi[], void *ws,
+                             size_t ws_bytes, hipStream_t st, ndgp_plan **out) {
+    if (!out) return fail(NDGP_EINVAL, "plan must not be NULL");
+    *out = nullptr;
+    Cfg c;
+    std::string why;
+    if (!resolve(grid, params, c, why)) return fail(NDGP_EINVAL, why);
+    if (c.np > 0 && c.mode != NDGP_MODE_INTERPOLATED)
+        return fail(NDGP_EINVAL, "plans relax the domain level only: patches need "
+                                 "NDGP_MODE_INTERPOLATED");
+    ndgp_status s = check_arrays(c, delta, phi, false);
+    if (s != NDGP_OK) return s;
+    const size_t need = total_bytes(c);
+    if (!ws || ws_bytes < need)
+        return fail(NDGP_ENOMEM, "workspace smaller than ndgp_workspace_bytes() = " +
+                                     std::to_string(need));
+    ndgp_plan *pl = new ndgp_plan();
+    pl->t0 = std::chrono::steady_clock::now();
+    pl->P.c = c;
+    carve(pl->P, aligned_base(ws));
+    pl->P.base[0].phi = phi[0];
+    pl->st = st;
+    for (int l = 0; l <= c.np; ++l) {
+        pl->delta[l] = delta[l];
+        pl->phi[l] = phi[l];
+    }
+    std::memset(&pl->R, 0, sizeof(pl->R));
+    for (int l = 0; l <= NDGP_MAX_PATCHES; ++l) pl->R.rel_res[l] = -1.0;
+    try {
+        pl->slot = pinned_slots().acquire();
+        HIP_TRY(hipEventCreateWithFlags(&pl->ev, hipEventDisableTiming));
+        Runner run = plan_runner(pl);
+        const size_t cells0 = (size_t)c.n * c.n * c.n;
+        HIP_TRY(hipMemsetAsync(pl->P.fallbacks, 0, sizeof(unsigned), st));
+        run.enqueue_sum(delta[0], cells0, false, 0);
+        launch_source(delta[0], cells0, pl->P.scal + 0, 1.0 / (double)cells0, c.fsrc * c.h * c.h,
+                      pl->P.base[0].s, st);
+        run.enqueue_sum(pl->P.base[0].s, cells0, true, 1);
+        if (!(c.flags & NDGP_WARM_START)) run.nested_start(pl->P.base, c.nl);
+        run.enqueue_residual(pl->P.base, pl->P.base32);
+        HIP_TRY(hipMemcpyAsync(pl->slot, pl->P.scal, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                               st));
+        plan_record(pl);
+    } catch (...) {
+        if (pl->ev) (void)hipEventDestroy(pl->ev);
+        if (pl->slot) pinned_slots().release(pl->slot);
+        delete pl;
+        throw;
+    }
+    *out = pl;
+    return NDGP_OK;
+}
+
+ndgp_status plan_finish(ndgp_plan *pl, int32_t *done, ndgp_report *rep) {
+    if (done) *done = 1;
+    if (rep) *rep = pl->R;
+    if (pl->status != NDGP_OK) g_err = pl->message;
+    return pl->status;
+}
+
+void plan_fail(ndgp_plan *pl, ndgp_status st, const char *msg) {
+    if (pl->status == NDGP_OK) {
+        pl->status = st;
+        pl->message = msg;
+    }
+}
+
+ndgp_status plan_poll_impl(ndgp_plan *pl, int32_t *done, ndgp_report *rep) {
+    if (!pl) return fail(NDGP_EINVAL, "plan must not be NULL");
+    if (done) *done = 0;
+    if (pl->state == ndgp_plan::DONE) return plan_finish(pl, done, rep);
+    if (pl->state == ndgp_plan::READY) return NDGP_OK;
+    const hipError_t q = hipEventQuery(pl->ev);
+    if (q == hipErrorNotReady) return NDGP_OK;
+    HIP_TRY(q);
+    const Cfg &c = pl->P.c;
+    const size_t cells0 = (size_t)c.n * c.n * c.n;
+    if (pl->state == ndgp_plan::FINISHING) {
+        unsigned fb = 0;
+        std::memcpy(&fb, pl->slot + 4, sizeof(unsigned));
+        pl->R.fallbacks = (int32_t)fb;
+        pl->R.phi_mean = pl->slot[3] / (double)cells0;
+        pl->R.t_total_ms = std::chrono::duration<double, std::milli>(
+                               std::chrono::steady_clock::now() - pl->t0)
+                               .count();
+        pl->state = ndgp_plan::DONE;
+        return plan_finish(pl, done, rep);
+    }
+    // RUNNING and its work has completed: a residual norm is in slot[2]
+    if (!pl->started) {
+        pl->started = true;
+        const double dsum = pl->slot[0];
+        if (!std::isfinite(dsum)) {
+            plan_fail(pl, NDGP_EINVAL, "delta[0] has non-finite values");
+            pl->state = ndgp_plan::DONE;
+            return plan_finish(pl, done, rep);
+        }
+        pl->R.removed_mean = dsum / (double)cells0;
+        pl->snorm2 = pl->slot[1];
+        if (pl->snorm2 == 0.0) { // no source: phi = 0
+            pl->R.rel_res[0] = 0.0;
+            plan_enqueue_tail(pl, true);
+            return NDGP_OK;
+        }
+        pl->rel = pl->rel0 = pl->prev = std::sqrt(pl->slot[2] / pl->snorm2);
+    } else {
+        pl->rel = std::sqrt(pl->slot[2] / pl->snorm2);
+        const int cyc = pl->R.cycles[0];
+        if (cyc - 1 < NDGP_HIST_LEN) {
+            pl->R.res_hist[cyc - 1] = pl->rel;
+            pl->R.hist_len = cyc;
+        }
+        if (!std::isfinite(pl->rel) || pl->rel > 1e6 * std::max(pl->rel0, 1.0)) {
+            pl->R.rel_res[0] = pl->rel;
+            plan_fail(pl, NDGP_ENOCONV, "multigrid diverged");
+            plan_enqueue_tail(pl, false);
+            return NDGP_OK;
+        }
+        if (c.tol == 0.0) pl->slow = pl->rel > 0.7 * pl->prev ? pl->slow + 1 : 0;
+        pl->prev = pl->rel;
+    }
+    pl->R.rel_res[0] = pl->rel;
+    const bool converged = c.tol > 0.0 && pl->rel <= c.tol;
+    const bool stalled = c.tol == 0.0 && pl->slow >= 2;
+    if (converged || stalled || pl->R.cycles[0] >= c.maxc) {
+        if (c.tol > 0.0 && pl->rel > c.tol)
+            plan_fail(pl, NDGP_ENOCONV, "tolerance not reached within max_cycles");
+        if (c.tol == 0.0 && pl->rel > 1e-11)
+            plan_fail(pl, NDGP_ENOCONV, "stagnated above rounding level");
+        plan_enqueue_tail(pl, false);
+        return NDGP_OK;
+    }
+    pl->state = ndgp_plan::READY;
+    return NDGP_OK;
+}
+
+ndgp_status plan_step_impl(ndgp_plan *pl) {
+    if (!pl) return fail(NDGP_EINVAL, "plan must not be NULL");
+    if (pl->state != ndgp_plan::READY) return NDGP_OK;
+    Runner run = plan_runner(pl);
+    if (pl->P.c.prec == NDGP_PREC_MIXED)
+        run.mixed_outer(pl->P.base, pl->P.base32, pl->P.c.nl);
+    else
+        run.vcycle(pl->P.base, pl->P.c.nl, 0);
+    run.enqueue_residual(pl->P.base, pl->P.base32);
+    HIP_TRY(hipMemcpyAsync(pl->slot + 2, pl->P.scal + 2, sizeof(double), hipMemcpyDeviceToHost,
+                           pl->st));
+    plan_record(pl);
+    pl->R.cycles[0] += 1;
+    pl->state = ndgp_plan::RUNNING;
+    return NDGP_OK;
+}
+
 ndgp_status diff_norms_impl(const double *a, const double *b, size_t count, double out[3],
                             void *ws, size_t ws_bytes, hipStream_t st) {
     if (!a || !out) return fail(NDGP_EINVAL, "a and out must not be NULL");
@@ -803,6 +1026,31 @@ ndgp_status ndgp_residual(const ndgp_grid *grid, const ndgp_params *params, int3
 ndgp_status ndgp_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_MAX_PATCHES],
                        double *const force[1 + NDGP_MAX_PATCHES], hipStream_t stream) {
     return guarded([&] { return force_impl(grid, phi, force, stream); });
+}
+
+ndgp_status ndgp_plan_create(const ndgp_grid *grid, const ndgp_params *params,
+                             const double *const delta[1 + NDGP_MAX_PATCHES],
+                             double *const phi[1 + NDGP_MAX_PATCHES], void *workspace,
+                             size_t workspace_bytes, hipStream_t stream, ndgp_plan **plan) {
+    return guarded([&] {
+        return plan_create_impl(grid, params, delta, phi, workspace, workspace_bytes, stream,
+                                plan);
+    });
+}
+
+ndgp_status ndgp_plan_poll(ndgp_plan *plan, int32_t *done, ndgp_report *report) {
+    return guarded([&] { return plan_poll_impl(plan, done, report); });
+}
+
+ndgp_status ndgp_plan_step(ndgp_plan *plan) {
+    return guarded([&] { return plan_step_impl(plan); });
+}
+
+void ndgp_plan_destroy(ndgp_plan *plan) {
+    if (!plan) return;
+    if (plan->ev) (void)hipEventDestroy(plan->ev);
+    if (plan->slot) pinned_slots().release(plan->slot);
+    delete plan;
 }
 
 ndgp_status ndgp_diff_norms(const double *a, const double *b, size_t count, double out[3],

@@ -91,6 +91,15 @@ def lib():
                                     ctypes.c_size_t, vp]
         L.ndgp_force.restype = ctypes.c_int
         L.ndgp_force.argtypes = [ctypes.POINTER(_Grid), arr3, arr3, vp]
+        L.ndgp_plan_create.restype = ctypes.c_int
+        L.ndgp_plan_create.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), arr3, arr3,
+                                       vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+        L.ndgp_plan_poll.restype = ctypes.c_int
+        L.ndgp_plan_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_Report)]
+        L.ndgp_plan_step.restype = ctypes.c_int
+        L.ndgp_plan_step.argtypes = [vp]
+        L.ndgp_plan_destroy.restype = None
+        L.ndgp_plan_destroy.argtypes = [vp]
         L.ndgp_diff_norms.restype = ctypes.c_int
         L.ndgp_diff_norms.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
                                       vp, ctypes.c_size_t, vp]
@@ -326,3 +335,57 @@ def diff_norms(a: torch.Tensor, b: Optional[torch.Tensor] = None, stream=None):
     _check(lib().ndgp_diff_norms(_dev(a, None, "a"), _dev(b, None, "b") if b is not None else None,
                                  a.numel(), out, ws.data_ptr(), ws.numel(), _stream(stream)))
     return out[0], out[1], out[2]
+
+
+class Plan:
+    """A non-blocking solve (ndgp_plan_*): create, then alternate poll() and
+    step() until poll() reports done.  Keeps its tensors alive."""
+
+    def __init__(self, grid: Grid, params: Params, delta, phi=None, ws=None, stream=None):
+        self.grid, self.params = grid, params
+        self._g, self._p = grid._c(), params._c()
+        dev0 = delta[0].device
+        self.phi = phi if phi is not None else alloc_phi(grid, device=dev0)
+        self.delta = list(delta)
+        dptr = [_dev(delta[0], (grid.n,) * 3, "delta[0]")]
+        for q, pt in enumerate(grid.patches):
+            d = delta[q + 1] if q + 1 < len(delta) else None
+            dptr.append(_dev(d, (pt.n,) * 3, f"delta[{q + 1}]") if d is not None else None)
+        pptr = [_dev(self.phi[0], (grid.n,) * 3, "phi[0]")]
+        for q, pt in enumerate(grid.patches):
+            pptr.append(_dev(self.phi[q + 1], (pt.n + 2,) * 3, f"phi[{q + 1}]"))
+        nb = workspace_bytes(grid, params)
+        self.ws = ws if ws is not None else torch.empty(nb, dtype=torch.uint8, device=dev0)
+        self.stream = stream
+        self._h = ctypes.c_void_p()
+        _check(lib().ndgp_plan_create(ctypes.byref(self._g), ctypes.byref(self._p), _arr3(dptr),
+                                      _arr3(pptr), self.ws.data_ptr(), self.ws.numel(),
+                                      _stream(stream), ctypes.byref(self._h)))
+        self.report = None
+
+    def poll(self) -> bool:
+        done = ctypes.c_int32()
+        rep = _Report()
+        st = lib().ndgp_plan_poll(self._h, ctypes.byref(done), ctypes.byref(rep))
+        if done.value:
+            if st not in (NDGP_OK, NDGP_ENOCONV):
+                self.report = _report(rep, st)
+                _check(st)
+            self.report = _report(rep, st)
+            return True
+        _check(st)
+        return False
+
+    def step(self):
+        _check(lib().ndgp_plan_step(self._h))
+
+    def close(self):
+        if self._h:
+            lib().ndgp_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -31,6 +31,7 @@ __all__ = [
     "patch_delta",
     "densest_tophat_centre",
     "patch_origin_centred",
+    "lognormal_delta_torch",
 ]
 
 
@@ -189,3 +190,34 @@ def patch_delta(field: Field, n_base: int, chain, n_patch: int) -> np.ndarray:
     rho /= field.rho_mean
     rho -= 1.0
     return rho
+
+
+def lognormal_delta_torch(n: int, sigma: float, seed: int, device="cuda", slope: float = -2.0):
+    """The lognormal recipe of ``lognormal_rho`` drawn with torch on a device
+    (for request streams, where host generation would dominate), returned as
+    the density contrast rho / mean(rho) - 1.  Deterministic for a given seed
+    and device; not the same numbers as the numpy generator."""
+    import torch
+    if n < 2 or n & (n - 1):
+        raise ValueError("n must be a power of two >= 2")
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    w = torch.randn((n, n, n), generator=g, device=device, dtype=torch.float64)
+    wk = torch.fft.rfftn(w)
+    del w
+    kz = torch.fft.fftfreq(n, device=device, dtype=torch.float64) * n
+    kx = torch.fft.rfftfreq(n, device=device, dtype=torch.float64) * n
+    k2 = (kz[:, None, None] ** 2 + kz[None, :, None] ** 2) + kx[None, None, :] ** 2
+    keep = (k2 > 0) & (k2 <= (n / 2) ** 2)
+    filt = torch.where(keep, k2.clamp_min(1e-300) ** (slope / 4.0), torch.zeros_like(k2))
+    wk *= filt
+    del filt, k2, keep
+    f = torch.fft.irfftn(wk, s=(n, n, n))
+    del wk
+    f -= f.mean()
+    sd = f.std(unbiased=False)
+    f *= sigma / sd
+    torch.exp(f, out=f)
+    f /= f.mean()
+    f -= 1.0
+    return f.contiguous()

@@ -1,0 +1,92 @@
+"""The non-blocking plan API and the continuous-batching loop on the GPU."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1511_08200_amd import ndgp, serving, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-serving] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ndgp.lib()
+
+
+@pytest.mark.parametrize("precision", [ndgp.PREC_FP64, ndgp.PREC_MIXED])
+def test_plan_equals_blocking_solve(precision):
+    """A plan driven by poll/step gives the same bits as ndgp_solve."""
+    say(f"plan vs solve precision={precision}")
+    n = 64
+    f = synth.make_field(n, 2.0, 77, n_tophats=5)
+    d = torch.from_numpy(f.delta).cuda()
+    c = synth.densest_tophat_centre(f)
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(64.0, n),
+                     patches=[ndgp.Patch(32, synth.patch_origin_centred(c, 16))])
+    params = ndgp.Params(rc=2.0, tol=1e-10, mode=ndgp.MODE_INTERPOLATED, precision=precision)
+    phi_a, rep_a = ndgp.solve(grid, params, [d])
+    plan = ndgp.Plan(grid, params, [d])
+    steps = 0
+    while not plan.poll():
+        plan.step()
+        steps += 1
+        assert steps < 10**6
+    torch.cuda.synchronize()
+    rep_b = plan.report
+    assert rep_b.status == 0 and rep_b.cycles[0] == rep_a.cycles[0]
+    assert rep_b.history == rep_a.history
+    for x, y in zip(phi_a, plan.phi):
+        assert torch.equal(x, y)
+    plan.close()
+
+
+def test_plan_reports_bad_input():
+    n = 32
+    bad = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    bad[1, 2, 3] = float("inf")
+    plan = ndgp.Plan(ndgp.Grid(n=n, h=1e-3), ndgp.Params(rc=1.0), [bad])
+    with pytest.raises(ndgp.NdgpError) as e:
+        while not plan.poll():
+            plan.step()
+    assert e.value.status == ndgp.NDGP_EINVAL
+    plan.close()
+    with pytest.raises(ndgp.NdgpError):  # full-mode patches are not served
+        ndgp.Plan(ndgp.Grid(n=n, h=1e-3, patches=[ndgp.Patch(16, (8, 8, 8))]),
+                  ndgp.Params(rc=1.0, mode=ndgp.MODE_FULL), [bad, bad[:16, :16, :16].contiguous()])
+
+
+def test_continuous_batching_isolation():
+    """Requests of mixed sizes and r_c run concurrently on several streams;
+    each result equals the same request solved alone, bit for bit."""
+    trace = serving.make_trace(count=24, rate=400.0, seed=9, sizes=(32, 64, 128))
+    say("serving 24 requests, 6 slots")
+    results, summary, kept = serving.serve(trace, budget_bytes=4e9, max_active=6,
+                                           keep_results=True)
+    say(f"summary {summary}")
+    assert summary["completed"] == 24 and summary["failed"] == 0
+    assert summary["peak_active"] >= 2
+    for r in results:
+        delta, phi_mix, grid, params = kept[r.idx]
+        phi_alone, rep = ndgp.solve(grid, params, [delta])
+        assert rep.cycles[0] == r.cycles
+        for x, y in zip(phi_alone, phi_mix):
+            assert torch.equal(x, y), f"request {r.idx} differs"
+
+
+def test_budget_limits_admission():
+    trace = serving.make_trace(count=6, rate=1e6, seed=3, sizes=(64,))
+    one = serving.request_bytes(*serving._shape_only(trace[0], ndgp.PREC_MIXED, 1e-10))
+    results, summary = serving.serve(trace, budget_bytes=1.5 * one, max_active=4)
+    assert summary["completed"] == 6 and summary["peak_active"] == 1
