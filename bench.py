@@ -229,6 +229,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=("256", "512"), default="256",
+                    help="timed workload: 256^3 lognormal+top-hats (default) or the 512^3 "
+                         "lognormal sigma 2.5 field (for profiling the HBM-bound regime)")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=4)
@@ -250,9 +253,15 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     ndgp.lib()
 
-    n, box, rc = 256, 256.0, 1.0
-    log("generating 256^3 input")
-    f = make_domain(n, box, 2.0, 50, 1513)
+    if args.workload == "512":
+        n, box, rc, sigma, tophats, seed = 512, 512.0, 1.0, 2.5, 0, 1515
+        wl = "ndgp-512^3-fp64-lognormal-sigma2.5, box 512 Mpc/h, r_cH0=1, tol 1e-10, V(2,2) 7 levels, + force"
+    else:
+        n, box, rc, sigma, tophats, seed = 256, 256.0, 1.0, 2.0, 50, 1513
+        wl = ("ndgp-256^3-fp64-lognormal-sigma2+50tophats, box 256 Mpc/h, r_cH0=1, tol 1e-10, "
+              "V(2,2) 6 levels, + force")
+    log(f"generating {n}^3 input")
+    f = make_domain(n, box, sigma, tophats, seed)
     grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
     params = ndgp.Params(rc=rc, tol=1e-10, profile=True)
     log("timing")
@@ -266,9 +275,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "ndgp-256^3-fp64-lognormal-sigma2+50tophats, box 256 Mpc/h, "
-                               "r_cH0=1, tol 1e-10, V(2,2) 6 levels, + force",
-                   "n": n, "cycles": cycles, "rel_res": reps[-1].rel_res[0],
+        "config": {"workload": wl, "n": n, "cycles": cycles, "rel_res": reps[-1].rel_res[0],
                    "solves_per_s": 1.0 / dt},
         "roofline": roofline(reps, n),
     }
