@@ -162,7 +162,7 @@ size_t ndgp_workspace_bytes(const ndgp_grid *grid, const ndgp_params *params);
  *                 same mean density as the domain (unused in interpolated mode,
  *                 may be NULL there)
  *   phi[0]        out: domain phi, n^3, zero mean (in: initial guess with
- *                 NDGP_WARM_START)
+ *                 NDGP_WARM_START); 16-byte aligned
  *   phi[1..2]     out: patch phi, padded (patch_n+2)^3 with its ghost shell
  *                 (the fixed boundary values interpolated from the parent)
  *   report        optional (NULL allowed)
@@ -245,7 +245,7 @@ void ndgp_plan_destroy(ndgp_plan *plan);
  * array; the workspace needs NDGP_DIFF_NORMS_WORKSPACE bytes.  Deterministic;
  * blocks until out is written.
  */
-#define NDGP_DIFF_NORMS_WORKSPACE 65536
+#define NDGP_DIFF_NORMS_WORKSPACE 131072
 ndgp_status ndgp_diff_norms(const double *a, const double *b, size_t count, double out[3],
                             void *workspace, size_t workspace_bytes, hipStream_t stream);
 

@@ -86,23 +86,24 @@ __device__ __forceinline__ Terms stencil_terms(const double v[19]) {
     const double dyp = v[3] - u, dym = v[4] - u;
     const double dzp = v[5] - u, dzm = v[6] - u;
     const double Dxx = dxp + dxm, Dyy = dyp + dym, Dzz = dzp + dzm;
-    double e, c, c2, see;
-    e = v[7] - u;  see = e;  c = e - dxp - dyp; c2 = c * c;
-    e = v[8] - u;  see += e; c = e - dxp - dym; c2 = fma(c, c, c2);
-    e = v[9] - u;  see += e; c = e - dxm - dyp; c2 = fma(c, c, c2);
-    e = v[10] - u; see += e; c = e - dxm - dym; c2 = fma(c, c, c2);
-    e = v[11] - u; see += e; c = e - dxp - dzp; c2 = fma(c, c, c2);
-    e = v[12] - u; see += e; c = e - dxp - dzm; c2 = fma(c, c, c2);
-    e = v[13] - u; see += e; c = e - dxm - dzp; c2 = fma(c, c, c2);
-    e = v[14] - u; see += e; c = e - dxm - dzm; c2 = fma(c, c, c2);
-    e = v[15] - u; see += e; c = e - dyp - dzp; c2 = fma(c, c, c2);
-    e = v[16] - u; see += e; c = e - dyp - dzm; c2 = fma(c, c, c2);
-    e = v[17] - u; see += e; c = e - dym - dzp; c2 = fma(c, c, c2);
-    e = v[18] - u; see += e; c = e - dym - dzm; c2 = fma(c, c, c2);
+    // corner (s,t) of plane a-b: C = v_st - (d_a,s + f_b,t), with f_b,t = v[face]
+    double c, c2, sv;
+    c = v[7] - (dxp + v[3]);  c2 = c * c;          sv = v[7];
+    c = v[8] - (dxp + v[4]);  c2 = fma(c, c, c2);  sv += v[8];
+    c = v[9] - (dxm + v[3]);  c2 = fma(c, c, c2);  sv += v[9];
+    c = v[10] - (dxm + v[4]); c2 = fma(c, c, c2);  sv += v[10];
+    c = v[11] - (dxp + v[5]); c2 = fma(c, c, c2);  sv += v[11];
+    c = v[12] - (dxp + v[6]); c2 = fma(c, c, c2);  sv += v[12];
+    c = v[13] - (dxm + v[5]); c2 = fma(c, c, c2);  sv += v[13];
+    c = v[14] - (dxm + v[6]); c2 = fma(c, c, c2);  sv += v[14];
+    c = v[15] - (dyp + v[5]); c2 = fma(c, c, c2);  sv += v[15];
+    c = v[16] - (dyp + v[6]); c2 = fma(c, c, c2);  sv += v[16];
+    c = v[17] - (dym + v[5]); c2 = fma(c, c, c2);  sv += v[17];
+    c = v[18] - (dym + v[6]); c2 = fma(c, c, c2);  sv += v[18];
     Terms t;
     t.lap = (Dxx + Dyy) + Dzz;
     t.nl = fma(Dxx, Dyy, fma(Dxx, Dzz, Dyy * Dzz)) - 0.25 * c2;
-    t.see = see;
+    t.see = fma(-12.0, u, sv);
     return t;
 }
 

@@ -11,7 +11,7 @@ namespace ndgp {
 
 constexpr int kMaxLevels = 12;
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
-constexpr int kReduceBlocks = 512; // fixed partial count of the deterministic reductions
+constexpr int kReduceBlocks = 4096; // fixed partial count of the deterministic reductions
 constexpr int kCoarsestMax = 8;    // the single-workgroup coarsest solve holds <= 8^3 cells
 constexpr int kCoarsestSweeps = 48;
 

@@ -353,6 +353,74 @@ k_prolong(double *__restrict__ phi_f, Ix<PER> ixf, const double *__restrict__ ph
     if (!PER && dyn_bc_f) write_owned_ghosts(phi_f, hat_f, ixf, i, j, k, val);
 }
 
+// The same transfer with one thread per COARSE cell: its 27 coarse values are
+// loaded once and its 8 children written, the two x-children of a row as one
+// 16-byte access on periodic levels.  Each child gets exactly the arithmetic
+// of k_prolong (same weights, same order of the fma chain).
+template <bool PER, bool CORRECT>
+__global__ void __launch_bounds__(kBlock)
+k_prolong8(double *__restrict__ phi_f, Ix<PER> ixf, const double *__restrict__ phi_c,
+           const double *__restrict__ hat_c, Ix<PER> ixc, const double *__restrict__ hat_f,
+           int dyn_bc_f) {
+    const int nc = ixc.n, lgc = ixc.lg;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (1 << (3 * lgc))) return;
+    const int I = t & (nc - 1), J = (t >> lgc) & (nc - 1), K = t >> (2 * lgc);
+    double cv[3][3][3];
+#pragma unroll
+    for (int dk = 0; dk < 3; ++dk)
+#pragma unroll
+        for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+            for (int di = 0; di < 3; ++di) {
+                const int q = ixc(I + di - 1, J + dj - 1, K + dk - 1);
+                cv[dk][dj][di] = CORRECT ? phi_c[q] - hat_c[q] : phi_c[q];
+            }
+#pragma unroll
+    for (int ck = 0; ck < 2; ++ck)
+#pragma unroll
+        for (int cj = 0; cj < 2; ++cj) {
+            double out[2];
+#pragma unroll
+            for (int ci = 0; ci < 2; ++ci) {
+                const int si = ci ? 1 : -1, sj = cj ? 1 : -1, sk = ck ? 1 : -1;
+                double acc = 0.0;
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) {
+                            const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (c ? 0.25 : 0.75);
+                            acc = fma(w, cv[1 + c * sk][1 + b * sj][1 + a * si], acc);
+                        }
+                out[ci] = acc;
+            }
+            const int i = 2 * I, j = 2 * J + cj, k = 2 * K + ck;
+            const int q0 = ixf(i, j, k);
+            if constexpr (PER) {
+                double2 *p2 = reinterpret_cast<double2 *>(phi_f + q0);
+                double2 old = CORRECT ? *p2 : make_double2(0.0, 0.0);
+                if (CORRECT) {
+                    old.x += out[0];
+                    old.y += out[1];
+                } else {
+                    old.x = out[0];
+                    old.y = out[1];
+                }
+                *p2 = old;
+            } else {
+#pragma unroll
+                for (int ci = 0; ci < 2; ++ci) {
+                    const int q = ixf(i + ci, j, k);
+                    const double val = CORRECT ? phi_f[q] + out[ci] : out[ci];
+                    phi_f[q] = val;
+                    if (dyn_bc_f) write_owned_ghosts(phi_f, hat_f, ixf, i + ci, j, k, val);
+                }
+            }
+        }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_restrict_source(const double *__restrict__ s_f, int nf, double *__restrict__ s_c, int lgc) {
     const int nc = 1 << lgc;
@@ -541,6 +609,10 @@ void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigne
         constexpr int TZ = 32;
         k_sweep_fused<TX, TY, TZ, NT><<<dim3(tiles, L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
                                                                           L.alpha, fallbacks);
+    } else if (L.n <= 128) { // enough workgroups to fill the chip
+        constexpr int TZ = 8;
+        k_sweep_fused<TX, TY, TZ, NT><<<dim3(tiles, L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
+                                                                          L.alpha, fallbacks);
     } else {
         constexpr int TZ = 16;
         k_sweep_fused<TX, TY, TZ, NT><<<dim3(tiles, L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
@@ -596,26 +668,26 @@ void launch_coarse_source(const Level &C, hipStream_t st) {
 }
 
 void launch_prolong_correct(const Level &F, const Level &C, hipStream_t st) {
-    const unsigned nb = blocks_for(F.cells());
+    const unsigned nb = blocks_for(C.cells());
     if (F.periodic)
-        k_prolong<true, true><<<nb, kBlock, 0, st>>>(F.phi, make_ix<true>(F.n, F.lg), C.phi,
-                                                     C.hat, make_ix<true>(C.n, C.lg), nullptr, 0);
+        k_prolong8<true, true><<<nb, kBlock, 0, st>>>(F.phi, make_ix<true>(F.n, F.lg), C.phi,
+                                                      C.hat, make_ix<true>(C.n, C.lg), nullptr, 0);
     else
-        k_prolong<false, true><<<nb, kBlock, 0, st>>>(F.phi, make_ix<false>(F.n, F.lg), C.phi,
-                                                      C.hat, make_ix<false>(C.n, C.lg), F.hat,
-                                                      F.dyn_bc ? 1 : 0);
+        k_prolong8<false, true><<<nb, kBlock, 0, st>>>(F.phi, make_ix<false>(F.n, F.lg), C.phi,
+                                                       C.hat, make_ix<false>(C.n, C.lg), F.hat,
+                                                       F.dyn_bc ? 1 : 0);
 }
 
 void launch_prolong_full(const Level &F, const Level &C, hipStream_t st) {
-    const unsigned nb = blocks_for(F.cells());
+    const unsigned nb = blocks_for(C.cells());
     if (F.periodic)
-        k_prolong<true, false><<<nb, kBlock, 0, st>>>(F.phi, make_ix<true>(F.n, F.lg), C.phi,
-                                                      nullptr, make_ix<true>(C.n, C.lg), nullptr,
-                                                      0);
+        k_prolong8<true, false><<<nb, kBlock, 0, st>>>(F.phi, make_ix<true>(F.n, F.lg), C.phi,
+                                                       nullptr, make_ix<true>(C.n, C.lg), nullptr,
+                                                       0);
     else
-        k_prolong<false, false><<<nb, kBlock, 0, st>>>(F.phi, make_ix<false>(F.n, F.lg), C.phi,
-                                                       nullptr, make_ix<false>(C.n, C.lg), F.hat,
-                                                       F.dyn_bc ? 1 : 0);
+        k_prolong8<false, false><<<nb, kBlock, 0, st>>>(F.phi, make_ix<false>(F.n, F.lg), C.phi,
+                                                        nullptr, make_ix<false>(C.n, C.lg),
+                                                        F.hat, F.dyn_bc ? 1 : 0);
 }
 
 void launch_restrict_source(const Level &F, const Level &C, hipStream_t st) {

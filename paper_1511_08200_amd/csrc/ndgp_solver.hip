@@ -566,6 +566,8 @@ ndgp_status check_arrays(const Cfg &c, const double *const *delta, double *const
                          bool need_patch_delta) {
     if (!delta || !phi || !delta[0] || !phi[0])
         return fail(NDGP_EINVAL, "delta[0] and phi[0] must not be NULL");
+    if (reinterpret_cast<uintptr_t>(phi[0]) % 16 != 0)
+        return fail(NDGP_EINVAL, "phi[0] must be 16-byte aligned");
     for (int q = 0; q < c.np; ++q) {
         if (!phi[q + 1]) return fail(NDGP_EINVAL, "phi of every patch must not be NULL");
         if (need_patch_delta && !delta[q + 1])

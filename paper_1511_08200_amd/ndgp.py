@@ -322,7 +322,7 @@ def force(grid: Grid, phi: Sequence[torch.Tensor], stream=None) -> list:
     return out
 
 
-DIFF_NORMS_WORKSPACE = 65536
+DIFF_NORMS_WORKSPACE = 131072
 
 
 def diff_norms(a: torch.Tensor, b: Optional[torch.Tensor] = None, stream=None):
