@@ -181,6 +181,17 @@ __device__ __forceinline__ void write_owned_ghosts(double *__restrict__ out,
     }
 }
 
+// Workgroups of a launch are dealt to the 8 XCDs of the chip round robin
+// (workgroup id modulo 8), and each XCD has its own L2.  Renumber so that XCD
+// x runs a contiguous run of logical tiles: spatial neighbours then share the
+// L2 that holds their common halo lines.  Identity when the grid is not a
+// multiple of 8.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_local_id(int lin, int total) {
+    if (total % kXcds) return lin;
+    return (lin % kXcds) * (total / kXcds) + lin / kXcds;
+}
+
 // ------------------------------------------------------------------------
 // deterministic block sum (kBlock = 256 threads = 4 waves of 64)
 

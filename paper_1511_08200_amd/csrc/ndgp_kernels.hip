@@ -84,9 +84,12 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
 
     const int n = 1 << lg, m = n - 1;
     const int ntx = n / TX;
-    const int x0 = (blockIdx.x % ntx) * TX;
-    const int y0 = (blockIdx.x / ntx) * TY;
-    const int z0 = blockIdx.y * TZ;
+    const int tiles = ntx * (n / TY);
+    const int logical = xcd_local_id(blockIdx.x, gridDim.x); // tile fastest, then z-chunk
+    const int tile = logical % tiles;
+    const int x0 = (tile % ntx) * TX;
+    const int y0 = (tile / ntx) * TY;
+    const int z0 = (logical / tiles) * TZ;
     const int tid = threadIdx.x;
     unsigned fb = 0;
 
@@ -192,6 +195,82 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         black_and_store(k, sb);
     }
     if (fb) atomicAdd(fallbacks, fb);
+}
+
+// Residual norm of a large periodic level through LDS: a workgroup streams a
+// TX x TY column along z over tz planes, holding four planes of phi with a
+// one-cell halo; each phi and S value is read from HBM about once.  One
+// partial sum per workgroup (fixed order), optional r_out = r * scale.
+template <int TX, int TY>
+__global__ void __launch_bounds__(kBlock)
+k_residual_tiled(const double *__restrict__ phi, const double *__restrict__ s, int lg, int tz,
+                 double al, double *__restrict__ partials, double *__restrict__ r_out,
+                 double r_scale) {
+    constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
+    constexpr int PRE = (PLANE + kBlock - 1) / kBlock;
+    constexpr int CELLS = TX * TY / kBlock; // output cells per thread per plane
+    static_assert(TX * TY % kBlock == 0, "tile");
+    __shared__ double P[4][PLANE];
+    const int n = 1 << lg, m = n - 1;
+    const int ntx = n / TX;
+    const int tiles = ntx * (n / TY);
+    const int logical = xcd_local_id(blockIdx.x, gridDim.x);
+    const int tile = logical % tiles;
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY, z0 = (logical / tiles) * tz;
+    const int tid = threadIdx.x;
+    int pq[PRE], pxy[PRE];
+#pragma unroll
+    for (int e = 0; e < PRE; ++e) {
+        const int q = tid + e * kBlock;
+        pq[e] = q < PLANE ? q : -1;
+        const int yy = q / PX, xx = q - yy * PX;
+        pxy[e] = (((y0 - 1 + yy) & m) << lg) | ((x0 - 1 + xx) & m);
+    }
+    double pre[PRE];
+    auto fetch = [&](int z) {
+        const int zo = (z & m) << (2 * lg);
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pq[e] >= 0) pre[e] = phi[zo | pxy[e]];
+    };
+    auto commit = [&](int z) {
+        double *dst = P[z & 3];
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pq[e] >= 0) dst[pq[e]] = pre[e];
+    };
+    double acc = 0.0;
+    fetch(z0 - 1);
+    commit(z0 - 1);
+    fetch(z0);
+    commit(z0);
+    fetch(z0 + 1);
+    for (int k = z0; k < z0 + tz; ++k) {
+        commit(k + 1); // slot of plane k-3, last read at step k-2
+        if (k + 2 <= z0 + tz) fetch(k + 2);
+        __syncthreads();
+        const double(*pm)[PX] = reinterpret_cast<const double(*)[PX]>(P[(k - 1) & 3]);
+        const double(*p0)[PX] = reinterpret_cast<const double(*)[PX]>(P[k & 3]);
+        const double(*pp)[PX] = reinterpret_cast<const double(*)[PX]>(P[(k + 1) & 3]);
+#pragma unroll
+        for (int e = 0; e < CELLS; ++e) {
+            const int q = tid + e * kBlock;
+            const int yt = q / TX, xt = q - yt * TX;
+            const int rr = yt + 1, c = xt + 1;
+            const double v[19] = {
+                p0[rr][c], p0[rr][c + 1], p0[rr][c - 1], p0[rr + 1][c], p0[rr - 1][c],
+                pp[rr][c], pm[rr][c],
+                p0[rr + 1][c + 1], p0[rr - 1][c + 1], p0[rr + 1][c - 1], p0[rr - 1][c - 1],
+                pp[rr][c + 1], pm[rr][c + 1], pp[rr][c - 1], pm[rr][c - 1],
+                pp[rr + 1][c], pm[rr + 1][c], pp[rr - 1][c], pm[rr - 1][c]};
+            const int g = ((k << lg | (y0 + yt)) << lg) | (x0 + xt);
+            const double r = s[g] - apply_L(stencil_terms(v), al);
+            acc = fma(r, r, acc);
+            if (r_out) r_out[g] = r * r_scale;
+        }
+    }
+    const double b = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = b;
 }
 
 template <bool PER>
@@ -607,21 +686,33 @@ void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigne
     const int tiles = (L.n / TX) * (L.n / TY);
     if (L.n >= 512) {
         constexpr int TZ = 32;
-        k_sweep_fused<TX, TY, TZ, NT><<<dim3(tiles, L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
+        k_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
                                                                           L.alpha, fallbacks);
     } else if (L.n <= 128) { // enough workgroups to fill the chip
         constexpr int TZ = 8;
-        k_sweep_fused<TX, TY, TZ, NT><<<dim3(tiles, L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
+        k_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
                                                                           L.alpha, fallbacks);
     } else {
         constexpr int TZ = 16;
-        k_sweep_fused<TX, TY, TZ, NT><<<dim3(tiles, L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
+        k_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
                                                                           L.alpha, fallbacks);
     }
 }
 
 void launch_residual_sumsq(const Level &L, double *partials, double *r_out, double r_scale,
                            hipStream_t st) {
+    if (L.periodic && L.n >= 128) {
+        constexpr int TX = 64, TY = 16;
+        const int tiles = (L.n / TX) * (L.n / TY);
+        int chunks = L.n / 8; // z-chunks of 8 planes, at most kReduceBlocks workgroups
+        while (tiles * chunks > kReduceBlocks) chunks /= 2;
+        // blocks beyond the grid contribute zeros to the fixed-size final sum
+        const size_t unused = (size_t)(kReduceBlocks - tiles * chunks);
+        if (unused) k_fill<<<blocks_for(unused), kBlock, 0, st>>>(partials + tiles * chunks, unused, 0.0);
+        k_residual_tiled<TX, TY><<<tiles * chunks, kBlock, 0, st>>>(
+            L.phi, L.s, L.lg, L.n / chunks, L.alpha, partials, r_out, r_scale);
+        return;
+    }
     if (L.periodic)
         k_residual_sumsq<true><<<kReduceBlocks, kBlock, 0, st>>>(
             L.phi, L.s, make_ix<true>(L.n, L.lg), L.alpha, partials, r_out, r_scale);
