@@ -58,29 +58,32 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
 // values), bit for bit.
 //
 // A workgroup owns a TX x TY column of the x-y plane over TZ planes and
-// streams along z.  Per output plane k it keeps in LDS
-//   P: the old field on planes k..k+2, TX+4 x TY+4 (halo 2),
-//   R: planes k-1..k+1 after the red pass, TX+2 x TY+2 (halo 1): red cells
-//      relaxed, black cells old,
-// relaxes the red cells of plane k+1 over the tile plus halo 1 (the black
-// pass of the tile's edge cells needs them), then the black cells of plane k
-// over the tile, and writes plane k.  Plane k+3 is read into registers
-// while plane k is relaxed.  HBM sees each old value and each source value
-// once and each new value once: 24 bytes per cell and sweep, plus the halo
-// re-reads, which neighbouring workgroups mostly find in L2.
+// streams along z.  LDS keeps every plane split by colour, so that lanes
+// working on consecutive cells of one colour touch consecutive words (no
+// bank conflicts):
+//   P: the old field, tile + 2-cell halo, planes k-1 .. k+2 (+1 being filled);
+//   R: red cells after the red pass, planes k-1 .. k+1.
+// Step k relaxes the red cells of plane k+1 over the tile plus a 1-cell halo
+// (the black cells at the tile's edge need them), then the black cells of
+// plane k over the tile (red neighbours from R, black ones from P), and
+// writes plane k.  The next old plane is read into registers meanwhile.  HBM
+// sees each old value and each source value once and each new value once:
+// 24 bytes per cell and sweep; tiles are ordered per XCD so that their halo
+// lines are shared in L2.
 template <int TX, int TY, int TZ, int NT>
 __global__ void __launch_bounds__(NT)
 k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
               const double *__restrict__ s, int lg, double al, unsigned *__restrict__ fallbacks) {
-    constexpr int PX = TX + 4, PY = TY + 4, RX = TX + 2, RY = TY + 2;
+    constexpr int PX = TX + 4, PY = TY + 4;   // plane with halo 2
+    constexpr int HX = PX / 2;                // cells of one colour per row
     constexpr int PLANE = PX * PY;
-    constexpr int PRE = (PLANE + NT - 1) / NT; // prefetched values per thread
-    constexpr int RED_ROW = RX / 2;            // red (or black) cells per region row
-    constexpr int RED_CELLS = RED_ROW * RY;
-    constexpr int SEGS = TX * TY / 2;          // 2-cell (one red, one black) output segments
-    static_assert(TX % 2 == 0 && TY % 2 == 0 && SEGS == NT, "one output segment per thread");
-    __shared__ double P[3][PLANE];
-    __shared__ double R[3][RY][RX];
+    constexpr int HALF = HX * PY;             // one colour of one plane
+    constexpr int PRE = (PLANE + NT - 1) / NT;
+    constexpr int RED_ROW = (TX + 2) / 2;     // red cells per row of the halo-1 region
+    constexpr int RED_CELLS = RED_ROW * (TY + 2);
+    static_assert(TX % 2 == 0 && TY % 2 == 0 && TX * TY / 2 == NT, "one black cell per thread");
+    __shared__ double P[5][2][PY][HX];
+    __shared__ double R[3][PY][HX];
 
     const int n = 1 << lg, m = n - 1;
     const int ntx = n / TX;
@@ -93,104 +96,107 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     const int tid = threadIdx.x;
     unsigned fb = 0;
 
-    auto gidx = [&](int x, int y, int z) {
-        return ((((z & m) << lg) | (y & m)) << lg) | (x & m);
-    };
-    auto slot = [](int z) { return (z + 3 * 4096) % 3; };
+    auto zoff = [&](int z) { return (z & m) << (2 * lg); };
+    auto pslot = [](int z) { return (z + 5 * 4096) % 5; };
+    auto rslot = [](int z) { return (z + 3 * 4096) % 3; };
 
+    // this thread's share of a plane: global x-y offset, LDS split position
+    int pxy[PRE], pidx[PRE], ppar[PRE];
+#pragma unroll
+    for (int e = 0; e < PRE; ++e) {
+        const int q = tid + e * NT;
+        const int r = q / PX, c = q - r * PX;
+        pxy[e] = (((y0 - 2 + r) & m) << lg) | ((x0 - 2 + c) & m);
+        pidx[e] = q < PLANE ? r * HX + (c >> 1) : -1;
+        ppar[e] = (c + r) & 1; // colour = ppar ^ (z & 1)  (x0, y0 even)
+    }
     double pre[PRE];
     auto fetch = [&](int z) {
+        const int zo = zoff(z);
 #pragma unroll
-        for (int e = 0; e < PRE; ++e) {
-            const int q = tid + e * NT;
-            if (q < PLANE) {
-                const int yy = q / PX, xx = q - yy * PX;
-                pre[e] = pin[gidx(x0 - 2 + xx, y0 - 2 + yy, z)];
-            }
-        }
+        for (int e = 0; e < PRE; ++e)
+            if (pidx[e] >= 0) pre[e] = pin[zo | pxy[e]];
     };
     auto commit = [&](int z) {
-        double *dst = P[slot(z)];
+        double *base = &P[pslot(z)][0][0][0];
+        const int zp = z & 1;
 #pragma unroll
-        for (int e = 0; e < PRE; ++e) {
-            const int q = tid + e * NT;
-            if (q < PLANE) dst[q] = pre[e];
-        }
+        for (int e = 0; e < PRE; ++e)
+            if (pidx[e] >= 0) base[(ppar[e] ^ zp) * HALF + pidx[e]] = pre[e];
     };
 
-    // R plane z: black cells copied, red cells relaxed from P planes z-1..z+1
+    // red cells of plane z over the tile + 1-cell halo -> R(z)
     auto red_plane = [&](int z) {
-        const double(*pm)[PX] = reinterpret_cast<const double(*)[PX]>(P[slot(z - 1)]);
-        const double(*p0)[PX] = reinterpret_cast<const double(*)[PX]>(P[slot(z)]);
-        const double(*pp)[PX] = reinterpret_cast<const double(*)[PX]>(P[slot(z + 1)]);
-        double(*r)[RX] = R[slot(z)];
+        const double(*m0)[HX] = P[pslot(z - 1)][0], (*m1)[HX] = P[pslot(z - 1)][1];
+        const double(*c0)[HX] = P[pslot(z)][0], (*c1)[HX] = P[pslot(z)][1];
+        const double(*p0)[HX] = P[pslot(z + 1)][0], (*p1)[HX] = P[pslot(z + 1)][1];
+        double(*rz)[HX] = R[rslot(z)];
+        const int zo = zoff(z);
         for (int q = tid; q < RED_CELLS; q += NT) {
-            const int yr = q / RED_ROW, c2 = q - yr * RED_ROW;
-            const int y = y0 - 1 + yr;
-            // region column xr <-> global x = x0 - 1 + xr; red: (x + y + z) even
-            const int xr_red = 2 * c2 + ((1 + y + z) & 1);
-            const int xr_blk = 2 * c2 + ((y + z) & 1);
-            const double sv = s[gidx(x0 - 1 + xr_red, y, z)];
-            r[yr][xr_blk] = p0[yr + 1][xr_blk + 1];
-            const int c = xr_red + 1, rr = yr + 1;
+            const int rr = 1 + q / RED_ROW, jj = q - (rr - 1) * RED_ROW;
+            const int p = (rr + z) & 1;         // red cell at column c = 2j + p
+            const int j = jj + 1 - p;           // c in [1, PX-2]
+            const int a = j + p, b = j + p - 1; // split index of columns c+1, c-1
             const double v[19] = {
-                p0[rr][c], p0[rr][c + 1], p0[rr][c - 1], p0[rr + 1][c], p0[rr - 1][c],
-                pp[rr][c], pm[rr][c],
-                p0[rr + 1][c + 1], p0[rr - 1][c + 1], p0[rr + 1][c - 1], p0[rr - 1][c - 1],
-                pp[rr][c + 1], pm[rr][c + 1], pp[rr][c - 1], pm[rr][c - 1],
-                pp[rr + 1][c], pm[rr + 1][c], pp[rr - 1][c], pm[rr - 1][c]};
-            r[yr][xr_red] = relax_cell(v, sv, al, fb);
+                c0[rr][j], c1[rr][a], c1[rr][b], c1[rr + 1][j], c1[rr - 1][j],
+                p1[rr][j], m1[rr][j],
+                c0[rr + 1][a], c0[rr - 1][a], c0[rr + 1][b], c0[rr - 1][b],
+                p0[rr][a], m0[rr][a], p0[rr][b], m0[rr][b],
+                p0[rr + 1][j], m0[rr + 1][j], p0[rr - 1][j], m0[rr - 1][j]};
+            const int gx = x0 - 2 + 2 * j + p, gy = y0 - 2 + rr;
+            const double sv = s[zo | ((gy & m) << lg) | (gx & m)];
+            rz[rr][j] = relax_cell(v, sv, al, fb);
         }
     };
 
-    // black cell of plane k in this thread's segment, then write the segment
-    const int yt = tid / (TX / 2), xs = (tid - yt * (TX / 2)) * 2;
-    auto black_and_store = [&](int k, double sv) {
-        const double(*rm)[RX] = R[slot(k - 1)];
-        const double(*r0)[RX] = R[slot(k)];
-        const double(*rp)[RX] = R[slot(k + 1)];
-        const int y = y0 + yt;
-        const int b = (1 + y + k + x0 + xs) & 1; // black cell's offset in the segment
-        const int c = xs + b + 1, rr = yt + 1;
-        const double v[19] = {
-            r0[rr][c], r0[rr][c + 1], r0[rr][c - 1], r0[rr + 1][c], r0[rr - 1][c],
-            rp[rr][c], rm[rr][c],
-            r0[rr + 1][c + 1], r0[rr - 1][c + 1], r0[rr + 1][c - 1], r0[rr - 1][c - 1],
-            rp[rr][c + 1], rm[rr][c + 1], rp[rr][c - 1], rm[rr][c - 1],
-            rp[rr + 1][c], rm[rr + 1][c], rp[rr - 1][c], rm[rr - 1][c]};
-        const double vb = relax_cell(v, sv, al, fb);
-        const double vr = r0[rr][xs + (1 - b) + 1];
-        double *dst = pout + gidx(x0 + xs, y, k);
-        dst[0] = b ? vr : vb;
-        dst[1] = b ? vb : vr;
-    };
+    // this thread's black cell: row rt, split index jt (pair of columns 2jt, 2jt+1)
+    const int rt = 2 + tid / (TX / 2), jt = 1 + tid % (TX / 2);
+    const int yt = y0 - 2 + rt;
+    const int xy_t = (yt << lg) | (x0 - 2 + 2 * jt);
     auto black_source = [&](int k) {
-        const int y = y0 + yt;
-        const int b = (1 + y + k + x0 + xs) & 1;
-        return s[gidx(x0 + xs + b, y, k)];
+        const int pb = (1 + rt + k) & 1;
+        return s[zoff(k) | xy_t | pb];
+    };
+    auto black_and_store = [&](int k, double sv) {
+        const double(*rm)[HX] = R[rslot(k - 1)], (*r0)[HX] = R[rslot(k)],
+                     (*rp)[HX] = R[rslot(k + 1)];
+        const double(*m1)[HX] = P[pslot(k - 1)][1], (*c1)[HX] = P[pslot(k)][1],
+                     (*p1)[HX] = P[pslot(k + 1)][1];
+        const int pb = (1 + rt + k) & 1; // black cell at column 2jt + pb
+        const int j = jt, rr = rt, a = j + pb, b = j + pb - 1;
+        const double v[19] = {
+            c1[rr][j], r0[rr][a], r0[rr][b], r0[rr + 1][j], r0[rr - 1][j],
+            rp[rr][j], rm[rr][j],
+            c1[rr + 1][a], c1[rr - 1][a], c1[rr + 1][b], c1[rr - 1][b],
+            p1[rr][a], m1[rr][a], p1[rr][b], m1[rr][b],
+            p1[rr + 1][j], m1[rr + 1][j], p1[rr - 1][j], m1[rr - 1][j]};
+        const double vb = relax_cell(v, sv, al, fb);
+        const double vr = r0[rr][j]; // the red cell of the pair, column 2jt + 1 - pb
+        double *dst = pout + (zoff(k) | xy_t);
+        dst[0] = pb ? vr : vb;
+        dst[1] = pb ? vb : vr;
     };
 
+    // planes needed: P z0-2 .. z0+TZ+1, R z0-1 .. z0+TZ
     fetch(z0 - 2);
     commit(z0 - 2);
     fetch(z0 - 1);
     commit(z0 - 1);
     fetch(z0);
     commit(z0);
-    __syncthreads();
-    red_plane(z0 - 1);
     fetch(z0 + 1);
     __syncthreads();
+    red_plane(z0 - 1);
     commit(z0 + 1);
     fetch(z0 + 2);
     __syncthreads();
     red_plane(z0);
-    __syncthreads();
     for (int k = z0; k < z0 + TZ; ++k) {
-        commit(k + 2); // into the slot of plane k-1, last read by red_plane(k)
+        commit(k + 2); // the slot of plane k-3: last read by black(k-2) and red(k-2)
         if (k + 3 <= z0 + TZ + 1) fetch(k + 3);
         const double sb = black_source(k);
         __syncthreads();
-        red_plane(k + 1);
+        red_plane(k + 1); // writes the R slot of plane k-2, last read by black(k-1)
         __syncthreads();
         black_and_store(k, sb);
     }
