@@ -125,17 +125,39 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
             if (pidx[e] >= 0) base[(ppar[e] ^ zp) * HALF + pidx[e]] = pre[e];
     };
 
+    // red cells of the halo-1 region: thread slot e covers q = tid + e * NT
+    int red_rr[2], red_jj[2];
+    bool red_on[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int q = tid + e * NT;
+        red_on[e] = q < RED_CELLS;
+        red_rr[e] = 1 + q / RED_ROW;
+        red_jj[e] = q - (red_rr[e] - 1) * RED_ROW;
+    }
+    // the sources of plane z's red cells, loaded a step ahead of their use
+    auto red_sources = [&](int z, double out[2]) {
+        const int zo = zoff(z);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int rr = red_rr[e];
+            const int p = (rr + z) & 1;
+            const int gx = x0 - 2 + 2 * (red_jj[e] + 1 - p) + p, gy = y0 - 2 + rr;
+            out[e] = s[zo | ((gy & m) << lg) | (gx & m)]; // in bounds also when !red_on[e]
+        }
+    };
     // red cells of plane z over the tile + 1-cell halo -> R(z)
-    auto red_plane = [&](int z) {
+    auto red_plane = [&](int z, const double src[2]) {
         const double(*m0)[HX] = P[pslot(z - 1)][0], (*m1)[HX] = P[pslot(z - 1)][1];
         const double(*c0)[HX] = P[pslot(z)][0], (*c1)[HX] = P[pslot(z)][1];
         const double(*p0)[HX] = P[pslot(z + 1)][0], (*p1)[HX] = P[pslot(z + 1)][1];
         double(*rz)[HX] = R[rslot(z)];
-        const int zo = zoff(z);
-        for (int q = tid; q < RED_CELLS; q += NT) {
-            const int rr = 1 + q / RED_ROW, jj = q - (rr - 1) * RED_ROW;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (!red_on[e]) continue;
+            const int rr = red_rr[e];
             const int p = (rr + z) & 1;         // red cell at column c = 2j + p
-            const int j = jj + 1 - p;           // c in [1, PX-2]
+            const int j = red_jj[e] + 1 - p;    // c in [1, PX-2]
             const int a = j + p, b = j + p - 1; // split index of columns c+1, c-1
             const double v[19] = {
                 c0[rr][j], c1[rr][a], c1[rr][b], c1[rr + 1][j], c1[rr - 1][j],
@@ -143,9 +165,7 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
                 c0[rr + 1][a], c0[rr - 1][a], c0[rr + 1][b], c0[rr - 1][b],
                 p0[rr][a], m0[rr][a], p0[rr][b], m0[rr][b],
                 p0[rr + 1][j], m0[rr + 1][j], p0[rr - 1][j], m0[rr - 1][j]};
-            const int gx = x0 - 2 + 2 * j + p, gy = y0 - 2 + rr;
-            const double sv = s[zo | ((gy & m) << lg) | (gx & m)];
-            rz[rr][j] = relax_cell(v, sv, al, fb);
+            rz[rr][j] = relax_cell(v, src[e], al, fb);
         }
     };
 
@@ -177,28 +197,46 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         dst[1] = pb ? vb : vr;
     };
 
-    // planes needed: P z0-2 .. z0+TZ+1, R z0-1 .. z0+TZ
+    // planes needed: P z0-2 .. z0+TZ+1, R z0-1 .. z0+TZ.  Source values are
+    // loaded a step ahead and before the next plane's field values, so that
+    // waiting for them never waits for the prefetch as well; the loop is
+    // unrolled by two so that no loaded register is copied (a copy would wait).
     fetch(z0 - 2);
     commit(z0 - 2);
     fetch(z0 - 1);
     commit(z0 - 1);
     fetch(z0);
     commit(z0);
+    double ra[2], rb[2], ba, bb;
+    red_sources(z0 - 1, ra);
     fetch(z0 + 1);
     __syncthreads();
-    red_plane(z0 - 1);
+    red_plane(z0 - 1, ra);
     commit(z0 + 1);
+    red_sources(z0, ra);
     fetch(z0 + 2);
     __syncthreads();
-    red_plane(z0);
-    for (int k = z0; k < z0 + TZ; ++k) {
+    red_plane(z0, ra);
+    red_sources(z0 + 1, ra);
+    ba = black_source(z0);
+    // one step: red(k+1), black(k); loads the sources of red(k+2), black(k+1)
+    // and the field of plane k+3 (on the last step one plane past the ones
+    // used: in bounds, never committed)
+    auto step = [&](int k, const double (&use_r)[2], double use_b, double (&next_r)[2],
+                    double &next_b) {
         commit(k + 2); // the slot of plane k-3: last read by black(k-2) and red(k-2)
-        if (k + 3 <= z0 + TZ + 1) fetch(k + 3);
-        const double sb = black_source(k);
+        red_sources(k + 2, next_r);
+        next_b = black_source(k + 1);
+        fetch(k + 3);
         __syncthreads();
-        red_plane(k + 1); // writes the R slot of plane k-2, last read by black(k-1)
+        red_plane(k + 1, use_r); // writes the R slot of plane k-2, last read by black(k-1)
         __syncthreads();
-        black_and_store(k, sb);
+        black_and_store(k, use_b);
+    };
+    static_assert(TZ % 2 == 0, "the z loop is unrolled by two");
+    for (int k = z0; k < z0 + TZ; k += 2) {
+        step(k, ra, ba, rb, bb);
+        step(k + 1, rb, bb, ra, ba);
     }
     if (fb) atomicAdd(fallbacks, fb);
 }
