@@ -82,6 +82,7 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     constexpr int RED_ROW = (TX + 2) / 2;     // red cells per row of the halo-1 region
     constexpr int RED_CELLS = RED_ROW * (TY + 2);
     static_assert(TX % 2 == 0 && TY % 2 == 0 && TX * TY / 2 == NT, "one black cell per thread");
+    static_assert(RED_CELLS <= 2 * NT, "at most two red cells per thread");
     __shared__ double P[5][2][PY][HX];
     __shared__ double R[3][PY][HX];
 
@@ -728,16 +729,12 @@ void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigne
                         hipStream_t st) {
     constexpr int TX = 64, TY = 16, NT = 512;
     const int tiles = (L.n / TX) * (L.n / TY);
-    if (L.n >= 512) {
+    if (L.n >= 256) {
         constexpr int TZ = 32;
         k_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
                                                                           L.alpha, fallbacks);
-    } else if (L.n <= 128) { // enough workgroups to fill the chip
+    } else { // 128^3: short chunks, enough workgroups to fill the chip
         constexpr int TZ = 8;
-        k_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
-                                                                          L.alpha, fallbacks);
-    } else {
-        constexpr int TZ = 16;
         k_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
                                                                           L.alpha, fallbacks);
     }
