@@ -90,9 +90,10 @@ typedef enum {
                               otherwise the guess comes from nested iteration */
 #define NDGP_PROFILE 2u    /* time the domain level's relaxation sweeps with HIP
                               events on `stream` (ndgp_report.t_smooth_ms) */
-#define NDGP_TWO_PASS 4u   /* relax every level with two launches per red-black
-                              sweep (one per colour) instead of the fused
-                              one-launch sweep; same results, bit for bit */
+#define NDGP_TWO_PASS 4u   /* one launch per colour, per transfer and per level:
+                              no fused one-launch sweep on large levels and no
+                              one-workgroup bottom of the V-cycle on levels of
+                              at most 16^3 cells; same results, bit for bit */
 
 typedef struct {
     int32_t n;             /* domain cells per side: power of two, 8..1024              */

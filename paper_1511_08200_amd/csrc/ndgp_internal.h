@@ -13,7 +13,7 @@ constexpr int kMaxLevels = 12;
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kReduceBlocks = 4096; // fixed partial count of the deterministic reductions
 constexpr int kCoarsestMax = 8;    // the single-workgroup coarsest solve holds <= 8^3 cells
-constexpr int kCoarsestSweeps = 48;
+constexpr int kCoarsestSweeps = 16;
 
 // One grid of a multigrid hierarchy.
 //  periodic: phi/alt/hat are natural n^3 with periodic wrap-around;
@@ -81,6 +81,16 @@ void launch_prolong_full(const Level &F, const Level &C, hipStream_t st);
 void launch_restrict_source(const Level &F, const Level &C, hipStream_t st);
 // Many red-black sweeps of a <= 8^3 level in one workgroup (LDS resident).
 void launch_coarsest(const Level &L, int sweeps, unsigned *fallbacks, hipStream_t st);
+// The V-cycle of level l (n <= 16, periodic) and every coarser level in one
+// workgroup with its arrays in LDS; bit for bit the per-level launches.
+constexpr int kBottomMaxLevels = 4;
+struct BottomLevels {
+    int levels;                       // l .. nl-1
+    double alpha[kBottomMaxLevels];   // per level, cell units
+};
+bool bottom_ok(const Level *H, int l, int nl);
+void launch_bottom(const Level *H, int l, int nl, int nu1, int nu2, int csweeps,
+                   unsigned *fallbacks, hipStream_t st);
 // s = f * (delta - sum[0] * inv_count_mean)     (sum: device scalar)
 void launch_source(const double *delta, size_t count, const double *sum, double inv_count_mean,
                    double f, double *s, hipStream_t st);

@@ -383,18 +383,15 @@ k_reduce_final(const double *__restrict__ partials, double *__restrict__ out) {
     if (threadIdx.x == 0) out[0] = b;
 }
 
-// FAS restriction fused with the residual: one thread per coarse cell holds
-// the 4x4x4 block of fine values around its 8 children (the 8 block corners
-// are never part of a child's 19-point stencil and are not loaded).
+// FAS restriction fused with the residual, for one coarse cell (I, J, K): the
+// mean of its 8 children's phi and 4 x the mean of their residuals s - L[phi],
+// from the 4x4x4 block of fine values around the children (the 8 block
+// corners are never part of a child's 19-point stencil and are not loaded).
 template <bool PER>
-__global__ void __launch_bounds__(kBlock)
-k_restrict_residual(const double *__restrict__ phi_f, const double *__restrict__ s_f,
-                    Ix<PER> ixf, double al_f, double *__restrict__ hat_c,
-                    double *__restrict__ s_c, Ix<PER> ixc) {
-    const int nc = ixc.n, lgc = ixc.lg, nf = ixf.n;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= (1 << (3 * lgc))) return;
-    const int I = t & (nc - 1), J = (t >> lgc) & (nc - 1), K = t >> (2 * lgc);
+__device__ __forceinline__ void restrict_cell(const double *__restrict__ phi_f,
+                                              const double *__restrict__ s_f, const Ix<PER> &ixf,
+                                              int nf, double al_f, int I, int J, int K,
+                                              double &hat, double &sc) {
     const int i0 = 2 * I - 1, j0 = 2 * J - 1, k0 = 2 * K - 1;
     double b[4][4][4];
 #pragma unroll
@@ -426,8 +423,24 @@ k_restrict_residual(const double *__restrict__ phi_f, const double *__restrict__
                 sphi += v[0];
                 sr += r;
             }
-    hat_c[ixc(I, J, K)] = sphi * 0.125;
-    s_c[t] = sr * 0.5; // 4 * mean: the coarse cell is twice as wide
+    hat = sphi * 0.125;
+    sc = sr * 0.5; // 4 * mean: the coarse cell is twice as wide
+}
+
+// one thread per coarse cell
+template <bool PER>
+__global__ void __launch_bounds__(kBlock)
+k_restrict_residual(const double *__restrict__ phi_f, const double *__restrict__ s_f,
+                    Ix<PER> ixf, double al_f, double *__restrict__ hat_c,
+                    double *__restrict__ s_c, Ix<PER> ixc) {
+    const int nc = ixc.n, lgc = ixc.lg;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (1 << (3 * lgc))) return;
+    const int I = t & (nc - 1), J = (t >> lgc) & (nc - 1), K = t >> (2 * lgc);
+    double hat, sc;
+    restrict_cell(phi_f, s_f, ixf, ixf.n, al_f, I, J, K, hat, sc);
+    hat_c[ixc(I, J, K)] = hat;
+    s_c[t] = sc;
 }
 
 template <bool PER>
@@ -615,6 +628,143 @@ k_coarsest(double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix, d
         }
     }
     for (int q = threadIdx.x; q < slots; q += blockDim.x) phi[q] = A[q];
+    if (fb) atomicAdd(fallbacks, fb);
+}
+
+// The bottom of a periodic V-cycle in one workgroup: every level from one of
+// at most 16^3 cells down to the coarsest, with all its arrays in LDS, so
+// that the small levels cost one launch instead of about a dozen per cycle.
+// Each step has exactly the arithmetic, in the same order, of the per-level
+// kernels (k_smooth_half, k_restrict_residual, k_coarse_source, k_coarsest,
+// k_prolong), so the result is bit for bit the one of those launches.  A
+// half sweep computes the new values of its colour into registers, waits for
+// the whole workgroup, then stores them: every read sees the values of the
+// start of the half sweep, as with the out-of-place kernels.
+constexpr int kBottomThreads = 1024;
+constexpr int kBottomCells = 4096 + 512 + 64 + 8; // 16^3 + 8^3 + 4^3 + 2^3
+
+__global__ void __launch_bounds__(kBottomThreads)
+k_bottom(double *__restrict__ phi, const double *__restrict__ s, int lg0, BottomLevels bl,
+         int nu1, int nu2, int csweeps, unsigned *__restrict__ fallbacks) {
+    __shared__ double PHI[kBottomCells];
+    __shared__ double SRC[kBottomCells];
+    __shared__ double HAT[kBottomCells - 4096];
+    const int tid = threadIdx.x;
+    const int nb = bl.levels;
+    // level q starts at off(q) in PHI and SRC, at hoff(q) in HAT (q >= 1)
+    auto off = [&](int q) {
+        int o = 0;
+        for (int p = 0; p < q; ++p) o += 1 << (3 * (lg0 - p));
+        return o;
+    };
+    auto hoff = [&](int q) { return off(q) - (1 << (3 * lg0)); };
+    auto alpha = [&](int q) {
+        return q == 0 ? bl.alpha[0] : q == 1 ? bl.alpha[1] : q == 2 ? bl.alpha[2] : bl.alpha[3];
+    };
+    unsigned fb = 0;
+    const int cells0 = 1 << (3 * lg0);
+    for (int t = tid; t < cells0; t += kBottomThreads) {
+        PHI[t] = phi[t];
+        SRC[t] = s[t];
+    }
+    __syncthreads();
+
+    auto smooth = [&](int q, int sweeps) {
+        const int lg = lg0 - q, n = 1 << lg, half = n >> 1;
+        const Ix<true> ix = {n, lg, n + 2};
+        double *ph = PHI + off(q);
+        const double *sr = SRC + off(q);
+        const double al = alpha(q);
+        const int ncol = (n * n * n) >> 1; // cells of one colour: at most 2 per thread
+        // new value of the t-th cell of colour col, or at = -1 past the last
+        auto cell = [&](int t, int col, double &val, int &at) {
+            at = -1;
+            if (t >= ncol) return;
+            const int m = t & (half - 1);
+            const int row = t >> (lg - 1);
+            const int j = row & (n - 1), k = row >> lg;
+            const int i = 2 * m + ((col ^ j ^ k) & 1);
+            double v[19];
+            gather(ph, ix, i, j, k, v);
+            val = relax_cell(v, sr[((k << lg) + j) * n + i], al, fb);
+            at = ix(i, j, k);
+        };
+        for (int sw = 0; sw < sweeps; ++sw)
+            for (int col = 0; col < 2; ++col) {
+                double v0 = 0.0, v1 = 0.0;
+                int a0, a1;
+                cell(tid, col, v0, a0);
+                __builtin_amdgcn_sched_barrier(0); // one cell at a time: no spills
+                cell(tid + kBottomThreads, col, v1, a1);
+                __syncthreads();
+                if (a0 >= 0) ph[a0] = v0;
+                if (a1 >= 0) ph[a1] = v1;
+                __syncthreads();
+            }
+    };
+
+    for (int q = 0; q + 1 < nb; ++q) {
+        smooth(q, nu1);
+        const int lgf = lg0 - q, lgc = lgf - 1, nc = 1 << lgc;
+        const Ix<true> ixf = {1 << lgf, lgf, (1 << lgf) + 2};
+        const Ix<true> ixc = {nc, lgc, nc + 2};
+        double *hc = HAT + hoff(q + 1), *sc = SRC + off(q + 1), *pc = PHI + off(q + 1);
+        for (int t = tid; t < nc * nc * nc; t += kBottomThreads) {
+            const int I = t & (nc - 1), J = (t >> lgc) & (nc - 1), K = t >> (2 * lgc);
+            // restrict_cell's sums, each child's stencil gathered on its own
+            const double *pf = PHI + off(q), *sf = SRC + off(q);
+            const int nf = 1 << lgf;
+            double sphi = 0.0, sr = 0.0;
+#pragma unroll 1
+            for (int ch = 0; ch < 8; ++ch) {
+                const int fi = 2 * I + (ch & 1), fj = 2 * J + ((ch >> 1) & 1),
+                          fk = 2 * K + (ch >> 2);
+                double v[19];
+                gather(pf, ixf, fi, fj, fk, v);
+                const double r = sf[(fk * nf + fj) * nf + fi] - apply_L(stencil_terms(v), alpha(q));
+                sphi += v[0];
+                sr += r;
+            }
+            hc[t] = sphi * 0.125;
+            sc[t] = sr * 0.5;
+        }
+        __syncthreads();
+        for (int t = tid; t < nc * nc * nc; t += kBottomThreads) {
+            const int i = t & (nc - 1), j = (t >> lgc) & (nc - 1), k = t >> (2 * lgc);
+            double v[19];
+            gather(hc, ixc, i, j, k, v);
+            sc[t] = apply_L(stencil_terms(v), alpha(q + 1)) + sc[t];
+            pc[t] = v[0];
+        }
+        __syncthreads();
+    }
+    smooth(nb - 1, csweeps);
+    for (int q = nb - 2; q >= 0; --q) {
+        const int lgf = lg0 - q, nf = 1 << lgf, lgc = lgf - 1, nc = 1 << lgc;
+        const Ix<true> ixc = {nc, lgc, nc + 2};
+        const double *pc = PHI + off(q + 1), *hc = HAT + hoff(q + 1);
+        double *pf = PHI + off(q);
+        for (int t = tid; t < nf * nf * nf; t += kBottomThreads) {
+            const int i = t & (nf - 1), j = (t >> lgf) & (nf - 1), k = t >> (2 * lgf);
+            const int I = i >> 1, J = j >> 1, K = k >> 1;
+            const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (c ? 0.25 : 0.75);
+                        const int qq = ixc(I + a * si, J + b * sj, K + c * sk);
+                        acc = fma(w, pc[qq] - hc[qq], acc);
+                    }
+            pf[t] = pf[t] + acc;
+        }
+        __syncthreads();
+        smooth(q, nu2);
+    }
+    for (int t = tid; t < cells0; t += kBottomThreads) phi[t] = PHI[t];
     if (fb) atomicAdd(fallbacks, fb);
 }
 
@@ -834,6 +984,22 @@ void launch_coarsest(const Level &L, int sweeps, unsigned *fallbacks, hipStream_
     else
         k_coarsest<false><<<1, threads, 0, st>>>(L.phi, L.s, make_ix<false>(L.n, L.lg), L.alpha,
                                                  sweeps, fallbacks, L.hat, L.dyn_bc ? 1 : 0);
+}
+
+bool bottom_ok(const Level *H, int l, int nl) {
+    if (l + 1 >= nl || nl - l > kBottomMaxLevels) return false;
+    for (int q = l; q < nl; ++q)
+        if (!H[q].periodic) return false;
+    return H[l].n <= 16 && H[nl - 1].n >= 2;
+}
+
+void launch_bottom(const Level *H, int l, int nl, int nu1, int nu2, int csweeps,
+                   unsigned *fallbacks, hipStream_t st) {
+    BottomLevels bl{};
+    bl.levels = nl - l;
+    for (int q = 0; q < bl.levels; ++q) bl.alpha[q] = H[l + q].alpha;
+    k_bottom<<<1, kBottomThreads, 0, st>>>(H[l].phi, H[l].s, H[l].lg, bl, nu1, nu2, csweeps,
+                                           fallbacks);
 }
 
 void launch_source(const double *delta, size_t count, const double *sum, double inv_count_mean,

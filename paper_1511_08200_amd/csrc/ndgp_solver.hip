@@ -437,6 +437,10 @@ struct Runner {
             launch_coarsest(L, kCoarsestSweeps, P.fallbacks, st);
             return;
         }
+        if (!(P.c.flags & NDGP_TWO_PASS) && bottom_ok(H, l, nl)) {
+            launch_bottom(H, l, nl, P.c.nu1, P.c.nu2, kCoarsestSweeps, P.fallbacks, st);
+            return;
+        }
         smooth(L, P.c.nu1);
         Level &C = H[l + 1];
         launch_restrict_residual(L, C, st);

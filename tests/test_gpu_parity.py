@@ -157,16 +157,20 @@ def test_scale_law_bitwise_and_determinism():
     assert np.array_equal(p3, p1)
 
 
-@pytest.mark.parametrize("n", [128, 256])
-def test_fused_sweep_bitwise_equals_two_pass(n):
-    """The one-launch LDS sweep and the one-colour-per-launch kernels give the
-    same bits for the whole solve."""
-    say(f"fused vs two-pass n={n}")
+@pytest.mark.parametrize("n,levels", [(16, 0), (32, 0), (64, 0), (64, 5), (64, 6), (128, 0),
+                                      (256, 0)])
+def test_fused_kernels_bitwise_equal_per_level_launches(n, levels):
+    """The one-launch LDS sweep (n >= 128) and the one-workgroup bottom of the
+    V-cycle (levels of at most 16^3, coarsest 8^3, 4^3 or 2^3) give the same
+    bits for the whole solve as one launch per colour, per transfer and per
+    level."""
+    say(f"fused vs per-level launches n={n} levels={levels}")
     f = synth.make_field(n, 2.0, 31, n_tophats=10)
     grid = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n))
     d = dev(f.delta)
-    a, ra = ndgp.solve(grid, ndgp.Params(rc=1.0, tol=1e-10), [d])
-    b, rb = ndgp.solve(grid, ndgp.Params(rc=1.0, tol=1e-10, two_pass=True), [d])
+    a, ra = ndgp.solve(grid, ndgp.Params(rc=1.0, tol=1e-10, n_levels=levels), [d])
+    b, rb = ndgp.solve(grid, ndgp.Params(rc=1.0, tol=1e-10, n_levels=levels, two_pass=True),
+                       [d])
     torch.cuda.synchronize()
     assert ra.cycles == rb.cycles and ra.history == rb.history
     assert torch.equal(a[0], b[0])
