@@ -61,6 +61,11 @@ void launch_smooth_half(const Level &L, const double *pin, double *pout, int col
 bool fused_sweep_ok(const Level &L);
 void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
                         hipStream_t st);
+// The same sweep starting from pin + P(C.phi - C.hat) (the coarse-grid
+// correction, added on load): bit for bit launch_prolong_correct followed by
+// launch_sweep_fused.
+void launch_sweep_fused_prolong(const Level &L, const Level &C, const double *pin, double *pout,
+                                unsigned *fallbacks, hipStream_t st);
 // Per-block partial sums of r^2, r = s - L[phi]; optionally r_out = r * scale.
 void launch_residual_sumsq(const Level &L, double *partials, double *r_out, double r_scale,
                            hipStream_t st);

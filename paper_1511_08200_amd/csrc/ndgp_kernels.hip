@@ -55,36 +55,46 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
 // One full red-black sweep of a periodic level in one launch, with the same
 // semantics as two k_smooth_half launches (colour 0 from pin, then colour 1
 // from that result; same-colour neighbours always at their pass-start
-// values), bit for bit.
+// values), bit for bit.  With PRO the sweep starts from pin plus the
+// interpolated coarse-grid correction P(phi_c - hat_c), added as each old
+// value is loaded, with the arithmetic of k_prolong8: the same bits as a
+// k_prolong8 launch followed by the sweep, without the extra pass over HBM.
 //
 // A workgroup owns a TX x TY column of the x-y plane over TZ planes and
 // streams along z.  LDS keeps every plane split by colour, so that lanes
 // working on consecutive cells of one colour touch consecutive words (no
 // bank conflicts):
-//   P: the old field, tile + 2-cell halo, planes k-1 .. k+2 (+1 being filled);
-//   R: red cells after the red pass, planes k-1 .. k+1.
+//   PR, PB: the old field's red and black cells, tile + 2-cell halo, red on
+//           planes k .. k+2, black on planes k-2 .. k+2;
+//   R:  red cells after the red pass, planes k-1 .. k+1;
+//   E:  (PRO) the coarse correction under the tile, three coarse planes.
 // Step k relaxes the red cells of plane k+1 over the tile plus a 1-cell halo
 // (the black cells at the tile's edge need them), then the black cells of
-// plane k over the tile (red neighbours from R, black ones from P), and
+// plane k over the tile (red neighbours from R, black ones from PB), and
 // writes plane k.  The next old plane is read into registers meanwhile.  HBM
 // sees each old value and each source value once and each new value once:
-// 24 bytes per cell and sweep; tiles are ordered per XCD so that their halo
-// lines are shared in L2.
-template <int TX, int TY, int TZ, int NT>
+// 24 bytes per cell and sweep (PRO: + 2 x 8 bytes per coarse cell); tiles
+// are ordered per XCD so that their halo lines are shared in L2.
+template <int TX, int TY, int TZ, int NT, bool PRO>
 __global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(4))) // two workgroups per CU: at most 128 VGPRs
 k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
-              const double *__restrict__ s, int lg, double al, unsigned *__restrict__ fallbacks) {
+              const double *__restrict__ s, int lg, double al, unsigned *__restrict__ fallbacks,
+              const double *__restrict__ phi_c, const double *__restrict__ hat_c) {
     constexpr int PX = TX + 4, PY = TY + 4;   // plane with halo 2
     constexpr int HX = PX / 2;                // cells of one colour per row
     constexpr int PLANE = PX * PY;
-    constexpr int HALF = HX * PY;             // one colour of one plane
     constexpr int PRE = (PLANE + NT - 1) / NT;
     constexpr int RED_ROW = (TX + 2) / 2;     // red cells per row of the halo-1 region
     constexpr int RED_CELLS = RED_ROW * (TY + 2);
+    constexpr int EX = TX / 2 + 4, EY = TY / 2 + 4; // coarse cells under the plane, +-1
     static_assert(TX % 2 == 0 && TY % 2 == 0 && TX * TY / 2 == NT, "one black cell per thread");
     static_assert(RED_CELLS <= 2 * NT, "at most two red cells per thread");
-    __shared__ double P[5][2][PY][HX];
+    static_assert(EX * EY <= NT, "one coarse value per thread");
+    __shared__ double PR[3][PY][HX];
+    __shared__ double PB[5][PY][HX];
     __shared__ double R[3][PY][HX];
+    __shared__ double E[PRO ? 3 : 1][EY * EX];
 
     const int n = 1 << lg, m = n - 1;
     const int ntx = n / TX;
@@ -98,11 +108,13 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     unsigned fb = 0;
 
     auto zoff = [&](int z) { return (z & m) << (2 * lg); };
-    auto pslot = [](int z) { return (z + 5 * 4096) % 5; };
-    auto rslot = [](int z) { return (z + 3 * 4096) % 3; };
+    auto s5 = [](int z) { return (z + 5 * 4096) % 5; };
+    auto s3 = [](int z) { return (z + 3 * 4096) % 3; };
 
-    // this thread's share of a plane: global x-y offset, LDS split position
-    int pxy[PRE], pidx[PRE], ppar[PRE];
+    // this thread's share of a plane: global x-y offset, LDS split position,
+    // and (PRO) its coarse cell in E with the steps towards the neighbours
+    // on its side
+    int pxy[PRE], pidx[PRE], ppar[PRE], eat[PRE], edx[PRE], edy[PRE];
 #pragma unroll
     for (int e = 0; e < PRE; ++e) {
         const int q = tid + e * NT;
@@ -110,6 +122,10 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         pxy[e] = (((y0 - 2 + r) & m) << lg) | ((x0 - 2 + c) & m);
         pidx[e] = q < PLANE ? r * HX + (c >> 1) : -1;
         ppar[e] = (c + r) & 1; // colour = ppar ^ (z & 1)  (x0, y0 even)
+        // fine x0-2+c lies in coarse cell x0/2-1+(c>>1), E column (c>>1)+1
+        eat[e] = ((r >> 1) + 1) * EX + (c >> 1) + 1;
+        edx[e] = (c & 1) ? 1 : -1;
+        edy[e] = (r & 1) ? EX : -EX;
     }
     double pre[PRE];
     auto fetch = [&](int z) {
@@ -119,11 +135,51 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
             if (pidx[e] >= 0) pre[e] = pin[zo | pxy[e]];
     };
     auto commit = [&](int z) {
-        double *base = &P[pslot(z)][0][0][0];
+        double *red = &PR[s3(z)][0][0], *blk = &PB[s5(z)][0][0];
         const int zp = z & 1;
+        const double *e0 = nullptr, *e1 = nullptr;
+        if constexpr (PRO) {
+            const int K = z >> 1, sk = (z & 1) ? 1 : -1; // parent plane, neighbour side
+            e0 = E[s3(K)];
+            e1 = E[s3(K + sk)];
+        }
 #pragma unroll
         for (int e = 0; e < PRE; ++e)
-            if (pidx[e] >= 0) base[(ppar[e] ^ zp) * HALF + pidx[e]] = pre[e];
+            if (pidx[e] >= 0) {
+                double v = pre[e];
+                if constexpr (PRO) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int cz = 0; cz < 2; ++cz) {
+                        const double *ep = cz ? e1 : e0;
+#pragma unroll
+                        for (int b = 0; b < 2; ++b)
+#pragma unroll
+                            for (int a = 0; a < 2; ++a) {
+                                const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (cz ? 0.25 : 0.75);
+                                acc = fma(w, ep[eat[e] + b * edy[e] + a * edx[e]], acc);
+                            }
+                    }
+                    v = v + acc;
+                }
+                ((ppar[e] ^ zp) ? blk : red)[pidx[e]] = v;
+            }
+    };
+    // (PRO) coarse plane K of the correction: loaded into registers, then
+    // stored into its E slot
+    const int nc = n >> 1, mc = nc - 1, lgc = lg - 1;
+    const int eq = PRO && tid < EX * EY ? tid : -1;
+    const int exy = (((y0 / 2 - 2 + tid / EX) & mc) << lgc) | ((x0 / 2 - 2 + tid % EX) & mc);
+    double ea = 0.0, eb = 0.0;
+    auto e_load = [&](int K) {
+        if (eq >= 0) {
+            const int q = ((K & mc) << (2 * lgc)) | exy;
+            ea = phi_c[q];
+            eb = hat_c[q];
+        }
+    };
+    auto e_store = [&](int K) {
+        if (eq >= 0) E[s3(K)][eq] = ea - eb;
     };
 
     // red cells of the halo-1 region: thread slot e covers q = tid + e * NT
@@ -149,10 +205,10 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     };
     // red cells of plane z over the tile + 1-cell halo -> R(z)
     auto red_plane = [&](int z, const double src[2]) {
-        const double(*m0)[HX] = P[pslot(z - 1)][0], (*m1)[HX] = P[pslot(z - 1)][1];
-        const double(*c0)[HX] = P[pslot(z)][0], (*c1)[HX] = P[pslot(z)][1];
-        const double(*p0)[HX] = P[pslot(z + 1)][0], (*p1)[HX] = P[pslot(z + 1)][1];
-        double(*rz)[HX] = R[rslot(z)];
+        const double(*m0)[HX] = PR[s3(z - 1)], (*m1)[HX] = PB[s5(z - 1)];
+        const double(*c0)[HX] = PR[s3(z)], (*c1)[HX] = PB[s5(z)];
+        const double(*p0)[HX] = PR[s3(z + 1)], (*p1)[HX] = PB[s5(z + 1)];
+        double(*rz)[HX] = R[s3(z)];
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             if (!red_on[e]) continue;
@@ -179,10 +235,8 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         return s[zoff(k) | xy_t | pb];
     };
     auto black_and_store = [&](int k, double sv) {
-        const double(*rm)[HX] = R[rslot(k - 1)], (*r0)[HX] = R[rslot(k)],
-                     (*rp)[HX] = R[rslot(k + 1)];
-        const double(*m1)[HX] = P[pslot(k - 1)][1], (*c1)[HX] = P[pslot(k)][1],
-                     (*p1)[HX] = P[pslot(k + 1)][1];
+        const double(*rm)[HX] = R[s3(k - 1)], (*r0)[HX] = R[s3(k)], (*rp)[HX] = R[s3(k + 1)];
+        const double(*m1)[HX] = PB[s5(k - 1)], (*c1)[HX] = PB[s5(k)], (*p1)[HX] = PB[s5(k + 1)];
         const int pb = (1 + rt + k) & 1; // black cell at column 2jt + pb
         const int j = jt, rr = rt, a = j + pb, b = j + pb - 1;
         const double v[19] = {
@@ -198,10 +252,17 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         dst[1] = pb ? vb : vr;
     };
 
-    // planes needed: P z0-2 .. z0+TZ+1, R z0-1 .. z0+TZ.  Source values are
-    // loaded a step ahead and before the next plane's field values, so that
-    // waiting for them never waits for the prefetch as well; the loop is
-    // unrolled by two so that no loaded register is copied (a copy would wait).
+    // Planes needed: old z0-2 .. z0+TZ+1 (black) / z0-1 .. z0+TZ+1 (red), R
+    // z0-1 .. z0+TZ; with PRO the coarse planes z0/2-2 .. z0/2+TZ/2+1.  Old
+    // plane z needs coarse planes z/2-1, z/2 (z even) or (z-1)/2, (z+1)/2.
+    const int c0 = z0 >> 1;
+    if constexpr (PRO) {
+        for (int K = c0 - 2; K <= c0; ++K) {
+            e_load(K);
+            e_store(K);
+        }
+        __syncthreads();
+    }
     fetch(z0 - 2);
     commit(z0 - 2);
     fetch(z0 - 1);
@@ -211,33 +272,45 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     double ra[2], rb[2], ba, bb;
     red_sources(z0 - 1, ra);
     fetch(z0 + 1);
+    if constexpr (PRO) e_load(c0 + 1);
     __syncthreads();
     red_plane(z0 - 1, ra);
+    __syncthreads(); // red(z0-1) has read the red slot that plane z0+1 takes
+    if constexpr (PRO) {
+        e_store(c0 + 1); // the slot of coarse plane c0-2, last used by plane z0-2
+        __syncthreads();
+    }
     commit(z0 + 1);
     red_sources(z0, ra);
     fetch(z0 + 2);
     __syncthreads();
     red_plane(z0, ra);
+    __syncthreads(); // red(z0) has read the red slot that plane z0+2 takes
     red_sources(z0 + 1, ra);
     ba = black_source(z0);
+    if constexpr (PRO) e_load(c0 + 2);
     // one step: red(k+1), black(k); loads the sources of red(k+2), black(k+1)
     // and the field of plane k+3 (on the last step one plane past the ones
-    // used: in bounds, never committed)
-    auto step = [&](int k, const double (&use_r)[2], double use_b, double (&next_r)[2],
-                    double &next_b) {
-        commit(k + 2); // the slot of plane k-3: last read by black(k-2) and red(k-2)
+    // used: in bounds, never committed).  With PRO an even step stores
+    // coarse plane k/2+2 (first needed by plane k+3, in the slot of plane
+    // k/2-1, last needed by plane k) and an odd step loads the next one.
+    auto step = [&](int k, bool even, const double (&use_r)[2], double use_b,
+                    double (&next_r)[2], double &next_b) {
+        commit(k + 2); // red slot of plane k-1 (last read by red(k)), black of k-3
         red_sources(k + 2, next_r);
         next_b = black_source(k + 1);
+        if (PRO && !even) e_load((k + 1) / 2 + 2);
         fetch(k + 3);
         __syncthreads();
+        if (PRO && even) e_store(k / 2 + 2);
         red_plane(k + 1, use_r); // writes the R slot of plane k-2, last read by black(k-1)
         __syncthreads();
         black_and_store(k, use_b);
     };
     static_assert(TZ % 2 == 0, "the z loop is unrolled by two");
     for (int k = z0; k < z0 + TZ; k += 2) {
-        step(k, ra, ba, rb, bb);
-        step(k + 1, rb, bb, ra, ba);
+        step(k, true, ra, ba, rb, bb);
+        step(k + 1, false, rb, bb, ra, ba);
     }
     if (fb) atomicAdd(fallbacks, fb);
 }
@@ -875,19 +948,30 @@ void launch_smooth_half(const Level &L, const double *pin, double *pout, int col
 
 bool fused_sweep_ok(const Level &L) { return L.periodic && L.n >= 128; }
 
-void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
-                        hipStream_t st) {
+template <bool PRO>
+void sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
+                 const double *phi_c, const double *hat_c, hipStream_t st) {
     constexpr int TX = 64, TY = 16, NT = 512;
     const int tiles = (L.n / TX) * (L.n / TY);
     if (L.n >= 256) {
         constexpr int TZ = 32;
-        k_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
-                                                                          L.alpha, fallbacks);
+        k_sweep_fused<TX, TY, TZ, NT, PRO><<<tiles * (L.n / TZ), NT, 0, st>>>(
+            pin, pout, L.s, L.lg, L.alpha, fallbacks, phi_c, hat_c);
     } else { // 128^3: short chunks, enough workgroups to fill the chip
         constexpr int TZ = 8;
-        k_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(pin, pout, L.s, L.lg,
-                                                                          L.alpha, fallbacks);
+        k_sweep_fused<TX, TY, TZ, NT, PRO><<<tiles * (L.n / TZ), NT, 0, st>>>(
+            pin, pout, L.s, L.lg, L.alpha, fallbacks, phi_c, hat_c);
     }
+}
+
+void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
+                        hipStream_t st) {
+    sweep_fused<false>(L, pin, pout, fallbacks, nullptr, nullptr, st);
+}
+
+void launch_sweep_fused_prolong(const Level &L, const Level &C, const double *pin, double *pout,
+                                unsigned *fallbacks, hipStream_t st) {
+    sweep_fused<true>(L, pin, pout, fallbacks, C.phi, C.hat, st);
 }
 
 void launch_residual_sumsq(const Level &L, double *partials, double *r_out, double r_scale,

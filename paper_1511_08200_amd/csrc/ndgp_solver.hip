@@ -409,24 +409,34 @@ struct Runner {
 
     // `sweeps` red-black sweeps; the iterate ends in the buffer it started in
     // (the fused kernel swaps once per sweep, so an odd last sweep takes the
-    // two-launch path, which swaps twice).
-    void smooth(Level &L, int sweeps) {
+    // two-launch path, which swaps twice).  With C the coarse-grid correction
+    // from C is added first: on load in the first fused sweep, else by its
+    // own launch.
+    void smooth(Level &L, int sweeps, const Level *C = nullptr) {
         const bool fused = !(P.c.flags & NDGP_TWO_PASS) && fused_sweep_ok(L);
         const int nf = fused ? (sweeps & ~1) : 0;
+        int s = 0;
+        if (C && nf == 0) launch_prolong_correct(L, *C, st);
+        if (C && nf > 0) {
+            launch_sweep_fused_prolong(L, *C, L.phi, L.alt, P.fallbacks, st);
+            std::swap(L.phi, L.alt);
+            s = 1;
+        }
+        // the timed launches: plain fused sweeps (or half sweeps) only
         const bool timed = timer && timer->on && L.s == timed_s;
         if (timed) timer->mark(st);
-        for (int s = 0; s < nf; ++s) {
+        for (; s < nf; ++s) {
             launch_sweep_fused(L, L.phi, L.alt, P.fallbacks, st);
             std::swap(L.phi, L.alt);
         }
-        for (int s = nf; s < sweeps; ++s)
+        for (s = nf; s < sweeps; ++s)
             for (int col = 0; col < 2; ++col) {
                 launch_smooth_half(L, L.phi, L.alt, col, P.fallbacks, st);
                 std::swap(L.phi, L.alt);
             }
         if (timed) {
             timer->mark(st);
-            timer->launches += nf + 2 * (sweeps - nf);
+            timer->launches += (C && nf > 0 ? nf - 1 : nf) + 2 * (sweeps - nf);
             timer->cells_per_launch = nf ? L.cells() : L.cells() / 2;
         }
     }
@@ -446,8 +456,7 @@ struct Runner {
         launch_restrict_residual(L, C, st);
         launch_coarse_source(C, st);
         vcycle(H, nl, l + 1);
-        launch_prolong_correct(L, C, st);
-        smooth(L, P.c.nu2);
+        smooth(L, P.c.nu2, &C);
     }
 
     // Initial guess by nested iteration: average the source down, solve the
