@@ -90,8 +90,9 @@ typedef enum {
                               otherwise the guess comes from nested iteration */
 #define NDGP_PROFILE 2u    /* time the domain level's relaxation sweeps with HIP
                               events on `stream` (ndgp_report.t_smooth_ms) */
-#define NDGP_TWO_PASS 4u   /* one launch per colour, per transfer and per level:
-                              no fused one-launch sweep on large levels and no
+#define NDGP_TWO_PASS 4u   /* one launch per colour, per transfer and per level,
+                              one thread per cell: no fused one-launch sweep or
+                              LDS-tiled restriction on large levels and no
                               one-workgroup bottom of the V-cycle on levels of
                               at most 16^3 cells; same results, bit for bit */
 

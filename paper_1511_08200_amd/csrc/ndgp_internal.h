@@ -75,7 +75,8 @@ void launch_partial_sums(const double *a, size_t count, bool squares, double *pa
 // out[0] = sum of the kReduceBlocks partials, in a fixed order.
 void launch_reduce_final(const double *partials, double *out, hipStream_t st);
 // FAS restriction: C.hat = mean of children of F.phi; C.s = 4 * mean of children residuals.
-void launch_restrict_residual(const Level &F, const Level &C, hipStream_t st);
+// tiled: through LDS on periodic levels of n >= 128 (same bits).
+void launch_restrict_residual(const Level &F, const Level &C, bool tiled, hipStream_t st);
 // FAS coarse source C.s = L_C[C.hat] + C.s; C.phi = C.hat (interior).
 void launch_coarse_source(const Level &C, hipStream_t st);
 // F.phi += trilinear(C.phi - C.hat)

@@ -315,6 +315,92 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     if (fb) atomicAdd(fallbacks, fb);
 }
 
+// FAS restriction with the residual on a large periodic level, through LDS:
+// a workgroup streams a TX x TY fine column along z over tz planes (tz even)
+// as k_residual_tiled does, and each thread owns one coarse cell of the
+// tile, whose 4 children in a fine plane it finishes per step.  Per coarse
+// cell the sums run over the children in restrict_cell's order, so the
+// coarse values are bit for bit k_restrict_residual's.
+template <int TX, int TY>
+__global__ void __launch_bounds__(kBlock)
+k_restrict_tiled(const double *__restrict__ phi, const double *__restrict__ s, int lg, int tz,
+                 double al, double *__restrict__ hat_c, double *__restrict__ s_c) {
+    constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
+    constexpr int PRE = (PLANE + kBlock - 1) / kBlock;
+    static_assert(TX * TY == 4 * kBlock, "one coarse cell per thread");
+    __shared__ double P[4][PLANE];
+    const int n = 1 << lg, m = n - 1, lgc = lg - 1;
+    const int ntx = n / TX;
+    const int tiles = ntx * (n / TY);
+    const int logical = xcd_local_id(blockIdx.x, gridDim.x);
+    const int tile = logical % tiles;
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY, z0 = (logical / tiles) * tz;
+    const int tid = threadIdx.x;
+    int pq[PRE], pxy[PRE];
+#pragma unroll
+    for (int e = 0; e < PRE; ++e) {
+        const int q = tid + e * kBlock;
+        pq[e] = q < PLANE ? q : -1;
+        const int yy = q / PX, xx = q - yy * PX;
+        pxy[e] = (((y0 - 1 + yy) & m) << lg) | ((x0 - 1 + xx) & m);
+    }
+    double pre[PRE];
+    auto fetch = [&](int z) {
+        const int zo = (z & m) << (2 * lg);
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pq[e] >= 0) pre[e] = phi[zo | pxy[e]];
+    };
+    auto commit = [&](int z) {
+        double *dst = P[z & 3];
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pq[e] >= 0) dst[pq[e]] = pre[e];
+    };
+    // this thread's coarse cell: (x0/2 + ic, y0/2 + jc); children 2ic + ci, 2jc + cj
+    const int ic = tid % (TX / 2), jc = tid / (TX / 2);
+    double sphi = 0.0, sr = 0.0;
+    fetch(z0 - 1);
+    commit(z0 - 1);
+    fetch(z0);
+    commit(z0);
+    fetch(z0 + 1);
+    for (int k = z0; k < z0 + tz; ++k) {
+        commit(k + 1); // slot of plane k-3, last read at step k-2
+        if (k + 2 <= z0 + tz) fetch(k + 2);
+        __syncthreads();
+        const double(*pm)[PX] = reinterpret_cast<const double(*)[PX]>(P[(k - 1) & 3]);
+        const double(*p0)[PX] = reinterpret_cast<const double(*)[PX]>(P[k & 3]);
+        const double(*pp)[PX] = reinterpret_cast<const double(*)[PX]>(P[(k + 1) & 3]);
+        if ((k & 1) == 0) {
+            sphi = 0.0;
+            sr = 0.0;
+        }
+#pragma unroll
+        for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+            for (int ci = 0; ci < 2; ++ci) {
+                const int xt = 2 * ic + ci, yt = 2 * jc + cj;
+                const int rr = yt + 1, c = xt + 1;
+                const double v[19] = {
+                    p0[rr][c], p0[rr][c + 1], p0[rr][c - 1], p0[rr + 1][c], p0[rr - 1][c],
+                    pp[rr][c], pm[rr][c],
+                    p0[rr + 1][c + 1], p0[rr - 1][c + 1], p0[rr + 1][c - 1], p0[rr - 1][c - 1],
+                    pp[rr][c + 1], pm[rr][c + 1], pp[rr][c - 1], pm[rr][c - 1],
+                    pp[rr + 1][c], pm[rr + 1][c], pp[rr - 1][c], pm[rr - 1][c]};
+                const int g = ((k << lg | (y0 + yt)) << lg) | (x0 + xt);
+                const double r = s[g] - apply_L(stencil_terms(v), al);
+                sphi += v[0];
+                sr += r;
+            }
+        if (k & 1) {
+            const int q = (((k >> 1) << lgc | (y0 / 2 + jc)) << lgc) | (x0 / 2 + ic);
+            hat_c[q] = sphi * 0.125;
+            s_c[q] = sr * 0.5; // 4 * mean: the coarse cell is twice as wide
+        }
+    }
+}
+
 // Residual norm of a large periodic level through LDS: a workgroup streams a
 // TX x TY column along z over tz planes, holding four planes of phi with a
 // one-cell halo; each phi and S value is read from HBM about once.  One
@@ -1010,9 +1096,15 @@ void launch_reduce_final(const double *partials, double *out, hipStream_t st) {
     k_reduce_final<<<1, kBlock, 0, st>>>(partials, out);
 }
 
-void launch_restrict_residual(const Level &F, const Level &C, hipStream_t st) {
+void launch_restrict_residual(const Level &F, const Level &C, bool tiled, hipStream_t st) {
     const unsigned nb = blocks_for(C.cells());
-    if (F.periodic)
+    if (tiled && F.periodic && F.n >= 128) {
+        constexpr int TX = 64, TY = 16;
+        const int tz = F.n >= 256 ? 8 : 4; // 128^3: enough workgroups to fill the chip
+        const int tiles = (F.n / TX) * (F.n / TY);
+        k_restrict_tiled<TX, TY><<<tiles * (F.n / tz), kBlock, 0, st>>>(F.phi, F.s, F.lg, tz,
+                                                                       F.alpha, C.hat, C.s);
+    } else if (F.periodic)
         k_restrict_residual<true><<<nb, kBlock, 0, st>>>(F.phi, F.s, make_ix<true>(F.n, F.lg),
                                                          F.alpha, C.hat, C.s,
                                                          make_ix<true>(C.n, C.lg));

@@ -453,7 +453,7 @@ struct Runner {
         }
         smooth(L, P.c.nu1);
         Level &C = H[l + 1];
-        launch_restrict_residual(L, C, st);
+        launch_restrict_residual(L, C, !(P.c.flags & NDGP_TWO_PASS), st);
         launch_coarse_source(C, st);
         vcycle(H, nl, l + 1);
         smooth(L, P.c.nu2, &C);
