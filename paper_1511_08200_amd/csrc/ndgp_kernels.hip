@@ -1032,22 +1032,25 @@ void launch_smooth_half(const Level &L, const double *pin, double *pout, int col
                                                     L.dyn_bc ? 1 : 0);
 }
 
+// (on 32^3 and 64^3 the one-workgroup-per-tile pipeline is slower than two
+// short launches: its prologue latency is not amortised over enough planes)
 bool fused_sweep_ok(const Level &L) { return L.periodic && L.n >= 128; }
+
+template <int TX, int TY, int TZ, int NT, bool PRO>
+void sweep_fused_tiles(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
+                       const double *phi_c, const double *hat_c, hipStream_t st) {
+    const int tiles = (L.n / TX) * (L.n / TY);
+    k_sweep_fused<TX, TY, TZ, NT, PRO><<<tiles * (L.n / TZ), NT, 0, st>>>(
+        pin, pout, L.s, L.lg, L.alpha, fallbacks, phi_c, hat_c);
+}
 
 template <bool PRO>
 void sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
                  const double *phi_c, const double *hat_c, hipStream_t st) {
-    constexpr int TX = 64, TY = 16, NT = 512;
-    const int tiles = (L.n / TX) * (L.n / TY);
-    if (L.n >= 256) {
-        constexpr int TZ = 32;
-        k_sweep_fused<TX, TY, TZ, NT, PRO><<<tiles * (L.n / TZ), NT, 0, st>>>(
-            pin, pout, L.s, L.lg, L.alpha, fallbacks, phi_c, hat_c);
-    } else { // 128^3: short chunks, enough workgroups to fill the chip
-        constexpr int TZ = 8;
-        k_sweep_fused<TX, TY, TZ, NT, PRO><<<tiles * (L.n / TZ), NT, 0, st>>>(
-            pin, pout, L.s, L.lg, L.alpha, fallbacks, phi_c, hat_c);
-    }
+    if (L.n >= 256) // long z-chunks: the halo planes are a small share
+        sweep_fused_tiles<64, 16, 32, 512, PRO>(L, pin, pout, fallbacks, phi_c, hat_c, st);
+    else // 128^3: short chunks, enough workgroups to fill the chip
+        sweep_fused_tiles<64, 16, 8, 512, PRO>(L, pin, pout, fallbacks, phi_c, hat_c, st);
 }
 
 void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
