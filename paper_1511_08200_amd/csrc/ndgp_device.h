@@ -135,7 +135,10 @@ __device__ __forceinline__ double fast_sqrt(double d) {
     return d > 0.0 ? s1 : 0.0;
 }
 
-__device__ __forceinline__ double relax_cell(const double v[19], double s, double al,
+// New value of one cell: the root of its own quadratic with the neighbours
+// held, u + w * du.  w = 1 takes the root itself (w * r is then exactly r);
+// w < 1 damps the step, for the safeguarded iteration of the driver.
+__device__ __forceinline__ double relax_cell(const double v[19], double s, double al, double w,
                                              unsigned &fallbacks) {
     const Terms t = stencil_terms(v);
     const double r = apply_L(t, al) - s;
@@ -146,7 +149,7 @@ __device__ __forceinline__ double relax_cell(const double v[19], double s, doubl
         ++fallbacks;
         return v[0] + B / (18.0 * al);
     }
-    return fma(r, fast_rcp(B + fast_sqrt(D)), v[0]);
+    return fma(w * r, fast_rcp(B + fast_sqrt(D)), v[0]);
 }
 
 // Coarse levels of a refinement: write the ghosts whose correction is taken

@@ -25,6 +25,7 @@ struct Level {
     int lg = 0;            // log2(n)
     bool periodic = true;
     double alpha = 0.0;    // cell-unit coefficient of the nonlinear term
+    double omega = 1.0;    // step factor of the per-cell update (1: the root itself)
     double *phi = nullptr; // current iterate
     double *alt = nullptr; // ping-pong partner of phi (same layout, same ghosts)
     double *s = nullptr;   // source, natural n^3
@@ -78,7 +79,8 @@ void launch_reduce_final(const double *partials, double *out, hipStream_t st);
 // tiled: through LDS on periodic levels of n >= 128 (same bits).
 void launch_restrict_residual(const Level &F, const Level &C, bool tiled, hipStream_t st);
 // FAS coarse source C.s = L_C[C.hat] + C.s; C.phi = C.hat (interior).
-void launch_coarse_source(const Level &C, hipStream_t st);
+// tiled: through LDS on periodic levels of n >= 128 (same bits).
+void launch_coarse_source(const Level &C, bool tiled, hipStream_t st);
 // F.phi += trilinear(C.phi - C.hat)
 void launch_prolong_correct(const Level &F, const Level &C, hipStream_t st);
 // F.phi = trilinear(C.phi)    (periodic levels; nested-iteration start)
@@ -93,6 +95,7 @@ constexpr int kBottomMaxLevels = 4;
 struct BottomLevels {
     int levels;                       // l .. nl-1
     double alpha[kBottomMaxLevels];   // per level, cell units
+    double omega;                     // step factor of the per-cell update
 };
 bool bottom_ok(const Level *H, int l, int nl);
 void launch_bottom(const Level *H, int l, int nl, int nu1, int nu2, int csweeps,
@@ -129,6 +132,7 @@ namespace ndgp {
 struct Level32 {
     int n = 0, lg = 0;
     double alpha = 0.0;
+    double omega = 1.0; // step factor of the per-cell update (1: the root itself)
     float *phi = nullptr;
     float *e = nullptr;
     float *ealt = nullptr;

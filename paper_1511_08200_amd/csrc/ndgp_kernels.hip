@@ -25,7 +25,7 @@ using namespace dev;
 template <bool PER>
 __global__ void __launch_bounds__(kBlock)
 k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
-              const double *__restrict__ s, Ix<PER> ix, double al, int colour,
+              const double *__restrict__ s, Ix<PER> ix, double al, double w, int colour,
               unsigned *__restrict__ fallbacks, const double *__restrict__ hat, int dyn_bc) {
     const int n = ix.n, lg = ix.lg;
     const int half = n >> 1;
@@ -41,7 +41,7 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
     double v[19];
     gather(pin, ix, iu, j, k, v);
     unsigned fb = 0;
-    const double un = relax_cell(v, s[((k << lg) + j) * n + iu], al, fb);
+    const double un = relax_cell(v, s[((k << lg) + j) * n + iu], al, w, fb);
     const double uc = pin[ix(ic, j, k)];
     pout[ix(iu, j, k)] = un;
     pout[ix(ic, j, k)] = uc;
@@ -79,8 +79,9 @@ template <int TX, int TY, int TZ, int NT, bool PRO>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(4))) // two workgroups per CU: at most 128 VGPRs
 k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
-              const double *__restrict__ s, int lg, double al, unsigned *__restrict__ fallbacks,
-              const double *__restrict__ phi_c, const double *__restrict__ hat_c) {
+              const double *__restrict__ s, int lg, double al, double w,
+              unsigned *__restrict__ fallbacks, const double *__restrict__ phi_c,
+              const double *__restrict__ hat_c) {
     constexpr int PX = TX + 4, PY = TY + 4;   // plane with halo 2
     constexpr int HX = PX / 2;                // cells of one colour per row
     constexpr int PLANE = PX * PY;
@@ -222,7 +223,7 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
                 c0[rr + 1][a], c0[rr - 1][a], c0[rr + 1][b], c0[rr - 1][b],
                 p0[rr][a], m0[rr][a], p0[rr][b], m0[rr][b],
                 p0[rr + 1][j], m0[rr + 1][j], p0[rr - 1][j], m0[rr - 1][j]};
-            rz[rr][j] = relax_cell(v, src[e], al, fb);
+            rz[rr][j] = relax_cell(v, src[e], al, w, fb);
         }
     };
 
@@ -245,7 +246,7 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
             c1[rr + 1][a], c1[rr - 1][a], c1[rr + 1][b], c1[rr - 1][b],
             p1[rr][a], m1[rr][a], p1[rr][b], m1[rr][b],
             p1[rr + 1][j], m1[rr + 1][j], p1[rr - 1][j], m1[rr - 1][j]};
-        const double vb = relax_cell(v, sv, al, fb);
+        const double vb = relax_cell(v, sv, al, w, fb);
         const double vr = r0[rr][j]; // the red cell of the pair, column 2jt + 1 - pb
         double *dst = pout + (zoff(k) | xy_t);
         dst[0] = pb ? vr : vb;
@@ -397,6 +398,77 @@ k_restrict_tiled(const double *__restrict__ phi, const double *__restrict__ s, i
             const int q = (((k >> 1) << lgc | (y0 / 2 + jc)) << lgc) | (x0 / 2 + ic);
             hat_c[q] = sphi * 0.125;
             s_c[q] = sr * 0.5; // 4 * mean: the coarse cell is twice as wide
+        }
+    }
+}
+
+// FAS coarse source on a large periodic level, through LDS: s = L[hat] + s
+// and phi = hat, streaming hat planes with a one-cell halo as
+// k_residual_tiled does.  Same expression per cell as k_coarse_source, so the
+// same bits; hat is read from HBM about once instead of through 19 gathers.
+template <int TX, int TY>
+__global__ void __launch_bounds__(kBlock)
+k_coarse_source_tiled(const double *__restrict__ hat, double *__restrict__ phi,
+                      double *__restrict__ s, int lg, int tz, double al) {
+    constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
+    constexpr int PRE = (PLANE + kBlock - 1) / kBlock;
+    constexpr int CELLS = TX * TY / kBlock; // output cells per thread per plane
+    static_assert(TX * TY % kBlock == 0, "tile");
+    __shared__ double P[4][PLANE];
+    const int n = 1 << lg, m = n - 1;
+    const int ntx = n / TX;
+    const int tiles = ntx * (n / TY);
+    const int logical = xcd_local_id(blockIdx.x, gridDim.x);
+    const int tile = logical % tiles;
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY, z0 = (logical / tiles) * tz;
+    const int tid = threadIdx.x;
+    int pq[PRE], pxy[PRE];
+#pragma unroll
+    for (int e = 0; e < PRE; ++e) {
+        const int q = tid + e * kBlock;
+        pq[e] = q < PLANE ? q : -1;
+        const int yy = q / PX, xx = q - yy * PX;
+        pxy[e] = (((y0 - 1 + yy) & m) << lg) | ((x0 - 1 + xx) & m);
+    }
+    double pre[PRE];
+    auto fetch = [&](int z) {
+        const int zo = (z & m) << (2 * lg);
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pq[e] >= 0) pre[e] = hat[zo | pxy[e]];
+    };
+    auto commit = [&](int z) {
+        double *dst = P[z & 3];
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pq[e] >= 0) dst[pq[e]] = pre[e];
+    };
+    fetch(z0 - 1);
+    commit(z0 - 1);
+    fetch(z0);
+    commit(z0);
+    fetch(z0 + 1);
+    for (int k = z0; k < z0 + tz; ++k) {
+        commit(k + 1); // slot of plane k-3, last read at step k-2
+        if (k + 2 <= z0 + tz) fetch(k + 2);
+        __syncthreads();
+        const double(*pm)[PX] = reinterpret_cast<const double(*)[PX]>(P[(k - 1) & 3]);
+        const double(*p0)[PX] = reinterpret_cast<const double(*)[PX]>(P[k & 3]);
+        const double(*pp)[PX] = reinterpret_cast<const double(*)[PX]>(P[(k + 1) & 3]);
+#pragma unroll
+        for (int e = 0; e < CELLS; ++e) {
+            const int q = tid + e * kBlock;
+            const int yt = q / TX, xt = q - yt * TX;
+            const int rr = yt + 1, c = xt + 1;
+            const double v[19] = {
+                p0[rr][c], p0[rr][c + 1], p0[rr][c - 1], p0[rr + 1][c], p0[rr - 1][c],
+                pp[rr][c], pm[rr][c],
+                p0[rr + 1][c + 1], p0[rr - 1][c + 1], p0[rr + 1][c - 1], p0[rr - 1][c - 1],
+                pp[rr][c + 1], pm[rr][c + 1], pp[rr][c - 1], pm[rr][c - 1],
+                pp[rr + 1][c], pm[rr + 1][c], pp[rr - 1][c], pm[rr - 1][c]};
+            const int g = ((k << lg | (y0 + yt)) << lg) | (x0 + xt);
+            s[g] = apply_L(stencil_terms(v), al) + s[g];
+            phi[g] = v[0];
         }
     }
 }
@@ -739,7 +811,7 @@ k_restrict_source(const double *__restrict__ s_f, int nf, double *__restrict__ s
 // values of its start (same semantics as k_smooth_half).
 template <bool PER>
 __global__ void __launch_bounds__(512)
-k_coarsest(double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix, double al,
+k_coarsest(double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix, double al, double w,
            int sweeps, unsigned *__restrict__ fallbacks, const double *__restrict__ hat,
            int dyn_bc) {
     __shared__ double A[(kCoarsestMax + 2) * (kCoarsestMax + 2) * (kCoarsestMax + 2)];
@@ -776,7 +848,7 @@ k_coarsest(double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix, d
                 if (mycol == col) {
                     double v[19];
                     gather(src, ix, i, j, k, v);
-                    val = relax_cell(v, sc, al, fb);
+                    val = relax_cell(v, sc, al, w, fb);
                 } else {
                     val = src[me];
                 }
@@ -845,7 +917,7 @@ k_bottom(double *__restrict__ phi, const double *__restrict__ s, int lg0, Bottom
             const int i = 2 * m + ((col ^ j ^ k) & 1);
             double v[19];
             gather(ph, ix, i, j, k, v);
-            val = relax_cell(v, sr[((k << lg) + j) * n + i], al, fb);
+            val = relax_cell(v, sr[((k << lg) + j) * n + i], al, bl.omega, fb);
             at = ix(i, j, k);
         };
         for (int sw = 0; sw < sweeps; ++sw)
@@ -1025,10 +1097,11 @@ void launch_smooth_half(const Level &L, const double *pin, double *pout, int col
     const unsigned nb = blocks_for(L.cells() / 2);
     if (L.periodic)
         k_smooth_half<true><<<nb, kBlock, 0, st>>>(pin, pout, L.s, make_ix<true>(L.n, L.lg),
-                                                   L.alpha, colour, fallbacks, nullptr, 0);
+                                                   L.alpha, L.omega, colour, fallbacks, nullptr,
+                                                   0);
     else
         k_smooth_half<false><<<nb, kBlock, 0, st>>>(pin, pout, L.s, make_ix<false>(L.n, L.lg),
-                                                    L.alpha, colour, fallbacks, L.hat,
+                                                    L.alpha, L.omega, colour, fallbacks, L.hat,
                                                     L.dyn_bc ? 1 : 0);
 }
 
@@ -1041,7 +1114,7 @@ void sweep_fused_tiles(const Level &L, const double *pin, double *pout, unsigned
                        const double *phi_c, const double *hat_c, hipStream_t st) {
     const int tiles = (L.n / TX) * (L.n / TY);
     k_sweep_fused<TX, TY, TZ, NT, PRO><<<tiles * (L.n / TZ), NT, 0, st>>>(
-        pin, pout, L.s, L.lg, L.alpha, fallbacks, phi_c, hat_c);
+        pin, pout, L.s, L.lg, L.alpha, L.omega, fallbacks, phi_c, hat_c);
 }
 
 template <bool PRO>
@@ -1117,9 +1190,15 @@ void launch_restrict_residual(const Level &F, const Level &C, bool tiled, hipStr
                                                           make_ix<false>(C.n, C.lg));
 }
 
-void launch_coarse_source(const Level &C, hipStream_t st) {
+void launch_coarse_source(const Level &C, bool tiled, hipStream_t st) {
     const unsigned nb = blocks_for(C.cells());
-    if (C.periodic)
+    if (tiled && C.periodic && C.n >= 128) {
+        constexpr int TX = 64, TY = 16;
+        const int tz = C.n >= 256 ? 8 : 4;
+        const int tiles = (C.n / TX) * (C.n / TY);
+        k_coarse_source_tiled<TX, TY><<<tiles * (C.n / tz), kBlock, 0, st>>>(C.hat, C.phi, C.s,
+                                                                            C.lg, tz, C.alpha);
+    } else if (C.periodic)
         k_coarse_source<true><<<nb, kBlock, 0, st>>>(C.hat, C.phi, C.s, make_ix<true>(C.n, C.lg),
                                                      C.alpha, 0);
     else
@@ -1159,10 +1238,11 @@ void launch_coarsest(const Level &L, int sweeps, unsigned *fallbacks, hipStream_
     const int threads = L.cells() < 64 ? 64 : (int)L.cells();
     if (L.periodic)
         k_coarsest<true><<<1, threads, 0, st>>>(L.phi, L.s, make_ix<true>(L.n, L.lg), L.alpha,
-                                                sweeps, fallbacks, nullptr, 0);
+                                                L.omega, sweeps, fallbacks, nullptr, 0);
     else
         k_coarsest<false><<<1, threads, 0, st>>>(L.phi, L.s, make_ix<false>(L.n, L.lg), L.alpha,
-                                                 sweeps, fallbacks, L.hat, L.dyn_bc ? 1 : 0);
+                                                 L.omega, sweeps, fallbacks, L.hat,
+                                                 L.dyn_bc ? 1 : 0);
 }
 
 bool bottom_ok(const Level *H, int l, int nl) {
@@ -1177,6 +1257,7 @@ void launch_bottom(const Level *H, int l, int nl, int nu1, int nu2, int csweeps,
     BottomLevels bl{};
     bl.levels = nl - l;
     for (int q = 0; q < bl.levels; ++q) bl.alpha[q] = H[l + q].alpha;
+    bl.omega = H[l].omega;
     k_bottom<<<1, kBottomThreads, 0, st>>>(H[l].phi, H[l].s, H[l].lg, bl, nu1, nu2, csweeps,
                                            fallbacks);
 }

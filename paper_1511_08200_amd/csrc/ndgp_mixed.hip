@@ -66,7 +66,7 @@ __device__ __forceinline__ CorrTerms corr_terms(const float vp[19], const float 
 // New correction at the cell: the root of its own quadratic (same algebra as
 // relax_cell, with w = phi + e in place of phi), discriminant and root in FP64.
 __device__ __forceinline__ float relax_corr_cell(const float vp[19], const float ve[19], float r,
-                                                 float al, unsigned &fallbacks) {
+                                                 float al, double w, unsigned &fallbacks) {
     const CorrTerms t = corr_terms(vp, ve, al);
     const double ad = (double)al;
     const double rT = (double)t.A - (double)r;
@@ -77,7 +77,7 @@ __device__ __forceinline__ float relax_corr_cell(const float vp[19], const float
         ++fallbacks;
         return (float)((double)ve[0] + B / (18.0 * ad));
     }
-    return (float)fma(rT, fast_rcp(B + fast_sqrt(D)), (double)ve[0]);
+    return (float)fma(w * rT, fast_rcp(B + fast_sqrt(D)), (double)ve[0]);
 }
 
 using IxP = Ix<true>;
@@ -138,7 +138,7 @@ k_avg32(const float *__restrict__ f, int nf, float *__restrict__ c, int lgc) {
 __global__ void __launch_bounds__(kBlock)
 k_corr_half(const float *__restrict__ ein, float *__restrict__ eout,
             const float *__restrict__ phi, const float *__restrict__ r, IxP ix, float al,
-            int colour, unsigned *__restrict__ fallbacks) {
+            double w, int colour, unsigned *__restrict__ fallbacks) {
     const int n = ix.n, lg = ix.lg;
     const int half = n >> 1;
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -154,7 +154,7 @@ k_corr_half(const float *__restrict__ ein, float *__restrict__ eout,
     gather(ein, ix, iu, j, k, ve);
     unsigned fb = 0;
     const int me = ix(iu, j, k);
-    eout[me] = relax_corr_cell(vp, ve, r[me], al, fb);
+    eout[me] = relax_corr_cell(vp, ve, r[me], al, w, fb);
     eout[ix(ic, j, k)] = ein[ix(ic, j, k)];
     if (fb) atomicAdd(fallbacks, fb);
 }
@@ -225,7 +225,7 @@ k_corr_prolong(float *__restrict__ e_f, IxP ixf, const float *__restrict__ e_c,
 
 __global__ void __launch_bounds__(512)
 k_corr_coarsest(float *__restrict__ e, const float *__restrict__ phi, const float *__restrict__ r,
-                IxP ix, float al, int sweeps, unsigned *__restrict__ fallbacks) {
+                IxP ix, float al, double w, int sweeps, unsigned *__restrict__ fallbacks) {
     constexpr int MAXC = kCoarsestMax * kCoarsestMax * kCoarsestMax;
     __shared__ float A[MAXC], B[MAXC], Ph[MAXC];
     const int n = ix.n, lg = ix.lg;
@@ -261,7 +261,7 @@ k_corr_coarsest(float *__restrict__ e, const float *__restrict__ phi, const floa
                 if (mycol == col) {
                     float ve[19];
                     gather(src, ix, i, j, k, ve);
-                    val = relax_corr_cell(vp, ve, rc, al, fb);
+                    val = relax_corr_cell(vp, ve, rc, al, w, fb);
                 } else {
                     val = src[me];
                 }
@@ -304,7 +304,8 @@ void launch_fill32(float *a, size_t count, float v, hipStream_t st) {
 void launch_corr_half(const Level32 &L, const float *ein, float *eout, int colour,
                       unsigned *fallbacks, hipStream_t st) {
     k_corr_half<<<nblocks(L.cells() / 2), kBlock, 0, st>>>(ein, eout, L.phi, L.r, ixp(L.n, L.lg),
-                                                          (float)L.alpha, colour, fallbacks);
+                                                          (float)L.alpha, L.omega, colour,
+                                                          fallbacks);
 }
 
 void launch_corr_restrict(const Level32 &F, const Level32 &C, hipStream_t st) {
@@ -325,7 +326,7 @@ void launch_corr_prolong(const Level32 &F, const Level32 &C, hipStream_t st) {
 void launch_corr_coarsest(const Level32 &L, int sweeps, unsigned *fallbacks, hipStream_t st) {
     const int threads = L.cells() < 64 ? 64 : (int)L.cells();
     k_corr_coarsest<<<1, threads, 0, st>>>(L.e, L.phi, L.r, ixp(L.n, L.lg), (float)L.alpha,
-                                           sweeps, fallbacks);
+                                           L.omega, sweeps, fallbacks);
 }
 
 } // namespace ndgp

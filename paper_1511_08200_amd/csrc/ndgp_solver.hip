@@ -357,6 +357,61 @@ struct SmoothTimer {
     }
 };
 
+// The bookkeeping of the cycle loop on one level, shared by the blocking
+// drivers and the plans: stopping test, divergence, and the safeguard.  The
+// red-black sweep updates same-colour edge neighbours simultaneously (Jacobi
+// within a colour); where the nonlinear coupling through those edges is
+// strong (extreme densities with large r_c) that iteration can amplify an
+// error mode, and the cycles diverge after first converging.  Damping the
+// step from the middle of such a run does not recover it (the iterate has
+// left the basin), but a run damped from its start converges.  So once the
+// residual has risen twice in a row well above rounding level with the plain
+// step, the level is solved again from its initial guess with the damped
+// step u + kDampedStep du everywhere.  Runs that never rise keep the plain
+// root, bit for bit.
+constexpr double kDampedStep = 0.8;
+constexpr double kDampAbove = 1e-9; // rel. residual; below it a rise is rounding noise
+
+struct CycleMonitor {
+    double tol = 0.0;
+    int maxc = 0;
+    double rel0 = 0.0, prev = 0.0, rel = 0.0;
+    int slow = 0, rising = 0;
+    bool damped = false;
+
+    void start(double r) { rel = rel0 = prev = r; }
+    bool converged() const { return tol > 0.0 && rel <= tol; }
+    bool diverged() const { return !std::isfinite(rel) || rel > 1e6 * std::max(rel0, 1.0); }
+    // after a cycle: true when the level is to be solved again with the damped step
+    bool record(double r) {
+        rel = r;
+        rising = rel > prev ? rising + 1 : 0;
+        bool damp = false;
+        if (!damped && rising >= 2 && rel > kDampAbove) {
+            damped = damp = true;
+            rising = slow = 0;
+        } else if (tol == 0.0) {
+            slow = rel > 0.7 * prev ? slow + 1 : 0;
+        }
+        prev = rel;
+        return damp;
+    }
+    bool stalled() const { return tol == 0.0 && slow >= 2; }
+    // the status once the loop has stopped (not diverged)
+    ndgp_status verdict() const {
+        if (tol > 0.0 && rel > tol) return fail(NDGP_ENOCONV, "tolerance not reached within max_cycles");
+        if (tol == 0.0 && rel > 1e-11) return fail(NDGP_ENOCONV, "stagnated above rounding level");
+        return NDGP_OK;
+    }
+};
+
+inline void set_step(Level *H, Level32 *H32, int nl, double w) {
+    for (int l = 0; l < nl; ++l) {
+        H[l].omega = w;
+        if (H32) H32[l].omega = w;
+    }
+}
+
 struct Runner {
     Plan &P;
     hipStream_t st;
@@ -454,7 +509,7 @@ struct Runner {
         smooth(L, P.c.nu1);
         Level &C = H[l + 1];
         launch_restrict_residual(L, C, !(P.c.flags & NDGP_TWO_PASS), st);
-        launch_coarse_source(C, st);
+        launch_coarse_source(C, !(P.c.flags & NDGP_TWO_PASS), st);
         vcycle(H, nl, l + 1);
         smooth(L, P.c.nu2, &C);
     }
@@ -508,70 +563,60 @@ struct Runner {
     // Outer iterations: r = s - L[phi] in FP64 (also the stopping test), the
     // FP32 copy of phi on every level, kMixedInner FP32 V-cycles on the
     // correction from e = 0, phi += e in FP64.
+    // cycles accumulates over a restart; *restart is set (and the call
+    // returns) when the safeguard asks for a damped solve from the start.
     ndgp_status drive_mixed(Level *H, Level32 *H32, int nl, double snorm2, int &outer,
-                            double &rel, double *hist, int *hist_len) {
-        const Cfg &c = P.c;
-        rel = std::sqrt(residual_to32(H[0], H32[0].r) / snorm2);
-        const double rel0 = rel;
-        double prev = rel;
-        int slow = 0;
-        outer = 0;
-        while (outer < c.maxc) {
-            if (c.tol > 0.0 && rel <= c.tol) break;
+                            double &rel, double *hist, int *hist_len, bool *restart) {
+        CycleMonitor m{P.c.tol, P.c.maxc};
+        m.damped = H[0].omega != 1.0;
+        m.start(std::sqrt(residual_to32(H[0], H32[0].r) / snorm2));
+        rel = m.rel;
+        while (outer < m.maxc && !m.converged()) {
             mixed_outer(H, H32, nl);
             ++outer;
-            rel = std::sqrt(residual_to32(H[0], H32[0].r) / snorm2);
+            const double r = std::sqrt(residual_to32(H[0], H32[0].r) / snorm2);
             if (hist && outer - 1 < NDGP_HIST_LEN) {
-                hist[outer - 1] = rel;
+                hist[outer - 1] = r;
                 *hist_len = outer;
             }
-            if (!std::isfinite(rel) || rel > 1e6 * std::max(rel0, 1.0))
-                return fail(NDGP_ENOCONV, "mixed-precision iteration diverged");
-            if (c.tol == 0.0) {
-                slow = rel > 0.7 * prev ? slow + 1 : 0;
-                if (slow >= 2) break;
+            const bool again = m.record(r);
+            rel = m.rel;
+            if (again && restart) {
+                *restart = true;
+                return NDGP_OK;
             }
-            prev = rel;
+            if (m.diverged()) return fail(NDGP_ENOCONV, "mixed-precision iteration diverged");
+            if (m.stalled()) break;
         }
-        if (c.tol > 0.0 && rel > c.tol)
-            return fail(NDGP_ENOCONV, "tolerance not reached within max_cycles");
-        if (c.tol == 0.0 && rel > 1e-11)
-            return fail(NDGP_ENOCONV, "stagnated above rounding level");
-        return NDGP_OK;
+        return m.verdict();
     }
 
     // V-cycles on H[0] until ||r|| <= tol ||s|| (tol > 0) or until the
-    // residual stops falling (tol == 0).
+    // residual stops falling (tol == 0); cycles and restart as drive_mixed.
     ndgp_status drive(Level *H, int nl, double snorm2, int &cycles, double &rel, double *hist,
-                      int *hist_len) {
-        const Cfg &c = P.c;
-        rel = std::sqrt(residual_sumsq(H[0]) / snorm2);
-        const double rel0 = rel;
-        double prev = rel;
-        int slow = 0;
-        cycles = 0;
-        while (cycles < c.maxc) {
-            if (c.tol > 0.0 && rel <= c.tol) break;
+                      int *hist_len, bool *restart) {
+        CycleMonitor m{P.c.tol, P.c.maxc};
+        m.damped = H[0].omega != 1.0;
+        m.start(std::sqrt(residual_sumsq(H[0]) / snorm2));
+        rel = m.rel;
+        while (cycles < m.maxc && !m.converged()) {
             vcycle(H, nl, 0);
             ++cycles;
-            rel = std::sqrt(residual_sumsq(H[0]) / snorm2);
+            const double r = std::sqrt(residual_sumsq(H[0]) / snorm2);
             if (hist && cycles - 1 < NDGP_HIST_LEN) {
-                hist[cycles - 1] = rel;
+                hist[cycles - 1] = r;
                 *hist_len = cycles;
             }
-            if (!std::isfinite(rel) || rel > 1e6 * std::max(rel0, 1.0))
-                return fail(NDGP_ENOCONV, "multigrid diverged");
-            if (c.tol == 0.0) {
-                slow = rel > 0.7 * prev ? slow + 1 : 0;
-                if (slow >= 2) break;
+            const bool again = m.record(r);
+            rel = m.rel;
+            if (again && restart) {
+                *restart = true;
+                return NDGP_OK;
             }
-            prev = rel;
+            if (m.diverged()) return fail(NDGP_ENOCONV, "multigrid diverged");
+            if (m.stalled()) break;
         }
-        if (c.tol > 0.0 && rel > c.tol)
-            return fail(NDGP_ENOCONV, "tolerance not reached within max_cycles");
-        if (c.tol == 0.0 && rel > 1e-11)
-            return fail(NDGP_ENOCONV, "stagnated above rounding level");
-        return NDGP_OK;
+        return m.verdict();
     }
 };
 
@@ -630,16 +675,24 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         launch_fill(phi[0], cells0, 0.0, st); // no source: phi = 0
         R.rel_res[0] = 0.0;
     } else {
-        if (!(c.flags & NDGP_WARM_START)) run.nested_start(P.base, c.nl);
-        timer.on = (c.flags & NDGP_PROFILE) != 0; // the V-cycles only, not the start
         double rel = 0.0;
-        if (c.prec == NDGP_PREC_MIXED)
-            status = run.drive_mixed(P.base, P.base32, c.nl, snorm2, R.cycles[0], rel,
-                                     R.res_hist, &R.hist_len);
-        else
-            status = run.drive(P.base, c.nl, snorm2, R.cycles[0], rel, R.res_hist, &R.hist_len);
+        for (bool first = true;; first = false) {
+            if (!first || !(c.flags & NDGP_WARM_START)) run.nested_start(P.base, c.nl);
+            timer.on = (c.flags & NDGP_PROFILE) != 0; // the V-cycles only, not the start
+            bool restart = false;
+            if (c.prec == NDGP_PREC_MIXED)
+                status = run.drive_mixed(P.base, P.base32, c.nl, snorm2, R.cycles[0], rel,
+                                         R.res_hist, &R.hist_len, first ? &restart : nullptr);
+            else
+                status = run.drive(P.base, c.nl, snorm2, R.cycles[0], rel, R.res_hist,
+                                   &R.hist_len, first ? &restart : nullptr);
+            timer.on = false;
+            if (!restart) break;
+            // the safeguard: solve again from the nested start with the damped step
+            set_step(P.base, c.prec == NDGP_PREC_MIXED ? P.base32 : nullptr, c.nl, kDampedStep);
+            R.damped_from[0] = R.cycles[0] + 1;
+        }
         R.rel_res[0] = rel;
-        timer.on = false;
         if (timer.launches) {
             R.t_smooth_ms = timer.total_ms();
             R.smooth_launches = timer.launches;
@@ -678,7 +731,15 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         double sn2 = run.sum(H[0].s, cq, true, 1);
         if (sn2 == 0.0) sn2 = std::max(run.residual_sumsq(H[0]), 1e-300);
         double rel = 0.0;
-        const ndgp_status sq = run.drive(H, c.pnl[q], sn2, R.cycles[q + 1], rel, nullptr, nullptr);
+        bool restart = false;
+        ndgp_status sq = run.drive(H, c.pnl[q], sn2, R.cycles[q + 1], rel, nullptr, nullptr,
+                                   &restart);
+        if (restart) { // the safeguard: from the interpolated guess again, damped
+            set_step(H, nullptr, c.pnl[q], kDampedStep);
+            R.damped_from[q + 1] = R.cycles[q + 1] + 1;
+            launch_interpolate(parent, npar, parent_periodic, b0, phi[q + 1], false, st);
+            sq = run.drive(H, c.pnl[q], sn2, R.cycles[q + 1], rel, nullptr, nullptr, nullptr);
+        }
         R.rel_res[q + 1] = rel;
         if (sq != NDGP_OK && status == NDGP_OK) status = sq;
     }
@@ -770,9 +831,9 @@ struct ndgp_plan {
     const double *delta[1 + NDGP_MAX_PATCHES] = {nullptr, nullptr, nullptr};
     double *phi[1 + NDGP_MAX_PATCHES] = {nullptr, nullptr, nullptr};
     enum State { RUNNING, READY, FINISHING, DONE } state = RUNNING;
-    bool started = false;
-    double snorm2 = 0.0, rel = 0.0, rel0 = 0.0, prev = 0.0;
-    int slow = 0;
+    bool started = false, restarting = false;
+    double snorm2 = 0.0;
+    CycleMonitor mon;
     ndgp_status status = NDGP_OK;
     std::string message;
     ndgp_report R;
@@ -911,31 +972,44 @@ ndgp_status plan_poll_impl(ndgp_plan *pl, int32_t *done, ndgp_report *rep) {
             plan_enqueue_tail(pl, true);
             return NDGP_OK;
         }
-        pl->rel = pl->rel0 = pl->prev = std::sqrt(pl->slot[2] / pl->snorm2);
+        pl->mon = CycleMonitor{c.tol, c.maxc};
+        pl->mon.start(std::sqrt(pl->slot[2] / pl->snorm2));
+    } else if (pl->restarting) { // the damped nested start has completed
+        pl->restarting = false;
+        pl->mon = CycleMonitor{c.tol, c.maxc};
+        pl->mon.damped = true;
+        pl->mon.start(std::sqrt(pl->slot[2] / pl->snorm2));
     } else {
-        pl->rel = std::sqrt(pl->slot[2] / pl->snorm2);
+        const double r = std::sqrt(pl->slot[2] / pl->snorm2);
         const int cyc = pl->R.cycles[0];
         if (cyc - 1 < NDGP_HIST_LEN) {
-            pl->R.res_hist[cyc - 1] = pl->rel;
+            pl->R.res_hist[cyc - 1] = r;
             pl->R.hist_len = cyc;
         }
-        if (!std::isfinite(pl->rel) || pl->rel > 1e6 * std::max(pl->rel0, 1.0)) {
-            pl->R.rel_res[0] = pl->rel;
+        if (pl->mon.record(r)) { // the safeguard: from the nested start again, damped
+            set_step(pl->P.base, c.prec == NDGP_PREC_MIXED ? pl->P.base32 : nullptr, c.nl,
+                     kDampedStep);
+            pl->R.damped_from[0] = cyc + 1;
+            pl->restarting = true;
+            Runner run = plan_runner(pl);
+            run.nested_start(pl->P.base, c.nl);
+            run.enqueue_residual(pl->P.base, pl->P.base32);
+            HIP_TRY(hipMemcpyAsync(pl->slot + 2, pl->P.scal + 2, sizeof(double),
+                                   hipMemcpyDeviceToHost, pl->st));
+            plan_record(pl);
+            return NDGP_OK; // still RUNNING
+        }
+        if (pl->mon.diverged()) {
+            pl->R.rel_res[0] = pl->mon.rel;
             plan_fail(pl, NDGP_ENOCONV, "multigrid diverged");
             plan_enqueue_tail(pl, false);
             return NDGP_OK;
         }
-        if (c.tol == 0.0) pl->slow = pl->rel > 0.7 * pl->prev ? pl->slow + 1 : 0;
-        pl->prev = pl->rel;
     }
-    pl->R.rel_res[0] = pl->rel;
-    const bool converged = c.tol > 0.0 && pl->rel <= c.tol;
-    const bool stalled = c.tol == 0.0 && pl->slow >= 2;
-    if (converged || stalled || pl->R.cycles[0] >= c.maxc) {
-        if (c.tol > 0.0 && pl->rel > c.tol)
-            plan_fail(pl, NDGP_ENOCONV, "tolerance not reached within max_cycles");
-        if (c.tol == 0.0 && pl->rel > 1e-11)
-            plan_fail(pl, NDGP_ENOCONV, "stagnated above rounding level");
+    pl->R.rel_res[0] = pl->mon.rel;
+    if (pl->mon.converged() || pl->mon.stalled() || pl->R.cycles[0] >= c.maxc) {
+        const ndgp_status v = pl->mon.verdict();
+        if (v != NDGP_OK) plan_fail(pl, v, g_err.c_str());
         plan_enqueue_tail(pl, false);
         return NDGP_OK;
     }

@@ -61,7 +61,8 @@ class _Report(ctypes.Structure):
                 ("fallbacks", ctypes.c_int32), ("hist_len", ctypes.c_int32),
                 ("res_hist", ctypes.c_double * HIST_LEN), ("t_total_ms", ctypes.c_double),
                 ("t_smooth_ms", ctypes.c_double), ("smooth_launches", ctypes.c_int32),
-                ("smooth_cells_per_launch", ctypes.c_int32)]
+                ("smooth_cells_per_launch", ctypes.c_int32),
+                ("damped_from", ctypes.c_int32 * (1 + MAX_PATCHES))]
 
 
 _lib = None
@@ -194,6 +195,7 @@ class Report:
     smooth_launches: int = 0
     smooth_cells_per_launch: int = 0
     status: int = NDGP_OK
+    damped_from: list = dataclasses.field(default_factory=list)
 
 
 def _report(r: _Report, status: int) -> Report:
@@ -201,7 +203,8 @@ def _report(r: _Report, status: int) -> Report:
                   phi_mean=r.phi_mean, fallbacks=r.fallbacks,
                   history=[r.res_hist[i] for i in range(r.hist_len)], t_total_ms=r.t_total_ms,
                   t_smooth_ms=r.t_smooth_ms, smooth_launches=r.smooth_launches,
-                  smooth_cells_per_launch=r.smooth_cells_per_launch, status=status)
+                  smooth_cells_per_launch=r.smooth_cells_per_launch, status=status,
+                  damped_from=list(r.damped_from))
 
 
 # --------------------------------------------------------------------------
