@@ -157,6 +157,11 @@ void launch_fill32(float *a, size_t count, float v, hipStream_t st);
 // L[phi + e] - L[phi] = r on a periodic level
 void launch_corr_half(const Level32 &L, const float *ein, float *eout, int colour,
                       unsigned *fallbacks, hipStream_t st);
+// Both colours of the correction in one launch through LDS tiles, n >= 128
+// (corr_fused_ok); bit for bit two launch_corr_half calls.
+bool corr_fused_ok(const Level32 &L);
+void launch_corr_sweep_fused(const Level32 &L, const float *ein, float *eout,
+                             unsigned *fallbacks, hipStream_t st);
 // C.ehat = mean children of F.e; C.r = 4 mean children of (r - A(e))
 void launch_corr_restrict(const Level32 &F, const Level32 &C, hipStream_t st);
 // C.r = A_C(C.ehat) + C.r; C.e = C.ehat

@@ -274,6 +274,195 @@ k_corr_coarsest(float *__restrict__ e, const float *__restrict__ phi, const floa
     if (fb) atomicAdd(fallbacks, fb);
 }
 
+// One full red-black sweep of the correction e on a large level in one
+// launch: the LDS-streamed z pipeline of the FP64 k_sweep_fused with FP32
+// planes of phi (both colours, static during the sweep) and of e (old red on
+// 3 planes, old black on 5, red after the red pass on 3), and the cell update
+// of k_corr_half, so the result is bit for bit two k_corr_half launches.
+template <int TX, int TY, int TZ, int NT>
+__global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(4))) // two workgroups per CU: at most 128 VGPRs
+k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
+                   const float *__restrict__ phi, const float *__restrict__ rr_in, int lg,
+                   float al, double w, unsigned *__restrict__ fallbacks) {
+    constexpr int PX = TX + 4, PY = TY + 4, HX = PX / 2, PLANE = PX * PY;
+    constexpr int PRE = (PLANE + NT - 1) / NT;
+    constexpr int RED_ROW = (TX + 2) / 2, RED_CELLS = RED_ROW * (TY + 2);
+    static_assert(TX % 2 == 0 && TY % 2 == 0 && TX * TY / 2 == NT, "one black cell per thread");
+    static_assert(RED_CELLS <= 2 * NT, "at most two red cells per thread");
+    __shared__ float F[5][2][PY][HX]; // phi, both colours, planes k-2 .. k+2
+    __shared__ float ER[3][PY][HX];   // old e, red cells
+    __shared__ float EB[5][PY][HX];   // old e, black cells
+    __shared__ float R[3][PY][HX];    // e after the red pass, red cells
+
+    const int n = 1 << lg, m = n - 1;
+    const int ntx = n / TX;
+    const int tiles = ntx * (n / TY);
+    const int logical = xcd_local_id(blockIdx.x, gridDim.x);
+    const int tile = logical % tiles;
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY, z0 = (logical / tiles) * TZ;
+    const int tid = threadIdx.x;
+    unsigned fb = 0;
+    auto zoff = [&](int z) { return (z & m) << (2 * lg); };
+    auto s5 = [](int z) { return (z + 5 * 4096) % 5; };
+    auto s3 = [](int z) { return (z + 3 * 4096) % 3; };
+
+    int pxy[PRE], pidx[PRE], ppar[PRE];
+#pragma unroll
+    for (int e = 0; e < PRE; ++e) {
+        const int q = tid + e * NT;
+        const int r = q / PX, c = q - r * PX;
+        pxy[e] = (((y0 - 2 + r) & m) << lg) | ((x0 - 2 + c) & m);
+        pidx[e] = q < PLANE ? r * HX + (c >> 1) : -1;
+        ppar[e] = (c + r) & 1; // colour = ppar ^ (z & 1)
+    }
+    float pre_p[PRE], pre_e[PRE];
+    auto fetch = [&](int z) {
+        const int zo = zoff(z);
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pidx[e] >= 0) {
+                pre_p[e] = phi[zo | pxy[e]];
+                pre_e[e] = ein[zo | pxy[e]];
+            }
+    };
+    auto commit = [&](int z) {
+        float *f0 = &F[s5(z)][0][0][0], *f1 = &F[s5(z)][1][0][0];
+        float *red = &ER[s3(z)][0][0], *blk = &EB[s5(z)][0][0];
+        const int zp = z & 1;
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pidx[e] >= 0) {
+                const bool b = (ppar[e] ^ zp) != 0;
+                (b ? f1 : f0)[pidx[e]] = pre_p[e];
+                (b ? blk : red)[pidx[e]] = pre_e[e];
+            }
+    };
+
+    int red_rr[2], red_jj[2];
+    bool red_on[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int q = tid + e * NT;
+        red_on[e] = q < RED_CELLS;
+        red_rr[e] = 1 + q / RED_ROW;
+        red_jj[e] = q - (red_rr[e] - 1) * RED_ROW;
+    }
+    auto red_sources = [&](int z, float out[2]) {
+        const int zo = zoff(z);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int rr = red_rr[e];
+            const int p = (rr + z) & 1;
+            const int gx = x0 - 2 + 2 * (red_jj[e] + 1 - p) + p, gy = y0 - 2 + rr;
+            out[e] = rr_in[zo | ((gy & m) << lg) | (gx & m)]; // in bounds also when !red_on[e]
+        }
+    };
+    auto red_plane = [&](int z, const float src[2]) {
+        const float(*pm0)[HX] = F[s5(z - 1)][0], (*pm1)[HX] = F[s5(z - 1)][1];
+        const float(*pc0)[HX] = F[s5(z)][0], (*pc1)[HX] = F[s5(z)][1];
+        const float(*pp0)[HX] = F[s5(z + 1)][0], (*pp1)[HX] = F[s5(z + 1)][1];
+        const float(*m0)[HX] = ER[s3(z - 1)], (*m1)[HX] = EB[s5(z - 1)];
+        const float(*c0)[HX] = ER[s3(z)], (*c1)[HX] = EB[s5(z)];
+        const float(*p0)[HX] = ER[s3(z + 1)], (*p1)[HX] = EB[s5(z + 1)];
+        float(*rz)[HX] = R[s3(z)];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (!red_on[e]) continue;
+            const int rr = red_rr[e];
+            const int p = (rr + z) & 1;
+            const int j = red_jj[e] + 1 - p;
+            const int a = j + p, b = j + p - 1;
+            const float vp[19] = {
+                pc0[rr][j], pc1[rr][a], pc1[rr][b], pc1[rr + 1][j], pc1[rr - 1][j],
+                pp1[rr][j], pm1[rr][j],
+                pc0[rr + 1][a], pc0[rr - 1][a], pc0[rr + 1][b], pc0[rr - 1][b],
+                pp0[rr][a], pm0[rr][a], pp0[rr][b], pm0[rr][b],
+                pp0[rr + 1][j], pm0[rr + 1][j], pp0[rr - 1][j], pm0[rr - 1][j]};
+            const float ve[19] = {
+                c0[rr][j], c1[rr][a], c1[rr][b], c1[rr + 1][j], c1[rr - 1][j],
+                p1[rr][j], m1[rr][j],
+                c0[rr + 1][a], c0[rr - 1][a], c0[rr + 1][b], c0[rr - 1][b],
+                p0[rr][a], m0[rr][a], p0[rr][b], m0[rr][b],
+                p0[rr + 1][j], m0[rr + 1][j], p0[rr - 1][j], m0[rr - 1][j]};
+            rz[rr][j] = relax_corr_cell(vp, ve, src[e], al, w, fb);
+        }
+    };
+
+    const int rt = 2 + tid / (TX / 2), jt = 1 + tid % (TX / 2);
+    const int yt = y0 - 2 + rt;
+    const int xy_t = (yt << lg) | (x0 - 2 + 2 * jt);
+    auto black_source = [&](int k) {
+        const int pb = (1 + rt + k) & 1;
+        return rr_in[zoff(k) | xy_t | pb];
+    };
+    auto black_and_store = [&](int k, float sv) {
+        const float(*pm0)[HX] = F[s5(k - 1)][0], (*pm1)[HX] = F[s5(k - 1)][1];
+        const float(*pc0)[HX] = F[s5(k)][0], (*pc1)[HX] = F[s5(k)][1];
+        const float(*pp0)[HX] = F[s5(k + 1)][0], (*pp1)[HX] = F[s5(k + 1)][1];
+        const float(*rm)[HX] = R[s3(k - 1)], (*r0)[HX] = R[s3(k)], (*rp)[HX] = R[s3(k + 1)];
+        const float(*m1)[HX] = EB[s5(k - 1)], (*c1)[HX] = EB[s5(k)], (*p1)[HX] = EB[s5(k + 1)];
+        const int pb = (1 + rt + k) & 1;
+        const int j = jt, rr = rt, a = j + pb, b = j + pb - 1;
+        const float vp[19] = {
+            pc1[rr][j], pc0[rr][a], pc0[rr][b], pc0[rr + 1][j], pc0[rr - 1][j],
+            pp0[rr][j], pm0[rr][j],
+            pc1[rr + 1][a], pc1[rr - 1][a], pc1[rr + 1][b], pc1[rr - 1][b],
+            pp1[rr][a], pm1[rr][a], pp1[rr][b], pm1[rr][b],
+            pp1[rr + 1][j], pm1[rr + 1][j], pp1[rr - 1][j], pm1[rr - 1][j]};
+        const float ve[19] = {
+            c1[rr][j], r0[rr][a], r0[rr][b], r0[rr + 1][j], r0[rr - 1][j],
+            rp[rr][j], rm[rr][j],
+            c1[rr + 1][a], c1[rr - 1][a], c1[rr + 1][b], c1[rr - 1][b],
+            p1[rr][a], m1[rr][a], p1[rr][b], m1[rr][b],
+            p1[rr + 1][j], m1[rr + 1][j], p1[rr - 1][j], m1[rr - 1][j]};
+        const float vb = relax_corr_cell(vp, ve, sv, al, w, fb);
+        const float vr = r0[rr][j];
+        float *dst = eout + (zoff(k) | xy_t);
+        dst[0] = pb ? vr : vb;
+        dst[1] = pb ? vb : vr;
+    };
+
+    // the FP64 kernel's schedule: phi and old e on planes z0-2 .. z0+TZ+1
+    fetch(z0 - 2);
+    commit(z0 - 2);
+    fetch(z0 - 1);
+    commit(z0 - 1);
+    fetch(z0);
+    commit(z0);
+    float ra[2], rb[2], ba, bb;
+    red_sources(z0 - 1, ra);
+    fetch(z0 + 1);
+    __syncthreads();
+    red_plane(z0 - 1, ra);
+    __syncthreads(); // red(z0-1) has read the red slot that plane z0+1 takes
+    commit(z0 + 1);
+    red_sources(z0, ra);
+    fetch(z0 + 2);
+    __syncthreads();
+    red_plane(z0, ra);
+    __syncthreads();
+    red_sources(z0 + 1, ra);
+    ba = black_source(z0);
+    auto step = [&](int k, const float (&use_r)[2], float use_b, float (&next_r)[2],
+                    float &next_b) {
+        commit(k + 2); // red e slot of plane k-1, black e and phi slots of plane k-3
+        red_sources(k + 2, next_r);
+        next_b = black_source(k + 1);
+        fetch(k + 3);
+        __syncthreads();
+        red_plane(k + 1, use_r);
+        __syncthreads();
+        black_and_store(k, use_b);
+    };
+    static_assert(TZ % 2 == 0, "the z loop is unrolled by two");
+    for (int k = z0; k < z0 + TZ; k += 2) {
+        step(k, ra, ba, rb, bb);
+        step(k + 1, rb, bb, ra, ba);
+    }
+    if (fb) atomicAdd(fallbacks, fb);
+}
+
 inline unsigned nblocks(size_t total) { return (unsigned)((total + kBlock - 1) / kBlock); }
 
 inline IxP ixp(int n, int lg) { return IxP{n, lg, n + 2}; }
@@ -306,6 +495,23 @@ void launch_corr_half(const Level32 &L, const float *ein, float *eout, int colou
     k_corr_half<<<nblocks(L.cells() / 2), kBlock, 0, st>>>(ein, eout, L.phi, L.r, ixp(L.n, L.lg),
                                                           (float)L.alpha, L.omega, colour,
                                                           fallbacks);
+}
+
+bool corr_fused_ok(const Level32 &L) { return L.n >= 128; }
+
+void launch_corr_sweep_fused(const Level32 &L, const float *ein, float *eout,
+                             unsigned *fallbacks, hipStream_t st) {
+    constexpr int TX = 64, TY = 16, NT = 512;
+    const int tiles = (L.n / TX) * (L.n / TY);
+    if (L.n >= 256) {
+        constexpr int TZ = 32;
+        k_corr_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(
+            ein, eout, L.phi, L.r, L.lg, (float)L.alpha, L.omega, fallbacks);
+    } else {
+        constexpr int TZ = 8;
+        k_corr_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(
+            ein, eout, L.phi, L.r, L.lg, (float)L.alpha, L.omega, fallbacks);
+    }
 }
 
 void launch_corr_restrict(const Level32 &F, const Level32 &C, hipStream_t st) {

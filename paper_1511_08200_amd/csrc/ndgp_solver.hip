@@ -531,8 +531,15 @@ struct Runner {
 
     // ---- mixed precision: FP32 FAS on the correction e of
     //      L[phi + e] - L[phi] = r, inside an FP64 defect-correction loop
+    // as smooth(): fused sweeps on large levels, an odd last sweep in two launches
     void corr_smooth(Level32 &L, int sweeps) {
-        for (int s = 0; s < sweeps; ++s)
+        const bool fused = !(P.c.flags & NDGP_TWO_PASS) && corr_fused_ok(L);
+        const int nf = fused ? (sweeps & ~1) : 0;
+        for (int s = 0; s < nf; ++s) {
+            launch_corr_sweep_fused(L, L.e, L.ealt, P.fallbacks, st);
+            std::swap(L.e, L.ealt);
+        }
+        for (int s = nf; s < sweeps; ++s)
             for (int col = 0; col < 2; ++col) {
                 launch_corr_half(L, L.e, L.ealt, col, P.fallbacks, st);
                 std::swap(L.e, L.ealt);

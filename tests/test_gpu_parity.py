@@ -177,6 +177,22 @@ def test_fused_kernels_bitwise_equal_per_level_launches(n, levels):
     assert torch.equal(a[0], b[0])
 
 
+@pytest.mark.parametrize("n", [128, 256])
+def test_fused_corr_sweep_bitwise_equals_per_colour_launches(n):
+    """Mixed precision: the one-launch LDS sweep of the FP32 correction gives
+    the same bits for the whole solve as one k_corr_half launch per colour."""
+    say(f"mixed fused vs per-colour n={n}")
+    f = synth.make_field(n, 2.0, 37, n_tophats=10)
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n))
+    d = dev(f.delta)
+    p = dict(rc=1.0, tol=1e-10, precision=ndgp.PREC_MIXED)
+    a, ra = ndgp.solve(grid, ndgp.Params(**p), [d])
+    b, rb = ndgp.solve(grid, ndgp.Params(two_pass=True, **p), [d])
+    torch.cuda.synchronize()
+    assert ra.cycles == rb.cycles and ra.history == rb.history
+    assert torch.equal(a[0], b[0])
+
+
 MIXED_TOL = 1e-8
 
 
