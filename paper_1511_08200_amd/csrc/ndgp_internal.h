@@ -70,6 +70,10 @@ void launch_sweep_fused_prolong(const Level &L, const Level &C, const double *pi
 // Per-block partial sums of r^2, r = s - L[phi]; optionally r_out = r * scale.
 void launch_residual_sumsq(const Level &L, double *partials, double *r_out, double r_scale,
                            hipStream_t st);
+// The LDS-tiled residual (periodic, n >= 128: residual_tiled_ok) with r rounded
+// to FP32 into r32 and the partial sums of r^2 (FP64).
+bool residual_tiled_ok(const Level &L);
+void launch_residual_tiled_to32(const Level &L, float *r32, double *partials, hipStream_t st);
 // Per-block partial sums of a[i]^2 (squares != 0) or a[i] over count values.
 void launch_partial_sums(const double *a, size_t count, bool squares, double *partials,
                          hipStream_t st);

@@ -476,11 +476,12 @@ k_coarse_source_tiled(const double *__restrict__ hat, double *__restrict__ phi,
 // Residual norm of a large periodic level through LDS: a workgroup streams a
 // TX x TY column along z over tz planes, holding four planes of phi with a
 // one-cell halo; each phi and S value is read from HBM about once.  One
-// partial sum per workgroup (fixed order), optional r_out = r * scale.
-template <int TX, int TY>
+// partial sum per workgroup (fixed order), optional r_out = r * scale (FP64,
+// or rounded to FP32 for the mixed-precision loop).
+template <int TX, int TY, class OutT>
 __global__ void __launch_bounds__(kBlock)
 k_residual_tiled(const double *__restrict__ phi, const double *__restrict__ s, int lg, int tz,
-                 double al, double *__restrict__ partials, double *__restrict__ r_out,
+                 double al, double *__restrict__ partials, OutT *__restrict__ r_out,
                  double r_scale) {
     constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
     constexpr int PRE = (PLANE + kBlock - 1) / kBlock;
@@ -542,7 +543,7 @@ k_residual_tiled(const double *__restrict__ phi, const double *__restrict__ s, i
             const int g = ((k << lg | (y0 + yt)) << lg) | (x0 + xt);
             const double r = s[g] - apply_L(stencil_terms(v), al);
             acc = fma(r, r, acc);
-            if (r_out) r_out[g] = r * r_scale;
+            if (r_out) r_out[g] = (OutT)(r * r_scale);
         }
     }
     const double b = block_sum(acc);
@@ -1136,18 +1137,24 @@ void launch_sweep_fused_prolong(const Level &L, const Level &C, const double *pi
     sweep_fused<true>(L, pin, pout, fallbacks, C.phi, C.hat, st);
 }
 
+template <class OutT>
+void residual_tiled(const Level &L, double *partials, OutT *r_out, double r_scale,
+                    hipStream_t st) {
+    constexpr int TX = 64, TY = 16;
+    const int tiles = (L.n / TX) * (L.n / TY);
+    int chunks = L.n / 8; // z-chunks of 8 planes, at most kReduceBlocks workgroups
+    while (tiles * chunks > kReduceBlocks) chunks /= 2;
+    // blocks beyond the grid contribute zeros to the fixed-size final sum
+    const size_t unused = (size_t)(kReduceBlocks - tiles * chunks);
+    if (unused) k_fill<<<blocks_for(unused), kBlock, 0, st>>>(partials + tiles * chunks, unused, 0.0);
+    k_residual_tiled<TX, TY, OutT><<<tiles * chunks, kBlock, 0, st>>>(
+        L.phi, L.s, L.lg, L.n / chunks, L.alpha, partials, r_out, r_scale);
+}
+
 void launch_residual_sumsq(const Level &L, double *partials, double *r_out, double r_scale,
                            hipStream_t st) {
     if (L.periodic && L.n >= 128) {
-        constexpr int TX = 64, TY = 16;
-        const int tiles = (L.n / TX) * (L.n / TY);
-        int chunks = L.n / 8; // z-chunks of 8 planes, at most kReduceBlocks workgroups
-        while (tiles * chunks > kReduceBlocks) chunks /= 2;
-        // blocks beyond the grid contribute zeros to the fixed-size final sum
-        const size_t unused = (size_t)(kReduceBlocks - tiles * chunks);
-        if (unused) k_fill<<<blocks_for(unused), kBlock, 0, st>>>(partials + tiles * chunks, unused, 0.0);
-        k_residual_tiled<TX, TY><<<tiles * chunks, kBlock, 0, st>>>(
-            L.phi, L.s, L.lg, L.n / chunks, L.alpha, partials, r_out, r_scale);
+        residual_tiled<double>(L, partials, r_out, r_scale, st);
         return;
     }
     if (L.periodic)
@@ -1156,6 +1163,12 @@ void launch_residual_sumsq(const Level &L, double *partials, double *r_out, doub
     else
         k_residual_sumsq<false><<<kReduceBlocks, kBlock, 0, st>>>(
             L.phi, L.s, make_ix<false>(L.n, L.lg), L.alpha, partials, r_out, r_scale);
+}
+
+bool residual_tiled_ok(const Level &L) { return L.periodic && L.n >= 128; }
+
+void launch_residual_tiled_to32(const Level &L, float *r32, double *partials, hipStream_t st) {
+    residual_tiled<float>(L, partials, r32, 1.0, st);
 }
 
 void launch_partial_sums(const double *a, size_t count, bool squares, double *partials,

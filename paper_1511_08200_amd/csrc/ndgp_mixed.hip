@@ -470,6 +470,10 @@ inline IxP ixp(int n, int lg) { return IxP{n, lg, n + 2}; }
 } // namespace
 
 void launch_residual_to32(const Level &L, float *r32, double *partials, hipStream_t st) {
+    if (residual_tiled_ok(L)) {
+        launch_residual_tiled_to32(L, r32, partials, st);
+        return;
+    }
     k_residual_to32<<<kReduceBlocks, kBlock, 0, st>>>(L.phi, L.s, ixp(L.n, L.lg), L.alpha, r32,
                                                       partials);
 }
