@@ -146,17 +146,26 @@ def patch_workload(ndgp, torch, steps):
     deltas = [f.delta, synth.patch_delta(f, n, [o1], 128), synth.patch_delta(f, n, [o1, o2], 128)]
     grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n),
                      patches=[ndgp.Patch(128, o1), ndgp.Patch(128, o2)])
-    out = {"workload": "256^3 + 2 nested 128^3 patches (2x, 4x), FP64, r_cH0=1",
+    out = {"workload": "256^3 + 2 nested 128^3 patches (2x, 4x), r_cH0=1; FP64 full, FP64 "
+                       "interpolated, mixed precision interpolated",
            "origins": [list(o1), list(o2)]}
     res = {}
-    for name, mode in (("full", ndgp.MODE_FULL), ("interpolated", ndgp.MODE_INTERPOLATED)):
-        params = ndgp.Params(rc=rc, tol=1e-10, mode=mode)
+    for name, mode, prec in (("full", ndgp.MODE_FULL, ndgp.PREC_FP64),
+                             ("interpolated", ndgp.MODE_INTERPOLATED, ndgp.PREC_FP64),
+                             ("mixed_interpolated", ndgp.MODE_INTERPOLATED, ndgp.PREC_MIXED)):
+        params = ndgp.Params(rc=rc, tol=1e-10, mode=mode, precision=prec)
         dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, deltas, steps, 1)
         res[name] = (phi, reps[-1])
         out[name] = {"ms_to_tol": round(dt * 1e3, 2), "cycles": reps[-1].cycles,
                      "rel_res": reps[-1].rel_res}
     out["speedup_interpolated_vs_full"] = round(out["full"]["ms_to_tol"]
                                                 / out["interpolated"]["ms_to_tol"], 2)
+    # mixed precision + interpolated levels against the plain FP64 full solve
+    out["speedup_mixed_interpolated_vs_fp64_full"] = round(
+        out["full"]["ms_to_tol"] / out["mixed_interpolated"]["ms_to_tol"], 2)
+    a, b = res["mixed_interpolated"][0][0], res["interpolated"][0][0]
+    out["mixed_vs_fp64_domain_rel_l2"] = float(torch.linalg.vector_norm(a - b)
+                                               / torch.linalg.vector_norm(b))
     # force of the truncated run against the fully relaxed one (Eqs. errors,
     # errors2): relative to the full fifth force and to the GR force, whose
     # potential solves lap Psi = (3 beta / 2) S, i.e. 3 beta / 2 times the r_c = 0 field

@@ -156,6 +156,8 @@ void launch_to32(const double *a, float *b, size_t count, hipStream_t st);
 void launch_avg32(const Level32 &F, const Level32 &C, hipStream_t st);
 // phi64 += double(e32)
 void launch_add32(double *phi, const float *e, size_t count, hipStream_t st);
+// phi += e and phi32 = (float)phi in one pass (same bits as launch_add32 + launch_to32)
+void launch_add_to32(double *phi, const float *e, float *phi32, size_t count, hipStream_t st);
 void launch_fill32(float *a, size_t count, float v, hipStream_t st);
 // one colour of a red-black sweep of the correction equation
 // L[phi + e] - L[phi] = r on a periodic level
@@ -166,8 +168,9 @@ void launch_corr_half(const Level32 &L, const float *ein, float *eout, int colou
 bool corr_fused_ok(const Level32 &L);
 void launch_corr_sweep_fused(const Level32 &L, const float *ein, float *eout,
                              unsigned *fallbacks, hipStream_t st);
-// C.ehat = mean children of F.e; C.r = 4 mean children of (r - A(e))
-void launch_corr_restrict(const Level32 &F, const Level32 &C, hipStream_t st);
+// C.ehat = mean children of F.e; C.r = 4 mean children of (r - A(e));
+// tiled: through LDS for n >= 128 (same bits)
+void launch_corr_restrict(const Level32 &F, const Level32 &C, bool tiled, hipStream_t st);
 // C.r = A_C(C.ehat) + C.r; C.e = C.ehat
 void launch_corr_coarse_source(const Level32 &C, hipStream_t st);
 // F.e += trilinear(C.e - C.ehat)

@@ -112,6 +112,17 @@ k_add32(double *__restrict__ phi, const float *__restrict__ e, size_t count) {
     if (t < count) phi[t] += (double)e[t];
 }
 
+// phi += e, and the FP32 copy of the result for the next outer iteration
+__global__ void __launch_bounds__(kBlock)
+k_add_to32(double *__restrict__ phi, const float *__restrict__ e, float *__restrict__ phi32,
+           size_t count) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= count) return;
+    const double v = phi[t] + (double)e[t];
+    phi[t] = v;
+    phi32[t] = (float)v;
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_fill32(float *__restrict__ a, size_t count, float v) {
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -463,6 +474,104 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
     if (fb) atomicAdd(fallbacks, fb);
 }
 
+// Restriction of the correction equation on a large level through LDS: phi
+// and e planes (one-cell halo) stream along z as in the FP64 k_restrict_tiled,
+// one thread per coarse cell finishing its 4 children per fine plane, with
+// k_corr_restrict's expressions and summation order (same bits).
+template <int TX, int TY>
+__global__ void __launch_bounds__(kBlock)
+k_corr_restrict_tiled(const float *__restrict__ e_f, const float *__restrict__ phi_f,
+                      const float *__restrict__ r_f, int lg, int tz, float al_f,
+                      float *__restrict__ ehat_c, float *__restrict__ r_c) {
+    constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
+    constexpr int PRE = (PLANE + kBlock - 1) / kBlock;
+    static_assert(TX * TY == 4 * kBlock, "one coarse cell per thread");
+    __shared__ float PP[4][PLANE], PE[4][PLANE];
+    const int n = 1 << lg, m = n - 1, lgc = lg - 1;
+    const int ntx = n / TX;
+    const int tiles = ntx * (n / TY);
+    const int logical = xcd_local_id(blockIdx.x, gridDim.x);
+    const int tile = logical % tiles;
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY, z0 = (logical / tiles) * tz;
+    const int tid = threadIdx.x;
+    int pq[PRE], pxy[PRE];
+#pragma unroll
+    for (int e = 0; e < PRE; ++e) {
+        const int q = tid + e * kBlock;
+        pq[e] = q < PLANE ? q : -1;
+        const int yy = q / PX, xx = q - yy * PX;
+        pxy[e] = (((y0 - 1 + yy) & m) << lg) | ((x0 - 1 + xx) & m);
+    }
+    float pre_p[PRE], pre_e[PRE];
+    auto fetch = [&](int z) {
+        const int zo = (z & m) << (2 * lg);
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pq[e] >= 0) {
+                pre_p[e] = phi_f[zo | pxy[e]];
+                pre_e[e] = e_f[zo | pxy[e]];
+            }
+    };
+    auto commit = [&](int z) {
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pq[e] >= 0) {
+                PP[z & 3][pq[e]] = pre_p[e];
+                PE[z & 3][pq[e]] = pre_e[e];
+            }
+    };
+    const int ic = tid % (TX / 2), jc = tid / (TX / 2);
+    float se = 0.f, sr = 0.f;
+    fetch(z0 - 1);
+    commit(z0 - 1);
+    fetch(z0);
+    commit(z0);
+    fetch(z0 + 1);
+    for (int k = z0; k < z0 + tz; ++k) {
+        commit(k + 1); // slot of plane k-3, last read at step k-2
+        if (k + 2 <= z0 + tz) fetch(k + 2);
+        __syncthreads();
+        const float(*fm)[PX] = reinterpret_cast<const float(*)[PX]>(PP[(k - 1) & 3]);
+        const float(*f0)[PX] = reinterpret_cast<const float(*)[PX]>(PP[k & 3]);
+        const float(*fp)[PX] = reinterpret_cast<const float(*)[PX]>(PP[(k + 1) & 3]);
+        const float(*em)[PX] = reinterpret_cast<const float(*)[PX]>(PE[(k - 1) & 3]);
+        const float(*e0)[PX] = reinterpret_cast<const float(*)[PX]>(PE[k & 3]);
+        const float(*ep)[PX] = reinterpret_cast<const float(*)[PX]>(PE[(k + 1) & 3]);
+        if ((k & 1) == 0) {
+            se = 0.f;
+            sr = 0.f;
+        }
+#pragma unroll
+        for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+            for (int ci = 0; ci < 2; ++ci) {
+                const int xt = 2 * ic + ci, yt = 2 * jc + cj;
+                const int rr = yt + 1, c = xt + 1;
+                const float vp[19] = {
+                    f0[rr][c], f0[rr][c + 1], f0[rr][c - 1], f0[rr + 1][c], f0[rr - 1][c],
+                    fp[rr][c], fm[rr][c],
+                    f0[rr + 1][c + 1], f0[rr - 1][c + 1], f0[rr + 1][c - 1], f0[rr - 1][c - 1],
+                    fp[rr][c + 1], fm[rr][c + 1], fp[rr][c - 1], fm[rr][c - 1],
+                    fp[rr + 1][c], fm[rr + 1][c], fp[rr - 1][c], fm[rr - 1][c]};
+                const float ve[19] = {
+                    e0[rr][c], e0[rr][c + 1], e0[rr][c - 1], e0[rr + 1][c], e0[rr - 1][c],
+                    ep[rr][c], em[rr][c],
+                    e0[rr + 1][c + 1], e0[rr - 1][c + 1], e0[rr + 1][c - 1], e0[rr - 1][c - 1],
+                    ep[rr][c + 1], em[rr][c + 1], ep[rr][c - 1], em[rr][c - 1],
+                    ep[rr + 1][c], em[rr + 1][c], ep[rr - 1][c], em[rr - 1][c]};
+                const CorrTerms ct = corr_terms(vp, ve, al_f);
+                const int g = ((k << lg | (y0 + yt)) << lg) | (x0 + xt);
+                se += ve[0];
+                sr += r_f[g] - ct.A;
+            }
+        if (k & 1) {
+            const int q = (((k >> 1) << lgc | (y0 / 2 + jc)) << lgc) | (x0 / 2 + ic);
+            ehat_c[q] = se * 0.125f;
+            r_c[q] = sr * 0.5f; // 4 * mean: the coarse cell is twice as wide
+        }
+    }
+}
+
 inline unsigned nblocks(size_t total) { return (unsigned)((total + kBlock - 1) / kBlock); }
 
 inline IxP ixp(int n, int lg) { return IxP{n, lg, n + 2}; }
@@ -488,6 +597,10 @@ void launch_avg32(const Level32 &F, const Level32 &C, hipStream_t st) {
 
 void launch_add32(double *phi, const float *e, size_t count, hipStream_t st) {
     k_add32<<<nblocks(count), kBlock, 0, st>>>(phi, e, count);
+}
+
+void launch_add_to32(double *phi, const float *e, float *phi32, size_t count, hipStream_t st) {
+    k_add_to32<<<nblocks(count), kBlock, 0, st>>>(phi, e, phi32, count);
 }
 
 void launch_fill32(float *a, size_t count, float v, hipStream_t st) {
@@ -518,7 +631,15 @@ void launch_corr_sweep_fused(const Level32 &L, const float *ein, float *eout,
     }
 }
 
-void launch_corr_restrict(const Level32 &F, const Level32 &C, hipStream_t st) {
+void launch_corr_restrict(const Level32 &F, const Level32 &C, bool tiled, hipStream_t st) {
+    if (tiled && F.n >= 128) {
+        constexpr int TX = 64, TY = 16;
+        const int tz = F.n >= 256 ? 8 : 4;
+        const int tiles = (F.n / TX) * (F.n / TY);
+        k_corr_restrict_tiled<TX, TY><<<tiles * (F.n / tz), kBlock, 0, st>>>(
+            F.e, F.phi, F.r, F.lg, tz, (float)F.alpha, C.ehat, C.r);
+        return;
+    }
     k_corr_restrict<<<nblocks(C.cells()), kBlock, 0, st>>>(F.e, F.phi, F.r, ixp(F.n, F.lg),
                                                           (float)F.alpha, C.ehat, C.r, C.lg);
 }

@@ -250,6 +250,7 @@ struct Plan {
     double *partials = nullptr;
     double *scal = nullptr; // [0] sum delta, [1] sum s^2, [2] sum r^2, [3] sum phi
     unsigned *fallbacks = nullptr;
+    bool phi32_fresh = false; // base32[0].phi holds (float) base[0].phi
 };
 
 // Lays out every array in `base` (or only counts bytes when base == nullptr).
@@ -441,13 +442,15 @@ struct Runner {
     }
 
     // one outer iteration of the mixed-precision loop (without its residual)
+    // (phi += e also leaves the FP32 copy of phi for the next iteration)
     void mixed_outer(Level *H, Level32 *H32, int nl) {
         const size_t cells = H[0].cells();
-        launch_to32(H[0].phi, H32[0].phi, cells, st);
+        if (!P.phi32_fresh) launch_to32(H[0].phi, H32[0].phi, cells, st);
         for (int l = 1; l < nl; ++l) launch_avg32(H32[l - 1], H32[l], st);
         launch_fill32(H32[0].e, cells, 0.f, st);
         for (int q = 0; q < kMixedInner; ++q) corr_vcycle(H32, nl, 0);
-        launch_add32(H[0].phi, H32[0].e, cells, st);
+        launch_add_to32(H[0].phi, H32[0].e, H32[0].phi, cells, st);
+        P.phi32_fresh = true;
     }
 
     double sum(const double *a, size_t count, bool squares, int slot) {
@@ -520,6 +523,7 @@ struct Runner {
     // applied to the multigrid levels; a zero guess can diverge for strongly
     // screened sources).
     void nested_start(Level *H, int nl) {
+        P.phi32_fresh = false;
         for (int l = 1; l < nl; ++l) launch_restrict_source(H[l - 1], H[l], st);
         launch_fill(H[nl - 1].phi, H[nl - 1].slots(), 0.0, st);
         launch_coarsest(H[nl - 1], kCoarsestSweeps, P.fallbacks, st);
@@ -531,7 +535,9 @@ struct Runner {
 
     // ---- mixed precision: FP32 FAS on the correction e of
     //      L[phi + e] - L[phi] = r, inside an FP64 defect-correction loop
-    // as smooth(): fused sweeps on large levels, an odd last sweep in two launches
+    // as smooth(): fused sweeps on large levels, an odd last sweep in two
+    // launches.  (Adding the coarse-grid correction on load, as the FP64
+    // sweep does, spills registers here and is slower than its own launch.)
     void corr_smooth(Level32 &L, int sweeps) {
         const bool fused = !(P.c.flags & NDGP_TWO_PASS) && corr_fused_ok(L);
         const int nf = fused ? (sweeps & ~1) : 0;
@@ -554,7 +560,7 @@ struct Runner {
         }
         corr_smooth(L, P.c.nu1);
         Level32 &C = H[l + 1];
-        launch_corr_restrict(L, C, st);
+        launch_corr_restrict(L, C, !(P.c.flags & NDGP_TWO_PASS), st);
         launch_corr_coarse_source(C, st);
         corr_vcycle(H, nl, l + 1);
         launch_corr_prolong(L, C, st);
