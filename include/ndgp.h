@@ -139,8 +139,9 @@ typedef struct {
     int32_t smooth_launches; /* relaxation kernel launches inside t_smooth_ms           */
     int32_t smooth_cells_per_launch; /* cells one such launch updates                   */
     int32_t damped_from[1 + NDGP_MAX_PATCHES]; /* per level: the first cycle (outer
-                              iteration) relaxed with the damped step u + 0.8 du after
-                              the residual rose twice in a row; 0 = never damped        */
+                              iteration) of the solve restarted with the damped step
+                              u + 0.8 du after the residual grew to twice its smallest
+                              value; 0 = never damped                                   */
 } ndgp_report;
 
 /* Library ABI version (NDGP_ABI_VERSION of the build). */

@@ -366,34 +366,36 @@ struct SmoothTimer {
 // error mode, and the cycles diverge after first converging.  Damping the
 // step from the middle of such a run does not recover it (the iterate has
 // left the basin), but a run damped from its start converges.  So once the
-// residual has risen twice in a row well above rounding level with the plain
-// step, the level is solved again from its initial guess with the damped
-// step u + kDampedStep du everywhere.  Runs that never rise keep the plain
-// root, bit for bit.
+// residual has grown to kRiseFactor times the smallest one seen (well above
+// rounding level) with the plain step, the level is solved again from its
+// initial guess with the damped step u + kDampedStep du everywhere.  Plateaus
+// with small ups and downs, common before the screened regions settle, do
+// not trigger it; runs that never grow keep the plain root, bit for bit.
 constexpr double kDampedStep = 0.8;
+constexpr double kRiseFactor = 2.0;
 constexpr double kDampAbove = 1e-9; // rel. residual; below it a rise is rounding noise
 
 struct CycleMonitor {
     double tol = 0.0;
     int maxc = 0;
-    double rel0 = 0.0, prev = 0.0, rel = 0.0;
-    int slow = 0, rising = 0;
+    double rel0 = 0.0, prev = 0.0, rel = 0.0, best = 0.0;
+    int slow = 0;
     bool damped = false;
 
-    void start(double r) { rel = rel0 = prev = r; }
+    void start(double r) { rel = rel0 = prev = best = r; }
     bool converged() const { return tol > 0.0 && rel <= tol; }
     bool diverged() const { return !std::isfinite(rel) || rel > 1e6 * std::max(rel0, 1.0); }
     // after a cycle: true when the level is to be solved again with the damped step
     bool record(double r) {
         rel = r;
-        rising = rel > prev ? rising + 1 : 0;
         bool damp = false;
-        if (!damped && rising >= 2 && rel > kDampAbove) {
+        if (!damped && rel > kRiseFactor * best && rel > kDampAbove) {
             damped = damp = true;
-            rising = slow = 0;
+            slow = 0;
         } else if (tol == 0.0) {
             slow = rel > 0.7 * prev ? slow + 1 : 0;
         }
+        best = std::min(best, rel);
         prev = rel;
         return damp;
     }

@@ -349,9 +349,10 @@ def test_full_size_residual_by_oracle(n, box, sigma, tophats, rc, seed, prec):
 def test_damped_step_safeguard_on_extreme_source(prec):
     """A lognormal field with sigma_ln 2.47 (delta up to ~1e5 in one cell) at
     r_cH0 = 5 on 1 Mpc/h cells: the plain red-black cycles first converge,
-    then the residual rises and diverges.  The driver's safeguard switches to
-    the damped step after two rises and the solve reaches the tolerance; the
-    answer's residual, evaluated by the oracle on the whole grid, meets it."""
+    then the residual rises and diverges.  The driver's safeguard restarts with
+    the damped step once the residual has doubled and the solve reaches the
+    tolerance; the answer's residual, evaluated by the oracle on the whole
+    grid, meets it."""
     n, rc, sigma, seed = 256, 5.0, 2.4694042826895837, 100881
     say(f"safeguard n={n} rc={rc} precision={prec}")
     d = synth.lognormal_delta_torch(n, sigma, seed, device="cuda")
