@@ -52,6 +52,33 @@ def test_plan_equals_blocking_solve(precision):
     plan.close()
 
 
+@pytest.mark.parametrize("precision", [ndgp.PREC_FP64, ndgp.PREC_MIXED])
+def test_plan_restart_safeguard_equals_blocking_solve(precision):
+    """The divergent extreme request of the serving trace (sigma_ln 2.47,
+    r_cH0 = 5, 1 Mpc/h cells): a plan restarts with the damped step at the
+    same cycle as the blocking solve and gives the same bits."""
+    say(f"plan restart precision={precision}")
+    n, rc, sigma, seed = 256, 5.0, 2.4694042826895837, 100881
+    d = synth.lognormal_delta_torch(n, sigma, seed, device="cuda")
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n))
+    params = ndgp.Params(rc=rc, tol=1e-10, precision=precision, max_cycles=60)
+    phi_a, rep_a = ndgp.solve(grid, params, [d])
+    plan = ndgp.Plan(grid, params, [d])
+    steps = 0
+    while not plan.poll():
+        plan.step()
+        steps += 1
+        assert steps < 10**7
+    torch.cuda.synchronize()
+    rep_b = plan.report
+    say(f"  cycles={rep_b.cycles[0]} damped_from={rep_b.damped_from[0]}")
+    assert rep_b.status == 0 and rep_a.damped_from[0] > 0
+    assert rep_b.damped_from == rep_a.damped_from and rep_b.cycles == rep_a.cycles
+    assert rep_b.history == rep_a.history
+    assert torch.equal(phi_a[0], plan.phi[0])
+    plan.close()
+
+
 def test_plan_reports_bad_input():
     n = 32
     bad = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
