@@ -85,7 +85,6 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     constexpr int PX = TX + 4, PY = TY + 4;   // plane with halo 2
     constexpr int HX = PX / 2;                // cells of one colour per row
     constexpr int PLANE = PX * PY;
-    constexpr int PRE = (PLANE + NT - 1) / NT;
     constexpr int RED_ROW = (TX + 2) / 2;     // red cells per row of the halo-1 region
     constexpr int RED_CELLS = RED_ROW * (TY + 2);
     constexpr int EX = TX / 2 + 4, EY = TY / 2 + 4; // coarse cells under the plane, +-1
@@ -112,28 +111,31 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     auto s5 = [](int z) { return (z + 5 * 4096) % 5; };
     auto s3 = [](int z) { return (z + 3 * 4096) % 3; };
 
-    // this thread's share of a plane: global x-y offset, LDS split position,
-    // and (PRO) its coarse cell in E with the steps towards the neighbours
-    // on its side
-    int pxy[PRE], pidx[PRE], ppar[PRE], eat[PRE], edx[PRE], edy[PRE];
+    // this thread's share of a plane, in 16-byte pairs of cells (columns 2j,
+    // 2j+1 of a row: one red, one black, both at split index j): global x-y
+    // offset, LDS split position, colour of the pair's first cell, and (PRO)
+    // their coarse cell in E with the step towards the neighbour row
+    constexpr int PAIRS = PLANE / 2;
+    constexpr int PRE2 = (PAIRS + NT - 1) / NT;
+    int pxy[PRE2], pidx[PRE2], ppar[PRE2], eat[PRE2], edy[PRE2];
 #pragma unroll
-    for (int e = 0; e < PRE; ++e) {
+    for (int e = 0; e < PRE2; ++e) {
         const int q = tid + e * NT;
-        const int r = q / PX, c = q - r * PX;
-        pxy[e] = (((y0 - 2 + r) & m) << lg) | ((x0 - 2 + c) & m);
-        pidx[e] = q < PLANE ? r * HX + (c >> 1) : -1;
-        ppar[e] = (c + r) & 1; // colour = ppar ^ (z & 1)  (x0, y0 even)
-        // fine x0-2+c lies in coarse cell x0/2-1+(c>>1), E column (c>>1)+1
-        eat[e] = ((r >> 1) + 1) * EX + (c >> 1) + 1;
-        edx[e] = (c & 1) ? 1 : -1;
+        const int r = q / HX, j = q - r * HX;
+        pxy[e] = (((y0 - 2 + r) & m) << lg) | ((x0 - 2 + 2 * j) & m);
+        pidx[e] = q < PAIRS ? r * HX + j : -1;
+        ppar[e] = r & 1; // colour of column 2j = ppar ^ (z & 1)  (x0, y0 even)
+        // fine x0-2+2j+i lies in coarse cell x0/2-1+j, E column j+1; the
+        // neighbour column is on the left for i = 0, on the right for i = 1
+        eat[e] = ((r >> 1) + 1) * EX + j + 1;
         edy[e] = (r & 1) ? EX : -EX;
     }
-    double pre[PRE];
+    double2 pre[PRE2];
     auto fetch = [&](int z) {
         const int zo = zoff(z);
 #pragma unroll
-        for (int e = 0; e < PRE; ++e)
-            if (pidx[e] >= 0) pre[e] = pin[zo | pxy[e]];
+        for (int e = 0; e < PRE2; ++e)
+            if (pidx[e] >= 0) pre[e] = *reinterpret_cast<const double2 *>(pin + (zo | pxy[e]));
     };
     auto commit = [&](int z) {
         double *red = &PR[s3(z)][0][0], *blk = &PB[s5(z)][0][0];
@@ -145,25 +147,31 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
             e1 = E[s3(K + sk)];
         }
 #pragma unroll
-        for (int e = 0; e < PRE; ++e)
+        for (int e = 0; e < PRE2; ++e)
             if (pidx[e] >= 0) {
-                double v = pre[e];
+                double v[2] = {pre[e].x, pre[e].y};
                 if constexpr (PRO) {
-                    double acc = 0.0;
 #pragma unroll
-                    for (int cz = 0; cz < 2; ++cz) {
-                        const double *ep = cz ? e1 : e0;
+                    for (int i = 0; i < 2; ++i) {
+                        const int edx = i ? 1 : -1;
+                        double acc = 0.0;
 #pragma unroll
-                        for (int b = 0; b < 2; ++b)
+                        for (int cz = 0; cz < 2; ++cz) {
+                            const double *ep = cz ? e1 : e0;
 #pragma unroll
-                            for (int a = 0; a < 2; ++a) {
-                                const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (cz ? 0.25 : 0.75);
-                                acc = fma(w, ep[eat[e] + b * edy[e] + a * edx[e]], acc);
-                            }
+                            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                                for (int a = 0; a < 2; ++a) {
+                                    const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (cz ? 0.25 : 0.75);
+                                    acc = fma(w, ep[eat[e] + b * edy[e] + a * edx], acc);
+                                }
+                        }
+                        v[i] = v[i] + acc;
                     }
-                    v = v + acc;
                 }
-                ((ppar[e] ^ zp) ? blk : red)[pidx[e]] = v;
+                const bool first_black = (ppar[e] ^ zp) != 0;
+                red[pidx[e]] = first_black ? v[1] : v[0];
+                blk[pidx[e]] = first_black ? v[0] : v[1];
             }
     };
     // (PRO) coarse plane K of the correction: loaded into registers, then
