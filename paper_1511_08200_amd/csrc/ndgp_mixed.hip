@@ -297,7 +297,7 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
                    const float *__restrict__ phi, const float *__restrict__ rr_in, int lg,
                    float al, double w, unsigned *__restrict__ fallbacks) {
     constexpr int PX = TX + 4, PY = TY + 4, HX = PX / 2, PLANE = PX * PY;
-    constexpr int PRE = (PLANE + NT - 1) / NT;
+    constexpr int PRE = (PLANE / 2 + NT - 1) / NT; // pairs of cells per thread
     constexpr int RED_ROW = (TX + 2) / 2, RED_CELLS = RED_ROW * (TY + 2);
     static_assert(TX % 2 == 0 && TY % 2 == 0 && TX * TY / 2 == NT, "one black cell per thread");
     static_assert(RED_CELLS <= 2 * NT, "at most two red cells per thread");
@@ -318,23 +318,25 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
     auto s5 = [](int z) { return (z + 5 * 4096) % 5; };
     auto s3 = [](int z) { return (z + 3 * 4096) % 3; };
 
+    // pairs of cells (columns 2j, 2j+1 of a row: one red, one black, split
+    // index j), loaded 8 bytes at a time
     int pxy[PRE], pidx[PRE], ppar[PRE];
 #pragma unroll
     for (int e = 0; e < PRE; ++e) {
         const int q = tid + e * NT;
-        const int r = q / PX, c = q - r * PX;
-        pxy[e] = (((y0 - 2 + r) & m) << lg) | ((x0 - 2 + c) & m);
-        pidx[e] = q < PLANE ? r * HX + (c >> 1) : -1;
-        ppar[e] = (c + r) & 1; // colour = ppar ^ (z & 1)
+        const int r = q / HX, j = q - r * HX;
+        pxy[e] = (((y0 - 2 + r) & m) << lg) | ((x0 - 2 + 2 * j) & m);
+        pidx[e] = q < PLANE / 2 ? r * HX + j : -1;
+        ppar[e] = r & 1; // colour of column 2j = ppar ^ (z & 1)
     }
-    float pre_p[PRE], pre_e[PRE];
+    float2 pre_p[PRE], pre_e[PRE];
     auto fetch = [&](int z) {
         const int zo = zoff(z);
 #pragma unroll
         for (int e = 0; e < PRE; ++e)
             if (pidx[e] >= 0) {
-                pre_p[e] = phi[zo | pxy[e]];
-                pre_e[e] = ein[zo | pxy[e]];
+                pre_p[e] = *reinterpret_cast<const float2 *>(phi + (zo | pxy[e]));
+                pre_e[e] = *reinterpret_cast<const float2 *>(ein + (zo | pxy[e]));
             }
     };
     auto commit = [&](int z) {
@@ -344,9 +346,11 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
 #pragma unroll
         for (int e = 0; e < PRE; ++e)
             if (pidx[e] >= 0) {
-                const bool b = (ppar[e] ^ zp) != 0;
-                (b ? f1 : f0)[pidx[e]] = pre_p[e];
-                (b ? blk : red)[pidx[e]] = pre_e[e];
+                const bool fb1 = (ppar[e] ^ zp) != 0; // column 2j black
+                f0[pidx[e]] = fb1 ? pre_p[e].y : pre_p[e].x;
+                f1[pidx[e]] = fb1 ? pre_p[e].x : pre_p[e].y;
+                red[pidx[e]] = fb1 ? pre_e[e].y : pre_e[e].x;
+                blk[pidx[e]] = fb1 ? pre_e[e].x : pre_e[e].y;
             }
     };
 
