@@ -1,0 +1,135 @@
+"""Screening in NFW haloes and the truncation-level chooser (Sec. II.B,
+Sec. III.B, Sec. V).
+
+The first group pins the CPU oracle (oracle/nfw.py) to facts that do not come
+from it: the spherical equation it must solve, its unscreened limit, the
+definition of M_200, the mass independence the paper notes, and the numbers the
+paper prints (tests/golden/paper_values.json).  The second group checks the
+library's host functions against the oracle.  No GPU is involved.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import nfw as N
+from oracle import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_values.json")
+PAPER = json.load(open(GOLDEN))
+BETA = O.beta_lcdm(1.0, PAPER["cosmology"]["omega_m0"], PAPER["cosmology"]["rc_H0"])
+RC = PAPER["cosmology"]["rc_H0"]
+CS = (4.0, 5.0, 7.0, 10.0, 12.0)   # concentrations of galaxy- to cluster-size haloes
+
+
+# ---------------------------------------------------------------------------
+# pins of the oracle
+
+def test_m200_is_the_mass_inside_r200():
+    """Eqs. (nfwparams) and (r200): integrating the density out to R_200 gives
+    M_200, and the mean density inside R_200 is 200 rho_c."""
+    for m in (1e11, 1e13, 1e15):
+        for c in CS:
+            for ez in (1.0, 3.0):
+                R = N.r200(m, ez)
+                assert N.enclosed_mass(R, m, c, ez) == pytest.approx(m, rel=1e-12)
+                assert m / (4 / 3 * math.pi * R**3) == pytest.approx(200 * N.rho_crit(ez),
+                                                                   rel=1e-13)
+
+
+def test_critical_density_value():
+    """rho_c0 = 3 H0^2 / (8 pi G) = 2.775e11 h^2 M_sun / Mpc^3 (textbook value)."""
+    assert N.rho_crit() == pytest.approx(2.775e11, rel=1e-3)
+
+
+def test_closed_form_solves_the_spherical_equation():
+    """Eq. (eomvarphi_sph): phi_r / r + (2 r_c^2 / (3 beta)) (phi_r / r)^2 =
+    (2 / (3 beta)) G M / r^3, in units c = 1 (lengths Mpc/h, velocities in c)."""
+    c_kms = N.C_OVER_H0_MPC_H * N.H0_KMS_MPC_H
+    rc_len = RC * N.C_OVER_H0_MPC_H
+    for m in (1e12, 1e14):
+        for s in (0.05, 0.5, 2.0, 20.0):
+            r = s * N.r200(m)
+            gm = N.G_MPC_KMS2_MSUN * N.enclosed_mass(r, m, 6.0) / c_kms**2   # Mpc/h
+            phi_r = 2.0 * N.force_ratio(r, m, 6.0, RC, BETA) * gm / r**2       # F5 = phi_r / 2
+            u = phi_r / r
+            lhs = u + 2 * rc_len**2 / (3 * BETA) * u * u
+            rhs = 2 / (3 * BETA) * gm / r**3
+            assert lhs == pytest.approx(rhs, rel=1e-11)
+
+
+def test_unscreened_limits():
+    """Eq. (forcelarge): F_5th -> F_GR / (3 beta) far outside the Vainshtein
+    radius; r_c = 0 removes the screening everywhere; deep inside, the ratio
+    goes to zero (Eq. forcesmall)."""
+    for m in (1e12, 1e14):
+        R = N.r200(m)
+        assert N.force_ratio(1e4 * R, m, 5.0, RC, BETA) * 3 * BETA == pytest.approx(1.0, abs=1e-4)
+        assert N.force_ratio(0.3 * R, m, 5.0, 0.0, BETA) == 1.0 / (3 * BETA)
+        assert N.force_ratio(1e-4 * R, m, 5.0, RC, BETA) < 1e-3
+
+
+def test_mass_independence_and_concentration_trend():
+    """Sec. II.B: at fixed r / R_200 the ratio does not depend on M_200; a
+    higher concentration puts more mass inside r < R_200 and screens more
+    there; at R_200 itself every concentration encloses M_200 alike."""
+    R = N.r200(1e13)
+    for s in (0.1, 0.5, 1.0, 3.0):
+        for c in CS:
+            vals = [N.force_ratio(s * N.r200(m), m, c, RC, BETA) for m in (1e11, 1e13, 1e15)]
+            assert vals[0] == pytest.approx(vals[1], rel=1e-11)
+            assert vals[2] == pytest.approx(vals[1], rel=1e-11)
+    for s in (0.05, 0.3, 0.7):
+        by_c = [N.force_ratio(s * R, 1e13, c, RC, BETA) for c in CS]
+        assert all(a > b for a, b in zip(by_c, by_c[1:]))
+    at_r200 = [N.force_ratio(R, 1e13, c, RC, BETA) for c in CS]
+    assert max(at_r200) == pytest.approx(min(at_r200), rel=1e-11)
+
+
+def test_ratio_grows_with_radius():
+    m, c = 1e13, 6.0
+    rs = np.geomspace(1e-3, 1e2, 60) * N.r200(m)
+    vals = [N.force_ratio(r, m, c, RC, BETA) for r in rs]
+    assert all(a < b for a, b in zip(vals, vals[1:]))
+
+
+def test_paper_screening_numbers():
+    """The numbers the paper prints for its nDGP model at z = 0: about 2% at
+    R_200 / 2; screening setting in inside about 10 R_200; and at the cell size
+    of the most aggressive truncation, 0.24 Mpc/h, G_eff - 1 at most
+    {7, 4, 2}% for M_200 = 10^{12, 13, 14} M_sun/h (read as upper bounds; the
+    lower bounds at half of them catch a factor-two slip)."""
+    ns = PAPER["nfw_screening"]
+    for c in CS:
+        half = N.force_ratio(N.r200(1e13) / 2, 1e13, c, RC, BETA)
+        assert 0.75 * ns["force_ratio_below_half_r200"] < half < 1.25 * ns["force_ratio_below_half_r200"]
+        far = N.force_ratio(ns["screening_onset_r_over_r200"] * N.r200(1e13), 1e13, c, RC, BETA)
+        assert 0.95 < far * 3 * BETA < 1.0          # barely screened at 10 R_200
+        at_r200 = N.force_ratio(N.r200(1e13), 1e13, c, RC, BETA)
+        assert at_r200 * 3 * BETA < 0.5             # strongly screened at R_200
+    g = PAPER["nfw_truncation_guide"]
+    for m, top in zip(g["m200_msun_h"], g["g_eff_minus_1_at_most"]):
+        for c in CS:
+            v = N.force_ratio(g["r_mpc_h"], m, c, RC, BETA)
+            assert 0.5 * top < v <= top, (m, c, v)
+
+
+def test_screening_radius_and_level_by_brute_force():
+    """r_t solves ratio(r_t) = fraction, and the level is the first k with
+    h / 2^k <= r_t, checked against a scan of the levels."""
+    h = PAPER["simulation"]["box_mpc_h"] / PAPER["simulation"]["particles_per_side"]
+    for m in (1e12, 1e13, 1e14):
+        for frac in (0.01, 0.02, 0.07):
+            rt = N.screening_radius(frac, m, 5.0, RC, BETA)
+            assert N.force_ratio(rt, m, 5.0, RC, BETA) == pytest.approx(frac, rel=1e-10)
+            k = N.truncation_level(h, frac, m, 5.0, RC, BETA)
+            levels = [j for j in range(1, 40) if h / 2**j <= rt]
+            assert k == levels[0]
+            if k > 1:
+                assert h / 2 ** (k - 1) > rt
+    assert N.screening_radius(0.2, 1e13, 5.0, RC, BETA) == math.inf   # above 1/(3 beta)
+    assert N.screening_radius(0.0, 1e13, 5.0, RC, BETA) == 0.0
