@@ -14,9 +14,10 @@ The JSON line also carries:
                 launch stream during the timed steps; algorithmic bytes per
                 cell update = 24 (read phi and S, write phi; FP64);
   cpu_baseline  the CPU oracle on a bounded sample of the same workload;
-  extra         the 256^3 + two 128^3 patch workload in both modes (time to
-                tolerance, force difference of the interpolated mode) and
-                512^3 solves at three r_c, with the relaxation roofline there.
+  extra         the 256^3 + four nested 128^3 patch workload at the truncation
+                levels l_d+1, l_d+2, l_d+4 and the full run (time to tolerance,
+                force difference against the full run per level) and 512^3
+                solves at three r_c, with the relaxation roofline there.
 
     python bench.py [--steps K] [--warmup W] [--no-extra] [--no-cpu]
 """
@@ -133,57 +134,74 @@ def cpu_baseline(delta, h, rc, cycles):
 
 
 def patch_workload(ndgp, torch, steps):
-    """256^3 domain + 128^3 patches at 2x and 4x resolution centred on the
-    largest top-hat; full and interpolated modes; force difference."""
+    """256^3 domain + four nested 128^3 patches (2x, 4x, 8x, 16x resolution)
+    centred on the largest top-hat; time to tolerance for every truncation
+    level (the paper's l_trunc = l_d + 1, 2, 4 and the full run, Table I) and
+    for mixed precision with every patch interpolated; force differences of
+    each truncated run against the full one, per level."""
     from paper_1511_08200_amd import synth
-    n, box, rc = 256, 256.0, 1.0
+    n, box, rc, m, depth = 256, 256.0, 1.0, 128, 4
     f = make_domain(n, box, 2.0, 50, 1513)
     c = synth.densest_tophat_centre(f)
-    o1 = synth.patch_origin_centred(c, 64)
-    c1 = tuple((c[a] - o1[a]) * 2 for a in range(3))
-    o2 = synth.patch_origin_centred(c1, 64)
-    o2 = tuple(min(max(v, 8), 128 - 64 - 8) for v in o2)
-    deltas = [f.delta, synth.patch_delta(f, n, [o1], 128), synth.patch_delta(f, n, [o1, o2], 128)]
-    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n),
-                     patches=[ndgp.Patch(128, o1), ndgp.Patch(128, o2)])
-    out = {"workload": "256^3 + 2 nested 128^3 patches (2x, 4x), r_cH0=1; FP64 full, FP64 "
-                       "interpolated, mixed precision interpolated",
-           "origins": [list(o1), list(o2)]}
+    chain, deltas, patches = [], [f.delta], []
+    for q in range(depth):
+        o = synth.patch_origin_centred(c, m // 2)
+        if q > 0:
+            o = tuple(min(max(v, 8), m - m // 2 - 8) for v in o)
+        chain.append(o)
+        deltas.append(synth.patch_delta(f, n, chain, m))
+        patches.append(ndgp.Patch(m, o))
+        c = tuple((c[a] - o[a]) * 2 for a in range(3))
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n), patches=patches)
+    out = {"workload": "256^3 + 4 nested 128^3 patches (2x..16x), lognormal sigma 2 + 50 "
+                       "top-hats, r_cH0=1, tol 1e-10; truncation levels 1 (all interpolated), "
+                       "2, 4, 5 (full); mixed precision with every patch interpolated",
+           "origins": [list(o) for o in chain]}
+    runs = (("full", ndgp.MODE_FULL, 0, ndgp.PREC_FP64),
+            ("trunc4", ndgp.MODE_TRUNCATED, 4, ndgp.PREC_FP64),
+            ("trunc2", ndgp.MODE_TRUNCATED, 2, ndgp.PREC_FP64),
+            ("interpolated", ndgp.MODE_INTERPOLATED, 0, ndgp.PREC_FP64),
+            ("mixed_interpolated", ndgp.MODE_INTERPOLATED, 0, ndgp.PREC_MIXED))
     res = {}
-    for name, mode, prec in (("full", ndgp.MODE_FULL, ndgp.PREC_FP64),
-                             ("interpolated", ndgp.MODE_INTERPOLATED, ndgp.PREC_FP64),
-                             ("mixed_interpolated", ndgp.MODE_INTERPOLATED, ndgp.PREC_MIXED)):
-        params = ndgp.Params(rc=rc, tol=1e-10, mode=mode, precision=prec)
+    for name, mode, k, prec in runs:
+        params = ndgp.Params(rc=rc, tol=1e-10, mode=mode, trunc_level=k, precision=prec)
         dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, deltas, steps, 1)
-        res[name] = (phi, reps[-1])
+        res[name] = [p.clone() for p in phi]
         out[name] = {"ms_to_tol": round(dt * 1e3, 2), "cycles": reps[-1].cycles,
                      "rel_res": reps[-1].rel_res}
-    out["speedup_interpolated_vs_full"] = round(out["full"]["ms_to_tol"]
-                                                / out["interpolated"]["ms_to_tol"], 2)
+        del phi, dd
+    t_full = out["full"]["ms_to_tol"]
+    out["speedup_vs_full"] = {k: round(t_full / out[k]["ms_to_tol"], 2)
+                              for k in ("trunc4", "trunc2", "interpolated", "mixed_interpolated")}
+    out["speedup_interpolated_vs_full"] = out["speedup_vs_full"]["interpolated"]
     # mixed precision + interpolated levels against the plain FP64 full solve
-    out["speedup_mixed_interpolated_vs_fp64_full"] = round(
-        out["full"]["ms_to_tol"] / out["mixed_interpolated"]["ms_to_tol"], 2)
-    a, b = res["mixed_interpolated"][0][0], res["interpolated"][0][0]
+    out["speedup_mixed_interpolated_vs_fp64_full"] = out["speedup_vs_full"]["mixed_interpolated"]
+    a, b = res["mixed_interpolated"][0], res["interpolated"][0]
     out["mixed_vs_fp64_domain_rel_l2"] = float(torch.linalg.vector_norm(a - b)
                                                / torch.linalg.vector_norm(b))
-    # force of the truncated run against the fully relaxed one (Eqs. errors,
+    # force of each truncated run against the fully relaxed one (Eqs. errors,
     # errors2): relative to the full fifth force and to the GR force, whose
     # potential solves lap Psi = (3 beta / 2) S, i.e. 3 beta / 2 times the r_c = 0 field
     beta = ndgp.beta_lcdm(1.0, 0.3, rc)
     phi_gr, _ = ndgp.solve(grid, ndgp.Params(rc=0.0, beta=beta, tol=1e-10),
                            [torch.from_numpy(d).to("cuda") for d in deltas])
-    F_full = ndgp.force(grid, res["full"][0])
-    F_int = ndgp.force(grid, res["interpolated"][0])
+    F_full = ndgp.force(grid, res["full"])
     F_lin = ndgp.force(grid, phi_gr)
-    diffs = []
-    for lvl in (1, 2):
-        dd2, ff2, _ = ndgp.diff_norms(F_int[lvl], F_full[lvl])
-        _, gr2, _ = ndgp.diff_norms(F_lin[lvl])
-        gr2 *= (3 * beta) ** 2
-        diffs.append({"level": lvl, "rel_to_F5_full": float(np.sqrt(dd2 / ff2)),
-                      "rel_to_F_GR": float(np.sqrt(dd2 / gr2)),
-                      "F5_over_FGR": float(np.sqrt(ff2 / gr2))})
-    out["force_difference"] = diffs
+    gr2 = []
+    for lvl in range(1, depth + 1):
+        _, g2, _ = ndgp.diff_norms(F_lin[lvl])
+        gr2.append(g2 * (3 * beta) ** 2)
+    out["force_difference"] = {}
+    for name in ("trunc4", "trunc2", "interpolated"):
+        F_t = ndgp.force(grid, res[name])
+        rows = []
+        for lvl in range(1, depth + 1):
+            dd2, ff2, _ = ndgp.diff_norms(F_t[lvl], F_full[lvl])
+            rows.append({"level": lvl, "rel_to_F5_full": float(np.sqrt(dd2 / ff2)),
+                         "rel_to_F_GR": float(np.sqrt(dd2 / gr2[lvl - 1])),
+                         "F5_over_FGR": float(np.sqrt(ff2 / gr2[lvl - 1]))})
+        out["force_difference"][name] = rows
+        del F_t
     return out
 
 

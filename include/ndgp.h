@@ -12,11 +12,13 @@
  *     lap(phi) + alpha [ ... ] = S,   alpha = r_c^2/(3 beta a^2),
  *                                     S = Omega_m (delta - mean delta)/(a beta).
  *
- * It is solved on a periodic domain grid and on up to two static nested
+ * It is solved on a periodic domain grid and on up to four static nested
  * refinement patches (Sec. III.A: domain level first, then refinements with
  * boundary values and initial guess interpolated from the coarser level).
  * In NDGP_MODE_INTERPOLATED the refinements keep the interpolated guess as
- * their answer: the paper's speed-up, Sec. III.B.  The fifth force is
+ * their answer: the paper's speed-up, Sec. III.B.  NDGP_MODE_TRUNCATED
+ * relaxes the refinements below a given level and interpolates from there on
+ * (the truncation criteria l >= l_trunc of Sec. IV.A).  The fifth force is
  * -grad(phi)/2 (Eq. modpoisson) by central differences (Sec. III.B).
  *
  * Discretisation (the paper defers it to another work): cell-centred fields;
@@ -56,8 +58,8 @@
 extern "C" {
 #endif
 
-#define NDGP_ABI_VERSION 1
-#define NDGP_MAX_PATCHES 2
+#define NDGP_ABI_VERSION 2
+#define NDGP_MAX_PATCHES 4
 #define NDGP_HIST_LEN 64
 
 typedef enum {
@@ -70,8 +72,15 @@ typedef enum {
 } ndgp_status;
 
 typedef enum {
-    NDGP_MODE_FULL = 0,        /* refinements relaxed to convergence (Sec. III.A)     */
-    NDGP_MODE_INTERPOLATED = 1 /* refinements = interpolated coarse field (Sec. III.B) */
+    NDGP_MODE_FULL = 0,         /* refinements relaxed to convergence (Sec. III.A)    */
+    NDGP_MODE_INTERPOLATED = 1, /* refinements = interpolated coarse field (Sec. III.B) */
+    NDGP_MODE_TRUNCATED = 2     /* refinements 1 .. trunc_level-1 relaxed, trunc_level ..
+                                   n_patch interpolated from their relaxed or
+                                   interpolated parent (Sec. III.B, Sec. IV.A: the
+                                   paper's l_trunc is l_d + trunc_level, so its
+                                   criteria l_d+1, l_d+2, l_d+4 are trunc_level 1, 2,
+                                   4; 1 is NDGP_MODE_INTERPOLATED, n_patch+1 is
+                                   NDGP_MODE_FULL)                                     */
 } ndgp_mode;
 
 typedef enum {
@@ -99,13 +108,15 @@ typedef enum {
 typedef struct {
     int32_t n;             /* domain cells per side: power of two, 8..1024              */
     double h;              /* domain cell size in c/H0 (> 0)                            */
-    int32_t n_patch;       /* number of nested refinement levels, 0..2                 */
+    int32_t n_patch;       /* number of nested refinement levels, 0..NDGP_MAX_PATCHES  */
     int32_t patch_n[NDGP_MAX_PATCHES];       /* cells per side, power of two, 8..512   */
     int32_t patch_origin[NDGP_MAX_PATCHES][3]; /* lower corner (x,y,z) in PARENT cells;
                                                   patch 1 may wrap around the periodic
-                                                  domain; patch 2 must lie inside patch 1
-                                                  with room for the interpolation
-                                                  stencils of all its multigrid levels */
+                                                  domain; patch q > 1 must lie inside
+                                                  patch q-1 with room for the
+                                                  interpolation stencils of all its
+                                                  multigrid levels (of its finest level
+                                                  only if it is interpolated)           */
 } ndgp_grid;
 
 typedef struct {
@@ -121,6 +132,8 @@ typedef struct {
     int32_t mode;      /* ndgp_mode                                                    */
     int32_t precision; /* ndgp_precision                                               */
     uint32_t flags;    /* NDGP_WARM_START | NDGP_PROFILE | NDGP_TWO_PASS               */
+    int32_t trunc_level; /* NDGP_MODE_TRUNCATED: first interpolated refinement level,
+                            1..n_patch+1; ignored by the other modes                    */
 } ndgp_params;
 
 typedef struct {
@@ -162,14 +175,16 @@ size_t ndgp_workspace_bytes(const ndgp_grid *grid, const ndgp_params *params);
 
 /*
  * Solve Eq. (eomvarphi) on the domain grid and every patch (Sec. III.A), or
- * fill the patches by interpolation (Sec. III.B, NDGP_MODE_INTERPOLATED).
+ * fill the patches by interpolation (Sec. III.B, NDGP_MODE_INTERPOLATED), or
+ * relax the patches below trunc_level and interpolate the rest
+ * (NDGP_MODE_TRUNCATED).
  *   delta[0]      domain density contrast, n^3 (its mean is projected out)
- *   delta[1..2]   patch density contrasts, patch_n^3, measured against the
- *                 same mean density as the domain (unused in interpolated mode,
- *                 may be NULL there)
+ *   delta[q]      patch density contrasts, patch_n^3, measured against the
+ *                 same mean density as the domain (needed only for relaxed
+ *                 patches; may be NULL for interpolated ones)
  *   phi[0]        out: domain phi, n^3, zero mean (in: initial guess with
  *                 NDGP_WARM_START); 16-byte aligned
- *   phi[1..2]     out: patch phi, padded (patch_n+2)^3 with its ghost shell
+ *   phi[q]        out: patch phi, padded (patch_n+2)^3 with its ghost shell
  *                 (the fixed boundary values interpolated from the parent)
  *   report        optional (NULL allowed)
  * Blocks until the domain level converged (one 8-byte device-to-host read of
@@ -214,7 +229,8 @@ ndgp_status ndgp_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_M
  * one host thread can keep many solves in flight on different streams
  * (continuous batching).  A plan owns nothing on the device: delta, phi and
  * the workspace stay the caller's and must stay alive until the plan is done
- * or destroyed.  Patches are supported in NDGP_MODE_INTERPOLATED only.  The
+ * or destroyed.  Patches must all be interpolated: NDGP_MODE_INTERPOLATED, or
+ * NDGP_MODE_TRUNCATED with trunc_level 1.  The
  * number of V-cycles a plan runs depends only on its own residual history,
  * so its result is bit for bit the one ndgp_solve gives, whatever else runs.
  *

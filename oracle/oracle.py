@@ -260,10 +260,16 @@ class Problem:
 
 
 def solve_problem(p: Problem, interpolated: bool = False, tol: float = 0.0,
-                  max_cycles: int = 200):
+                  max_cycles: int = 200, trunc_level: int | None = None):
     """The whole path: domain level, then every patch level from its parent
-    (Sec. III.A), or by interpolation only (Sec. III.B).  Returns
-    (phis, infos): phis[0] natural zero-mean, phis[1:] padded with ghosts."""
+    (Sec. III.A), or by interpolation only (Sec. III.B).  ``trunc_level`` k
+    relaxes patch levels 1..k-1 and interpolates levels k and up, each from
+    its own (relaxed or interpolated) parent: the truncation l >= l_trunc of
+    Sec. IV.A with l_trunc = l_d + k.  k = 1 is ``interpolated=True``.
+    Returns (phis, infos): phis[0] natural zero-mean, phis[1:] padded with
+    ghosts."""
+    if trunc_level is None:
+        trunc_level = 1 if interpolated else len(p.delta)
     al = alpha(p.rc, p.beta, p.a)
     S0, mean = source(p.delta[0], p.omega_m, p.a, p.beta)
     phi0, info0 = solve_periodic(S0, p.h, al, tol=tol, max_cycles=max_cycles)
@@ -273,7 +279,7 @@ def solve_problem(p: Problem, interpolated: bool = False, tol: float = 0.0,
         h = h / 2
         S = source_shift(p.delta[lvl], mean, p.omega_m, p.a, p.beta)
         ph, inf = solve_patch(S, h, al, parent, parent_periodic, p.origins[lvl - 1],
-                              interp_only=interpolated, tol=tol, max_cycles=max_cycles)
+                              interp_only=lvl >= trunc_level, tol=tol, max_cycles=max_cycles)
         phis.append(ph)
         infos.append(inf)
         parent, parent_periodic = ph, False

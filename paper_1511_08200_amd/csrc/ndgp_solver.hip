@@ -99,9 +99,10 @@ struct Cfg {
     int n = 0, lgn = 0, nl = 0;
     double h = 0.0;
     int np = 0;
-    int pn[NDGP_MAX_PATCHES] = {0, 0};
-    int po[NDGP_MAX_PATCHES][3] = {{0, 0, 0}, {0, 0, 0}};
-    int pnl[NDGP_MAX_PATCHES] = {0, 0};
+    int nrelax = 0; // patches 0 .. nrelax-1 are relaxed, the rest interpolated
+    int pn[NDGP_MAX_PATCHES] = {};
+    int po[NDGP_MAX_PATCHES][3] = {};
+    int pnl[NDGP_MAX_PATCHES] = {};
     double alpha = 0.0; // r_c^2 / (3 beta a^2), physical
     double fsrc = 0.0;  // Omega_m / (a beta)
     double tol = 0.0;
@@ -172,7 +173,8 @@ bool resolve(const ndgp_grid *g, const ndgp_params *p, Cfg &c, std::string &why)
         why = "n_levels must coarsen the domain grid to at most 8 and at least 2 cells per side";
         return false;
     }
-    if (p->mode != NDGP_MODE_FULL && p->mode != NDGP_MODE_INTERPOLATED) {
+    if (p->mode != NDGP_MODE_FULL && p->mode != NDGP_MODE_INTERPOLATED &&
+        p->mode != NDGP_MODE_TRUNCATED) {
         why = "unknown mode";
         return false;
     }
@@ -191,13 +193,23 @@ bool resolve(const ndgp_grid *g, const ndgp_params *p, Cfg &c, std::string &why)
     c.alpha = p->rc * p->rc / (3.0 * p->beta * p->a * p->a);
     c.fsrc = p->omega_m / (p->a * p->beta);
     if (g->n_patch < 0 || g->n_patch > NDGP_MAX_PATCHES) {
-        why = "n_patch must be 0, 1 or 2";
+        why = "n_patch must be in [0, " + std::to_string(NDGP_MAX_PATCHES) + "]";
         return false;
     }
     c.np = g->n_patch;
+    // Sec. IV.A: levels from l_trunc = l_d + trunc_level on are interpolated
+    if (c.mode == NDGP_MODE_TRUNCATED) {
+        if (p->trunc_level < 1 || p->trunc_level > c.np + 1) {
+            why = "trunc_level must be in [1, n_patch + 1]";
+            return false;
+        }
+        c.nrelax = p->trunc_level - 1;
+    } else {
+        c.nrelax = c.mode == NDGP_MODE_FULL ? c.np : 0;
+    }
     for (int q = 0; q < c.np; ++q) {
         const int m = g->patch_n[q];
-        const int parent_n = q == 0 ? c.n : c.pn[0];
+        const int parent_n = q == 0 ? c.n : c.pn[q - 1];
         if (!pow2(m) || m < 8 || m > 512 || m > 2 * parent_n) {
             why = "patch_n must be a power of two in [8, 512] covering at most its parent";
             return false;
@@ -212,11 +224,12 @@ bool resolve(const ndgp_grid *g, const ndgp_params *p, Cfg &c, std::string &why)
             }
             c.po[q][a] = o;
         }
-        if (q == 1) {
-            const int need = c.mode == NDGP_MODE_FULL ? c.pnl[1] : 1;
-            if (!child_fits(c.pn[0], c.po[1], m, need)) {
-                why = "patch 2 must lie inside patch 1 with room for the interpolation stencils "
-                      "of its multigrid levels";
+        if (q >= 1) {
+            const int need = q < c.nrelax ? c.pnl[q] : 1;
+            if (!child_fits(c.pn[q - 1], c.po[q], m, need)) {
+                why = "patch " + std::to_string(q + 1) + " must lie inside patch " +
+                      std::to_string(q) + " with room for the interpolation stencils of its " +
+                      (q < c.nrelax ? "multigrid levels" : "cells");
                 return false;
             }
         }
@@ -282,8 +295,8 @@ size_t carve(Plan &P, char *base) {
             L.ehat = l ? cv.take<float>(L.cells()) : nullptr;
         }
     }
-    if (c.mode == NDGP_MODE_FULL) {
-        for (int q = 0; q < c.np; ++q) {
+    {
+        for (int q = 0; q < c.nrelax; ++q) {
             const double hp = c.hl(q + 1);
             for (int m = 0; m < c.pnl[q]; ++m) {
                 Level &L = P.patch[q][m];
@@ -635,16 +648,15 @@ struct Runner {
     }
 };
 
-ndgp_status check_arrays(const Cfg &c, const double *const *delta, double *const *phi,
-                         bool need_patch_delta) {
+ndgp_status check_arrays(const Cfg &c, const double *const *delta, double *const *phi) {
     if (!delta || !phi || !delta[0] || !phi[0])
         return fail(NDGP_EINVAL, "delta[0] and phi[0] must not be NULL");
     if (reinterpret_cast<uintptr_t>(phi[0]) % 16 != 0)
         return fail(NDGP_EINVAL, "phi[0] must be 16-byte aligned");
     for (int q = 0; q < c.np; ++q) {
         if (!phi[q + 1]) return fail(NDGP_EINVAL, "phi of every patch must not be NULL");
-        if (need_patch_delta && !delta[q + 1])
-            return fail(NDGP_EINVAL, "delta of every patch must not be NULL in full mode");
+        if (q < c.nrelax && !delta[q + 1])
+            return fail(NDGP_EINVAL, "delta of every relaxed patch must not be NULL");
     }
     return NDGP_OK;
 }
@@ -657,7 +669,7 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     std::string why;
     if (!resolve(grid, params, P.c, why)) return fail(NDGP_EINVAL, why);
     const Cfg &c = P.c;
-    ndgp_status s = check_arrays(c, delta, phi, c.mode == NDGP_MODE_FULL);
+    ndgp_status s = check_arrays(c, delta, phi);
     if (s != NDGP_OK) return s;
     const size_t need = total_bytes(c);
     if (!ws || ws_bytes < need)
@@ -726,10 +738,10 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     for (int q = 0; q < c.np; ++q) {
         const bool parent_periodic = q == 0;
         const double *parent = phi[q];
-        const int npar = q == 0 ? c.n : c.pn[0];
+        const int npar = q == 0 ? c.n : c.pn[q - 1];
         ChildBox b0{{c.po[q][0], c.po[q][1], c.po[q][2]}, 0, c.pn[q]};
         launch_interpolate(parent, npar, parent_periodic, b0, phi[q + 1], false, st);
-        if (c.mode == NDGP_MODE_INTERPOLATED) continue; // Sec. III.B: keep the guess
+        if (q >= c.nrelax) continue; // Sec. III.B: a truncated level keeps the guess
         Level *H = P.patch[q];
         H[0].phi = phi[q + 1];
         launch_interpolate(parent, npar, parent_periodic, b0, H[0].alt, true, st);
@@ -820,7 +832,7 @@ ndgp_status force_impl(const ndgp_grid *grid, const double *const phi[], double 
     p.beta = 1.0;
     p.a = 1.0;
     p.omega_m = 1.0;
-    p.mode = NDGP_MODE_INTERPOLATED; // geometry checks only need level 0 of patch 2
+    p.mode = NDGP_MODE_INTERPOLATED; // geometry checks only need the finest patch levels
     Cfg c;
     std::string why;
     if (!resolve(grid, &p, c, why)) return fail(NDGP_EINVAL, why);
@@ -843,8 +855,8 @@ struct ndgp_plan {
     double *slot = nullptr; // pinned: [0] sum delta, [1] sum s^2, [2] sum r^2,
                             //         [3] sum phi, [4] fallbacks (bits)
     hipEvent_t ev = nullptr;
-    const double *delta[1 + NDGP_MAX_PATCHES] = {nullptr, nullptr, nullptr};
-    double *phi[1 + NDGP_MAX_PATCHES] = {nullptr, nullptr, nullptr};
+    const double *delta[1 + NDGP_MAX_PATCHES] = {};
+    double *phi[1 + NDGP_MAX_PATCHES] = {};
     enum State { RUNNING, READY, FINISHING, DONE } state = RUNNING;
     bool started = false, restarting = false;
     double snorm2 = 0.0;
@@ -871,8 +883,8 @@ void plan_enqueue_tail(ndgp_plan *pl, bool zero_field) {
     launch_shift_by_mean(pl->phi[0], cells0, pl->P.scal + 3, pl->st);
     for (int q = 0; q < c.np; ++q) {
         ChildBox b0{{c.po[q][0], c.po[q][1], c.po[q][2]}, 0, c.pn[q]};
-        launch_interpolate(pl->phi[q], q == 0 ? c.n : c.pn[0], q == 0, b0, pl->phi[q + 1], false,
-                           pl->st);
+        launch_interpolate(pl->phi[q], q == 0 ? c.n : c.pn[q - 1], q == 0, b0, pl->phi[q + 1],
+                           false, pl->st);
     }
     HIP_TRY(hipMemcpyAsync(pl->slot + 3, pl->P.scal + 3, sizeof(double), hipMemcpyDeviceToHost,
                            pl->st));
@@ -890,10 +902,10 @@ ndgp_status plan_create_impl(const ndgp_grid *grid, const ndgp_params *params,
     Cfg c;
     std::string why;
     if (!resolve(grid, params, c, why)) return fail(NDGP_EINVAL, why);
-    if (c.np > 0 && c.mode != NDGP_MODE_INTERPOLATED)
-        return fail(NDGP_EINVAL, "plans relax the domain level only: patches need "
-                                 "NDGP_MODE_INTERPOLATED");
-    ndgp_status s = check_arrays(c, delta, phi, false);
+    if (c.nrelax > 0)
+        return fail(NDGP_EINVAL, "plans relax the domain level only: patches must all be "
+                                 "interpolated");
+    ndgp_status s = check_arrays(c, delta, phi);
     if (s != NDGP_OK) return s;
     const size_t need = total_bytes(c);
     if (!ws || ws_bytes < need)

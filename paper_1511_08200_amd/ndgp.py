@@ -22,12 +22,13 @@ LIB_PATH = os.path.join(HERE, "libndgp.so")
 C_OVER_H0_MPC_H = 2997.92458  # c / H0 in Mpc/h
 
 NDGP_OK, NDGP_EINVAL, NDGP_ENOMEM, NDGP_ENOCONV, NDGP_EDEVICE = 0, -1, -2, -3, -4
-MODE_FULL, MODE_INTERPOLATED = 0, 1
+MODE_FULL, MODE_INTERPOLATED, MODE_TRUNCATED = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 WARM_START = 1
 PROFILE = 2
 TWO_PASS = 4
-MAX_PATCHES = 2
+MAX_PATCHES = 4
+ABI_VERSION = 2
 HIST_LEN = 64
 
 _STATUS = {NDGP_EINVAL: "EINVAL", NDGP_ENOMEM: "ENOMEM", NDGP_ENOCONV: "ENOCONV",
@@ -51,7 +52,8 @@ class _Params(ctypes.Structure):
                 ("omega_m", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
                 ("n_levels", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("trunc_level", ctypes.c_int32)]
 
 
 class _Report(ctypes.Structure):
@@ -77,6 +79,9 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         L.ndgp_version.restype = ctypes.c_int32
+        if L.ndgp_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {L.ndgp_version()}, this binding "
+                               f"needs {ABI_VERSION}: rebuild it")
         L.ndgp_last_error.restype = ctypes.c_char_p
         L.ndgp_beta_lcdm.restype = ctypes.c_double
         L.ndgp_beta_lcdm.argtypes = [ctypes.c_double] * 3
@@ -139,6 +144,8 @@ class Grid:
     patches: list = dataclasses.field(default_factory=list)
 
     def _c(self) -> _Grid:
+        if len(self.patches) > MAX_PATCHES:
+            raise ValueError(f"at most {MAX_PATCHES} nested patches")
         g = _Grid()
         g.n, g.h, g.n_patch = self.n, self.h, len(self.patches)
         for q, p in enumerate(self.patches):
@@ -166,6 +173,7 @@ class Params:
     nu2: int = 2
     n_levels: int = 0
     mode: int = MODE_FULL
+    trunc_level: int = 0  # MODE_TRUNCATED: first interpolated refinement level
     precision: int = PREC_FP64
     warm_start: bool = False
     profile: bool = False
@@ -176,7 +184,7 @@ class Params:
         p.rc, p.a, p.omega_m, p.tol = self.rc, self.a, self.omega_m, self.tol
         p.beta = self.beta if self.beta is not None else beta_lcdm(self.a, self.omega_m, self.rc)
         p.max_cycles, p.nu1, p.nu2, p.n_levels = self.max_cycles, self.nu1, self.nu2, self.n_levels
-        p.mode, p.precision = self.mode, self.precision
+        p.mode, p.precision, p.trunc_level = self.mode, self.precision, self.trunc_level
         p.flags = ((WARM_START if self.warm_start else 0) | (PROFILE if self.profile else 0)
                    | (TWO_PASS if self.two_pass else 0))
         return p

@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_version_and_beta(L):
-    assert L.ndgp_version() == 1
+    assert L.ndgp_version() == 2
     for rc in (0.5, 1.0, 2.0, 5.0):
         assert ndgp.beta_lcdm(1.0, 0.3, rc) == pytest.approx(1 + 1.7 * rc, rel=1e-14)
     # a < 1: against Eq. (beta) with a numerical Hdot
@@ -124,8 +124,59 @@ def test_workspace_bytes_and_validation(L):
     assert b"patch 2" in L.ndgp_last_error()
 
 
+def _nested(g, depth, m=32, origin=8):
+    """``depth`` patches of m cells, each centred in its parent of m cells."""
+    g.n_patch = depth
+    for q in range(depth):
+        g.patch_n[q] = m
+        g.patch_origin[q][:] = [origin] * 3
+
+
+def test_truncation_level_validation_and_workspace(L):
+    """NDGP_MODE_TRUNCATED: trunc_level in [1, n_patch + 1]; only the relaxed
+    patches get multigrid hierarchies, so the workspace grows with the level,
+    from the interpolated mode's (level 1) to the full mode's (n_patch + 1)."""
+    g, p = _args(mode=ndgp.MODE_FULL)
+    _nested(g, 4)
+    full = L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p))
+    p.mode = ndgp.MODE_INTERPOLATED
+    interp = L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p))
+    assert 0 < interp < full
+    p.mode = ndgp.MODE_TRUNCATED
+    sizes = []
+    for k in range(1, 6):
+        p.trunc_level = k
+        sizes.append(L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
+    assert sizes[0] == interp and sizes[-1] == full
+    assert all(a < b for a, b in zip(sizes, sizes[1:]))
+    for k in (0, 6, -1):
+        p.trunc_level = k
+        assert L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) == 0
+        assert b"trunc_level" in L.ndgp_last_error()
+    # other modes ignore trunc_level
+    p.mode, p.trunc_level = ndgp.MODE_FULL, 99
+    assert L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) == full
+    p.mode = 3
+    assert L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) == 0
+    # a patch next to its parent's edge fits as an interpolated level (its own
+    # cells only) but not as a relaxed one (the 8^3 level's stencil reaches out)
+    g, p = _args(mode=ndgp.MODE_TRUNCATED, trunc_level=3)
+    _nested(g, 3)
+    g.patch_origin[2][:] = [16, 8, 8]
+    assert L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) > 0
+    p.trunc_level = 4
+    assert L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) == 0
+    assert b"patch 3" in L.ndgp_last_error()
+    # at most NDGP_MAX_PATCHES levels
+    g, p = _args()
+    g.n_patch = ndgp.MAX_PATCHES + 1
+    assert L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) == 0
+    with pytest.raises(ValueError):
+        ndgp.Grid(n=32, h=1e-3, patches=[ndgp.Patch(32, (8, 8, 8))] * 5)._c()
+
+
 def test_solve_rejects_bad_arguments_before_gpu_work(L):
-    arr = (ctypes.c_void_p * 3)()
+    arr = (ctypes.c_void_p * (1 + ndgp.MAX_PATCHES))()
     g, p = _args(n=12)
     st = L.ndgp_solve(ctypes.byref(g), ctypes.byref(p), arr, arr, None, 0, None, None)
     assert st == ndgp.NDGP_EINVAL

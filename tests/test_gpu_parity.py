@@ -173,7 +173,7 @@ def test_fused_kernels_bitwise_equal_per_level_launches(n, levels):
                        [d])
     torch.cuda.synchronize()
     assert ra.cycles == rb.cycles and ra.history == rb.history
-    assert ra.damped_from == [0, 0, 0] # the safeguard stays off for ordinary fields
+    assert not any(ra.damped_from)  # the safeguard stays off for ordinary fields
     assert torch.equal(a[0], b[0])
 
 
@@ -285,6 +285,61 @@ def test_patches_match_oracle(interpolated, wrap):
         assert np.abs(fg[lvl] - fo).max() <= 1e-13 * np.abs(fo).max()
         fo_or = O.force(phio[lvl], grid.level_h(lvl), periodic=(lvl == 0))
         assert rel(fg[lvl], fo_or) <= 1e-10
+
+
+def deep_patch_problem(n=32, m=32, depth=4, seed=12):
+    """``depth`` nested patches of m cells (ratio 2 each), centred on the
+    largest top-hat and kept 2 parent cells inside their parent."""
+    f = synth.make_field(n, 2.0, seed, n_tophats=6)
+    c = synth.densest_tophat_centre(f)
+    chain, deltas, patches = [], [f.delta], []
+    for q in range(depth):
+        o = synth.patch_origin_centred(c, m // 2)
+        if q > 0:
+            o = tuple(min(max(v, 2), m - m // 2 - 2) for v in o)
+        chain.append(o)
+        deltas.append(synth.patch_delta(f, n, chain, m))
+        patches.append(ndgp.Patch(m, o))
+        c = tuple((c[a] - o[a]) * 2 for a in range(3))
+    return f, deltas, ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n), patches=patches)
+
+
+@pytest.mark.parametrize("trunc", [1, 2, 3, 4, 5])
+def test_truncation_levels_match_oracle(trunc):
+    """NDGP_MODE_TRUNCATED on four nested patches (Sec. IV.A, l_trunc =
+    l_d + trunc): the relaxed levels are those of the full mode bit for bit,
+    the truncated ones are interpolated from their own parent, and every level
+    matches the oracle's truncated path."""
+    say(f"truncation level {trunc}: 32^3 + 4 nested 32^3 patches")
+    rc = 1.0
+    f, deltas, grid = deep_patch_problem()
+    beta = O.beta_lcdm(1.0, 0.3, rc)
+    prob = O.Problem(delta=deltas, h=grid.h, rc=rc, beta=beta,
+                     origins=tuple(p.origin for p in grid.patches))
+    phio, infos = O.solve_problem(prob, trunc_level=trunc)
+    for inf in infos[:trunc]:
+        assert inf.status == 0
+    phit, rept = gpu_solve(deltas, grid, rc=rc, tol=0.0, max_cycles=200,
+                           mode=ndgp.MODE_TRUNCATED, trunc_level=trunc)
+    say(f"  cycles={rept.cycles} rel_res={rept.rel_res}")
+    assert rept.status == 0
+    phif, repf = gpu_solve(deltas, grid, rc=rc, tol=0.0, max_cycles=200, mode=ndgp.MODE_FULL)
+    for lvl in range(5):
+        e = rel(phit[lvl], phio[lvl])
+        say(f"  level {lvl}: rel err {e:.2e}")
+        assert e <= PHI_TOL
+        if lvl < trunc:
+            assert np.array_equal(phit[lvl], phif[lvl])
+            assert rept.cycles[lvl] == repf.cycles[lvl] and rept.rel_res[lvl] >= 0.0
+        else:
+            assert rept.cycles[lvl] == 0 and rept.rel_res[lvl] == -1.0
+            pq = grid.patches[lvl - 1]
+            want = O.interpolate(phit[lvl - 1], lvl == 1, pq.origin, 0, pq.n)
+            assert np.abs(phit[lvl] - want).max() <= 1e-14 * np.abs(want).max()
+    fg = [x.cpu().numpy() for x in ndgp.force(grid, [dev(p) for p in phit])]
+    for lvl in range(5):
+        fo = O.force(phio[lvl], grid.level_h(lvl), periodic=(lvl == 0))
+        assert rel(fg[lvl], fo) <= 1e-10
 
 
 def test_patch_residual_level():

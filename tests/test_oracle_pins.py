@@ -611,6 +611,66 @@ def test_patch_manufactured_solution(oracle_mod):
     np.testing.assert_allclose(phi_i, lin_child, rtol=1e-13)
 
 
+def trilinear_child(parent, periodic, origin, nc):
+    """Cell-centred trilinear interpolation written from its definition: the
+    child cell i (in [-1, nc]) of a ratio-2 box with lower corner ``origin``
+    sits at parent index coordinate origin + (i + 1/2)/2 - 1/2, between the
+    parent centres floor(.) and floor(.) + 1 with linear weights per axis.
+    A periodic parent is natural (indices wrap), any other has a one-cell
+    shell (index -1 at position 0)."""
+    idx, wts = [], []
+    for a in range(3):
+        x = origin[a] + (np.arange(-1, nc + 1) + 0.5) / 2 - 0.5
+        i0 = np.floor(x).astype(int)
+        idx.append(i0)
+        wts.append(x - i0)
+
+    def at(i):
+        return i % parent.shape[0] if periodic else i + 1
+
+    out = np.zeros((nc + 2,) * 3)
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                w = ((wts[2] if dz else 1 - wts[2])[:, None, None]
+                     * (wts[1] if dy else 1 - wts[1])[None, :, None]
+                     * (wts[0] if dx else 1 - wts[0])[None, None, :])
+                out += w * parent[np.ix_(at(idx[2] + dz), at(idx[1] + dy), at(idx[0] + dx))]
+    return out
+
+
+def test_truncation_level_composition(oracle_mod):
+    """Sec. III.B / IV.A: with truncation level k the refinements 1..k-1 are
+    solved as in the full run and every level from k on is the trilinear
+    interpolation of its own parent (itself interpolated beyond k), interior
+    and ghost shell alike.  Four nested 16^3 patches, one wrapping the
+    periodic domain; the interpolation is recomputed from its definition."""
+    O = oracle_mod
+    n, m = 16, 16
+    f = synth.make_field(n, 2.0, 21, n_tophats=3)
+    origins = [(-3, 4, 5), (4, 4, 4), (3, 5, 4), (4, 4, 3)]
+    chain, deltas = [], [f.delta]
+    for o in origins:
+        chain.append(o)
+        deltas.append(synth.patch_delta(f, n, chain, m))
+    beta = O.beta_lcdm(1.0, 0.3, 1.0)
+    prob = O.Problem(delta=deltas, h=4.0 / 2997.92458, rc=1.0, beta=beta, origins=tuple(origins))
+    full, finfo = O.solve_problem(prob)
+    assert all(i.status == 0 and i.rel_res < 1e-11 for i in finfo)
+    for k in (1, 3):
+        phis, infos = O.solve_problem(prob, trunc_level=k)
+        np.testing.assert_array_equal(phis[0], full[0])
+        for lvl in range(1, 5):
+            if lvl < k:
+                np.testing.assert_array_equal(phis[lvl], full[lvl])
+                continue
+            assert infos[lvl].cycles == 0
+            want = trilinear_child(phis[lvl - 1], lvl == 1, origins[lvl - 1], m)
+            np.testing.assert_allclose(phis[lvl], want, rtol=0, atol=1e-15 * np.abs(want).max())
+        # the interpolated levels differ from the relaxed ones: truncation is not a no-op
+        assert rel(phis[4][1:-1, 1:-1, 1:-1], full[4][1:-1, 1:-1, 1:-1]) > 1e-6
+
+
 # ---------------------------------------------------------------------------
 # force, Sec. III.B
 
