@@ -169,6 +169,42 @@ const char *ndgp_last_error(void);
    H0 = 1.  Host function. */
 double ndgp_beta_lcdm(double a, double omega_m, double rc);
 
+/*
+ * Screening in NFW haloes, to choose the truncation level (Sec. II.B, Sec. V).
+ * Host functions; no GPU work.  Masses in M_sun/h, lengths in Mpc/h, both
+ * physical (at z = 0 the same as comoving); e_z = H(z)/H0 (1 at z = 0); rc is
+ * r_c H0 and beta is beta(a) of Eq. (beta).  Invalid arguments give NaN (or -1)
+ * and a message for ndgp_last_error().
+ *
+ * ndgp_nfw_r200           R_200 of Eq. (r200), read with exponent 1/3: the
+ *                         radius inside which the mean density is 200 times
+ *                         the critical density 3 H(z)^2 / (8 pi G).
+ * ndgp_nfw_force_ratio    G_eff - 1 = F_5th / F_GR at radius r of an NFW halo
+ *                         (Eqs. nfw, nfwparams) from the spherical solution,
+ *                         Eqs. (eomvarphi_sph2) and (rv).  Depends on r / R_200
+ *                         and c200 only; tends to 1/(3 beta) far outside
+ *                         (Eq. forcelarge) and to 0 deep inside.
+ * ndgp_nfw_screening_radius  r_t: the radius where G_eff - 1 has fallen to
+ *                         `fraction` (Sec. V); +inf if the unscreened value
+ *                         1/(3 beta) is not above it (or rc = 0), 0 for
+ *                         fraction <= 0.
+ * ndgp_nfw_trunc_level    the first truncated refinement level k >= 1
+ *                         (NDGP_MODE_TRUNCATED's trunc_level, the paper's
+ *                         l_trunc - l_d): the coarsest refinement whose cell
+ *                         size h_domain / 2^k is at most r_t (Sec. V: the
+ *                         truncated levels are those with cells smaller than
+ *                         r_t).  h_domain is the domain cell size in the same
+ *                         physical Mpc/h.  A result above n_patch means no
+ *                         patch is truncated.
+ */
+double ndgp_nfw_r200(double m200, double e_z);
+double ndgp_nfw_force_ratio(double r, double m200, double c200, double rc, double beta,
+                            double e_z);
+double ndgp_nfw_screening_radius(double fraction, double m200, double c200, double rc,
+                                 double beta, double e_z);
+int32_t ndgp_nfw_trunc_level(double h_domain, double fraction, double m200, double c200,
+                             double rc, double beta, double e_z);
+
 /* Bytes of device workspace that ndgp_solve / ndgp_residual need for this
    grid and these parameters (0 if the arguments are invalid). */
 size_t ndgp_workspace_bytes(const ndgp_grid *grid, const ndgp_params *params);

@@ -124,6 +124,9 @@ void launch_diff_partials(const double *a, const double *b, size_t count, double
 // dst[i] = src[i]
 void launch_copy(const double *src, double *dst, size_t count, hipStream_t st);
 
+// message for ndgp_last_error() in the calling thread
+void set_last_error(const char *msg);
+
 } // namespace ndgp
 
 namespace ndgp {

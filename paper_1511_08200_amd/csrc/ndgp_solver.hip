@@ -1097,6 +1097,8 @@ ndgp_status guarded(F &&f) {
 // ------------------------------------------------------------------------
 // C ABI
 
+void ndgp::set_last_error(const char *msg) { g_err = msg; }
+
 extern "C" {
 
 int32_t ndgp_version(void) { return NDGP_ABI_VERSION; }

@@ -11,6 +11,7 @@ one-cell ghost shell, shape (m+2, m+2, m+2).
 from __future__ import annotations
 
 import ctypes
+import math
 import dataclasses
 import os
 from typing import Optional, Sequence
@@ -85,6 +86,15 @@ def lib():
         L.ndgp_last_error.restype = ctypes.c_char_p
         L.ndgp_beta_lcdm.restype = ctypes.c_double
         L.ndgp_beta_lcdm.argtypes = [ctypes.c_double] * 3
+        d = ctypes.c_double
+        L.ndgp_nfw_r200.restype = d
+        L.ndgp_nfw_r200.argtypes = [d, d]
+        L.ndgp_nfw_force_ratio.restype = d
+        L.ndgp_nfw_force_ratio.argtypes = [d] * 6
+        L.ndgp_nfw_screening_radius.restype = d
+        L.ndgp_nfw_screening_radius.argtypes = [d] * 6
+        L.ndgp_nfw_trunc_level.restype = ctypes.c_int32
+        L.ndgp_nfw_trunc_level.argtypes = [d] * 7
         L.ndgp_workspace_bytes.restype = ctypes.c_size_t
         L.ndgp_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params)]
         arr3 = vp * (1 + MAX_PATCHES)
@@ -129,6 +139,39 @@ def cell_size(box_mpc_h: float, n: int) -> float:
 def beta_lcdm(a: float, omega_m: float, rc: float) -> float:
     """beta(a) of Eq. (beta) for an LCDM expansion history (library routine)."""
     return float(lib().ndgp_beta_lcdm(a, omega_m, rc))
+
+
+def _finite_or_raise(v: float) -> float:
+    if math.isnan(v):
+        raise ValueError(lib().ndgp_last_error().decode())
+    return float(v)
+
+
+def nfw_r200(m200: float, e_z: float = 1.0) -> float:
+    """R_200 in Mpc/h of a halo of M_200 M_sun/h (Eq. r200)."""
+    return _finite_or_raise(lib().ndgp_nfw_r200(m200, e_z))
+
+
+def nfw_force_ratio(r: float, m200: float, c200: float, rc: float, beta: float,
+                    e_z: float = 1.0) -> float:
+    """G_eff - 1 = F_5th / F_GR at radius r (Mpc/h) of an NFW halo."""
+    return _finite_or_raise(lib().ndgp_nfw_force_ratio(r, m200, c200, rc, beta, e_z))
+
+
+def nfw_screening_radius(fraction: float, m200: float, c200: float, rc: float, beta: float,
+                         e_z: float = 1.0) -> float:
+    """r_t (Mpc/h): where G_eff - 1 has fallen to ``fraction``."""
+    return _finite_or_raise(lib().ndgp_nfw_screening_radius(fraction, m200, c200, rc, beta, e_z))
+
+
+def nfw_trunc_level(h_domain: float, fraction: float, m200: float, c200: float, rc: float,
+                    beta: float, e_z: float = 1.0) -> int:
+    """First truncated refinement level (Params.trunc_level) for a halo whose
+    fifth force must be below ``fraction`` of gravity wherever it is truncated."""
+    k = int(lib().ndgp_nfw_trunc_level(h_domain, fraction, m200, c200, rc, beta, e_z))
+    if k < 0:
+        raise ValueError(lib().ndgp_last_error().decode())
+    return k
 
 
 @dataclasses.dataclass

@@ -133,3 +133,57 @@ def test_screening_radius_and_level_by_brute_force():
                 assert h / 2 ** (k - 1) > rt
     assert N.screening_radius(0.2, 1e13, 5.0, RC, BETA) == math.inf   # above 1/(3 beta)
     assert N.screening_radius(0.0, 1e13, 5.0, RC, BETA) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# the library's host functions against the oracle
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1511_08200_amd import ndgp
+    if not os.path.exists(ndgp.LIB_PATH):
+        from paper_1511_08200_amd import build
+        build.build()
+    return ndgp
+
+
+def test_library_r200_and_ratio_match_oracle(lib):
+    for ez in (1.0, 2.2):
+        for m in (1e11, 1e12, 1e13, 1e14, 1e15):
+            assert lib.nfw_r200(m, ez) == pytest.approx(N.r200(m, ez), rel=1e-14)
+            R = N.r200(m, ez)
+            for c in CS:
+                for s in (1e-3, 0.01, 0.1, 0.5, 1.0, 2.0, 10.0, 100.0):
+                    want = N.force_ratio(s * R, m, c, RC, BETA, ez)
+                    got = lib.nfw_force_ratio(s * R, m, c, RC, BETA, ez)
+                    assert got == pytest.approx(want, rel=1e-11), (m, c, s)
+    # r_c = 0: no screening
+    assert lib.nfw_force_ratio(0.1, 1e13, 5.0, 0.0, BETA) == pytest.approx(1 / (3 * BETA), rel=1e-15)
+
+
+def test_library_screening_radius_and_level_match_oracle(lib):
+    h = PAPER["simulation"]["box_mpc_h"] / PAPER["simulation"]["particles_per_side"]
+    for m in (1e12, 1e13, 1e14):
+        for c in (5.0, 10.0):
+            for frac in (0.005, 0.02, 0.07, 0.12):
+                want = N.screening_radius(frac, m, c, RC, BETA)
+                got = lib.nfw_screening_radius(frac, m, c, RC, BETA)
+                assert got == pytest.approx(want, rel=1e-9), (m, c, frac)
+                assert lib.nfw_trunc_level(h, frac, m, c, RC, BETA) == \
+                    N.truncation_level(h, frac, m, c, RC, BETA)
+    assert lib.nfw_screening_radius(0.2, 1e13, 5.0, RC, BETA) == math.inf
+    assert lib.nfw_screening_radius(0.0, 1e13, 5.0, RC, BETA) == 0.0
+    assert lib.nfw_trunc_level(h, 0.2, 1e13, 5.0, RC, BETA) == 1   # nothing is screened: l_d + 1
+
+
+def test_library_rejects_bad_arguments(lib):
+    with pytest.raises(ValueError, match="m200"):
+        lib.nfw_force_ratio(0.1, -1.0, 5.0, RC, BETA)
+    with pytest.raises(ValueError, match="r > 0"):
+        lib.nfw_force_ratio(0.0, 1e13, 5.0, RC, BETA)
+    with pytest.raises(ValueError):
+        lib.nfw_r200(1e13, 0.0)
+    with pytest.raises(ValueError, match="fraction"):
+        lib.nfw_trunc_level(0.5, 0.0, 1e13, 5.0, RC, BETA)
+    with pytest.raises(ValueError, match="h_domain"):
+        lib.nfw_trunc_level(-0.5, 0.02, 1e13, 5.0, RC, BETA)
