@@ -880,8 +880,9 @@ k_coarsest(double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix, d
 // half sweep computes the new values of its colour into registers, waits for
 // the whole workgroup, then stores them: every read sees the values of the
 // start of the half sweep, as with the out-of-place kernels.
-constexpr int kBottomThreads = 1024;
-constexpr int kBottomCells = 4096 + 512 + 64 + 8; // 16^3 + 8^3 + 4^3 + 2^3
+constexpr int kBottomThreads = 512;
+constexpr int kBottomPerThread = 2048 / kBottomThreads; // cells of one colour at 16^3
+constexpr int kBottomCells = 4096 + 512 + 64 + 8;       // 16^3 + 8^3 + 4^3 + 2^3
 
 __global__ void __launch_bounds__(kBottomThreads)
 k_bottom(double *__restrict__ phi, const double *__restrict__ s, int lg0, BottomLevels bl,
@@ -915,7 +916,7 @@ k_bottom(double *__restrict__ phi, const double *__restrict__ s, int lg0, Bottom
         double *ph = PHI + off(q);
         const double *sr = SRC + off(q);
         const double al = alpha(q);
-        const int ncol = (n * n * n) >> 1; // cells of one colour: at most 2 per thread
+        const int ncol = (n * n * n) >> 1; // cells of one colour
         // new value of the t-th cell of colour col, or at = -1 past the last
         auto cell = [&](int t, int col, double &val, int &at) {
             at = -1;
@@ -931,14 +932,18 @@ k_bottom(double *__restrict__ phi, const double *__restrict__ s, int lg0, Bottom
         };
         for (int sw = 0; sw < sweeps; ++sw)
             for (int col = 0; col < 2; ++col) {
-                double v0 = 0.0, v1 = 0.0;
-                int a0, a1;
-                cell(tid, col, v0, a0);
-                __builtin_amdgcn_sched_barrier(0); // one cell at a time: no spills
-                cell(tid + kBottomThreads, col, v1, a1);
+                double v[kBottomPerThread];
+                int at[kBottomPerThread];
+#pragma unroll
+                for (int c = 0; c < kBottomPerThread; ++c) {
+                    v[c] = 0.0;
+                    cell(tid + c * kBottomThreads, col, v[c], at[c]);
+                    __builtin_amdgcn_sched_barrier(0); // one cell at a time: no spills
+                }
                 __syncthreads();
-                if (a0 >= 0) ph[a0] = v0;
-                if (a1 >= 0) ph[a1] = v1;
+#pragma unroll
+                for (int c = 0; c < kBottomPerThread; ++c)
+                    if (at[c] >= 0) ph[at[c]] = v[c];
                 __syncthreads();
             }
     };
