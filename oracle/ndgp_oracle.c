@@ -217,6 +217,9 @@ typedef struct {
     double *phihat; /* padded: restriction of the finer phi (FAS); NULL on the top level */
     double *work;   /* padded scratch */
     double *ghost;  /* padded: fixed boundary values (Dirichlet levels); NULL if periodic */
+    const unsigned char *mask; /* natural n^3: 0 = cell held at its initial value
+                                  (cell-wise truncation); NULL = every cell relaxed */
+    unsigned char *mask_own;   /* coarse levels: the mask this level owns */
 } level_t;
 
 typedef struct {
@@ -234,6 +237,7 @@ static void hier_free(hier_t *H)
         free(H->lv[l].phihat);
         free(H->lv[l].work);
         free(H->lv[l].ghost);
+        free(H->lv[l].mask_own);
     }
     H->nl = 0;
 }
@@ -317,6 +321,7 @@ static void newton_gs_sweep(const hier_t *H, level_t *L)
         for (int k = pk; k < n; k += 2)
             for (int j = pj; j < n; j += 2)
                 for (int i = pi; i < n; i += 2) {
+                    if (L->mask && !L->mask[((int64_t)k * n + j) * n + i]) continue;
                     /* Newton-Raphson on the cell's own equation, Eq. (newton),
                        repeated until the cell residual stops changing. */
                     const int64_t c = pidx(n, i, j, k);
@@ -349,8 +354,11 @@ static double residual(const hier_t *H, level_t *L)
         double s = 0.0;
         for (int j = 0; j < n; ++j)
             for (int i = 0; i < n; ++i) {
-                const double r = L->S[pidx(n, i, j, k)]
-                                 - op_cell(L->phi, n, i, j, k, L->h, H->alpha, NULL);
+                /* a held cell is not part of the equations being solved */
+                const int held = L->mask && !L->mask[((int64_t)k * n + j) * n + i];
+                const double r = held ? 0.0
+                                      : L->S[pidx(n, i, j, k)]
+                                            - op_cell(L->phi, n, i, j, k, L->h, H->alpha, NULL);
                 L->work[pidx(n, i, j, k)] = r;
                 s += r * r;
             }
@@ -397,12 +405,14 @@ static void restrict_avg(int nf, const double *fine, double *coarse)
 /* fine += trilinear interpolation of the coarse correction.  A fine cell
    centre lies a quarter of a coarse cell from its parent's centre along each
    axis: weight 3/4 on the parent and 1/4 on the neighbour on its side. */
-static void prolong_add(int nc, const double *corr, int nf, double *fine)
+static void prolong_add(int nc, const double *corr, int nf, double *fine,
+                        const unsigned char *mask)
 {
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < nf; ++k)
         for (int j = 0; j < nf; ++j)
             for (int i = 0; i < nf; ++i) {
+                if (mask && !mask[((int64_t)k * nf + j) * nf + i]) continue; /* held */
                 const int I = i >> 1, J = j >> 1, K = k >> 1;
                 const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
                 double v = 0.0;
@@ -457,7 +467,7 @@ static void vcycle(hier_t *H, int l, const mgopt_t *o)
     const int64_t pc = (int64_t)(nc + 2) * (nc + 2) * (nc + 2);
     for (int64_t q = 0; q < pc; ++q) C->work[q] = C->phi[q] - C->phihat[q];
     if (H->periodic) fill_periodic(nc, C->work);
-    prolong_add(nc, C->work, L->n, L->phi);
+    prolong_add(nc, C->work, L->n, L->phi, L->mask);
     apply_bc(H, L, L->phi);
 
     for (int s = 0; s < o->nu2; ++s) newton_gs_sweep(H, L);
@@ -470,7 +480,7 @@ static void prolong_full(const hier_t *H, level_t *C, level_t *F)
     apply_bc(H, C, C->phi);
     const int64_t pf = (int64_t)(F->n + 2) * (F->n + 2) * (F->n + 2);
     for (int64_t q = 0; q < pf; ++q) F->phi[q] = 0.0;
-    prolong_add(C->n, C->phi, F->n, F->phi);
+    prolong_add(C->n, C->phi, F->n, F->phi, NULL);
     apply_bc(H, F, F->phi);
 }
 
@@ -507,6 +517,7 @@ static int drive(hier_t *H, const mgopt_t *o, int max_cycles, double tol, double
     double rel = prev;
     while (cyc < max_cycles) {
         if (tol > 0 && rel <= tol) break;
+        if (rel == 0.0) break; /* exact, e.g. every cell held */
         vcycle(H, 0, o);
         ++cyc;
         rel = sqrt(residual(H, L)) / snorm;
@@ -686,6 +697,7 @@ int oracle_solve_periodic(int n, double h, double alpha, const double *S, double
 int oracle_solve_patch(int nc, double hc, double alpha, const double *S, const double *parent,
                        int np, int parent_periodic, const int origin[3], double *phi_pad,
                        int max_cycles, double tol, int nu1, int nu2, int interp_only,
+                       const unsigned char *mask,
                        double *hist, int hist_len, int *cycles_out, double *relres_out)
 {
     if (oracle_interpolate(parent, np, parent_periodic, origin, 0, nc, phi_pad, 0)) return -1;
@@ -707,6 +719,31 @@ int oracle_solve_patch(int nc, double hc, double alpha, const double *S, const d
     const int64_t pc = (int64_t)(nc + 2) * (nc + 2) * (nc + 2);
     memcpy(H.lv[0].phi, phi_pad, sizeof(double) * (size_t)pc);
     natural_to_padded(nc, S, H.lv[0].S);
+    H.lv[0].mask = mask;
+    /* coarse levels hold a cell whose eight children are all held: the held
+       regions stay fixed (zero correction) on every level of the cycle, which
+       keeps the coarse-grid correction consistent with them; a coarse cell
+       with any iterated child is iterated */
+    for (int l = 1; mask && l < H.nl; ++l) {
+        const int n = H.lv[l].n, nf = H.lv[l - 1].n;
+        const unsigned char *mf = H.lv[l - 1].mask;
+        unsigned char *mc = (unsigned char *)malloc((size_t)n * n * n);
+        if (!mc) {
+            hier_free(&H);
+            return -2;
+        }
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    int any = 0;
+                    for (int c = 0; c < 8; ++c)
+                        any |= mf[((int64_t)(2 * k + (c >> 2)) * nf + 2 * j + ((c >> 1) & 1)) * nf
+                                  + 2 * i + (c & 1)];
+                    mc[((int64_t)k * n + j) * n + i] = (unsigned char)(any != 0);
+                }
+        H.lv[l].mask_own = mc;
+        H.lv[l].mask = mc;
+    }
     mgopt_t o = {nu1, nu2, 400, 1e-6};
     double snorm = sum_sq_interior(nc, H.lv[0].S);
     int rc = 0;
@@ -722,6 +759,53 @@ int oracle_solve_patch(int nc, double hc, double alpha, const double *S, const d
     memcpy(phi_pad, H.lv[0].phi, sizeof(double) * (size_t)pc);
     hier_free(&H);
     return rc;
+}
+
+/*
+ * Cell-wise truncation, the generalisation Sec. III.C proposes: a cell of a
+ * refinement is iterated only if the fifth force on its parent cell is still
+ * large, |F_5th| >= threshold |F_GR|, with F_5th = -grad(phi)/2 and
+ * F_GR = -grad(Psi_N) by central differences on the parent level.  Written
+ * without roots or divisions (the spacing cancels):
+ *     sum_a (phi[P+e_a] - phi[P-e_a])^2  >=  (2 threshold)^2 sum_a (psi[P+e_a] - psi[P-e_a])^2
+ * The child box (nc^3, ratio 2, lower corner `origin` in parent cells) lies
+ * inside the parent; child cell i has parent cell origin + floor(i/2).  Parent
+ * arrays are periodic natural (np^3) or padded ((np+2)^3).  mask is natural
+ * nc^3: 1 = iterate, 0 = hold the interpolated value.  Returns -1 if a needed
+ * parent cell is outside the parent.
+ */
+int oracle_cell_mask(const double *phi_parent, const double *psi_parent, int np,
+                     int parent_periodic, const int origin[3], int nc, double threshold,
+                     unsigned char *mask)
+{
+    const double t2 = (2.0 * threshold) * (2.0 * threshold);
+    for (int k = 0; k < nc; ++k)
+        for (int j = 0; j < nc; ++j)
+            for (int i = 0; i < nc; ++i) {
+                const int P[3] = {origin[0] + i / 2, origin[1] + j / 2, origin[2] + k / 2};
+                double gphi = 0.0, gpsi = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    int up[3] = {P[0], P[1], P[2]}, dn[3] = {P[0], P[1], P[2]};
+                    up[a] += 1;
+                    dn[a] -= 1;
+                    int64_t qu, qd;
+                    if (parent_periodic) {
+                        qu = ((int64_t)wrap(up[2], np) * np + wrap(up[1], np)) * np + wrap(up[0], np);
+                        qd = ((int64_t)wrap(dn[2], np) * np + wrap(dn[1], np)) * np + wrap(dn[0], np);
+                    } else {
+                        for (int b = 0; b < 3; ++b)
+                            if (up[b] > np || dn[b] < -1) return -1;
+                        qu = pidx(np, up[0], up[1], up[2]);
+                        qd = pidx(np, dn[0], dn[1], dn[2]);
+                    }
+                    const double dp = phi_parent[qu] - phi_parent[qd];
+                    const double ds = psi_parent[qu] - psi_parent[qd];
+                    gphi += dp * dp;
+                    gpsi += ds * ds;
+                }
+                mask[((int64_t)k * nc + j) * nc + i] = gphi >= t2 * gpsi ? 1 : 0;
+            }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */

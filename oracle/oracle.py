@@ -73,10 +73,14 @@ def lib():
                                             dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                             ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ip, dp]
         L.oracle_solve_patch.restype = ctypes.c_int
+        u8p = ctypes.POINTER(ctypes.c_ubyte)
         L.oracle_solve_patch.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp,
                                          ctypes.c_int, ctypes.c_int, ip, dp, ctypes.c_int,
                                          ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                         ctypes.c_int, dp, ctypes.c_int, ip, dp]
+                                         ctypes.c_int, u8p, dp, ctypes.c_int, ip, dp]
+        L.oracle_cell_mask.restype = ctypes.c_int
+        L.oracle_cell_mask.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ip, ctypes.c_int,
+                                       ctypes.c_double, u8p]
         L.oracle_force.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_int, dp]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -217,9 +221,11 @@ def solve_periodic(S, h: float, alpha_: float, phi0=None, max_cycles: int = 200,
 
 def solve_patch(S, h: float, alpha_: float, parent, parent_periodic: bool, origin,
                 interp_only: bool = False, max_cycles: int = 200, tol: float = 0.0,
-                nu1: int = 2, nu2: int = 2):
+                nu1: int = 2, nu2: int = 2, mask=None):
     """Refined-patch solve with boundary values and initial guess interpolated
-    from the parent (periodic natural or padded).  Returns (phi_pad, info)."""
+    from the parent (periodic natural or padded).  ``mask`` (uint8, natural
+    nc^3): cells with 0 keep the interpolated guess and are not part of the
+    equations solved (cell-wise truncation).  Returns (phi_pad, info)."""
     Sc = _c(S)
     nc = Sc.shape[0]
     par = _c(parent)
@@ -229,13 +235,37 @@ def solve_patch(S, h: float, alpha_: float, parent, parent_periodic: bool, origi
     hist = np.zeros(max(max_cycles, 1))
     cyc = ctypes.c_int()
     rel = ctypes.c_double()
+    mk = None
+    if mask is not None:
+        mk = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert mk.shape == (nc, nc, nc)
     st = lib().oracle_solve_patch(nc, h, alpha_, _dp(Sc), _dp(par), np_,
                                   1 if parent_periodic else 0, o, _dp(out), max_cycles, tol,
-                                  nu1, nu2, 1 if interp_only else 0, _dp(hist), len(hist),
-                                  ctypes.byref(cyc), ctypes.byref(rel))
+                                  nu1, nu2, 1 if interp_only else 0,
+                                  None if mk is None else mk.ctypes.data_as(
+                                      ctypes.POINTER(ctypes.c_ubyte)),
+                                  _dp(hist), len(hist), ctypes.byref(cyc), ctypes.byref(rel))
     if st == -1:
         raise ValueError("patch reaches outside its parent")
     return out, SolveInfo(st, cyc.value, rel.value, hist[:cyc.value].copy())
+
+
+def cell_mask(phi_parent, psi_parent, parent_periodic: bool, origin, nc: int,
+              threshold: float) -> np.ndarray:
+    """Sec. III.C: 1 where the parent cell's fifth force is at least
+    ``threshold`` times its Newtonian force (central differences of phi/2 and
+    of the Newtonian potential psi on the parent level), else 0.  Parents are
+    periodic natural or padded; returns uint8 natural nc^3."""
+    ph, ps = _c(phi_parent), _c(psi_parent)
+    assert ph.shape == ps.shape
+    np_ = ph.shape[0] if parent_periodic else ph.shape[0] - 2
+    out = np.zeros((nc, nc, nc), dtype=np.uint8)
+    o = (ctypes.c_int * 3)(*[int(v) for v in origin])
+    rc = lib().oracle_cell_mask(_dp(ph), _dp(ps), np_, 1 if parent_periodic else 0, o, nc,
+                                float(threshold), out.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+    if rc:
+        raise ValueError("child box reaches outside the parent")
+    return out
 
 
 def force(phi, h: float, periodic: bool = True) -> np.ndarray:
@@ -260,14 +290,17 @@ class Problem:
 
 
 def solve_problem(p: Problem, interpolated: bool = False, tol: float = 0.0,
-                  max_cycles: int = 200, trunc_level: int | None = None):
+                  max_cycles: int = 200, trunc_level: int | None = None, cellwise=None):
     """The whole path: domain level, then every patch level from its parent
     (Sec. III.A), or by interpolation only (Sec. III.B).  ``trunc_level`` k
     relaxes patch levels 1..k-1 and interpolates levels k and up, each from
     its own (relaxed or interpolated) parent: the truncation l >= l_trunc of
     Sec. IV.A with l_trunc = l_d + k.  k = 1 is ``interpolated=True``.
-    Returns (phis, infos): phis[0] natural zero-mean, phis[1:] padded with
-    ghosts."""
+    ``cellwise = (psi, threshold)``: on every relaxed patch only the cells whose
+    parent cell has |F_5th| >= threshold |F_GR| are iterated (Sec. III.C), with
+    psi[l] the Newtonian potential of level l (natural domain, padded patches).
+    Returns (phis, infos, masks) with cellwise, else (phis, infos): phis[0]
+    natural zero-mean, phis[1:] padded with ghosts."""
     if trunc_level is None:
         trunc_level = 1 if interpolated else len(p.delta)
     al = alpha(p.rc, p.beta, p.a)
@@ -275,12 +308,22 @@ def solve_problem(p: Problem, interpolated: bool = False, tol: float = 0.0,
     phi0, info0 = solve_periodic(S0, p.h, al, tol=tol, max_cycles=max_cycles)
     phis, infos = [phi0], [info0]
     parent, parent_periodic, h = phi0, True, p.h
+    masks = [None]
     for lvl in range(1, len(p.delta)):
         h = h / 2
         S = source_shift(p.delta[lvl], mean, p.omega_m, p.a, p.beta)
+        mk = None
+        if cellwise is not None and lvl < trunc_level:
+            psi, thr = cellwise
+            mk = cell_mask(parent, psi[lvl - 1], parent_periodic, p.origins[lvl - 1],
+                           S.shape[0], thr)
         ph, inf = solve_patch(S, h, al, parent, parent_periodic, p.origins[lvl - 1],
-                              interp_only=lvl >= trunc_level, tol=tol, max_cycles=max_cycles)
+                              interp_only=lvl >= trunc_level, tol=tol, max_cycles=max_cycles,
+                              mask=mk)
         phis.append(ph)
         infos.append(inf)
+        masks.append(mk)
         parent, parent_periodic = ph, False
+    if cellwise is not None:
+        return phis, infos, masks
     return phis, infos

@@ -671,6 +671,134 @@ def test_truncation_level_composition(oracle_mod):
         assert rel(phis[4][1:-1, 1:-1, 1:-1], full[4][1:-1, 1:-1, 1:-1]) > 1e-6
 
 
+def test_cellwise_truncation_extremes(oracle_mod):
+    """Sec. III.C on a nested chain: threshold 0 iterates every cell (the full
+    run, bit for bit), an infinite threshold holds every cell (the
+    interpolated run), and in between the masks are constant on each parent's
+    eight children and nest the expected way (a higher threshold holds more)."""
+    O = oracle_mod
+    n, m = 16, 16
+    f = synth.make_field(n, 2.0, 21, n_tophats=3)
+    origins = [(-3, 4, 5), (4, 4, 4)]
+    chain, deltas = [], [f.delta]
+    for o in origins:
+        chain.append(o)
+        deltas.append(synth.patch_delta(f, n, chain, m))
+    beta = O.beta_lcdm(1.0, 0.3, 1.0)
+    h = 4.0 / 2997.92458
+    prob = O.Problem(delta=deltas, h=h, rc=1.0, beta=beta, origins=tuple(origins))
+    lin = O.Problem(delta=deltas, h=h, rc=0.0, beta=beta, origins=tuple(origins))
+    psi = [1.5 * beta * p for p in O.solve_problem(lin)[0]]   # lap Psi_N = (3 beta / 2) S
+    full, _ = O.solve_problem(prob)
+    interp, _ = O.solve_problem(prob, interpolated=True)
+    ph0, _, mk0 = O.solve_problem(prob, cellwise=(psi, 0.0))
+    phi_inf, _, mki = O.solve_problem(prob, cellwise=(psi, math.inf))
+    for lvl in range(3):
+        np.testing.assert_array_equal(ph0[lvl], full[lvl])
+        np.testing.assert_array_equal(phi_inf[lvl], interp[lvl])
+    assert all(int(k.sum()) == m**3 for k in mk0[1:])
+    assert all(int(k.sum()) == 0 for k in mki[1:])
+    _, _, lo = O.solve_problem(prob, cellwise=(psi, 0.05))
+    _, _, hi = O.solve_problem(prob, cellwise=(psi, 0.2))
+    for a, b in zip(lo[1:], hi[1:]):
+        blocks = a.reshape(m // 2, 2, m // 2, 2, m // 2, 2)
+        assert np.all(blocks.min(axis=(1, 3, 5)) == blocks.max(axis=(1, 3, 5)))
+    assert np.all(hi[1] <= lo[1])   # same parent field: a higher threshold holds more
+
+
+def test_cell_mask_by_brute_force(oracle_mod):
+    """Sec. III.C criterion |F_5th| >= threshold |F_GR| on the parent cell,
+    recomputed here with numpy gradients and magnitudes (roots and divisions,
+    unlike the oracle's squared form), periodic and padded parents."""
+    O = oracle_mod
+    rng = np.random.default_rng(5)
+    for periodic, np_, origin, nc in ((True, 16, (-3, 5, 12), 16), (False, 16, (2, 4, 3), 20)):
+        shape = (np_,) * 3 if periodic else (np_ + 2,) * 3
+        phi = rng.standard_normal(shape)
+        psi = rng.standard_normal(shape) * 3.0
+        thr = 0.17
+        got = O.cell_mask(phi, psi, periodic, origin, nc, thr)
+        want = np.zeros((nc,) * 3, dtype=np.uint8)
+        for k in range(nc):
+            for j in range(nc):
+                for i in range(nc):
+                    P = [origin[0] + i // 2, origin[1] + j // 2, origin[2] + k // 2]
+                    gphi, gpsi = [], []
+                    for a in range(3):
+                        up, dn = list(P), list(P)
+                        up[a] += 1
+                        dn[a] -= 1
+                        if periodic:
+                            fu = phi[up[2] % np_, up[1] % np_, up[0] % np_]
+                            fd = phi[dn[2] % np_, dn[1] % np_, dn[0] % np_]
+                            su = psi[up[2] % np_, up[1] % np_, up[0] % np_]
+                            sd = psi[dn[2] % np_, dn[1] % np_, dn[0] % np_]
+                        else:
+                            fu, fd = phi[up[2] + 1, up[1] + 1, up[0] + 1], phi[dn[2] + 1, dn[1] + 1, dn[0] + 1]
+                            su, sd = psi[up[2] + 1, up[1] + 1, up[0] + 1], psi[dn[2] + 1, dn[1] + 1, dn[0] + 1]
+                        gphi.append((fu - fd) / 2.0)
+                        gpsi.append((su - sd) / 2.0)
+                    f5 = 0.5 * math.sqrt(sum(g * g for g in gphi))
+                    fgr = math.sqrt(sum(g * g for g in gpsi))
+                    assert abs(f5 / fgr - thr) > 1e-9  # no tie decided by rounding
+                    want[k, j, i] = 1 if f5 >= thr * fgr else 0
+        np.testing.assert_array_equal(got, want)
+        assert 0 < int(got.sum()) < nc**3
+
+
+def test_masked_patch_solve(oracle_mod):
+    """Cell-wise truncation on a Dirichlet patch (Sec. III.C): held cells keep
+    the interpolated value and enter their active neighbours' stencils as fixed
+    values.  Manufactured: a linear parent (interpolated exactly) plus a bump
+    supported inside a sub-box; every held cell lies outside the bump, so the
+    masked solve must return linear + bump exactly.  An all-ones mask is the
+    unmasked solve bit for bit; an all-zeros mask is the interpolation."""
+    O = oracle_mod
+    np_, nc, origin = 16, 16, (4, 4, 4)
+    hp = 4.0 / 2997.92458
+    hc = hp / 2
+    ii = np.arange(-1, np_ + 1)
+    Z, Y, X = np.meshgrid(ii, ii, ii, indexing="ij")
+    g = np.array([2e-8, -1e-8, 3e-8])
+    parent = g[0] * X + g[1] * Y + g[2] * Z
+    cc = origin[0] + (np.arange(-1, nc + 1) + 0.5) * 0.5 - 0.5
+    z, y, x = np.meshgrid(cc, cc, cc, indexing="ij")
+    lin_child = g[0] * x + g[1] * y + g[2] * z
+    # bump on child cells 4..11 (padded positions 5..12), zero elsewhere
+    t = (np.arange(-1, nc + 1) - 3.5) / 8.0
+    b1 = np.where((t > 0) & (t < 1), np.sin(np.pi * np.clip(t, 0, 1)) ** 4, 0.0)
+    bump = 4e-8 * b1[:, None, None] * b1[None, :, None] * b1[None, None, :]
+    phis = lin_child + bump
+    al = 0.877
+    S = O.operator_padded(phis, hc, al)
+    support = bump[1:-1, 1:-1, 1:-1] != 0.0
+    # A mask decided per parent cell is constant on the 2x2x2 children of each
+    # parent: random blocks, with every block that meets the bump's support
+    # (grown by one cell) iterated; held cells elsewhere.
+    rng = np.random.default_rng(9)
+    blocks = (rng.random((nc // 2,) * 3) < 0.5).astype(np.uint8)
+    grown = support.copy()
+    for ax in range(3):
+        grown |= np.roll(support, 1, ax) | np.roll(support, -1, ax)
+    blocks[grown.reshape(nc // 2, 2, nc // 2, 2, nc // 2, 2).any(axis=(1, 3, 5))] = 1
+    mask = blocks.repeat(2, 0).repeat(2, 1).repeat(2, 2)
+    assert 0 < int(mask.sum()) < nc**3
+    phi, info = O.solve_patch(S, hc, al, parent, False, origin, mask=mask)
+    assert info.status == 0
+    assert rel(phi[1:-1, 1:-1, 1:-1], phis[1:-1, 1:-1, 1:-1]) < 1e-11
+    held = mask == 0
+    guess = O.interpolate(parent, False, origin, 0, nc)
+    np.testing.assert_array_equal(phi[1:-1, 1:-1, 1:-1][held], guess[1:-1, 1:-1, 1:-1][held])
+    ones = np.ones((nc,) * 3, dtype=np.uint8)
+    a, ia = O.solve_patch(S, hc, al, parent, False, origin, mask=ones)
+    b, ib = O.solve_patch(S, hc, al, parent, False, origin)
+    np.testing.assert_array_equal(a, b)
+    assert ia.cycles == ib.cycles
+    z0, iz = O.solve_patch(S, hc, al, parent, False, origin, mask=np.zeros_like(ones))
+    np.testing.assert_array_equal(z0, O.interpolate(parent, False, origin, 0, nc))
+    assert iz.cycles == 0
+
+
 # ---------------------------------------------------------------------------
 # force, Sec. III.B
 
