@@ -155,6 +155,10 @@ typedef struct {
                               iteration) of the solve restarted with the damped step
                               u + 0.8 du after the residual grew to twice its smallest
                               value; 0 = never damped                                   */
+    double iterated_fraction[1 + NDGP_MAX_PATCHES]; /* per level: share of the cells
+                              that were relaxed (1 for relaxed levels, 0 for levels
+                              filled by interpolation, in between with
+                              ndgp_solve_cellwise)                                     */
 } ndgp_report;
 
 /* Library ABI version (NDGP_ABI_VERSION of the build). */
@@ -232,6 +236,34 @@ ndgp_status ndgp_solve(const ndgp_grid *grid, const ndgp_params *params,
                        const double *const delta[1 + NDGP_MAX_PATCHES],
                        double *const phi[1 + NDGP_MAX_PATCHES], void *workspace,
                        size_t workspace_bytes, hipStream_t stream, ndgp_report *report);
+
+/*
+ * Cell-wise truncation, the generalisation Sec. III.C proposes: as ndgp_solve,
+ * but on every relaxed patch a cell is iterated only if the fifth force on its
+ * parent cell is still large, |F_5th| >= threshold |F_GR| (F_5th = -grad(phi)/2
+ * of the parent's final field, F_GR = -grad(psi), central differences on the
+ * parent level); the other cells keep the value interpolated from the parent
+ * and enter their neighbours' stencils as fixed values.  On the coarse levels
+ * of the patch's multigrid a cell is held when all eight of its children are.
+ * The relative residual of a patch counts the iterated cells only, against
+ * ||S|| over the whole patch.  Patches above trunc_level (NDGP_MODE_TRUNCATED)
+ * are interpolated as in ndgp_solve.
+ *   psi[l]        Newtonian potential of level l, same layout as phi[l] (domain
+ *                 natural n^3, patches padded with ghosts), for every level
+ *                 that is the parent of a relaxed patch; others may be NULL.
+ *                 Psi_N solves lap Psi_N = 4 pi G a^2 delta rho (Eq. modpoisson's
+ *                 GR part); in the units of this ABI that is (3 beta / 2) times
+ *                 the field ndgp_solve returns with rc = 0.
+ *   threshold     >= 0; 0 iterates every cell (ndgp_solve's result, bit for
+ *                 bit), +inf holds every cell (the interpolated patches).
+ * report->iterated_fraction gives the share of iterated cells per level.
+ */
+ndgp_status ndgp_solve_cellwise(const ndgp_grid *grid, const ndgp_params *params,
+                                const double *const delta[1 + NDGP_MAX_PATCHES],
+                                const double *const psi[1 + NDGP_MAX_PATCHES], double threshold,
+                                double *const phi[1 + NDGP_MAX_PATCHES], void *workspace,
+                                size_t workspace_bytes, hipStream_t stream,
+                                ndgp_report *report);
 
 /*
  * Discrete residual of Eq. (eomgen-disc) on one level, r = S - L_h[phi], and its

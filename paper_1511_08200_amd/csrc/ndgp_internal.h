@@ -35,6 +35,9 @@ struct Level {
     // cell, d = number of axes along which the ghost lies outside), so that
     // the coarse correction vanishes where the fine boundary values sit.
     bool dyn_bc = false;
+    // Cell-wise truncation: natural n^3, 0 = the cell is held at its value
+    // (no relaxation, no residual, no coarse-grid correction); null = none held.
+    const unsigned char *mask = nullptr;
 
     size_t cells() const { return (size_t)n * n * n; }
     size_t slots() const {
@@ -123,6 +126,17 @@ void launch_diff_partials(const double *a, const double *b, size_t count, double
                           hipStream_t st);
 // dst[i] = src[i]
 void launch_copy(const double *src, double *dst, size_t count, hipStream_t st);
+
+// Cell-wise truncation mask of a ratio-2 child box (m = 0) from its parent's
+// phi and Newtonian potential psi (same layout as phi: periodic natural or
+// padded): 1 where |grad phi| / 2 >= threshold |grad psi| on the parent cell.
+// partials[0..kReduceBlocks) receive per-block counts of the 1s.
+void launch_cell_mask(const double *phi_parent, const double *psi_parent, int np,
+                      bool parent_periodic, const ChildBox &b, double threshold,
+                      unsigned char *mask, double *partials, hipStream_t st);
+// mask_c (nc^3) = 1 where any of the eight children in mask_f ((2 nc)^3) is 1
+void launch_mask_restrict(const unsigned char *mask_f, int nc, unsigned char *mask_c,
+                          hipStream_t st);
 
 // message for ndgp_last_error() in the calling thread
 void set_last_error(const char *msg);

@@ -26,7 +26,8 @@ template <bool PER>
 __global__ void __launch_bounds__(kBlock)
 k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
               const double *__restrict__ s, Ix<PER> ix, double al, double w, int colour,
-              unsigned *__restrict__ fallbacks, const double *__restrict__ hat, int dyn_bc) {
+              unsigned *__restrict__ fallbacks, const double *__restrict__ hat, int dyn_bc,
+              const unsigned char *__restrict__ mask) {
     const int n = ix.n, lg = ix.lg;
     const int half = n >> 1;
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -38,10 +39,15 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
     const int off = (colour ^ j ^ k) & 1; // parity of i of the cell of this colour
     const int iu = 2 * m + off;
     const int ic = 2 * m + 1 - off;
-    double v[19];
-    gather(pin, ix, iu, j, k, v);
     unsigned fb = 0;
-    const double un = relax_cell(v, s[((k << lg) + j) * n + iu], al, w, fb);
+    double un;
+    if (mask && !mask[((k << lg) + j) * n + iu]) { // held (cell-wise truncation)
+        un = pin[ix(iu, j, k)];
+    } else {
+        double v[19];
+        gather(pin, ix, iu, j, k, v);
+        un = relax_cell(v, s[((k << lg) + j) * n + iu], al, w, fb);
+    }
     const double uc = pin[ix(ic, j, k)];
     pout[ix(iu, j, k)] = un;
     pout[ix(ic, j, k)] = uc;
@@ -562,15 +568,18 @@ template <bool PER>
 __global__ void __launch_bounds__(kBlock)
 k_residual_sumsq(const double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix,
                  double al, double *__restrict__ partials, double *__restrict__ r_out,
-                 double r_scale) {
+                 double r_scale, const unsigned char *__restrict__ mask) {
     const int n = ix.n, lg = ix.lg;
     const int total = 1 << (3 * lg);
     double acc = 0.0;
     for (int c = blockIdx.x * kBlock + threadIdx.x; c < total; c += gridDim.x * kBlock) {
         const int i = c & (n - 1), j = (c >> lg) & (n - 1), k = c >> (2 * lg);
-        double v[19];
-        gather(phi, ix, i, j, k, v);
-        const double r = s[c] - apply_L(stencil_terms(v), al);
+        double r = 0.0; // a held cell is not part of the equations solved
+        if (!mask || mask[c]) {
+            double v[19];
+            gather(phi, ix, i, j, k, v);
+            r = s[c] - apply_L(stencil_terms(v), al);
+        }
         acc = fma(r, r, acc);
         if (r_out) r_out[c] = r * r_scale;
     }
@@ -631,7 +640,8 @@ template <bool PER>
 __device__ __forceinline__ void restrict_cell(const double *__restrict__ phi_f,
                                               const double *__restrict__ s_f, const Ix<PER> &ixf,
                                               int nf, double al_f, int I, int J, int K,
-                                              double &hat, double &sc) {
+                                              double &hat, double &sc,
+                                              const unsigned char *__restrict__ mask_f) {
     const int i0 = 2 * I - 1, j0 = 2 * J - 1, k0 = 2 * K - 1;
     double b[4][4][4];
 #pragma unroll
@@ -659,7 +669,10 @@ __device__ __forceinline__ void restrict_cell(const double *__restrict__ phi_f,
                     b[z + 1][y][x + 1], b[z - 1][y][x + 1], b[z + 1][y][x - 1], b[z - 1][y][x - 1],
                     b[z + 1][y + 1][x], b[z - 1][y + 1][x], b[z + 1][y - 1][x], b[z - 1][y - 1][x]};
                 const int fi = 2 * I + ci, fj = 2 * J + cj, fk = 2 * K + ck;
-                const double r = s_f[((size_t)fk * nf + fj) * nf + fi] - apply_L(stencil_terms(v), al_f);
+                const size_t fc = ((size_t)fk * nf + fj) * nf + fi;
+                const double r = mask_f && !mask_f[fc]
+                                     ? 0.0 // held: no residual
+                                     : s_f[fc] - apply_L(stencil_terms(v), al_f);
                 sphi += v[0];
                 sr += r;
             }
@@ -672,13 +685,13 @@ template <bool PER>
 __global__ void __launch_bounds__(kBlock)
 k_restrict_residual(const double *__restrict__ phi_f, const double *__restrict__ s_f,
                     Ix<PER> ixf, double al_f, double *__restrict__ hat_c,
-                    double *__restrict__ s_c, Ix<PER> ixc) {
+                    double *__restrict__ s_c, Ix<PER> ixc, const unsigned char *__restrict__ mask_f) {
     const int nc = ixc.n, lgc = ixc.lg;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= (1 << (3 * lgc))) return;
     const int I = t & (nc - 1), J = (t >> lgc) & (nc - 1), K = t >> (2 * lgc);
     double hat, sc;
-    restrict_cell(phi_f, s_f, ixf, ixf.n, al_f, I, J, K, hat, sc);
+    restrict_cell(phi_f, s_f, ixf, ixf.n, al_f, I, J, K, hat, sc, mask_f);
     hat_c[ixc(I, J, K)] = hat;
     s_c[t] = sc;
 }
@@ -738,7 +751,7 @@ template <bool PER, bool CORRECT>
 __global__ void __launch_bounds__(kBlock)
 k_prolong8(double *__restrict__ phi_f, Ix<PER> ixf, const double *__restrict__ phi_c,
            const double *__restrict__ hat_c, Ix<PER> ixc, const double *__restrict__ hat_f,
-           int dyn_bc_f) {
+           int dyn_bc_f, const unsigned char *__restrict__ mask_f) {
     const int nc = ixc.n, lgc = ixc.lg;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= (1 << (3 * lgc))) return;
@@ -789,6 +802,8 @@ k_prolong8(double *__restrict__ phi_f, Ix<PER> ixf, const double *__restrict__ p
             } else {
 #pragma unroll
                 for (int ci = 0; ci < 2; ++ci) {
+                    // a held cell keeps its value: no correction
+                    if (mask_f && !mask_f[((size_t)k * ixf.n + j) * ixf.n + i + ci]) continue;
                     const int q = ixf(i + ci, j, k);
                     const double val = CORRECT ? phi_f[q] + out[ci] : out[ci];
                     phi_f[q] = val;
@@ -822,7 +837,7 @@ template <bool PER>
 __global__ void __launch_bounds__(512)
 k_coarsest(double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix, double al, double w,
            int sweeps, unsigned *__restrict__ fallbacks, const double *__restrict__ hat,
-           int dyn_bc) {
+           int dyn_bc, const unsigned char *__restrict__ mask) {
     __shared__ double A[(kCoarsestMax + 2) * (kCoarsestMax + 2) * (kCoarsestMax + 2)];
     __shared__ double B[(kCoarsestMax + 2) * (kCoarsestMax + 2) * (kCoarsestMax + 2)];
     const int n = ix.n, lg = ix.lg;
@@ -845,6 +860,7 @@ k_coarsest(double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix, d
         sc = s[t];
     }
     const int mycol = (i + j + k) & 1;
+    const bool held = active && mask && !mask[t];
     unsigned fb = 0;
     for (int sw = 0; sw < sweeps; ++sw) {
 #pragma unroll
@@ -854,7 +870,7 @@ k_coarsest(double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix, d
             if (active) {
                 const int me = ix(i, j, k);
                 double val;
-                if (mycol == col) {
+                if (mycol == col && !held) {
                     double v[19];
                     gather(src, ix, i, j, k, v);
                     val = relax_cell(v, sc, al, w, fb);
@@ -1101,10 +1117,82 @@ k_force(const double *__restrict__ phi, Ix<PER> ix, double c4h, double *__restri
     f[2 * (size_t)cells + t] = -(phi[ix(i, j, k + 1)] - phi[ix(i, j, k - 1)]) * c4h;
 }
 
+// Cell-wise truncation (the generalisation proposed in Sec. III.C): child
+// cell (i, j, k) of a ratio-2 box is iterated only if its parent cell P =
+// origin + (i, j, k) / 2 has |F_5th| >= threshold |F_GR|, F_5th = -grad(phi)/2
+// and F_GR = -grad(psi) by central differences on the parent level, compared
+// as sum (dphi)^2 >= (2 threshold)^2 sum (dpsi)^2 (no roots, no divisions;
+// the spacing cancels).  One grid-stride pass over the child cells with a
+// fixed grid, so the per-block counts of iterated cells sum deterministically.
+template <bool PER>
+__global__ void __launch_bounds__(kBlock)
+k_cell_mask(const double *__restrict__ phi, const double *__restrict__ psi, Ix<PER> ixp, int ox,
+            int oy, int oz, int lgc, double t2, unsigned char *__restrict__ mask,
+            double *__restrict__ partials) {
+    const int nc = 1 << lgc;
+    const int total = 1 << (3 * lgc);
+    double count = 0.0;
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < total; c += gridDim.x * kBlock) {
+        const int i = c & (nc - 1), j = (c >> lgc) & (nc - 1), k = c >> (2 * lgc);
+        const int P = ox + (i >> 1), Q = oy + (j >> 1), R = oz + (k >> 1);
+        const int up[3] = {ixp(P + 1, Q, R), ixp(P, Q + 1, R), ixp(P, Q, R + 1)};
+        const int dn[3] = {ixp(P - 1, Q, R), ixp(P, Q - 1, R), ixp(P, Q, R - 1)};
+        double gphi = 0.0, gpsi = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double dp = phi[up[a]] - phi[dn[a]];
+            const double ds = psi[up[a]] - psi[dn[a]];
+            gphi = fma(dp, dp, gphi);
+            gpsi = fma(ds, ds, gpsi);
+        }
+        const bool on = gphi >= t2 * gpsi;
+        mask[c] = on ? 1 : 0;
+        count += on ? 1.0 : 0.0;
+    }
+    const double b = block_sum(count);
+    if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
+// Coarse level of a masked hierarchy: a coarse cell is held only if all
+// eight of its children are held.
+__global__ void __launch_bounds__(kBlock)
+k_mask_restrict(const unsigned char *__restrict__ mf, int lgc, unsigned char *__restrict__ mc) {
+    const int nc = 1 << lgc, nf = 2 * nc;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (1 << (3 * lgc))) return;
+    const int I = t & (nc - 1), J = (t >> lgc) & (nc - 1), K = t >> (2 * lgc);
+    unsigned any = 0;
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch)
+        any |= mf[((size_t)(2 * K + (ch >> 2)) * nf + 2 * J + ((ch >> 1) & 1)) * nf + 2 * I +
+                  (ch & 1)];
+    mc[t] = any ? 1 : 0;
+}
+
 } // namespace
 
 // ------------------------------------------------------------------------
 // launchers
+
+void launch_cell_mask(const double *phi_parent, const double *psi_parent, int np,
+                      bool parent_periodic, const ChildBox &b, double threshold,
+                      unsigned char *mask, double *partials, hipStream_t st) {
+    const double t2 = (2.0 * threshold) * (2.0 * threshold);
+    const int lgp = log2i(np), lgc = log2i(b.nc);
+    if (parent_periodic)
+        k_cell_mask<true><<<kReduceBlocks, kBlock, 0, st>>>(
+            phi_parent, psi_parent, make_ix<true>(np, lgp), b.origin[0], b.origin[1],
+            b.origin[2], lgc, t2, mask, partials);
+    else
+        k_cell_mask<false><<<kReduceBlocks, kBlock, 0, st>>>(
+            phi_parent, psi_parent, make_ix<false>(np, lgp), b.origin[0], b.origin[1],
+            b.origin[2], lgc, t2, mask, partials);
+}
+
+void launch_mask_restrict(const unsigned char *mask_f, int nc, unsigned char *mask_c,
+                          hipStream_t st) {
+    k_mask_restrict<<<blocks_for((size_t)nc * nc * nc), kBlock, 0, st>>>(mask_f, log2i(nc), mask_c);
+}
 
 void launch_smooth_half(const Level &L, const double *pin, double *pout, int colour,
                         unsigned *fallbacks, hipStream_t st) {
@@ -1112,11 +1200,11 @@ void launch_smooth_half(const Level &L, const double *pin, double *pout, int col
     if (L.periodic)
         k_smooth_half<true><<<nb, kBlock, 0, st>>>(pin, pout, L.s, make_ix<true>(L.n, L.lg),
                                                    L.alpha, L.omega, colour, fallbacks, nullptr,
-                                                   0);
+                                                   0, nullptr);
     else
         k_smooth_half<false><<<nb, kBlock, 0, st>>>(pin, pout, L.s, make_ix<false>(L.n, L.lg),
                                                     L.alpha, L.omega, colour, fallbacks, L.hat,
-                                                    L.dyn_bc ? 1 : 0);
+                                                    L.dyn_bc ? 1 : 0, L.mask);
 }
 
 // (on 32^3 and 64^3 the one-workgroup-per-tile pipeline is slower than two
@@ -1172,10 +1260,10 @@ void launch_residual_sumsq(const Level &L, double *partials, double *r_out, doub
     }
     if (L.periodic)
         k_residual_sumsq<true><<<kReduceBlocks, kBlock, 0, st>>>(
-            L.phi, L.s, make_ix<true>(L.n, L.lg), L.alpha, partials, r_out, r_scale);
+            L.phi, L.s, make_ix<true>(L.n, L.lg), L.alpha, partials, r_out, r_scale, nullptr);
     else
         k_residual_sumsq<false><<<kReduceBlocks, kBlock, 0, st>>>(
-            L.phi, L.s, make_ix<false>(L.n, L.lg), L.alpha, partials, r_out, r_scale);
+            L.phi, L.s, make_ix<false>(L.n, L.lg), L.alpha, partials, r_out, r_scale, L.mask);
 }
 
 bool residual_tiled_ok(const Level &L) { return L.periodic && L.n >= 128; }
@@ -1209,11 +1297,11 @@ void launch_restrict_residual(const Level &F, const Level &C, bool tiled, hipStr
     } else if (F.periodic)
         k_restrict_residual<true><<<nb, kBlock, 0, st>>>(F.phi, F.s, make_ix<true>(F.n, F.lg),
                                                          F.alpha, C.hat, C.s,
-                                                         make_ix<true>(C.n, C.lg));
+                                                         make_ix<true>(C.n, C.lg), nullptr);
     else
         k_restrict_residual<false><<<nb, kBlock, 0, st>>>(F.phi, F.s, make_ix<false>(F.n, F.lg),
                                                           F.alpha, C.hat, C.s,
-                                                          make_ix<false>(C.n, C.lg));
+                                                          make_ix<false>(C.n, C.lg), F.mask);
 }
 
 void launch_coarse_source(const Level &C, bool tiled, hipStream_t st) {
@@ -1237,11 +1325,12 @@ void launch_prolong_correct(const Level &F, const Level &C, hipStream_t st) {
     const unsigned nb = blocks_for(C.cells());
     if (F.periodic)
         k_prolong8<true, true><<<nb, kBlock, 0, st>>>(F.phi, make_ix<true>(F.n, F.lg), C.phi,
-                                                      C.hat, make_ix<true>(C.n, C.lg), nullptr, 0);
+                                                      C.hat, make_ix<true>(C.n, C.lg), nullptr, 0,
+                                                      nullptr);
     else
         k_prolong8<false, true><<<nb, kBlock, 0, st>>>(F.phi, make_ix<false>(F.n, F.lg), C.phi,
                                                        C.hat, make_ix<false>(C.n, C.lg), F.hat,
-                                                       F.dyn_bc ? 1 : 0);
+                                                       F.dyn_bc ? 1 : 0, F.mask);
 }
 
 void launch_prolong_full(const Level &F, const Level &C, hipStream_t st) {
@@ -1249,11 +1338,11 @@ void launch_prolong_full(const Level &F, const Level &C, hipStream_t st) {
     if (F.periodic)
         k_prolong8<true, false><<<nb, kBlock, 0, st>>>(F.phi, make_ix<true>(F.n, F.lg), C.phi,
                                                        nullptr, make_ix<true>(C.n, C.lg), nullptr,
-                                                       0);
+                                                       0, nullptr);
     else
         k_prolong8<false, false><<<nb, kBlock, 0, st>>>(F.phi, make_ix<false>(F.n, F.lg), C.phi,
                                                         nullptr, make_ix<false>(C.n, C.lg),
-                                                        F.hat, F.dyn_bc ? 1 : 0);
+                                                        F.hat, F.dyn_bc ? 1 : 0, nullptr);
 }
 
 void launch_restrict_source(const Level &F, const Level &C, hipStream_t st) {
@@ -1264,11 +1353,11 @@ void launch_coarsest(const Level &L, int sweeps, unsigned *fallbacks, hipStream_
     const int threads = L.cells() < 64 ? 64 : (int)L.cells();
     if (L.periodic)
         k_coarsest<true><<<1, threads, 0, st>>>(L.phi, L.s, make_ix<true>(L.n, L.lg), L.alpha,
-                                                L.omega, sweeps, fallbacks, nullptr, 0);
+                                                L.omega, sweeps, fallbacks, nullptr, 0, nullptr);
     else
         k_coarsest<false><<<1, threads, 0, st>>>(L.phi, L.s, make_ix<false>(L.n, L.lg), L.alpha,
                                                  L.omega, sweeps, fallbacks, L.hat,
-                                                 L.dyn_bc ? 1 : 0);
+                                                 L.dyn_bc ? 1 : 0, L.mask);
 }
 
 bool bottom_ok(const Level *H, int l, int nl) {

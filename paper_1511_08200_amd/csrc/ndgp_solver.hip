@@ -260,6 +260,7 @@ struct Plan {
     Level base[kMaxLevels];
     Level32 base32[kMaxLevels]; // mixed precision only
     Level patch[NDGP_MAX_PATCHES][kMaxLevels];
+    unsigned char *mask[NDGP_MAX_PATCHES][kMaxLevels] = {}; // cell-wise truncation
     double *partials = nullptr;
     double *scal = nullptr; // [0] sum delta, [1] sum s^2, [2] sum r^2, [3] sum phi
     unsigned *fallbacks = nullptr;
@@ -310,6 +311,7 @@ size_t carve(Plan &P, char *base) {
                 L.s = cv.take<double>(L.cells());
                 L.hat = m ? cv.take<double>(L.slots()) : nullptr;
                 L.dyn_bc = m > 0;
+                P.mask[q][m] = cv.take<unsigned char>(L.cells());
             }
         }
     }
@@ -396,7 +398,8 @@ struct CycleMonitor {
     bool damped = false;
 
     void start(double r) { rel = rel0 = prev = best = r; }
-    bool converged() const { return tol > 0.0 && rel <= tol; }
+    // a zero residual is exact (e.g. a patch whose every cell is held)
+    bool converged() const { return rel == 0.0 || (tol > 0.0 && rel <= tol); }
     bool diverged() const { return !std::isfinite(rel) || rel > 1e6 * std::max(rel0, 1.0); }
     // after a cycle: true when the level is to be solved again with the damped step
     bool record(double r) {
@@ -661,9 +664,14 @@ ndgp_status check_arrays(const Cfg &c, const double *const *delta, double *const
     return NDGP_OK;
 }
 
+// Cell-wise truncation (Sec. III.C) when psi != nullptr: psi[l] is the
+// Newtonian potential of level l (layout of phi[l]) for every parent of a
+// relaxed patch, and threshold the fifth-to-Newtonian force ratio below
+// which a parent's children are held.
 ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
                        const double *const delta[], double *const phi[], void *ws,
-                       size_t ws_bytes, hipStream_t st, ndgp_report *rep) {
+                       size_t ws_bytes, hipStream_t st, ndgp_report *rep,
+                       const double *const *psi = nullptr, double threshold = 0.0) {
     const auto t0 = std::chrono::steady_clock::now();
     Plan P;
     std::string why;
@@ -671,6 +679,13 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     const Cfg &c = P.c;
     ndgp_status s = check_arrays(c, delta, phi);
     if (s != NDGP_OK) return s;
+    if (psi) {
+        if (!(threshold >= 0.0)) return fail(NDGP_EINVAL, "threshold must be >= 0 (not NaN)");
+        for (int q = 0; q < c.nrelax; ++q)
+            if (!psi[q])
+                return fail(NDGP_EINVAL, "psi of the domain and of every parent of a relaxed "
+                                         "patch must not be NULL");
+    }
     const size_t need = total_bytes(c);
     if (!ws || ws_bytes < need)
         return fail(NDGP_ENOMEM, "workspace smaller than ndgp_workspace_bytes() = " +
@@ -681,6 +696,8 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     ndgp_report R;
     std::memset(&R, 0, sizeof(R));
     for (int l = 0; l <= NDGP_MAX_PATCHES; ++l) R.rel_res[l] = -1.0;
+    R.iterated_fraction[0] = 1.0;
+    for (int q = 0; q < c.nrelax; ++q) R.iterated_fraction[q + 1] = 1.0;
     SlotGuard slot;
     SmoothTimer timer;
     Runner run{P, st, slot.p};
@@ -744,6 +761,18 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         if (q >= c.nrelax) continue; // Sec. III.B: a truncated level keeps the guess
         Level *H = P.patch[q];
         H[0].phi = phi[q + 1];
+        if (psi) { // Sec. III.C: iterate only where the parent's fifth force is large
+            launch_cell_mask(parent, psi[q], npar, parent_periodic, b0, threshold, P.mask[q][0],
+                             P.partials, st);
+            launch_reduce_final(P.partials, P.scal + 5, st);
+            H[0].mask = P.mask[q][0];
+            for (int m = 1; m < c.pnl[q]; ++m) {
+                launch_mask_restrict(P.mask[q][m - 1], H[m].n, P.mask[q][m], st);
+                H[m].mask = P.mask[q][m];
+            }
+            R.iterated_fraction[q + 1] =
+                run.read_scalar(P.scal + 5) / ((double)c.pn[q] * c.pn[q] * c.pn[q]);
+        }
         launch_interpolate(parent, npar, parent_periodic, b0, H[0].alt, true, st);
         for (int m = 1; m < c.pnl[q]; ++m) {
             ChildBox bm{{c.po[q][0], c.po[q][1], c.po[q][2]}, m, c.pn[q] >> m};
@@ -1128,6 +1157,19 @@ ndgp_status ndgp_solve(const ndgp_grid *grid, const ndgp_params *params,
                        size_t workspace_bytes, hipStream_t stream, ndgp_report *report) {
     return guarded([&] {
         return solve_impl(grid, params, delta, phi, workspace, workspace_bytes, stream, report);
+    });
+}
+
+ndgp_status ndgp_solve_cellwise(const ndgp_grid *grid, const ndgp_params *params,
+                                const double *const delta[1 + NDGP_MAX_PATCHES],
+                                const double *const psi[1 + NDGP_MAX_PATCHES], double threshold,
+                                double *const phi[1 + NDGP_MAX_PATCHES], void *workspace,
+                                size_t workspace_bytes, hipStream_t stream,
+                                ndgp_report *report) {
+    return guarded([&] {
+        if (!psi) return fail(NDGP_EINVAL, "psi must not be NULL");
+        return solve_impl(grid, params, delta, phi, workspace, workspace_bytes, stream, report,
+                          psi, threshold);
     });
 }
 

@@ -65,7 +65,8 @@ class _Report(ctypes.Structure):
                 ("res_hist", ctypes.c_double * HIST_LEN), ("t_total_ms", ctypes.c_double),
                 ("t_smooth_ms", ctypes.c_double), ("smooth_launches", ctypes.c_int32),
                 ("smooth_cells_per_launch", ctypes.c_int32),
-                ("damped_from", ctypes.c_int32 * (1 + MAX_PATCHES))]
+                ("damped_from", ctypes.c_int32 * (1 + MAX_PATCHES)),
+                ("iterated_fraction", ctypes.c_double * (1 + MAX_PATCHES))]
 
 
 _lib = None
@@ -101,6 +102,10 @@ def lib():
         L.ndgp_solve.restype = ctypes.c_int
         L.ndgp_solve.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), arr3, arr3, vp,
                                  ctypes.c_size_t, vp, ctypes.POINTER(_Report)]
+        L.ndgp_solve_cellwise.restype = ctypes.c_int
+        L.ndgp_solve_cellwise.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), arr3,
+                                          arr3, ctypes.c_double, arr3, vp, ctypes.c_size_t, vp,
+                                          ctypes.POINTER(_Report)]
         L.ndgp_residual.restype = ctypes.c_int
         L.ndgp_residual.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int32,
                                     arr3, vp, vp, ctypes.POINTER(ctypes.c_double), vp,
@@ -247,6 +252,7 @@ class Report:
     smooth_cells_per_launch: int = 0
     status: int = NDGP_OK
     damped_from: list = dataclasses.field(default_factory=list)
+    iterated_fraction: list = dataclasses.field(default_factory=list)
 
 
 def _report(r: _Report, status: int) -> Report:
@@ -255,7 +261,8 @@ def _report(r: _Report, status: int) -> Report:
                   history=[r.res_hist[i] for i in range(r.hist_len)], t_total_ms=r.t_total_ms,
                   t_smooth_ms=r.t_smooth_ms, smooth_launches=r.smooth_launches,
                   smooth_cells_per_launch=r.smooth_cells_per_launch, status=status,
-                  damped_from=list(r.damped_from))
+                  damped_from=list(r.damped_from),
+                  iterated_fraction=list(r.iterated_fraction))
 
 
 # --------------------------------------------------------------------------
@@ -335,6 +342,44 @@ def solve(grid: Grid, params: Params, delta: Sequence[torch.Tensor], phi=None, w
     rep = _Report()
     st = lib().ndgp_solve(ctypes.byref(g), ctypes.byref(p), _arr3(dptr), _arr3(pptr),
                           ws.data_ptr(), ws.numel(), _stream(stream), ctypes.byref(rep))
+    if check:
+        _check(st)
+    elif st != NDGP_OK and st != NDGP_ENOCONV:
+        _check(st)
+    return phi, _report(rep, st)
+
+
+def solve_cellwise(grid: Grid, params: Params, delta: Sequence[torch.Tensor],
+                   psi: Sequence[Optional[torch.Tensor]], threshold: float, phi=None, ws=None,
+                   stream=None, check: bool = True):
+    """Run ndgp_solve_cellwise: as solve(), but on every relaxed patch only the
+    cells whose parent has |F_5th| >= threshold |F_GR| are iterated (Sec.
+    III.C).  ``psi``: Newtonian potential per level, laid out like phi
+    (domain n^3, patches padded); entries not needed may be None."""
+    g, p = grid._c(), params._c()
+    if phi is None:
+        phi = alloc_phi(grid, device=delta[0].device)
+    dptr = [_dev(delta[0], (grid.n,) * 3, "delta[0]")]
+    sptr = []
+    for q, pt in enumerate(grid.patches):
+        if q + 1 < len(delta) and delta[q + 1] is not None:
+            dptr.append(_dev(delta[q + 1], (pt.n,) * 3, f"delta[{q + 1}]"))
+        else:
+            dptr.append(None)
+    for lvl in range(len(grid.patches) + 1):
+        t = psi[lvl] if lvl < len(psi) else None
+        shape = (grid.n,) * 3 if lvl == 0 else (grid.patches[lvl - 1].n + 2,) * 3
+        sptr.append(_dev(t, shape, f"psi[{lvl}]") if t is not None else None)
+    pptr = [_dev(phi[0], (grid.n,) * 3, "phi[0]")]
+    for q, pt in enumerate(grid.patches):
+        pptr.append(_dev(phi[q + 1], (pt.n + 2,) * 3, f"phi[{q + 1}]"))
+    nb = workspace_bytes(grid, params)
+    if ws is None:
+        ws = workspace(nb, delta[0].device)
+    rep = _Report()
+    st = lib().ndgp_solve_cellwise(ctypes.byref(g), ctypes.byref(p), _arr3(dptr), _arr3(sptr),
+                                   float(threshold), _arr3(pptr), ws.data_ptr(), ws.numel(),
+                                   _stream(stream), ctypes.byref(rep))
     if check:
         _check(st)
     elif st != NDGP_OK and st != NDGP_ENOCONV:

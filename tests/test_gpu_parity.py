@@ -342,6 +342,94 @@ def test_truncation_levels_match_oracle(trunc):
         assert rel(fg[lvl], fo) <= 1e-10
 
 
+def _parent_ratio(phi_par, psi_par, periodic, origin, nc):
+    """|F_5th| / |F_GR| = |grad phi| / (2 |grad psi|) at the parent cell of every
+    child cell (numpy, from the oracle's own fields)."""
+    idx = [origin[a] + np.arange(nc) // 2 for a in range(3)]
+    g_phi, g_psi = 0.0, 0.0
+    for a in range(3):
+        up = [ix.copy() for ix in idx]
+        dn = [ix.copy() for ix in idx]
+        up[a] = up[a] + 1
+        dn[a] = dn[a] - 1
+
+        def take(f, q):
+            if periodic:
+                n = f.shape[0]
+                return f[np.ix_(q[2] % n, q[1] % n, q[0] % n)]
+            return f[np.ix_(q[2] + 1, q[1] + 1, q[0] + 1)]
+        g_phi = g_phi + (take(phi_par, up) - take(phi_par, dn)) ** 2
+        g_psi = g_psi + (take(psi_par, up) - take(psi_par, dn)) ** 2
+    return np.sqrt(g_phi) / (2.0 * np.sqrt(g_psi))
+
+
+def test_cellwise_truncation_matches_oracle():
+    """ndgp_solve_cellwise (Sec. III.C) on a 32^3 domain with two nested 32^3
+    patches, the Newtonian potential from each side's own r_c = 0 solve: the
+    iterated cells are the oracle's exactly and every level matches the
+    oracle's masked solve.  Threshold 0 is ndgp_solve bit for bit, an infinite
+    one the interpolated mode bit for bit."""
+    rc = 1.0
+    f, deltas, grid = deep_patch_problem(depth=2)
+    beta = O.beta_lcdm(1.0, 0.3, rc)
+    origins = tuple(p.origin for p in grid.patches)
+    say("cellwise: oracle r_c = 0 and full solves")
+    lin = O.Problem(delta=deltas, h=grid.h, rc=0.0, beta=beta, origins=origins)
+    psi_o = [1.5 * beta * p for p in O.solve_problem(lin)[0]]
+    prob = O.Problem(delta=deltas, h=grid.h, rc=rc, beta=beta, origins=origins)
+    full_o, _ = O.solve_problem(prob)
+    # a threshold whose nearest parent ratio is far from it on both levels
+    r1 = np.sort(_parent_ratio(full_o[0], psi_o[0], True, origins[0], 32).ravel())
+    chosen = None
+    for qtl in (0.5, 0.4, 0.6, 0.3, 0.7):
+        k = int(qtl * (len(r1) - 1))
+        gaps = np.diff(r1[k - 50:k + 50])
+        g = int(np.argmax(gaps))
+        thr = 0.5 * (r1[k - 50 + g] + r1[k - 50 + g + 1])
+        phio, infos, masks = O.solve_problem(prob, cellwise=(psi_o, thr))
+        r2 = _parent_ratio(phio[1], psi_o[1], False, origins[1], 32)
+        m1 = np.min(np.abs(r1 / thr - 1.0))
+        m2 = np.min(np.abs(r2 / thr - 1.0))
+        if min(m1, m2) > 1e-7 and all(i.status == 0 for i in infos):
+            chosen = thr
+            break
+    assert chosen is not None
+    say(f"  threshold {chosen:.6g}: iterated {[int(mk.sum()) for mk in masks[1:]]} of {32**3}")
+    psi_g = ndgp.solve(grid, ndgp.Params(rc=0.0, beta=beta, tol=0.0, max_cycles=200),
+                       [dev(d) for d in deltas])[0]
+    psi_g = [1.5 * beta * p for p in psi_g]
+    params = ndgp.Params(rc=rc, tol=0.0, max_cycles=200)
+    phig, rep = ndgp.solve_cellwise(grid, params, [dev(d) for d in deltas], psi_g, chosen)
+    torch.cuda.synchronize()
+    say(f"  cycles={rep.cycles} iterated={rep.iterated_fraction[:3]}")
+    assert rep.status == 0
+    for lvl in (1, 2):
+        assert rep.iterated_fraction[lvl] == masks[lvl].sum() / 32**3
+        assert 0.0 < rep.iterated_fraction[lvl] < 1.0
+    for lvl in range(3):
+        e = rel(phig[lvl].cpu().numpy(), phio[lvl])
+        say(f"  level {lvl}: rel err {e:.2e}")
+        assert e <= PHI_TOL
+    # held cells keep exactly the interpolated value of the GPU's own parent
+    for lvl in (1, 2):
+        pq = grid.patches[lvl - 1]
+        want = O.interpolate(phig[lvl - 1].cpu().numpy(), lvl == 1, pq.origin, 0, pq.n)
+        held = masks[lvl] == 0
+        got = phig[lvl].cpu().numpy()[1:-1, 1:-1, 1:-1][held]
+        assert np.abs(got - want[1:-1, 1:-1, 1:-1][held]).max() <= 1e-14 * np.abs(want).max()
+    # the limits, bit for bit
+    dd = [dev(d) for d in deltas]
+    ph0, r0 = ndgp.solve_cellwise(grid, params, dd, psi_g, 0.0)
+    phf, rf = ndgp.solve(grid, params, dd)
+    phinf, _ = ndgp.solve_cellwise(grid, params, dd, psi_g, float("inf"))
+    phi_i, _ = ndgp.solve(grid, ndgp.Params(rc=rc, tol=0.0, max_cycles=200,
+                                            mode=ndgp.MODE_INTERPOLATED), dd)
+    for lvl in range(3):
+        assert torch.equal(ph0[lvl], phf[lvl])
+        assert torch.equal(phinf[lvl], phi_i[lvl])
+    assert r0.cycles == rf.cycles and r0.iterated_fraction[:3] == [1.0, 1.0, 1.0]
+
+
 def test_patch_residual_level():
     """ndgp_residual on a patch level uses the ghost shell as boundary."""
     f, deltas, grid = patch_problem()
