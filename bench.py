@@ -155,7 +155,8 @@ def patch_workload(ndgp, torch, steps):
     grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n), patches=patches)
     out = {"workload": "256^3 + 4 nested 128^3 patches (2x..16x), lognormal sigma 2 + 50 "
                        "top-hats, r_cH0=1, tol 1e-10; truncation levels 1 (all interpolated), "
-                       "2, 4, 5 (full); mixed precision with every patch interpolated",
+                       "2, 4, 5 (full); mixed precision with every patch interpolated; "
+                       "cell-wise truncation at F5/F_GR thresholds 0.02, 0.05, 0.08",
            "origins": [list(o) for o in chain]}
     runs = (("full", ndgp.MODE_FULL, 0, ndgp.PREC_FP64),
             ("trunc4", ndgp.MODE_TRUNCATED, 4, ndgp.PREC_FP64),
@@ -185,6 +186,30 @@ def patch_workload(ndgp, torch, steps):
     beta = ndgp.beta_lcdm(1.0, 0.3, rc)
     phi_gr, _ = ndgp.solve(grid, ndgp.Params(rc=0.0, beta=beta, tol=1e-10),
                            [torch.from_numpy(d).to("cuda") for d in deltas])
+    # cell-wise truncation (Sec. III.C): iterate a patch cell only where its
+    # parent's fifth force is at least a fraction of the Newtonian force
+    # (Psi_N = 3 beta / 2 times the r_c = 0 field)
+    psi = [1.5 * beta * p for p in phi_gr]
+    dd = [torch.from_numpy(d).to("cuda") for d in deltas]
+    full_params = ndgp.Params(rc=rc, tol=1e-10)
+    ws = ndgp.workspace(ndgp.workspace_bytes(grid, full_params))
+    out["cellwise"] = {}
+    for thr in (0.02, 0.05, 0.08):
+        phi_c = ndgp.alloc_phi(grid)
+        ndgp.solve_cellwise(grid, full_params, dd, psi, thr, phi=phi_c, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, rep_c = ndgp.solve_cellwise(grid, full_params, dd, psi, thr, phi=phi_c, ws=ws)
+            ndgp.force(grid, phi_c)
+        torch.cuda.synchronize()
+        dtc = (time.perf_counter() - t0) / steps
+        name = f"cellwise{thr:g}"
+        res[name] = phi_c
+        out["cellwise"][f"{thr:g}"] = {"ms_to_tol": round(dtc * 1e3, 2), "cycles": rep_c.cycles,
+                                       "iterated_fraction": rep_c.iterated_fraction,
+                                       "speedup_vs_full": round(t_full / (dtc * 1e3), 2)}
+    del ws, dd
     F_full = ndgp.force(grid, res["full"])
     F_lin = ndgp.force(grid, phi_gr)
     gr2 = []
@@ -192,7 +217,8 @@ def patch_workload(ndgp, torch, steps):
         _, g2, _ = ndgp.diff_norms(F_lin[lvl])
         gr2.append(g2 * (3 * beta) ** 2)
     out["force_difference"] = {}
-    for name in ("trunc4", "trunc2", "interpolated"):
+    for name in ("trunc4", "trunc2", "interpolated", "cellwise0.02", "cellwise0.05",
+                 "cellwise0.08"):
         F_t = ndgp.force(grid, res[name])
         rows = []
         for lvl in range(1, depth + 1):

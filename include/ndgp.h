@@ -244,7 +244,8 @@ ndgp_status ndgp_solve(const ndgp_grid *grid, const ndgp_params *params,
  * of the parent's final field, F_GR = -grad(psi), central differences on the
  * parent level); the other cells keep the value interpolated from the parent
  * and enter their neighbours' stencils as fixed values.  On the coarse levels
- * of the patch's multigrid a cell is held when all eight of its children are.
+ * of the patch's multigrid a cell is held when any of its eight children is,
+ * so that the held regions act as fixed boundaries on every level.
  * The relative residual of a patch counts the iterated cells only, against
  * ||S|| over the whole patch.  Patches above trunc_level (NDGP_MODE_TRUNCATED)
  * are interpolated as in ndgp_solve.

@@ -720,10 +720,13 @@ int oracle_solve_patch(int nc, double hc, double alpha, const double *S, const d
     memcpy(H.lv[0].phi, phi_pad, sizeof(double) * (size_t)pc);
     natural_to_padded(nc, S, H.lv[0].S);
     H.lv[0].mask = mask;
-    /* coarse levels hold a cell whose eight children are all held: the held
-       regions stay fixed (zero correction) on every level of the cycle, which
-       keeps the coarse-grid correction consistent with them; a coarse cell
-       with any iterated child is iterated */
+    /* coarse levels hold a cell if any of its eight children is held: the
+       coarse correction is then zero wherever it would reach a held fine cell,
+       so the held regions act as fixed boundaries on every level of the cycle.
+       (Iterating a coarse cell with any iterated child instead lets corrections
+       that do not vanish at the held cells leak into their iterated neighbours:
+       the cycles then stagnate near 1e-4 on screened patches, and diverge with
+       no coarse masks at all.) */
     for (int l = 1; mask && l < H.nl; ++l) {
         const int n = H.lv[l].n, nf = H.lv[l - 1].n;
         const unsigned char *mf = H.lv[l - 1].mask;
@@ -735,11 +738,11 @@ int oracle_solve_patch(int nc, double hc, double alpha, const double *S, const d
         for (int k = 0; k < n; ++k)
             for (int j = 0; j < n; ++j)
                 for (int i = 0; i < n; ++i) {
-                    int any = 0;
+                    int all = 1;
                     for (int c = 0; c < 8; ++c)
-                        any |= mf[((int64_t)(2 * k + (c >> 2)) * nf + 2 * j + ((c >> 1) & 1)) * nf
-                                  + 2 * i + (c & 1)];
-                    mc[((int64_t)k * n + j) * n + i] = (unsigned char)(any != 0);
+                        all &= mf[((int64_t)(2 * k + (c >> 2)) * nf + 2 * j + ((c >> 1) & 1)) * nf
+                                  + 2 * i + (c & 1)] != 0;
+                    mc[((int64_t)k * n + j) * n + i] = (unsigned char)all;
                 }
         H.lv[l].mask_own = mc;
         H.lv[l].mask = mc;

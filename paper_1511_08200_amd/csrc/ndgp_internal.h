@@ -134,7 +134,7 @@ void launch_copy(const double *src, double *dst, size_t count, hipStream_t st);
 void launch_cell_mask(const double *phi_parent, const double *psi_parent, int np,
                       bool parent_periodic, const ChildBox &b, double threshold,
                       unsigned char *mask, double *partials, hipStream_t st);
-// mask_c (nc^3) = 1 where any of the eight children in mask_f ((2 nc)^3) is 1
+// mask_c (nc^3) = 1 where all eight children in mask_f ((2 nc)^3) are 1
 void launch_mask_restrict(const unsigned char *mask_f, int nc, unsigned char *mask_c,
                           hipStream_t st);
 

@@ -1153,20 +1153,22 @@ k_cell_mask(const double *__restrict__ phi, const double *__restrict__ psi, Ix<P
     if (threadIdx.x == 0) partials[blockIdx.x] = b;
 }
 
-// Coarse level of a masked hierarchy: a coarse cell is held only if all
-// eight of its children are held.
+// Coarse level of a masked hierarchy: a coarse cell is iterated only if all
+// eight of its children are, so that no coarse correction reaches a held
+// fine cell's neighbourhood from a coarse cell that straddles it (the held
+// regions act as fixed boundaries on every level).
 __global__ void __launch_bounds__(kBlock)
 k_mask_restrict(const unsigned char *__restrict__ mf, int lgc, unsigned char *__restrict__ mc) {
     const int nc = 1 << lgc, nf = 2 * nc;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= (1 << (3 * lgc))) return;
     const int I = t & (nc - 1), J = (t >> lgc) & (nc - 1), K = t >> (2 * lgc);
-    unsigned any = 0;
+    bool all = true;
 #pragma unroll
     for (int ch = 0; ch < 8; ++ch)
-        any |= mf[((size_t)(2 * K + (ch >> 2)) * nf + 2 * J + ((ch >> 1) & 1)) * nf + 2 * I +
-                  (ch & 1)];
-    mc[t] = any ? 1 : 0;
+        all = all && mf[((size_t)(2 * K + (ch >> 2)) * nf + 2 * J + ((ch >> 1) & 1)) * nf +
+                        2 * I + (ch & 1)] != 0;
+    mc[t] = all ? 1 : 0;
 }
 
 } // namespace
