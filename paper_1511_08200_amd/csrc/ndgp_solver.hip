@@ -764,14 +764,12 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         if (psi) { // Sec. III.C: iterate only where the parent's fifth force is large
             launch_cell_mask(parent, psi[q], npar, parent_periodic, b0, threshold, P.mask[q][0],
                              P.partials, st);
-            launch_reduce_final(P.partials, P.scal + 5, st);
+            launch_reduce_final(P.partials, P.scal + 8 + q, st); // read after the last patch
             H[0].mask = P.mask[q][0];
             for (int m = 1; m < c.pnl[q]; ++m) {
                 launch_mask_restrict(P.mask[q][m - 1], H[m].n, P.mask[q][m], st);
                 H[m].mask = P.mask[q][m];
             }
-            R.iterated_fraction[q + 1] =
-                run.read_scalar(P.scal + 5) / ((double)c.pn[q] * c.pn[q] * c.pn[q]);
         }
         launch_interpolate(parent, npar, parent_periodic, b0, H[0].alt, true, st);
         for (int m = 1; m < c.pnl[q]; ++m) {
@@ -801,10 +799,16 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     }
     unsigned fb = 0;
     HIP_TRY(hipGetLastError());
+    if (psi && c.nrelax > 0) // iterated cells per masked patch, counted on the device
+        HIP_TRY(hipMemcpyAsync(slot.p + 8, P.scal + 8, c.nrelax * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(slot.p, P.fallbacks, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     std::memcpy(&fb, slot.p, sizeof(unsigned));
     R.fallbacks = (int32_t)fb;
+    if (psi)
+        for (int q = 0; q < c.nrelax; ++q)
+            R.iterated_fraction[q + 1] = slot.p[8 + q] / ((double)c.pn[q] * c.pn[q] * c.pn[q]);
     R.t_total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (rep) *rep = R;
