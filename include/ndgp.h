@@ -294,6 +294,50 @@ ndgp_status ndgp_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_M
                        double *const force[1 + NDGP_MAX_PATCHES], hipStream_t stream);
 
 /*
+ * Total force on every level (Eq. modpoisson: the dynamical potential is
+ * Psi_N + phi/2): F = -grad(Psi_N) - grad(phi)/2 by central differences,
+ * patches using their ghost shells.
+ *   phi[l]        as produced by ndgp_solve
+ *   psi[l]        Newtonian potential, same layout as phi[l] (see
+ *                 ndgp_solve_cellwise for its normalisation)
+ *   force[l]      out: 3 * cells(l) doubles, x then y then z, each natural
+ * Enqueues only; does not block.
+ */
+ndgp_status ndgp_total_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_MAX_PATCHES],
+                             const double *const psi[1 + NDGP_MAX_PATCHES],
+                             double *const force[1 + NDGP_MAX_PATCHES], hipStream_t stream);
+
+/*
+ * Effective gravity per refinement level, the cell analogue of the paper's
+ * G_eff against the AMR level (Sec. III.B, Sec. IV.B Fig. 3): for every cell,
+ * G_eff - 1 = |F_5th| / |F_GR| with F_5th = -grad(phi)/2 and F_GR =
+ * -grad(Psi_N), central differences (the spacing cancels; computed as
+ * sqrt(sum dphi^2 / sum dpsi^2) / 2, a cell with no Newtonian force counts as
+ * 0 without a fifth force, else +inf).  A cell of level l covered by patch
+ * l+1 is left out: every cell counts on the finest level that holds it.
+ *   edges         HOST, n_edges ascending values (1 <= n_edges <=
+ *                 NDGP_GEFF_MAX_EDGES): bin 0 holds x < edges[0], bin b holds
+ *                 edges[b-1] <= x < edges[b], bin n_edges holds x >= the last
+ *   out[l]        HOST: cells counted, sum, sum of squares, min and max of
+ *                 G_eff - 1 on level l (l = 0..n_patch)
+ *   hist          HOST, (n_patch + 1) * (n_edges + 1) counts, level-major
+ *   workspace     NDGP_GEFF_WORKSPACE bytes of device memory
+ * Deterministic (fixed-order sums; exact integer counts).  Blocks until out
+ * and hist are written.
+ */
+#define NDGP_GEFF_MAX_EDGES 255
+#define NDGP_GEFF_WORKSPACE 262144
+typedef struct {
+    int64_t cells;
+    double sum, sum_sq, min, max;
+} ndgp_geff_level;
+ndgp_status ndgp_geff_stats(const ndgp_grid *grid, const double *const phi[1 + NDGP_MAX_PATCHES],
+                            const double *const psi[1 + NDGP_MAX_PATCHES], const double *edges,
+                            int32_t n_edges, ndgp_geff_level out[1 + NDGP_MAX_PATCHES],
+                            int64_t *hist, void *workspace, size_t workspace_bytes,
+                            hipStream_t stream);
+
+/*
  * Serving: the same solve as ndgp_solve, split into non-blocking steps so that
  * one host thread can keep many solves in flight on different streams
  * (continuous batching).  A plan owns nothing on the device: delta, phi and

@@ -138,6 +138,20 @@ void launch_cell_mask(const double *phi_parent, const double *psi_parent, int np
 void launch_mask_restrict(const unsigned char *mask_f, int nc, unsigned char *mask_c,
                           hipStream_t st);
 
+// Total force F = -grad(psi) - grad(phi)/2 (Eq. modpoisson) on one level,
+// 3 * n^3 values (x, y, z); phi and psi in the level's layout.
+void launch_total_force(const double *phi, const double *psi, int n, bool periodic, double h,
+                        double *f, hipStream_t st);
+// G_eff - 1 = |F_5th| / |F_GR| over the cells of one level outside the child box
+// [child_origin, child_origin + child_half) (child_half = 0: none):
+// out[0..4] = count, sum, sum of squares, min, max (device); hist[0..n_edges]
+// = bin counts (device, zeroed here); partials: 5 * kReduceBlocks doubles.
+constexpr int kGeffMaxEdges = 255;
+void launch_geff_level(const double *phi, const double *psi, int n, bool periodic,
+                       const int child_origin[3], int child_half, const double *edges,
+                       int n_edges, double *partials, unsigned long long *hist, double *out,
+                       hipStream_t st);
+
 // message for ndgp_last_error() in the calling thread
 void set_last_error(const char *msg);
 

@@ -877,6 +877,83 @@ ndgp_status force_impl(const ndgp_grid *grid, const double *const phi[], double 
     return NDGP_OK;
 }
 
+// geometry-only view of a grid (the patch checks of the interpolated mode)
+bool resolve_grid(const ndgp_grid *grid, Cfg &c, std::string &why) {
+    if (!grid) {
+        why = "grid must not be NULL";
+        return false;
+    }
+    ndgp_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.beta = 1.0;
+    p.a = 1.0;
+    p.omega_m = 1.0;
+    p.mode = NDGP_MODE_INTERPOLATED;
+    return resolve(grid, &p, c, why);
+}
+
+ndgp_status total_force_impl(const ndgp_grid *grid, const double *const phi[],
+                             const double *const psi[], double *const force[], hipStream_t st) {
+    Cfg c;
+    std::string why;
+    if (!resolve_grid(grid, c, why)) return fail(NDGP_EINVAL, why);
+    if (!phi || !psi || !force) return fail(NDGP_EINVAL, "phi, psi and force must not be NULL");
+    for (int l = 0; l <= c.np; ++l)
+        if (!phi[l] || !psi[l] || !force[l])
+            return fail(NDGP_EINVAL, "phi/psi/force of every level must not be NULL");
+    for (int l = 0; l <= c.np; ++l)
+        launch_total_force(phi[l], psi[l], c.nlev(l), l == 0, c.hl(l), force[l], st);
+    HIP_TRY(hipGetLastError());
+    return NDGP_OK;
+}
+
+ndgp_status geff_stats_impl(const ndgp_grid *grid, const double *const phi[],
+                            const double *const psi[], const double *edges, int32_t n_edges,
+                            ndgp_geff_level *out, int64_t *hist, void *ws, size_t ws_bytes,
+                            hipStream_t st) {
+    Cfg c;
+    std::string why;
+    if (!resolve_grid(grid, c, why)) return fail(NDGP_EINVAL, why);
+    if (!phi || !psi || !edges || !out || !hist)
+        return fail(NDGP_EINVAL, "phi, psi, edges, out and hist must not be NULL");
+    for (int l = 0; l <= c.np; ++l)
+        if (!phi[l] || !psi[l]) return fail(NDGP_EINVAL, "phi/psi of every level must not be NULL");
+    if (n_edges < 1 || n_edges > NDGP_GEFF_MAX_EDGES)
+        return fail(NDGP_EINVAL, "n_edges must be in [1, NDGP_GEFF_MAX_EDGES]");
+    for (int b = 0; b < n_edges; ++b)
+        if (std::isnan(edges[b]) || (b && !(edges[b - 1] < edges[b])))
+            return fail(NDGP_EINVAL, "edges must be strictly ascending numbers");
+    static_assert(kGeffMaxEdges == NDGP_GEFF_MAX_EDGES, "edge limit");
+    Carver cv{aligned_base(ws)};
+    double *partials = cv.take<double>(5 * (size_t)kReduceBlocks);
+    double *d_edges = cv.take<double>(NDGP_GEFF_MAX_EDGES);
+    unsigned long long *d_hist = cv.take<unsigned long long>(NDGP_GEFF_MAX_EDGES + 1);
+    double *d_out = cv.take<double>(8);
+    if (!ws || cv.off + 256 > ws_bytes)
+        return fail(NDGP_ENOMEM, "workspace smaller than NDGP_GEFF_WORKSPACE");
+    SlotGuard slot; // pinned doubles for the five results of a level
+    std::vector<unsigned long long> h((size_t)n_edges + 1);
+    HIP_TRY(hipMemcpyAsync(d_edges, edges, sizeof(double) * n_edges, hipMemcpyHostToDevice, st));
+    for (int l = 0; l <= c.np; ++l) {
+        const int zero[3] = {0, 0, 0};
+        const bool child = l < c.np;
+        launch_geff_level(phi[l], psi[l], c.nlev(l), l == 0, child ? c.po[l] : zero,
+                          child ? c.pn[l] / 2 : 0, d_edges, n_edges, partials, d_hist, d_out, st);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(slot.p, d_out, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(h.data(), d_hist, sizeof(unsigned long long) * (n_edges + 1),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        out[l].cells = (int64_t)slot.p[0];
+        out[l].sum = slot.p[1];
+        out[l].sum_sq = slot.p[2];
+        out[l].min = slot.p[3];
+        out[l].max = slot.p[4];
+        for (int b = 0; b <= n_edges; ++b) hist[(size_t)l * (n_edges + 1) + b] = (int64_t)h[b];
+    }
+    return NDGP_OK;
+}
+
 } // namespace
 
 // ------------------------------------------------------------------------
@@ -1161,6 +1238,23 @@ ndgp_status ndgp_solve(const ndgp_grid *grid, const ndgp_params *params,
                        size_t workspace_bytes, hipStream_t stream, ndgp_report *report) {
     return guarded([&] {
         return solve_impl(grid, params, delta, phi, workspace, workspace_bytes, stream, report);
+    });
+}
+
+ndgp_status ndgp_total_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_MAX_PATCHES],
+                             const double *const psi[1 + NDGP_MAX_PATCHES],
+                             double *const force[1 + NDGP_MAX_PATCHES], hipStream_t stream) {
+    return guarded([&] { return total_force_impl(grid, phi, psi, force, stream); });
+}
+
+ndgp_status ndgp_geff_stats(const ndgp_grid *grid, const double *const phi[1 + NDGP_MAX_PATCHES],
+                            const double *const psi[1 + NDGP_MAX_PATCHES], const double *edges,
+                            int32_t n_edges, ndgp_geff_level out[1 + NDGP_MAX_PATCHES],
+                            int64_t *hist, void *workspace, size_t workspace_bytes,
+                            hipStream_t stream) {
+    return guarded([&] {
+        return geff_stats_impl(grid, phi, psi, edges, n_edges, out, hist, workspace,
+                               workspace_bytes, stream);
     });
 }
 

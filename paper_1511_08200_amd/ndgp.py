@@ -69,6 +69,14 @@ class _Report(ctypes.Structure):
                 ("iterated_fraction", ctypes.c_double * (1 + MAX_PATCHES))]
 
 
+class _GeffLevel(ctypes.Structure):
+    _fields_ = [("cells", ctypes.c_int64), ("sum", ctypes.c_double), ("sum_sq", ctypes.c_double),
+                ("min", ctypes.c_double), ("max", ctypes.c_double)]
+
+
+GEFF_MAX_EDGES = 255
+GEFF_WORKSPACE = 262144
+
 _lib = None
 
 
@@ -106,6 +114,13 @@ def lib():
         L.ndgp_solve_cellwise.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), arr3,
                                           arr3, ctypes.c_double, arr3, vp, ctypes.c_size_t, vp,
                                           ctypes.POINTER(_Report)]
+        L.ndgp_total_force.restype = ctypes.c_int
+        L.ndgp_total_force.argtypes = [ctypes.POINTER(_Grid), arr3, arr3, arr3, vp]
+        L.ndgp_geff_stats.restype = ctypes.c_int
+        L.ndgp_geff_stats.argtypes = [ctypes.POINTER(_Grid), arr3, arr3,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                      ctypes.POINTER(_GeffLevel),
+                                      ctypes.POINTER(ctypes.c_int64), vp, ctypes.c_size_t, vp]
         L.ndgp_residual.restype = ctypes.c_int
         L.ndgp_residual.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int32,
                                     arr3, vp, vp, ctypes.POINTER(ctypes.c_double), vp,
@@ -419,6 +434,53 @@ def force(grid: Grid, phi: Sequence[torch.Tensor], stream=None) -> list:
     _check(lib().ndgp_force(ctypes.byref(g), _arr3(pptr), _arr3([o.data_ptr() for o in out]),
                             _stream(stream)))
     return out
+
+
+def _level_ptrs(grid: Grid, fields, name):
+    out = []
+    for lvl in range(1 + len(grid.patches)):
+        n = grid.level_n(lvl)
+        shape = (n,) * 3 if lvl == 0 else (n + 2,) * 3
+        out.append(_dev(fields[lvl], shape, f"{name}[{lvl}]"))
+    return out
+
+
+def total_force(grid: Grid, phi: Sequence[torch.Tensor], psi: Sequence[torch.Tensor],
+                stream=None) -> list:
+    """F = -grad(psi) - grad(phi)/2 on every level (Eq. modpoisson): list of
+    (3, m, m, m) tensors; psi is the Newtonian potential laid out like phi."""
+    g = grid._c()
+    out = [torch.empty((3,) + (grid.level_n(l),) * 3, dtype=torch.float64, device=phi[0].device)
+           for l in range(1 + len(grid.patches))]
+    _check(lib().ndgp_total_force(ctypes.byref(g), _arr3(_level_ptrs(grid, phi, "phi")),
+                                  _arr3(_level_ptrs(grid, psi, "psi")),
+                                  _arr3([o.data_ptr() for o in out]), _stream(stream)))
+    return out
+
+
+def geff_stats(grid: Grid, phi: Sequence[torch.Tensor], psi: Sequence[torch.Tensor], edges,
+               stream=None):
+    """G_eff - 1 = |F_5th| / |F_GR| per level over the cells no finer patch
+    covers: (list of dicts with cells, sum, sum_sq, min, max, mean; int64
+    histogram array of shape (levels, len(edges) + 1))."""
+    import numpy as np
+    g = grid._c()
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    nl = 1 + len(grid.patches)
+    outs = (_GeffLevel * (1 + MAX_PATCHES))()
+    hist = np.zeros((nl, e.size + 1), dtype=np.int64)
+    ws = workspace(GEFF_WORKSPACE, phi[0].device)
+    _check(lib().ndgp_geff_stats(ctypes.byref(g), _arr3(_level_ptrs(grid, phi, "phi")),
+                                 _arr3(_level_ptrs(grid, psi, "psi")),
+                                 e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), e.size, outs,
+                                 hist.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 ws.data_ptr(), ws.numel(), _stream(stream)))
+    levels = []
+    for l in range(nl):
+        o = outs[l]
+        levels.append({"cells": int(o.cells), "sum": o.sum, "sum_sq": o.sum_sq, "min": o.min,
+                       "max": o.max, "mean": o.sum / o.cells if o.cells else float("nan")})
+    return levels, hist
 
 
 DIFF_NORMS_WORKSPACE = 131072

@@ -62,6 +62,7 @@ def test_struct_layout_matches_c(L, tmp_path):
         "ndgp_grid": [f for f, _ in ndgp._Grid._fields_],
         "ndgp_params": [f for f, _ in ndgp._Params._fields_],
         "ndgp_report": [f for f, _ in ndgp._Report._fields_],
+        "ndgp_geff_level": [f for f, _ in ndgp._GeffLevel._fields_],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ndgp.h"', "int main(void){"]
     for s, fs in fields.items():
@@ -80,7 +81,7 @@ def test_struct_layout_matches_c(L, tmp_path):
             parts = line.split()
             got[tuple(parts[:-1])] = int(parts[-1])
     for s, cls in (("ndgp_grid", ndgp._Grid), ("ndgp_params", ndgp._Params),
-                   ("ndgp_report", ndgp._Report)):
+                   ("ndgp_report", ndgp._Report), ("ndgp_geff_level", ndgp._GeffLevel)):
         assert got[(s, "size")] == ctypes.sizeof(cls)
         for f, _ in cls._fields_:
             assert got[(s, f)] == getattr(cls, f).offset, (s, f)

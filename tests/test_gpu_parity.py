@@ -430,6 +430,46 @@ def test_cellwise_truncation_matches_oracle():
     assert r0.cycles == rf.cycles and r0.iterated_fraction[:3] == [1.0, 1.0, 1.0]
 
 
+def test_total_force_and_geff_stats_match_oracle():
+    """ndgp_total_force and ndgp_geff_stats (Eq. modpoisson, Sec. III.B; the
+    per-level G_eff of Fig. 3 over cells) on seeded fields: a 32^3 domain and
+    two nested 32^3 patches, one wrapping the periodic domain.  Identical
+    inputs give identical per-cell ratios, so cell counts, histograms, min and
+    max agree exactly and the sums to rounding."""
+    from oracle import geff as G
+    f, deltas, grid = deep_patch_problem(depth=2)
+    rng = np.random.default_rng(77)
+    phis, psis = [], []
+    for lvl in range(3):
+        m = grid.level_n(lvl)
+        a = synth.make_field(m, 1.0, 300 + lvl).delta
+        b = synth.make_field(m, 1.0, 400 + lvl).delta * 3.0 + 0.5 * a
+        if lvl:  # patches: padded fields with arbitrary ghost values
+            a = np.pad(a, 1, mode="wrap") + 1e-3 * rng.standard_normal((m + 2,) * 3)
+            b = np.pad(b, 1, mode="wrap")
+        phis.append(a)
+        psis.append(b)
+    edges = np.geomspace(1e-3, 10.0, 41)
+    got, hist = ndgp.geff_stats(grid, [dev(x) for x in phis], [dev(x) for x in psis], edges)
+    want, hist_o = G.geff_stats(phis, psis, [p.origin for p in grid.patches],
+                                [p.n for p in grid.patches], edges)
+    np.testing.assert_array_equal(hist, hist_o)
+    for lvl in range(3):
+        say(f"  level {lvl}: {got[lvl]['cells']} cells, mean G_eff-1 {got[lvl]['mean']:.4f}")
+        assert got[lvl]["cells"] == want[lvl]["cells"] == hist[lvl].sum()
+        assert got[lvl]["min"] == want[lvl]["min"] and got[lvl]["max"] == want[lvl]["max"]
+        assert got[lvl]["sum"] == pytest.approx(want[lvl]["sum"], rel=1e-12)
+        assert got[lvl]["sum_sq"] == pytest.approx(want[lvl]["sum_sq"], rel=1e-12)
+    assert got[0]["cells"] == 32**3 - 16**3 and got[2]["cells"] == 32**3
+    F = ndgp.total_force(grid, [dev(x) for x in phis], [dev(x) for x in psis])
+    for lvl in range(3):
+        Fo = G.total_force(phis[lvl], psis[lvl], grid.level_h(lvl), lvl == 0)
+        Fg = F[lvl].cpu().numpy()
+        assert np.abs(Fg - Fo).max() <= 1e-13 * np.abs(Fo).max()
+    with pytest.raises(ndgp.NdgpError):
+        ndgp.geff_stats(grid, [dev(x) for x in phis], [dev(x) for x in psis], edges[::-1])
+
+
 def test_patch_residual_level():
     """ndgp_residual on a patch level uses the ghost shell as boundary."""
     f, deltas, grid = patch_problem()

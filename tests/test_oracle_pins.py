@@ -800,6 +800,59 @@ def test_masked_patch_solve(oracle_mod):
 
 
 # ---------------------------------------------------------------------------
+# total force and G_eff per level (Eq. modpoisson, Sec. III.B, Fig. 3)
+
+def test_geff_closed_forms():
+    """Uniform gradients on a patch level: G_eff - 1 = |g_phi| / (2 |g_psi|)
+    in every cell and F = -g_psi - g_phi / 2; periodic sine modes along x:
+    the ratio of amplitudes / 2 wherever the mode has a gradient; no Newtonian
+    force: inf, and 0 where there is no fifth force either."""
+    from oracle import geff as G
+    n, h = 8, 0.01
+    ii = np.arange(-1, n + 1) * h
+    Z, Y, X = np.meshgrid(ii, ii, ii, indexing="ij")
+    gphi, gpsi = np.array([3.0, -1.0, 2.0]), np.array([-0.5, 4.0, 1.5])
+    phi = gphi[0] * X + gphi[1] * Y + gphi[2] * Z
+    psi = gpsi[0] * X + gpsi[1] * Y + gpsi[2] * Z
+    x = G.geff_minus_one(phi, psi, False)
+    np.testing.assert_allclose(x, np.linalg.norm(gphi) / (2 * np.linalg.norm(gpsi)), rtol=1e-13)
+    F = G.total_force(phi, psi, h, False)
+    for a in range(3):
+        np.testing.assert_allclose(F[a], -gpsi[a] - gphi[a] / 2, rtol=1e-12)
+    m = 16
+    Xp = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")[2]
+    k = 2 * np.pi / m
+    x = G.geff_minus_one(0.3 * np.sin(k * (Xp + 0.5)), -1.2 * np.sin(k * (Xp + 0.5)), True)
+    np.testing.assert_allclose(x, 0.3 / (2 * 1.2), rtol=1e-13)
+    flat = np.zeros((m, m, m))
+    x = G.geff_minus_one(np.sin(k * (Xp + 0.5)), flat, True)
+    assert np.all(np.isinf(x))
+    assert np.all(G.geff_minus_one(flat, flat, True) == 0.0)
+
+
+def test_geff_level_bookkeeping():
+    """Each cell counts on the finest level that holds it: the child box's
+    (m/2)^3 parent cells drop out, also where the box wraps the periodic
+    domain; histogram bins are closed below, open above."""
+    from oracle import geff as G
+    keep = G.uncovered(16, True, (-3, 14, 5), 8)
+    assert keep.sum() == 16**3 - 4**3
+    assert not keep[5, 14, 13] and not keep[8, 1, 0] and keep[9, 14, 13]
+    keep = G.uncovered(16, False, (2, 3, 4), 16)
+    assert keep.sum() == 16**3 - 8**3 and not keep[4, 3, 2] and keep[4, 3, 1]
+    edges = [0.01, 0.125, 1.0]
+    phis = [np.zeros((4, 4, 4))]
+    psis = [np.zeros((4, 4, 4))]
+    out, hist = G.geff_stats(phis, psis, [], [], edges)
+    assert out[0]["cells"] == 64 and hist[0].tolist() == [64, 0, 0, 0]   # x = 0 < 0.01
+    Xp = np.meshgrid(np.arange(4), np.arange(4), np.arange(4), indexing="ij")[2]
+    s = np.sin(np.pi / 2 * (Xp + 0.5))
+    out, hist = G.geff_stats([0.25 * s], [s], [], [], edges)    # x = 0.125 exactly: bin 2
+    assert hist[0].tolist() == [0, 0, 64, 0]
+    assert out[0]["min"] == out[0]["max"] == 0.125
+
+
+# ---------------------------------------------------------------------------
 # force, Sec. III.B
 
 def test_force_central_differences(oracle_mod):
