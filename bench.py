@@ -216,6 +216,23 @@ def patch_workload(ndgp, torch, steps):
     for lvl in range(1, depth + 1):
         _, g2, _ = ndgp.diff_norms(F_lin[lvl])
         gr2.append(g2 * (3 * beta) ** 2)
+    # G_eff = 1 + |F5| / |F_GR| per level, each cell on the finest level that
+    # holds it (the cell analogue of Fig. 3): mean and 16/50/84 percentiles
+    # from a histogram with 100 log bins per decade
+    edges = np.logspace(-4, 0, 201)
+
+    def pct(h, q):
+        c = np.cumsum(h) / h.sum()
+        b = int(np.searchsorted(c, q))
+        return float(edges[min(max(b - 1, 0), len(edges) - 1)])
+
+    out["g_eff_per_level"] = {}
+    for name in ("full", "trunc2", "interpolated", "cellwise0.08"):
+        lv, hist = ndgp.geff_stats(grid, res[name], psi, edges)
+        out["g_eff_per_level"][name] = [
+            {"level": l, "cells": lv[l]["cells"], "mean_g_eff": 1.0 + lv[l]["mean"],
+             "p16_84": [1.0 + pct(hist[l], 0.16), 1.0 + pct(hist[l], 0.84)],
+             "median": 1.0 + pct(hist[l], 0.5)} for l in range(len(lv))]
     out["force_difference"] = {}
     for name in ("trunc4", "trunc2", "interpolated", "cellwise0.02", "cellwise0.05",
                  "cellwise0.08"):
