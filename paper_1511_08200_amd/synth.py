@@ -32,6 +32,7 @@ __all__ = [
     "densest_tophat_centre",
     "patch_origin_centred",
     "lognormal_delta_torch",
+    "make_particles",
 ]
 
 
@@ -221,3 +222,25 @@ def lognormal_delta_torch(n: int, sigma: float, seed: int, device="cuda", slope:
     f /= f.mean()
     f -= 1.0
     return f.contiguous()
+
+
+def make_particles(field: Field, n_particles: int, seed: int) -> np.ndarray:
+    """Equal-mass particles that sample a field: each particle picks a base
+    cell with probability proportional to rho = 1 + delta there, then a
+    uniform position inside it.  Returns float64 (3, n_particles): x, y, z in
+    units of the box, each in [0, 1) (structure of arrays)."""
+    n = field.delta.shape[0]
+    rng = np.random.default_rng(seed)
+    p = np.maximum(field.delta.ravel() + 1.0, 0.0)
+    p = p / p.sum()
+    counts = rng.multinomial(n_particles, p)
+    cells = np.repeat(np.arange(p.size), counts)
+    cells = cells[rng.permutation(n_particles)]  # particles in no spatial order
+    k, j, i = np.unravel_index(cells, (n, n, n))
+    u = rng.random((3, n_particles))
+    pos = np.empty((3, n_particles))
+    pos[0] = (i + u[0]) / n
+    pos[1] = (j + u[1]) / n
+    pos[2] = (k + u[2]) / n
+    np.minimum(pos, np.nextafter(1.0, 0.0), out=pos)  # stay inside [0, 1)
+    return pos
