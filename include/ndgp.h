@@ -338,6 +338,37 @@ ndgp_status ndgp_geff_stats(const ndgp_grid *grid, const double *const phi[1 + N
                             hipStream_t stream);
 
 /*
+ * Cloud-in-cell transfers between equal-mass particles and the grid levels
+ * (Sec. IV.A: density and forces are interpolated back and forth between the
+ * particles and the cells by cloud-in-cell).  Particle positions are DEVICE
+ * arrays in structure-of-arrays order: pos[0..N) = x, pos[N..2N) = y,
+ * pos[2N..3N) = z, in units of the box, each in [0, 1).  A patch compares
+ * positions with its cells modulo the box, so patch 1 may wrap the domain.
+ *
+ * ndgp_cic_density    delta[l] (natural n^3 / patch_n^3, the layout ndgp_solve
+ *                     takes) = count / mean - 1, mean = N / (n 2^l)^3 particles
+ *                     per level-l cell: every level is measured against the
+ *                     domain's mean density.  The weights are summed as
+ *                     64-bit fixed-point numbers (2^-36 of a particle), so the
+ *                     result is the same bits on every run.  1 <= N <=
+ *                     NDGP_CIC_MAX_PARTICLES.  Workspace:
+ *                     ndgp_cic_workspace_bytes(grid).  Enqueues only.
+ * ndgp_cic_force      out (3 * N, x then y then z) = cloud-in-cell interpolation
+ *                     of force[l] (3 * cells(l), as ndgp_force or
+ *                     ndgp_total_force write it) from the finest level whose
+ *                     eight cells around the particle all lie inside it.
+ *                     Enqueues only.
+ */
+#define NDGP_CIC_MAX_PARTICLES (1LL << 28)
+size_t ndgp_cic_workspace_bytes(const ndgp_grid *grid);
+ndgp_status ndgp_cic_density(const ndgp_grid *grid, const double *pos, int64_t n_particles,
+                             double *const delta[1 + NDGP_MAX_PATCHES], void *workspace,
+                             size_t workspace_bytes, hipStream_t stream);
+ndgp_status ndgp_cic_force(const ndgp_grid *grid, const double *const force[1 + NDGP_MAX_PATCHES],
+                           const double *pos, int64_t n_particles, double *out,
+                           hipStream_t stream);
+
+/*
  * Serving: the same solve as ndgp_solve, split into non-blocking steps so that
  * one host thread can keep many solves in flight on different streams
  * (continuous batching).  A plan owns nothing on the device: delta, phi and

@@ -119,3 +119,28 @@ def gather(forces, pos, n, origins=(), patch_ns=()):
         out[:, idx] = acc
         done[idx] = True
     return out
+
+
+def deposit_at(pos, n, cells, chunk=1 << 21):
+    """Domain-level cloud-in-cell density contrast at selected cells only
+    (flat indices (k n + j) n + i), the same definition as deposit(), for
+    particle sets too large to deposit whole.  Works through the particles in
+    chunks."""
+    pos = np.asarray(pos, dtype=np.float64)
+    N = pos.shape[1]
+    cells = np.asarray(cells, dtype=np.int64)
+    order = np.argsort(cells)
+    sorted_cells = cells[order]
+    count = np.zeros(cells.size)
+    for s in range(0, N, chunk):
+        p = pos[:, s:s + chunk]
+        terms = [_axis_terms(p[a] * n, 0.0, 0, n, True, n) for a in range(3)]
+        for iz, wz, _ in terms[2]:
+            for iy, wy, _ in terms[1]:
+                for ix, wx, _ in terms[0]:
+                    flat = (iz * n + iy) * n + ix
+                    at = np.searchsorted(sorted_cells, flat)
+                    at = np.minimum(at, sorted_cells.size - 1)
+                    hit = sorted_cells[at] == flat
+                    np.add.at(count, order[at[hit]], (wx * wy * wz)[hit])
+    return count / (N / float(n) ** 3) - 1.0

@@ -152,6 +152,27 @@ void launch_geff_level(const double *phi, const double *psi, int n, bool periodi
                        int n_edges, double *partials, unsigned long long *hist, double *out,
                        hipStream_t st);
 
+// Cloud-in-cell deposit of np particles (pos: x, y, z arrays of np doubles
+// each, box units) onto one level: m^3 cells of 2^-q domain cells with lower
+// corner `corner` (domain cells); q = 0 is the periodic domain (m = n).
+// acc: m^3 fixed-point accumulators; delta = count / mean - 1.
+void launch_cic_deposit(const double *pos, long long np, int n, const double corner[3], int q,
+                        int m, unsigned long long *acc, double *delta, hipStream_t st);
+// Geometry and per-level fields (3 * m^3, x then y then z) for the gather.
+constexpr int kCicMaxLevels = 5;
+struct CicLevels {
+    int levels;
+    int n;
+    int m[kCicMaxLevels];
+    double cells_per_domain[kCicMaxLevels];
+    double corner[kCicMaxLevels][3];
+    const double *force[kCicMaxLevels];
+};
+// out (3 * np, x then y then z) = cloud-in-cell interpolation of the finest
+// level whose eight cells around the particle lie inside it.
+void launch_cic_gather(const double *pos, long long np, const CicLevels &lv, double *out,
+                       hipStream_t st);
+
 // message for ndgp_last_error() in the calling thread
 void set_last_error(const char *msg);
 

@@ -1,0 +1,177 @@
+// ndgp_particles.hip -- cloud-in-cell transfers between equal-mass particles
+// and the grid levels (arXiv:1511.08200, Sec. IV.A: the density and the forces
+// go back and forth between particles and cells by cloud-in-cell).
+//
+// A particle is a cube of one cell's size centred on its position: along each
+// axis the cell whose centre lies below it gets 1 - t and the next one t (t:
+// distance from that centre in cells), and a cell gets the product of its
+// three axis weights.  Level 0 is the periodic domain; a patch level takes
+// the particles whose cube overlaps its cells, comparing positions with the
+// patch modulo the box (a patch may wrap the domain).
+//
+// Deposit: the weights are added as 64-bit fixed-point integers (2^-36 of a
+// particle), so the sums are exact and the same in any order -- the density
+// is bit for bit reproducible although thousands of threads add into one
+// cell.  Gather: every particle reads the finest level whose eight cells
+// around it all lie inside that level.
+
+#include "ndgp_device.h"
+
+#include <cmath>
+
+namespace ndgp {
+namespace {
+
+using namespace dev;
+
+constexpr double kCicOne = 68719476736.0; // 2^36: one particle in fixed point
+
+// The cells along one axis (up to two images of the particle, two cells each)
+// that lie in [0, m) of the level, with their weights.
+__device__ __forceinline__ int cic_axis(double x01, int n, double corner, double cells_per_domain,
+                                        int m, bool periodic, int idx[4], double w[4]) {
+    double d = x01 * (double)n - corner;
+    d = d - (double)n * floor(d / (double)n); // [0, n)
+    int cnt = 0;
+#pragma unroll
+    for (int img = 0; img < 2; ++img) {
+        if (periodic && img) break;
+        const double u = (img ? d - (double)n : d) * cells_per_domain - 0.5;
+        const double f = floor(u);
+        const double t = u - f;
+        const int i0 = (int)f;
+#pragma unroll
+        for (int off = 0; off < 2; ++off) {
+            int i = i0 + off;
+            if (periodic) i &= m - 1;
+            else if (i < 0 || i >= m) continue;
+            idx[cnt] = i;
+            w[cnt] = off ? t : 1.0 - t;
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cic_deposit(const double *__restrict__ pos, long long np, int n, double cx, double cy, double cz,
+              double cells_per_domain, int m, int periodic,
+              unsigned long long *__restrict__ acc) {
+    const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= np) return;
+    int ix[4], iy[4], iz[4];
+    double wx[4], wy[4], wz[4];
+    const int nx = cic_axis(pos[p], n, cx, cells_per_domain, m, periodic != 0, ix, wx);
+    if (!nx) return;
+    const int ny = cic_axis(pos[np + p], n, cy, cells_per_domain, m, periodic != 0, iy, wy);
+    if (!ny) return;
+    const int nz = cic_axis(pos[2 * np + p], n, cz, cells_per_domain, m, periodic != 0, iz, wz);
+    for (int c = 0; c < nz; ++c)
+        for (int b = 0; b < ny; ++b)
+            for (int a = 0; a < nx; ++a) {
+                const double w = (wx[a] * wy[b]) * wz[c];
+                const unsigned long long q = __double2ull_rn(w * kCicOne);
+                if (q)
+                    atomicAdd(&acc[((size_t)iz[c] * m + iy[b]) * m + ix[a]], q);
+            }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cic_finish(const unsigned long long *__restrict__ acc, size_t cells, double scale,
+             double *__restrict__ delta) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < cells) delta[t] = (double)acc[t] * scale - 1.0;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_zero_acc(unsigned long long *__restrict__ a, size_t count) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < count) a[t] = 0ull;
+}
+
+// The lower cell and weight along one axis if all of the particle's cells lie
+// inside the level (for a patch: the image whose two cells are in [0, m)).
+__device__ __forceinline__ bool cic_inside(double x01, int n, double corner,
+                                           double cells_per_domain, int m, bool periodic,
+                                           int &i0, double &t) {
+    double d = x01 * (double)n - corner;
+    d = d - (double)n * floor(d / (double)n);
+#pragma unroll
+    for (int img = 0; img < 2; ++img) {
+        if (periodic && img) break;
+        const double u = (img ? d - (double)n : d) * cells_per_domain - 0.5;
+        const double f = floor(u);
+        const int i = (int)f;
+        if (periodic || (i >= 0 && i + 1 <= m - 1)) {
+            i0 = i;
+            t = u - f;
+            return true;
+        }
+    }
+    return false;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cic_gather(const double *__restrict__ pos, long long np, CicLevels lv,
+             double *__restrict__ out) {
+    const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= np) return;
+    const double x = pos[p], y = pos[np + p], z = pos[2 * np + p];
+    for (int q = lv.levels - 1; q >= 0; --q) {
+        const bool per = q == 0;
+        const int m = lv.m[q];
+        const double cpd = lv.cells_per_domain[q];
+        int i0, j0, k0;
+        double tx, ty, tz;
+        if (!cic_inside(x, lv.n, lv.corner[q][0], cpd, m, per, i0, tx)) continue;
+        if (!cic_inside(y, lv.n, lv.corner[q][1], cpd, m, per, j0, ty)) continue;
+        if (!cic_inside(z, lv.n, lv.corner[q][2], cpd, m, per, k0, tz)) continue;
+        const double *f = lv.force[q];
+        const size_t cells = (size_t)m * m * m;
+        double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx) {
+                    const double w = ((dx ? tx : 1.0 - tx) * (dy ? ty : 1.0 - ty)) * (dz ? tz : 1.0 - tz);
+                    int ci = i0 + dx, cj = j0 + dy, ck = k0 + dz;
+                    if (per) {
+                        ci &= m - 1;
+                        cj &= m - 1;
+                        ck &= m - 1;
+                    }
+                    const size_t c = ((size_t)ck * m + cj) * m + ci;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) acc[a] = fma(w, f[a * cells + c], acc[a]);
+                }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[a * np + p] = acc[a];
+        return;
+    }
+}
+
+} // namespace
+
+void launch_cic_deposit(const double *pos, long long np, int n, const double corner[3], int q,
+                        int m, unsigned long long *acc, double *delta, hipStream_t st) {
+    const size_t cells = (size_t)m * m * m;
+    k_zero_acc<<<blocks_for(cells), kBlock, 0, st>>>(acc, cells);
+    if (np > 0)
+        k_cic_deposit<<<(unsigned)((np + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+            pos, np, n, corner[0], corner[1], corner[2], std::ldexp(1.0, q), m, q == 0 ? 1 : 0,
+            acc);
+    // delta = count / mean - 1, mean = np / (n 2^q)^3 particles per cell
+    const double cells_equiv = std::ldexp((double)n * n * n, 3 * q);
+    const double scale = np > 0 ? cells_equiv / ((double)np * kCicOne) : 0.0;
+    k_cic_finish<<<blocks_for(cells), kBlock, 0, st>>>(acc, cells, scale, delta);
+}
+
+void launch_cic_gather(const double *pos, long long np, const CicLevels &lv, double *out,
+                       hipStream_t st) {
+    if (np > 0)
+        k_cic_gather<<<(unsigned)((np + kBlock - 1) / kBlock), kBlock, 0, st>>>(pos, np, lv, out);
+}
+
+} // namespace ndgp

@@ -954,6 +954,75 @@ ndgp_status geff_stats_impl(const ndgp_grid *grid, const double *const phi[],
     return NDGP_OK;
 }
 
+// lower corner of every level in domain cells (level q + 1 at corner(q) +
+// origin(q) 2^-q)
+void level_corners(const Cfg &c, double corner[][3]) {
+    corner[0][0] = corner[0][1] = corner[0][2] = 0.0;
+    for (int q = 0; q < c.np; ++q)
+        for (int a = 0; a < 3; ++a)
+            corner[q + 1][a] = corner[q][a] + std::ldexp((double)c.po[q][a], -q);
+}
+
+size_t cic_bytes(const Cfg &c) {
+    Carver cv{nullptr};
+    for (int l = 0; l <= c.np; ++l) {
+        const size_t m = (size_t)c.nlev(l);
+        cv.take<unsigned long long>(m * m * m);
+    }
+    return cv.off + 256;
+}
+
+ndgp_status cic_density_impl(const ndgp_grid *grid, const double *pos, int64_t np,
+                             double *const delta[], void *ws, size_t ws_bytes, hipStream_t st) {
+    Cfg c;
+    std::string why;
+    if (!resolve_grid(grid, c, why)) return fail(NDGP_EINVAL, why);
+    if (!pos || !delta) return fail(NDGP_EINVAL, "pos and delta must not be NULL");
+    if (np < 1 || np > NDGP_CIC_MAX_PARTICLES)
+        return fail(NDGP_EINVAL, "n_particles must be in [1, NDGP_CIC_MAX_PARTICLES]");
+    for (int l = 0; l <= c.np; ++l)
+        if (!delta[l]) return fail(NDGP_EINVAL, "delta of every level must not be NULL");
+    if (!ws || ws_bytes < cic_bytes(c))
+        return fail(NDGP_ENOMEM, "workspace smaller than ndgp_cic_workspace_bytes() = " +
+                                     std::to_string(cic_bytes(c)));
+    double corner[1 + NDGP_MAX_PATCHES][3];
+    level_corners(c, corner);
+    Carver cv{aligned_base(ws)};
+    for (int l = 0; l <= c.np; ++l) {
+        const int m = c.nlev(l);
+        unsigned long long *acc = cv.take<unsigned long long>((size_t)m * m * m);
+        launch_cic_deposit(pos, (long long)np, c.n, corner[l], l, m, acc, delta[l], st);
+    }
+    HIP_TRY(hipGetLastError());
+    return NDGP_OK;
+}
+
+ndgp_status cic_force_impl(const ndgp_grid *grid, const double *const force[], const double *pos,
+                           int64_t np, double *out, hipStream_t st) {
+    Cfg c;
+    std::string why;
+    if (!resolve_grid(grid, c, why)) return fail(NDGP_EINVAL, why);
+    if (!pos || !force || !out) return fail(NDGP_EINVAL, "pos, force and out must not be NULL");
+    if (np < 1 || np > NDGP_CIC_MAX_PARTICLES)
+        return fail(NDGP_EINVAL, "n_particles must be in [1, NDGP_CIC_MAX_PARTICLES]");
+    static_assert(kCicMaxLevels == 1 + NDGP_MAX_PATCHES, "one gather slot per level");
+    CicLevels lv{};
+    lv.levels = c.np + 1;
+    lv.n = c.n;
+    double corner[1 + NDGP_MAX_PATCHES][3];
+    level_corners(c, corner);
+    for (int l = 0; l <= c.np; ++l) {
+        if (!force[l]) return fail(NDGP_EINVAL, "force of every level must not be NULL");
+        lv.m[l] = c.nlev(l);
+        lv.cells_per_domain[l] = std::ldexp(1.0, l);
+        for (int a = 0; a < 3; ++a) lv.corner[l][a] = corner[l][a];
+        lv.force[l] = force[l];
+    }
+    launch_cic_gather(pos, (long long)np, lv, out, st);
+    HIP_TRY(hipGetLastError());
+    return NDGP_OK;
+}
+
 } // namespace
 
 // ------------------------------------------------------------------------
@@ -1239,6 +1308,30 @@ ndgp_status ndgp_solve(const ndgp_grid *grid, const ndgp_params *params,
     return guarded([&] {
         return solve_impl(grid, params, delta, phi, workspace, workspace_bytes, stream, report);
     });
+}
+
+size_t ndgp_cic_workspace_bytes(const ndgp_grid *grid) {
+    Cfg c;
+    std::string why;
+    if (!resolve_grid(grid, c, why)) {
+        g_err = why;
+        return 0;
+    }
+    return cic_bytes(c);
+}
+
+ndgp_status ndgp_cic_density(const ndgp_grid *grid, const double *pos, int64_t n_particles,
+                             double *const delta[1 + NDGP_MAX_PATCHES], void *workspace,
+                             size_t workspace_bytes, hipStream_t stream) {
+    return guarded([&] {
+        return cic_density_impl(grid, pos, n_particles, delta, workspace, workspace_bytes, stream);
+    });
+}
+
+ndgp_status ndgp_cic_force(const ndgp_grid *grid, const double *const force[1 + NDGP_MAX_PATCHES],
+                           const double *pos, int64_t n_particles, double *out,
+                           hipStream_t stream) {
+    return guarded([&] { return cic_force_impl(grid, force, pos, n_particles, out, stream); });
 }
 
 ndgp_status ndgp_total_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_MAX_PATCHES],

@@ -114,6 +114,13 @@ def lib():
         L.ndgp_solve_cellwise.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), arr3,
                                           arr3, ctypes.c_double, arr3, vp, ctypes.c_size_t, vp,
                                           ctypes.POINTER(_Report)]
+        L.ndgp_cic_workspace_bytes.restype = ctypes.c_size_t
+        L.ndgp_cic_workspace_bytes.argtypes = [ctypes.POINTER(_Grid)]
+        L.ndgp_cic_density.restype = ctypes.c_int
+        L.ndgp_cic_density.argtypes = [ctypes.POINTER(_Grid), vp, ctypes.c_int64, arr3, vp,
+                                       ctypes.c_size_t, vp]
+        L.ndgp_cic_force.restype = ctypes.c_int
+        L.ndgp_cic_force.argtypes = [ctypes.POINTER(_Grid), arr3, vp, ctypes.c_int64, vp, vp]
         L.ndgp_total_force.restype = ctypes.c_int
         L.ndgp_total_force.argtypes = [ctypes.POINTER(_Grid), arr3, arr3, arr3, vp]
         L.ndgp_geff_stats.restype = ctypes.c_int
@@ -481,6 +488,44 @@ def geff_stats(grid: Grid, phi: Sequence[torch.Tensor], psi: Sequence[torch.Tens
         levels.append({"cells": int(o.cells), "sum": o.sum, "sum_sq": o.sum_sq, "min": o.min,
                        "max": o.max, "mean": o.sum / o.cells if o.cells else float("nan")})
     return levels, hist
+
+
+def cic_density(grid: Grid, pos: torch.Tensor, delta=None, ws=None, stream=None) -> list:
+    """Cloud-in-cell density contrast of equal-mass particles on every level
+    (ndgp_cic_density).  ``pos``: float64 device tensor (3, N), box units in
+    [0, 1).  Returns [domain n^3, patch m^3, ...] (the layout solve() takes)."""
+    if pos.dim() != 2 or pos.shape[0] != 3:
+        raise ValueError("pos must have shape (3, N)")
+    g = grid._c()
+    npart = pos.shape[1]
+    if delta is None:
+        delta = [torch.empty((grid.level_n(l),) * 3, dtype=torch.float64, device=pos.device)
+                 for l in range(1 + len(grid.patches))]
+    dptr = [_dev(delta[l], (grid.level_n(l),) * 3, f"delta[{l}]")
+            for l in range(1 + len(grid.patches))]
+    nb = int(lib().ndgp_cic_workspace_bytes(ctypes.byref(g)))
+    if nb == 0:
+        _check(NDGP_EINVAL)
+    if ws is None:
+        ws = workspace(nb, pos.device)
+    _check(lib().ndgp_cic_density(ctypes.byref(g), _dev(pos, (3, npart), "pos"), npart,
+                                  _arr3(dptr), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return delta
+
+
+def cic_force(grid: Grid, force: Sequence[torch.Tensor], pos: torch.Tensor, out=None,
+              stream=None) -> torch.Tensor:
+    """Cloud-in-cell interpolation of per-level forces (3, m, m, m) to the
+    particles (ndgp_cic_force): (3, N)."""
+    g = grid._c()
+    npart = pos.shape[1]
+    if out is None:
+        out = torch.empty((3, npart), dtype=torch.float64, device=pos.device)
+    fptr = [_dev(force[l], (3,) + (grid.level_n(l),) * 3, f"force[{l}]")
+            for l in range(1 + len(grid.patches))]
+    _check(lib().ndgp_cic_force(ctypes.byref(g), _arr3(fptr), _dev(pos, (3, npart), "pos"),
+                                npart, _dev(out, (3, npart), "out"), _stream(stream)))
+    return out
 
 
 DIFF_NORMS_WORKSPACE = 131072

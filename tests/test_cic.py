@@ -96,3 +96,12 @@ def test_particle_sampler_follows_the_field():
     counts = np.bincount((idx[2] * 16 + idx[1]) * 16 + idx[0], minlength=16**3)
     expect = (f.delta.ravel() + 1.0) / (f.delta.ravel() + 1.0).sum() * 400000
     assert np.corrcoef(counts, expect)[0, 1] > 0.99
+
+
+def test_deposit_at_selected_cells_is_deposit():
+    rng = np.random.default_rng(8)
+    pos = rng.random((3, 30000))
+    (d,) = C.deposit(pos, 16)
+    cells = rng.choice(16**3, size=200, replace=False)
+    np.testing.assert_allclose(C.deposit_at(pos, 16, cells, chunk=7000), d.ravel()[cells],
+                               rtol=0, atol=1e-12)

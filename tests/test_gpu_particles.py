@@ -1,0 +1,96 @@
+"""Cloud-in-cell transfers on the GPU (ndgp_cic_density, ndgp_cic_force;
+Sec. IV.A) against the CPU oracle (oracle/cic.py), through the C ABI."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cic as C
+from paper_1511_08200_amd import ndgp, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def nested(n=32, m=32, depth=2, seed=12):
+    f = synth.make_field(n, 2.0, seed, n_tophats=6)
+    c = synth.densest_tophat_centre(f)
+    chain = []
+    for q in range(depth):
+        o = synth.patch_origin_centred(c, m // 2)
+        if q > 0:
+            o = tuple(min(max(v, 2), m - m // 2 - 2) for v in o)
+        chain.append(o)
+        c = tuple((c[a] - o[a]) * 2 for a in range(3))
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n), patches=[ndgp.Patch(m, o) for o in chain])
+    return f, grid, chain
+
+
+def test_cic_density_matches_oracle_and_is_reproducible():
+    say("cic density: 32^3 + two nested 32^3 patches, 300k particles")
+    f, grid, chain = nested()
+    pos = synth.make_particles(f, 300000, 21)
+    want = C.deposit(pos, 32, origins=chain, patch_ns=[32, 32])
+    p = dev(pos)
+    got = [d.cpu().numpy() for d in ndgp.cic_density(grid, p)]
+    again = [d.cpu().numpy() for d in ndgp.cic_density(grid, p)]
+    for lvl in range(3):
+        scale = np.abs(want[lvl]).max() + 1.0
+        err = np.abs(got[lvl] - want[lvl]).max() / scale
+        say(f"  level {lvl}: max |delta - oracle| / scale = {err:.1e}")
+        assert err <= 1e-10
+        assert np.array_equal(got[lvl], again[lvl])
+    # the particles' mass: every particle is inside the periodic domain
+    assert abs(got[0].mean()) <= 1e-10
+    assert (got[0] >= -1.0 - 1e-12).all()
+
+
+def test_cic_force_matches_oracle():
+    say("cic force gather: seeded per-level fields")
+    f, grid, chain = nested()
+    pos = synth.make_particles(f, 200000, 22)
+    rng = np.random.default_rng(5)
+    forces = [rng.standard_normal((3, grid.level_n(l), grid.level_n(l), grid.level_n(l)))
+              for l in range(3)]
+    want = C.gather(forces, pos, 32, origins=chain, patch_ns=[32, 32])
+    got = ndgp.cic_force(grid, [dev(x) for x in forces], dev(pos)).cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_cic_full_size_sampled():
+    """256^3 particles on the 256^3 domain (one per cell on average, the
+    paper's N_p^(1/3) = 2^(l_d)): the GPU density at 3000 sampled cells equals
+    the oracle's definition evaluated at those cells, and the mean is zero."""
+    say("cic full size: 256^3 particles on 256^3, sampled cells")
+    n = 256
+    f = synth.make_field(n, 2.0, 1513, n_tophats=50)
+    pos = synth.make_particles(f, n**3, 7)
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(256.0, n))
+    (d,) = ndgp.cic_density(grid, dev(pos))
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().ravel()
+    rng = np.random.default_rng(0)
+    cells = rng.choice(n**3, size=3000, replace=False)
+    # include the densest cells, where thousands of weights meet
+    cells = np.unique(np.concatenate([cells, np.argsort(got)[-50:]]))
+    want = C.deposit_at(pos, n, cells)
+    err = np.abs(got[cells] - want).max() / (np.abs(want).max() + 1.0)
+    say(f"  sampled max rel err {err:.1e}, max delta {got.max():.1f}")
+    assert err <= 1e-10
+    assert abs(got.mean()) <= 1e-10
+
+
+def test_cic_rejects_bad_arguments():
+    grid = ndgp.Grid(n=32, h=ndgp.cell_size(32.0, 32))
+    with pytest.raises(ValueError):
+        ndgp.cic_density(grid, torch.zeros((2, 10), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ndgp.NdgpError):
+        ndgp.cic_density(grid, torch.zeros((3, 0), dtype=torch.float64, device="cuda"))
