@@ -248,6 +248,83 @@ def patch_workload(ndgp, torch, steps):
     return out
 
 
+def particle_workload(ndgp, torch, steps):
+    """One time step of the paper's loop around the solver (Sec. IV.A): 256^3
+    equal-mass particles sampled from the 256^3 benchmark field, their
+    cloud-in-cell density on the domain, the nDGP solve to 1e-10, the
+    Newtonian potential (r_c = 0 solve), the total force and its
+    cloud-in-cell interpolation back to the particles."""
+    from paper_1511_08200_amd import synth
+    n, box, rc = 256, 256.0, 1.0
+    f = make_domain(n, box, 2.0, 50, 1513)
+    pos = torch.from_numpy(synth.make_particles(f, n**3, 7)).to("cuda")
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
+    beta = ndgp.beta_lcdm(1.0, 0.3, rc)
+    p5 = ndgp.Params(rc=rc, tol=1e-10)
+    pn = ndgp.Params(rc=0.0, beta=beta, tol=1e-10)
+    delta = ndgp.cic_density(grid, pos)
+    phi, psi = ndgp.alloc_phi(grid), ndgp.alloc_phi(grid)
+    ws = ndgp.workspace(ndgp.workspace_bytes(grid, p5))
+    out = torch.empty_like(pos)
+    stages = {"cic_density": 0.0, "solve_ndgp": 0.0, "solve_newton": 0.0, "total_force": 0.0,
+              "cic_force": 0.0}
+    reps = None
+    for it in range(steps + 1):
+        t = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ndgp.cic_density(grid, pos, delta=delta)
+        torch.cuda.synchronize()
+        t["cic_density"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, reps = ndgp.solve(grid, p5, delta, phi=phi, ws=ws)
+        t["solve_ndgp"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, repn = ndgp.solve(grid, pn, delta, phi=psi, ws=ws)
+        psi[0].mul_(1.5 * beta)  # Psi_N = (3 beta / 2) x the r_c = 0 field
+        torch.cuda.synchronize()
+        t["solve_newton"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        F = ndgp.total_force(grid, phi, psi)
+        torch.cuda.synchronize()
+        t["total_force"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ndgp.cic_force(grid, F, pos, out=out)
+        torch.cuda.synchronize()
+        t["cic_force"] = time.perf_counter() - t0
+        if it:  # the first pass warms up
+            for k in stages:
+                stages[k] += t[k] / steps
+    total = sum(stages.values())
+    # the same particles sorted by cell, as a tree code keeps them: the
+    # deposit's atomics and the gather's reads then stay local
+    pos_sorted = torch.from_numpy(synth.make_particles(f, n**3, 7, cell_order=True)).to("cuda")
+    ndgp.cic_density(grid, pos_sorted, delta=delta)
+    ndgp.cic_force(grid, F, pos_sorted, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ndgp.cic_density(grid, pos_sorted, delta=delta)
+    torch.cuda.synchronize()
+    dep_sorted = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ndgp.cic_force(grid, F, pos_sorted, out=out)
+    torch.cuda.synchronize()
+    gat_sorted = (time.perf_counter() - t0) / steps
+    return {"cell_ordered_particles_ms": {"cic_density": round(dep_sorted * 1e3, 3),
+                                          "cic_force": round(gat_sorted * 1e3, 3)},
+            "workload": "256^3 particles sampled from the 256^3 field (lognormal sigma 2 + 50 "
+                        "top-hats, box 256 Mpc/h): CIC density, nDGP solve to 1e-10, Newtonian "
+                        "solve, total force, CIC force at the particles",
+            "ms": {k: round(v * 1e3, 3) for k, v in stages.items()},
+            "ms_per_step": round(total * 1e3, 2),
+            "particles_per_s_deposit": n**3 / stages["cic_density"],
+            "particles_per_s_gather": n**3 / stages["cic_force"],
+            "ndgp_cycles": reps.cycles[0], "newton_cycles": repn.cycles[0],
+            "max_delta": float(delta[0].max())}
+
+
 def large_workload(ndgp, torch, steps):
     """512^3 periodic, sigma_ln = 2.5, FP64, r_c H0 in {0.5, 1, 5}."""
     n, box = 512, 512.0
@@ -368,6 +445,8 @@ def main():
     if not args.no_extra:
         log("patch workload")
         line.setdefault("extra", {})["patches"] = patch_workload(ndgp, torch, 3)
+        log("particle workload")
+        line["extra"]["particles"] = particle_workload(ndgp, torch, 3)
         log("512^3 workload")
         line["extra"]["large"] = large_workload(ndgp, torch, 3)
         if args.serve_requests > 0:

@@ -360,6 +360,17 @@ ndgp_status ndgp_geff_stats(const ndgp_grid *grid, const double *const phi[1 + N
  *                     Enqueues only.
  */
 #define NDGP_CIC_MAX_PARTICLES (1LL << 28)
+/* Refinement criterion (Sec. IV.A): a cell is refined when the particles in
+   its volume number more than n_ref (the paper uses 4).  From the density
+   contrast ndgp_cic_density wrote for N particles: flags[l][c] = 1 where
+   (delta + 1) N / (n 2^l)^3 > n_ref, else 0 (device, cells(l) bytes each);
+   n_flagged[l] (HOST) = number of flagged cells.  Blocks until n_flagged is
+   written.  Workspace: NDGP_DIFF_NORMS_WORKSPACE bytes. */
+ndgp_status ndgp_refine_flags(const ndgp_grid *grid, const double *const delta[1 + NDGP_MAX_PATCHES],
+                              int64_t n_particles, double n_ref,
+                              unsigned char *const flags[1 + NDGP_MAX_PATCHES],
+                              int64_t n_flagged[1 + NDGP_MAX_PATCHES], void *workspace,
+                              size_t workspace_bytes, hipStream_t stream);
 size_t ndgp_cic_workspace_bytes(const ndgp_grid *grid);
 ndgp_status ndgp_cic_density(const ndgp_grid *grid, const double *pos, int64_t n_particles,
                              double *const delta[1 + NDGP_MAX_PATCHES], void *workspace,

@@ -158,6 +158,10 @@ void launch_geff_level(const double *phi, const double *psi, int n, bool periodi
 // acc: m^3 fixed-point accumulators; delta = count / mean - 1.
 void launch_cic_deposit(const double *pos, long long np, int n, const double corner[3], int q,
                         int m, unsigned long long *acc, double *delta, hipStream_t st);
+// flags = (delta + 1) mean > n_ref; partials[0..kReduceBlocks) = per-block
+// counts of flagged cells.
+void launch_refine_flags(const double *delta, size_t cells, double mean, double n_ref,
+                         unsigned char *flags, double *partials, hipStream_t st);
 // Geometry and per-level fields (3 * m^3, x then y then z) for the gather.
 constexpr int kCicMaxLevels = 5;
 struct CicLevels {

@@ -152,7 +152,29 @@ k_cic_gather(const double *__restrict__ pos, long long np, CicLevels lv,
     }
 }
 
+// Refinement criterion of Sec. IV.A: a cell is refined when the particles in
+// its volume number more than n_ref.  count = (delta + 1) mean with mean the
+// level's particles per cell; per-block counts of flagged cells.
+__global__ void __launch_bounds__(kBlock)
+k_refine_flags(const double *__restrict__ delta, size_t cells, double mean, double n_ref,
+               unsigned char *__restrict__ flags, double *__restrict__ partials) {
+    double nflag = 0.0;
+    for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < cells;
+         c += (size_t)gridDim.x * kBlock) {
+        const bool f = (delta[c] + 1.0) * mean > n_ref;
+        flags[c] = f ? 1 : 0;
+        nflag += f ? 1.0 : 0.0;
+    }
+    const double b = block_sum(nflag);
+    if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
 } // namespace
+
+void launch_refine_flags(const double *delta, size_t cells, double mean, double n_ref,
+                         unsigned char *flags, double *partials, hipStream_t st) {
+    k_refine_flags<<<kReduceBlocks, kBlock, 0, st>>>(delta, cells, mean, n_ref, flags, partials);
+}
 
 void launch_cic_deposit(const double *pos, long long np, int n, const double corner[3], int q,
                         int m, unsigned long long *acc, double *delta, hipStream_t st) {

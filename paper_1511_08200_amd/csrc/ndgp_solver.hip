@@ -997,6 +997,36 @@ ndgp_status cic_density_impl(const ndgp_grid *grid, const double *pos, int64_t n
     return NDGP_OK;
 }
 
+ndgp_status refine_flags_impl(const ndgp_grid *grid, const double *const delta[], int64_t np,
+                              double n_ref, unsigned char *const flags[], int64_t *n_flagged,
+                              void *ws, size_t ws_bytes, hipStream_t st) {
+    Cfg c;
+    std::string why;
+    if (!resolve_grid(grid, c, why)) return fail(NDGP_EINVAL, why);
+    if (!delta || !flags || !n_flagged)
+        return fail(NDGP_EINVAL, "delta, flags and n_flagged must not be NULL");
+    if (np < 1 || !std::isfinite(n_ref))
+        return fail(NDGP_EINVAL, "need n_particles >= 1 and a finite n_ref");
+    Carver cv{aligned_base(ws)};
+    double *partials = cv.take<double>(kReduceBlocks);
+    double *total = cv.take<double>(1 + NDGP_MAX_PATCHES);
+    if (!ws || cv.off + 256 > ws_bytes)
+        return fail(NDGP_ENOMEM, "workspace smaller than NDGP_DIFF_NORMS_WORKSPACE");
+    for (int l = 0; l <= c.np; ++l) {
+        if (!delta[l] || !flags[l]) return fail(NDGP_EINVAL, "delta/flags of every level must not be NULL");
+        const size_t m = (size_t)c.nlev(l);
+        const double mean = (double)np / std::ldexp((double)c.n * c.n * c.n, 3 * l);
+        launch_refine_flags(delta[l], m * m * m, mean, n_ref, flags[l], partials, st);
+        launch_reduce_final(partials, total + l, st);
+    }
+    SlotGuard slot;
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(slot.p, total, (c.np + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int l = 0; l <= c.np; ++l) n_flagged[l] = (int64_t)slot.p[l];
+    return NDGP_OK;
+}
+
 ndgp_status cic_force_impl(const ndgp_grid *grid, const double *const force[], const double *pos,
                            int64_t np, double *out, hipStream_t st) {
     Cfg c;
@@ -1332,6 +1362,17 @@ ndgp_status ndgp_cic_force(const ndgp_grid *grid, const double *const force[1 + 
                            const double *pos, int64_t n_particles, double *out,
                            hipStream_t stream) {
     return guarded([&] { return cic_force_impl(grid, force, pos, n_particles, out, stream); });
+}
+
+ndgp_status ndgp_refine_flags(const ndgp_grid *grid, const double *const delta[1 + NDGP_MAX_PATCHES],
+                              int64_t n_particles, double n_ref,
+                              unsigned char *const flags[1 + NDGP_MAX_PATCHES],
+                              int64_t n_flagged[1 + NDGP_MAX_PATCHES], void *workspace,
+                              size_t workspace_bytes, hipStream_t stream) {
+    return guarded([&] {
+        return refine_flags_impl(grid, delta, n_particles, n_ref, flags, n_flagged, workspace,
+                                 workspace_bytes, stream);
+    });
 }
 
 ndgp_status ndgp_total_force(const ndgp_grid *grid, const double *const phi[1 + NDGP_MAX_PATCHES],

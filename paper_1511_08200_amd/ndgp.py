@@ -121,6 +121,10 @@ def lib():
                                        ctypes.c_size_t, vp]
         L.ndgp_cic_force.restype = ctypes.c_int
         L.ndgp_cic_force.argtypes = [ctypes.POINTER(_Grid), arr3, vp, ctypes.c_int64, vp, vp]
+        L.ndgp_refine_flags.restype = ctypes.c_int
+        L.ndgp_refine_flags.argtypes = [ctypes.POINTER(_Grid), arr3, ctypes.c_int64,
+                                        ctypes.c_double, arr3, ctypes.POINTER(ctypes.c_int64),
+                                        vp, ctypes.c_size_t, vp]
         L.ndgp_total_force.restype = ctypes.c_int
         L.ndgp_total_force.argtypes = [ctypes.POINTER(_Grid), arr3, arr3, arr3, vp]
         L.ndgp_geff_stats.restype = ctypes.c_int
@@ -511,6 +515,44 @@ def cic_density(grid: Grid, pos: torch.Tensor, delta=None, ws=None, stream=None)
     _check(lib().ndgp_cic_density(ctypes.byref(g), _dev(pos, (3, npart), "pos"), npart,
                                   _arr3(dptr), ws.data_ptr(), ws.numel(), _stream(stream)))
     return delta
+
+
+def refine_flags(grid: Grid, delta: Sequence[torch.Tensor], n_particles: int,
+                 n_ref: float = 4.0, stream=None):
+    """Cells with more than n_ref particles (Sec. IV.A), from cic_density's
+    output: (list of uint8 device tensors, list of flagged counts)."""
+    g = grid._c()
+    nl = 1 + len(grid.patches)
+    flags = [torch.empty((grid.level_n(l),) * 3, dtype=torch.uint8, device=delta[0].device)
+             for l in range(nl)]
+    counts = (ctypes.c_int64 * (1 + MAX_PATCHES))()
+    ws = workspace(DIFF_NORMS_WORKSPACE, delta[0].device)
+    dptr = [_dev(delta[l], (grid.level_n(l),) * 3, f"delta[{l}]") for l in range(nl)]
+    _check(lib().ndgp_refine_flags(ctypes.byref(g), _arr3(dptr), int(n_particles), float(n_ref),
+                                   _arr3([f.data_ptr() for f in flags]), counts, ws.data_ptr(),
+                                   ws.numel(), _stream(stream)))
+    return flags, [int(counts[l]) for l in range(nl)]
+
+
+def suggest_patch_origin(flags_parent: "np.ndarray", m: int, periodic: bool = True):
+    """Integer lower corner (x, y, z) in parent cells of the m-cell patch
+    (m/2 parent cells wide) covering the most flagged parent cells: a static
+    stand-in for refining where the criterion asks (host helper, summed-area
+    table over the flags, with periodic wrap on the domain)."""
+    import numpy as np
+    f = np.asarray(flags_parent, dtype=np.int64)
+    w = m // 2
+    n = f.shape[0]
+    if periodic:
+        f = np.pad(f, ((0, w), (0, w), (0, w)), mode="wrap")
+    s = f.cumsum(0).cumsum(1).cumsum(2)
+    s = np.pad(s, ((1, 0), (1, 0), (1, 0)))
+    lim = n if periodic else n - w + 1
+    k, j, i = np.meshgrid(np.arange(lim), np.arange(lim), np.arange(lim), indexing="ij")
+    box = (s[k + w, j + w, i + w] - s[k, j + w, i + w] - s[k + w, j, i + w] - s[k + w, j + w, i]
+           + s[k, j, i + w] + s[k, j + w, i] + s[k + w, j, i] - s[k, j, i])
+    kk, jj, ii = np.unravel_index(int(np.argmax(box)), box.shape)
+    return (int(ii), int(jj), int(kk))
 
 
 def cic_force(grid: Grid, force: Sequence[torch.Tensor], pos: torch.Tensor, out=None,

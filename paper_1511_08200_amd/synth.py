@@ -224,18 +224,23 @@ def lognormal_delta_torch(n: int, sigma: float, seed: int, device="cuda", slope:
     return f.contiguous()
 
 
-def make_particles(field: Field, n_particles: int, seed: int) -> np.ndarray:
+def make_particles(field: Field, n_particles: int, seed: int,
+                   cell_order: bool = False) -> np.ndarray:
     """Equal-mass particles that sample a field: each particle picks a base
     cell with probability proportional to rho = 1 + delta there, then a
     uniform position inside it.  Returns float64 (3, n_particles): x, y, z in
-    units of the box, each in [0, 1) (structure of arrays)."""
+    units of the box, each in [0, 1) (structure of arrays).  The particles
+    come in random order, or sorted by base cell with cell_order (the order
+    a tree code keeps them in)."""
     n = field.delta.shape[0]
     rng = np.random.default_rng(seed)
     p = np.maximum(field.delta.ravel() + 1.0, 0.0)
     p = p / p.sum()
     counts = rng.multinomial(n_particles, p)
     cells = np.repeat(np.arange(p.size), counts)
-    cells = cells[rng.permutation(n_particles)]  # particles in no spatial order
+    perm = rng.permutation(n_particles)
+    if not cell_order:
+        cells = cells[perm]  # particles in no spatial order
     k, j, i = np.unravel_index(cells, (n, n, n))
     u = rng.random((3, n_particles))
     pos = np.empty((3, n_particles))

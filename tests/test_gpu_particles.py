@@ -94,3 +94,19 @@ def test_cic_rejects_bad_arguments():
         ndgp.cic_density(grid, torch.zeros((2, 10), dtype=torch.float64, device="cuda"))
     with pytest.raises(ndgp.NdgpError):
         ndgp.cic_density(grid, torch.zeros((3, 0), dtype=torch.float64, device="cuda"))
+
+
+def test_refine_flags_match_definition():
+    """Sec. IV.A criterion: cells holding more than n_ref particles, from a
+    density contrast; the same comparison in numpy decides every cell."""
+    f, grid, chain = nested()
+    npart = 32**3
+    rng = np.random.default_rng(3)
+    deltas = [synth.make_field(grid.level_n(l), 1.5, 50 + l).delta for l in range(3)]
+    flags, counts = ndgp.refine_flags(grid, [dev(d) for d in deltas], npart, 4.0)
+    for l in range(3):
+        mean = npart / float(32 * 2**l) ** 3
+        want = (deltas[l] + 1.0) * mean > 4.0
+        got = flags[l].cpu().numpy().astype(bool)
+        assert np.array_equal(got, want) and counts[l] == int(want.sum())
+    assert counts[0] > 0
