@@ -14,10 +14,15 @@ The JSON line also carries:
                 launch stream during the timed steps; algorithmic bytes per
                 cell update = 24 (read phi and S, write phi; FP64);
   cpu_baseline  the CPU oracle on a bounded sample of the same workload;
-  extra         the 256^3 + four nested 128^3 patch workload at the truncation
-                levels l_d+1, l_d+2, l_d+4 and the full run (time to tolerance,
-                force difference against the full run per level) and 512^3
-                solves at three r_c, with the relaxation roofline there.
+  extra         patches: 256^3 + two nested 128^3 patches, full vs interpolated
+                vs mixed + interpolated (time to tolerance, force difference);
+                truncation: 256^3 + four nested 128^3 patches at the truncation
+                levels l_d+1, l_d+2, l_d+4 and full, cell-wise truncation,
+                G_eff per level; particles: one time step around the solver
+                (cloud-in-cell density, nDGP and Newtonian solves, total force,
+                cloud-in-cell force); large: 512^3 solves at three r_c, FP64
+                and mixed, with the relaxation roofline; serving: the request
+                stream (Poisson arrivals) and saturation.
 
     python bench.py [--steps K] [--warmup W] [--no-extra] [--no-cpu]
 """
@@ -133,14 +138,15 @@ def cpu_baseline(delta, h, rc, cycles):
                       f"(rel. residual {info.rel_res:.2e}) in {dt:.1f} s"}
 
 
-def patch_workload(ndgp, torch, steps):
-    """256^3 domain + four nested 128^3 patches (2x, 4x, 8x, 16x resolution)
-    centred on the largest top-hat; time to tolerance for every truncation
-    level (the paper's l_trunc = l_d + 1, 2, 4 and the full run, Table I) and
-    for mixed precision with every patch interpolated; force differences of
-    each truncated run against the full one, per level."""
+def patch_workload(ndgp, torch, steps, depth):
+    """256^3 domain + `depth` nested 128^3 patches (2x, 4x, ... resolution)
+    centred on the largest top-hat.  depth 2: the full and the interpolated
+    mode and mixed precision with interpolated patches, with the force
+    difference.  depth 4: every truncation level (the paper's l_trunc = l_d + 1,
+    2, 4 and the full run, Table I), cell-wise truncation, and G_eff per
+    level; force differences of each truncated run against the full one."""
     from paper_1511_08200_amd import synth
-    n, box, rc, m, depth = 256, 256.0, 1.0, 128, 4
+    n, box, rc, m = 256, 256.0, 1.0, 128
     f = make_domain(n, box, 2.0, 50, 1513)
     c = synth.densest_tophat_centre(f)
     chain, deltas, patches = [], [f.delta], []
@@ -153,16 +159,25 @@ def patch_workload(ndgp, torch, steps):
         patches.append(ndgp.Patch(m, o))
         c = tuple((c[a] - o[a]) * 2 for a in range(3))
     grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n), patches=patches)
-    out = {"workload": "256^3 + 4 nested 128^3 patches (2x..16x), lognormal sigma 2 + 50 "
-                       "top-hats, r_cH0=1, tol 1e-10; truncation levels 1 (all interpolated), "
-                       "2, 4, 5 (full); mixed precision with every patch interpolated; "
-                       "cell-wise truncation at F5/F_GR thresholds 0.02, 0.05, 0.08",
-           "origins": [list(o) for o in chain]}
-    runs = (("full", ndgp.MODE_FULL, 0, ndgp.PREC_FP64),
-            ("trunc4", ndgp.MODE_TRUNCATED, 4, ndgp.PREC_FP64),
-            ("trunc2", ndgp.MODE_TRUNCATED, 2, ndgp.PREC_FP64),
-            ("interpolated", ndgp.MODE_INTERPOLATED, 0, ndgp.PREC_FP64),
-            ("mixed_interpolated", ndgp.MODE_INTERPOLATED, 0, ndgp.PREC_MIXED))
+    if depth == 2:
+        out = {"workload": "256^3 + 2 nested 128^3 patches (2x, 4x), lognormal sigma 2 + 50 "
+                           "top-hats, r_cH0=1, tol 1e-10; FP64 full, FP64 interpolated, mixed "
+                           "precision interpolated"}
+        runs = (("full", ndgp.MODE_FULL, 0, ndgp.PREC_FP64),
+                ("interpolated", ndgp.MODE_INTERPOLATED, 0, ndgp.PREC_FP64),
+                ("mixed_interpolated", ndgp.MODE_INTERPOLATED, 0, ndgp.PREC_MIXED))
+    else:
+        out = {"workload": f"256^3 + {depth} nested 128^3 patches (2x..{2**depth}x), lognormal "
+                           "sigma 2 + 50 top-hats, r_cH0=1, tol 1e-10; truncation levels 1 (all "
+                           f"interpolated), 2, 4, {depth + 1} (full); mixed precision with every "
+                           "patch interpolated; cell-wise truncation at F5/F_GR thresholds 0.02, "
+                           "0.05, 0.08; G_eff per level"}
+        runs = (("full", ndgp.MODE_FULL, 0, ndgp.PREC_FP64),
+                ("trunc4", ndgp.MODE_TRUNCATED, 4, ndgp.PREC_FP64),
+                ("trunc2", ndgp.MODE_TRUNCATED, 2, ndgp.PREC_FP64),
+                ("interpolated", ndgp.MODE_INTERPOLATED, 0, ndgp.PREC_FP64),
+                ("mixed_interpolated", ndgp.MODE_INTERPOLATED, 0, ndgp.PREC_MIXED))
+    out["origins"] = [list(o) for o in chain]
     res = {}
     for name, mode, k, prec in runs:
         params = ndgp.Params(rc=rc, tol=1e-10, mode=mode, trunc_level=k, precision=prec)
@@ -173,7 +188,7 @@ def patch_workload(ndgp, torch, steps):
         del phi, dd
     t_full = out["full"]["ms_to_tol"]
     out["speedup_vs_full"] = {k: round(t_full / out[k]["ms_to_tol"], 2)
-                              for k in ("trunc4", "trunc2", "interpolated", "mixed_interpolated")}
+                              for k, _, _, _ in runs if k != "full"}
     out["speedup_interpolated_vs_full"] = out["speedup_vs_full"]["interpolated"]
     # mixed precision + interpolated levels against the plain FP64 full solve
     out["speedup_mixed_interpolated_vs_fp64_full"] = out["speedup_vs_full"]["mixed_interpolated"]
@@ -193,8 +208,10 @@ def patch_workload(ndgp, torch, steps):
     dd = [torch.from_numpy(d).to("cuda") for d in deltas]
     full_params = ndgp.Params(rc=rc, tol=1e-10)
     ws = ndgp.workspace(ndgp.workspace_bytes(grid, full_params))
-    out["cellwise"] = {}
-    for thr in (0.02, 0.05, 0.08):
+    thresholds = (0.02, 0.05, 0.08) if depth > 2 else ()
+    if thresholds:
+        out["cellwise"] = {}
+    for thr in thresholds:
         phi_c = ndgp.alloc_phi(grid)
         ndgp.solve_cellwise(grid, full_params, dd, psi, thr, phi=phi_c, ws=ws)
         torch.cuda.synchronize()
@@ -227,15 +244,16 @@ def patch_workload(ndgp, torch, steps):
         return float(edges[min(max(b - 1, 0), len(edges) - 1)])
 
     out["g_eff_per_level"] = {}
-    for name in ("full", "trunc2", "interpolated", "cellwise0.08"):
+    for name in (("full", "trunc2", "interpolated", "cellwise0.08") if depth > 2
+                 else ("full", "interpolated")):
         lv, hist = ndgp.geff_stats(grid, res[name], psi, edges)
         out["g_eff_per_level"][name] = [
             {"level": l, "cells": lv[l]["cells"], "mean_g_eff": 1.0 + lv[l]["mean"],
              "p16_84": [1.0 + pct(hist[l], 0.16), 1.0 + pct(hist[l], 0.84)],
              "median": 1.0 + pct(hist[l], 0.5)} for l in range(len(lv))]
     out["force_difference"] = {}
-    for name in ("trunc4", "trunc2", "interpolated", "cellwise0.02", "cellwise0.05",
-                 "cellwise0.08"):
+    for name in [k for k, _, _, _ in runs if k not in ("full", "mixed_interpolated")] + \
+            [f"cellwise{t:g}" for t in thresholds]:
         F_t = ndgp.force(grid, res[name])
         rows = []
         for lvl in range(1, depth + 1):
@@ -444,7 +462,9 @@ def main():
         line["cpu_baseline"] = cpu_baseline(f.delta, grid.h, rc, args.cpu_cycles)
     if not args.no_extra:
         log("patch workload")
-        line.setdefault("extra", {})["patches"] = patch_workload(ndgp, torch, 3)
+        line.setdefault("extra", {})["patches"] = patch_workload(ndgp, torch, 3, 2)
+        log("truncation workload")
+        line["extra"]["truncation"] = patch_workload(ndgp, torch, 3, 4)
         log("particle workload")
         line["extra"]["particles"] = particle_workload(ndgp, torch, 3)
         log("512^3 workload")
