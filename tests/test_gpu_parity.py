@@ -67,6 +67,7 @@ def gpu_solve(delta_list, grid, **kw):
     (64, 64.0, 2.0, 20, 1.0, 8),       # lognormal + top-hats, several tiles
     (64, 128.0, 2.5, 0, 5.0, 9),       # strongest screening of the 512^3 set
     (16, 16.0, 1.0, 1, 0.5, 3),
+    (8, 16.0, 1.0, 0, 1.0, 4),          # the smallest grid: one level, the coarsest solve only
     (128, 128.0, 2.0, 30, 1.0, 10),    # large enough for the fused LDS sweep
 ])
 def test_periodic_solution_matches_oracle(n, box, sigma, tophats, rc, seed):
@@ -526,6 +527,43 @@ def test_full_size_residual_by_oracle(n, box, sigma, tophats, rc, seed, prec):
     ro_all = S - O.operator(phig, h, al)
     assert np.linalg.norm(ro_all) / np.linalg.norm(S) == pytest.approx(relg, rel=1e-6)
     assert relg <= 1e-10
+
+
+def test_largest_grid_sampled_residual():
+    """n = 1024, the largest grid the library takes (about 35 GB of device
+    memory with the workspace): lognormal sigma 2.5 drawn on the device, FP64
+    to 1e-10; the oracle's residual at 4096 sampled cells (boundary corners
+    included) equals the GPU residual there."""
+    n, box, rc = 1024, 1024.0, 1.0
+    say("largest grid n=1024: generating on the device")
+    d = synth.lognormal_delta_torch(n, 2.5, 1516)
+    h = ndgp.cell_size(box, n)
+    grid = ndgp.Grid(n=n, h=h)
+    params = ndgp.Params(rc=rc, tol=1e-10)
+    say("largest grid n=1024: solving")
+    phi, rep = ndgp.solve(grid, params, [d])
+    r, relg = ndgp.residual(grid, params, [d], phi[0])
+    torch.cuda.synchronize()
+    say(f"  cycles={rep.cycles[0]} rel_res={rep.rel_res[0]:.3e} t={rep.t_total_ms:.1f} ms")
+    assert rep.status == 0 and rep.rel_res[0] <= 1e-10 and relg <= 1e-10
+    rng = np.random.default_rng(1)
+    cells = rng.integers(0, n, size=(4096, 3))
+    cells[:4] = [[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 0], [n - 1, 0, n - 1]]
+    idx = torch.from_numpy(cells).to("cuda")
+    rg = r[idx[:, 2], idx[:, 1], idx[:, 0]].cpu().numpy()
+    del r
+    say("largest grid n=1024: oracle residual at sampled cells")
+    phig = phi[0].cpu().numpy()
+    del phi
+    delta = d.cpu().numpy()
+    del d
+    torch.cuda.empty_cache()
+    beta = O.beta_lcdm(1.0, 0.3, rc)
+    S, _ = O.source(delta, 0.3, 1.0, beta)
+    del delta
+    ro = S[cells[:, 2], cells[:, 1], cells[:, 0]] - O.operator_at(phig, h, O.alpha(rc, beta, 1.0),
+                                                                  cells)
+    assert np.abs(rg - ro).max() <= 1e-12 * np.abs(S).max()
 
 
 @pytest.mark.parametrize("prec", [ndgp.PREC_FP64, ndgp.PREC_MIXED])
