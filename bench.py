@@ -99,7 +99,7 @@ def solve_steps(ndgp, torch, grid, params, deltas, steps, warmup, with_force=Tru
 
 def kernel_name(cells, n):
     if cells == n**3:
-        tz = 32 if n >= 256 else 8
+        tz = 32 if n >= 256 else 4
         return (f"k_sweep_fused<64, 16, {tz}, 512, false> (one red-black sweep per launch, "
                 "LDS-streamed, FP64; the variant with the coarse-grid correction on load is "
                 "not in the timed set)")

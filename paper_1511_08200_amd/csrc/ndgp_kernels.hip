@@ -1226,8 +1226,8 @@ void sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fall
                  const double *phi_c, const double *hat_c, hipStream_t st) {
     if (L.n >= 256) // long z-chunks: the halo planes are a small share
         sweep_fused_tiles<64, 16, 32, 512, PRO>(L, pin, pout, fallbacks, phi_c, hat_c, st);
-    else // 128^3: short chunks, enough workgroups to fill the chip
-        sweep_fused_tiles<64, 16, 8, 512, PRO>(L, pin, pout, fallbacks, phi_c, hat_c, st);
+    else // 128^3: short chunks, two workgroups per CU (4 planes: 5% faster than 8)
+        sweep_fused_tiles<64, 16, 4, 512, PRO>(L, pin, pout, fallbacks, phi_c, hat_c, st);
 }
 
 void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
