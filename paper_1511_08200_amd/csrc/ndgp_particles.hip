@@ -53,27 +53,81 @@ __device__ __forceinline__ int cic_axis(double x01, int n, double corner, double
     return cnt;
 }
 
+// One thread per particle.  Particles whose eight cells are all in the level
+// (the usual case) are keyed by their lower cell; lanes of a wave that hold a
+// contiguous run of equal keys -- particles sorted by cell, as a tree code
+// keeps them, in a dense region -- first add their fixed-point weights with
+// shuffles (a segmented scan), and only the run's last lane sends the eight
+// atomics.  Integer sums: the same bits whatever the grouping.
 __global__ void __launch_bounds__(kBlock)
 k_cic_deposit(const double *__restrict__ pos, long long np, int n, double cx, double cy, double cz,
               double cells_per_domain, int m, int periodic,
               unsigned long long *__restrict__ acc) {
     const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= np) return;
+    const int lane = threadIdx.x & 63;
     int ix[4], iy[4], iz[4];
     double wx[4], wy[4], wz[4];
-    const int nx = cic_axis(pos[p], n, cx, cells_per_domain, m, periodic != 0, ix, wx);
-    if (!nx) return;
-    const int ny = cic_axis(pos[np + p], n, cy, cells_per_domain, m, periodic != 0, iy, wy);
-    if (!ny) return;
-    const int nz = cic_axis(pos[2 * np + p], n, cz, cells_per_domain, m, periodic != 0, iz, wz);
-    for (int c = 0; c < nz; ++c)
-        for (int b = 0; b < ny; ++b)
-            for (int a = 0; a < nx; ++a) {
-                const double w = (wx[a] * wy[b]) * wz[c];
-                const unsigned long long q = __double2ull_rn(w * kCicOne);
-                if (q)
-                    atomicAdd(&acc[((size_t)iz[c] * m + iy[b]) * m + ix[a]], q);
-            }
+    int nx = 0, ny = 0, nz = 0;
+    if (p < np) {
+        nx = cic_axis(pos[p], n, cx, cells_per_domain, m, periodic != 0, ix, wx);
+        ny = cic_axis(pos[np + p], n, cy, cells_per_domain, m, periodic != 0, iy, wy);
+        nz = cic_axis(pos[2 * np + p], n, cz, cells_per_domain, m, periodic != 0, iz, wz);
+    }
+    const bool whole = nx == 2 && ny == 2 && nz == 2 && ix[1] == ((ix[0] + 1) & (m - 1)) &&
+                       iy[1] == ((iy[0] + 1) & (m - 1)) && iz[1] == ((iz[0] + 1) & (m - 1));
+    if (!whole) { // partial overlap with a patch, or no particle: direct atomics
+        for (int c = 0; c < nz; ++c)
+            for (int b = 0; b < ny; ++b)
+                for (int a = 0; a < nx; ++a) {
+                    const double w = (wx[a] * wy[b]) * wz[c];
+                    const unsigned long long q = __double2ull_rn(w * kCicOne);
+                    if (q) atomicAdd(&acc[((size_t)iz[c] * m + iy[b]) * m + ix[a]], q);
+                }
+    }
+    // the eight weights of a whole particle, in fixed point
+    unsigned long long q[8];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                q[(c * 2 + b) * 2 + a] = whole ? __double2ull_rn(((wx[a] * wy[b]) * wz[c]) * kCicOne) : 0ull;
+    // key: lower cell of a whole particle, else unique to the lane
+    const long long key = whole ? (long long)(((size_t)iz[0] * m + iy[0]) * m + ix[0]) : -1 - lane;
+    const long long kprev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || kprev != key;
+    // start lane of this lane's run of equal keys (max over heads at or below)
+    int seg = head ? lane : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(seg, off, 64);
+        if (lane >= off) seg = seg > o ? seg : o;
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int so = __shfl_up(seg, off, 64);
+        unsigned long long qo[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) qo[r] = __shfl_up(q[r], off, 64);
+        if (lane >= off && so == seg) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) q[r] += qo[r];
+        }
+    }
+    const int snext = __shfl_down(seg, 1, 64);
+    const bool tail = lane == 63 || snext != seg;
+    if (whole && tail) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const unsigned long long v = q[(c * 2 + b) * 2 + a];
+                    if (v) atomicAdd(&acc[((size_t)iz[c] * m + iy[b]) * m + ix[a]], v);
+                }
+    }
 }
 
 __global__ void __launch_bounds__(kBlock)

@@ -418,6 +418,14 @@ def test_cellwise_truncation_matches_oracle():
         held = masks[lvl] == 0
         got = phig[lvl].cpu().numpy()[1:-1, 1:-1, 1:-1][held]
         assert np.abs(got - want[1:-1, 1:-1, 1:-1][held]).max() <= 1e-14 * np.abs(want).max()
+    # with a truncation level: patch 1 cell-wise, patch 2 interpolated from it
+    phot, _, mkt = O.solve_problem(prob, cellwise=(psi_o, chosen), trunc_level=2)
+    pt = ndgp.Params(rc=rc, tol=0.0, max_cycles=200, mode=ndgp.MODE_TRUNCATED, trunc_level=2)
+    phgt, rept = ndgp.solve_cellwise(grid, pt, [dev(d) for d in deltas], psi_g, chosen)
+    assert rept.status == 0 and rept.iterated_fraction[2] == 0.0 and rept.cycles[2] == 0
+    assert rept.iterated_fraction[1] == mkt[1].sum() / 32**3
+    for lvl in range(3):
+        assert rel(phgt[lvl].cpu().numpy(), phot[lvl]) <= PHI_TOL
     # the limits, bit for bit
     dd = [dev(d) for d in deltas]
     ph0, r0 = ndgp.solve_cellwise(grid, params, dd, psi_g, 0.0)
