@@ -345,6 +345,23 @@ def alloc_phi(grid: Grid, device="cuda") -> list:
     return out
 
 
+def _solve_ptrs(grid: Grid, delta, phi):
+    """Device pointers of delta (None where absent) and phi per level."""
+    dptr = [_dev(delta[0], (grid.n,) * 3, "delta[0]")]
+    pptr = [_dev(phi[0], (grid.n,) * 3, "phi[0]")]
+    for q, pt in enumerate(grid.patches):
+        d = delta[q + 1] if q + 1 < len(delta) else None
+        dptr.append(_dev(d, (pt.n,) * 3, f"delta[{q + 1}]") if d is not None else None)
+        pptr.append(_dev(phi[q + 1], (pt.n + 2,) * 3, f"phi[{q + 1}]"))
+    return dptr, pptr
+
+
+def _finish(st: int, rep: _Report, check: bool) -> Report:
+    if check or (st != NDGP_OK and st != NDGP_ENOCONV):
+        _check(st)
+    return _report(rep, st)
+
+
 def solve(grid: Grid, params: Params, delta: Sequence[torch.Tensor], phi=None, ws=None,
           stream=None, check: bool = True):
     """Run ndgp_solve.  ``delta``: [domain (n^3), patch1 (m^3), ...] device
@@ -353,26 +370,13 @@ def solve(grid: Grid, params: Params, delta: Sequence[torch.Tensor], phi=None, w
     g, p = grid._c(), params._c()
     if phi is None:
         phi = alloc_phi(grid, device=delta[0].device)
-    dptr = [_dev(delta[0], (grid.n,) * 3, "delta[0]")]
-    for q, pt in enumerate(grid.patches):
-        if q + 1 < len(delta) and delta[q + 1] is not None:
-            dptr.append(_dev(delta[q + 1], (pt.n,) * 3, f"delta[{q + 1}]"))
-        else:
-            dptr.append(None)
-    pptr = [_dev(phi[0], (grid.n,) * 3, "phi[0]")]
-    for q, pt in enumerate(grid.patches):
-        pptr.append(_dev(phi[q + 1], (pt.n + 2,) * 3, f"phi[{q + 1}]"))
-    nb = workspace_bytes(grid, params)
+    dptr, pptr = _solve_ptrs(grid, delta, phi)
     if ws is None:
-        ws = workspace(nb, delta[0].device)
+        ws = workspace(workspace_bytes(grid, params), delta[0].device)
     rep = _Report()
     st = lib().ndgp_solve(ctypes.byref(g), ctypes.byref(p), _arr3(dptr), _arr3(pptr),
                           ws.data_ptr(), ws.numel(), _stream(stream), ctypes.byref(rep))
-    if check:
-        _check(st)
-    elif st != NDGP_OK and st != NDGP_ENOCONV:
-        _check(st)
-    return phi, _report(rep, st)
+    return phi, _finish(st, rep, check)
 
 
 def solve_cellwise(grid: Grid, params: Params, delta: Sequence[torch.Tensor],
@@ -385,32 +389,19 @@ def solve_cellwise(grid: Grid, params: Params, delta: Sequence[torch.Tensor],
     g, p = grid._c(), params._c()
     if phi is None:
         phi = alloc_phi(grid, device=delta[0].device)
-    dptr = [_dev(delta[0], (grid.n,) * 3, "delta[0]")]
+    dptr, pptr = _solve_ptrs(grid, delta, phi)
     sptr = []
-    for q, pt in enumerate(grid.patches):
-        if q + 1 < len(delta) and delta[q + 1] is not None:
-            dptr.append(_dev(delta[q + 1], (pt.n,) * 3, f"delta[{q + 1}]"))
-        else:
-            dptr.append(None)
     for lvl in range(len(grid.patches) + 1):
         t = psi[lvl] if lvl < len(psi) else None
         shape = (grid.n,) * 3 if lvl == 0 else (grid.patches[lvl - 1].n + 2,) * 3
         sptr.append(_dev(t, shape, f"psi[{lvl}]") if t is not None else None)
-    pptr = [_dev(phi[0], (grid.n,) * 3, "phi[0]")]
-    for q, pt in enumerate(grid.patches):
-        pptr.append(_dev(phi[q + 1], (pt.n + 2,) * 3, f"phi[{q + 1}]"))
-    nb = workspace_bytes(grid, params)
     if ws is None:
-        ws = workspace(nb, delta[0].device)
+        ws = workspace(workspace_bytes(grid, params), delta[0].device)
     rep = _Report()
     st = lib().ndgp_solve_cellwise(ctypes.byref(g), ctypes.byref(p), _arr3(dptr), _arr3(sptr),
                                    float(threshold), _arr3(pptr), ws.data_ptr(), ws.numel(),
                                    _stream(stream), ctypes.byref(rep))
-    if check:
-        _check(st)
-    elif st != NDGP_OK and st != NDGP_ENOCONV:
-        _check(st)
-    return phi, _report(rep, st)
+    return phi, _finish(st, rep, check)
 
 
 def residual(grid: Grid, params: Params, delta: Sequence[torch.Tensor], phi: torch.Tensor,
