@@ -445,6 +445,13 @@ struct Runner {
         return host[0];
     }
 
+    // host[0..count) = dev[0..count) with one copy and one wait
+    void read_scalars(const double *dev, int count) {
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+
     // enqueue a reduction into P.scal[slot] without waiting for it
     void enqueue_sum(const double *a, size_t count, bool squares, int slot) {
         launch_partial_sums(a, count, squares, P.partials, st);
@@ -596,11 +603,14 @@ struct Runner {
     // correction from e = 0, phi += e in FP64.
     // cycles accumulates over a restart; *restart is set (and the call
     // returns) when the safeguard asks for a damped solve from the start.
+    // rr0 >= 0: the squared residual norm of the start, already enqueued
+    // (enqueue_residual) and read; else it is computed here
     ndgp_status drive_mixed(Level *H, Level32 *H32, int nl, double snorm2, int &outer,
-                            double &rel, double *hist, int *hist_len, bool *restart) {
+                            double &rel, double *hist, int *hist_len, bool *restart,
+                            double rr0 = -1.0) {
         CycleMonitor m{P.c.tol, P.c.maxc};
         m.damped = H[0].omega != 1.0;
-        m.start(std::sqrt(residual_to32(H[0], H32[0].r) / snorm2));
+        m.start(std::sqrt((rr0 >= 0.0 ? rr0 : residual_to32(H[0], H32[0].r)) / snorm2));
         rel = m.rel;
         while (outer < m.maxc && !m.converged()) {
             mixed_outer(H, H32, nl);
@@ -625,10 +635,10 @@ struct Runner {
     // V-cycles on H[0] until ||r|| <= tol ||s|| (tol > 0) or until the
     // residual stops falling (tol == 0); cycles and restart as drive_mixed.
     ndgp_status drive(Level *H, int nl, double snorm2, int &cycles, double &rel, double *hist,
-                      int *hist_len, bool *restart) {
+                      int *hist_len, bool *restart, double rr0 = -1.0) {
         CycleMonitor m{P.c.tol, P.c.maxc};
         m.damped = H[0].omega != 1.0;
-        m.start(std::sqrt(residual_sumsq(H[0]) / snorm2));
+        m.start(std::sqrt((rr0 >= 0.0 ? rr0 : residual_sumsq(H[0])) / snorm2));
         rel = m.rel;
         while (cycles < m.maxc && !m.converged()) {
             vcycle(H, nl, 0);
@@ -705,14 +715,20 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     run.timed_s = P.base[0].s;
     HIP_TRY(hipMemsetAsync(P.fallbacks, 0, sizeof(unsigned), st));
 
-    // domain source: S = Omega_m (delta - mean) / (a beta), in cell units (x h^2)
+    // domain source: S = Omega_m (delta - mean) / (a beta), in cell units (x
+    // h^2); its norm, the initial guess and the first residual norm are
+    // enqueued together and read with one wait
     const size_t cells0 = (size_t)c.n * c.n * c.n;
-    const double dsum = run.sum(delta[0], cells0, false, 0);
-    if (!std::isfinite(dsum)) return fail(NDGP_EINVAL, "delta[0] has non-finite values");
-    R.removed_mean = dsum / (double)cells0;
+    run.enqueue_sum(delta[0], cells0, false, 0);
     launch_source(delta[0], cells0, P.scal + 0, 1.0 / (double)cells0, c.fsrc * c.h * c.h,
                   P.base[0].s, st);
-    const double snorm2 = run.sum(P.base[0].s, cells0, true, 1);
+    run.enqueue_sum(P.base[0].s, cells0, true, 1);
+    if (!(c.flags & NDGP_WARM_START)) run.nested_start(P.base, c.nl);
+    run.enqueue_residual(P.base, P.base32);
+    run.read_scalars(P.scal, 3);
+    const double dsum = slot.p[0], snorm2 = slot.p[1], rr0 = slot.p[2];
+    if (!std::isfinite(dsum)) return fail(NDGP_EINVAL, "delta[0] has non-finite values");
+    R.removed_mean = dsum / (double)cells0;
 
     ndgp_status status = NDGP_OK;
     if (snorm2 == 0.0) {
@@ -721,15 +737,16 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     } else {
         double rel = 0.0;
         for (bool first = true;; first = false) {
-            if (!first || !(c.flags & NDGP_WARM_START)) run.nested_start(P.base, c.nl);
+            if (!first) run.nested_start(P.base, c.nl); // the first start is enqueued above
             timer.on = (c.flags & NDGP_PROFILE) != 0; // the V-cycles only, not the start
             bool restart = false;
             if (c.prec == NDGP_PREC_MIXED)
                 status = run.drive_mixed(P.base, P.base32, c.nl, snorm2, R.cycles[0], rel,
-                                         R.res_hist, &R.hist_len, first ? &restart : nullptr);
+                                         R.res_hist, &R.hist_len, first ? &restart : nullptr,
+                                         first ? rr0 : -1.0);
             else
                 status = run.drive(P.base, c.nl, snorm2, R.cycles[0], rel, R.res_hist,
-                                   &R.hist_len, first ? &restart : nullptr);
+                                   &R.hist_len, first ? &restart : nullptr, first ? rr0 : -1.0);
             timer.on = false;
             if (!restart) break;
             // the safeguard: solve again from the nested start with the damped step
