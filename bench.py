@@ -401,6 +401,8 @@ def main():
                     help="timed workload: 256^3 lognormal+top-hats (default) or the 512^3 "
                          "lognormal sigma 2.5 field (for profiling the HBM-bound regime)")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--extra", default="patches,truncation,particles,large,serving",
+                    help="comma-separated extra workloads to run after the timed one")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=4)
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -460,18 +462,27 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(f.delta, grid.h, rc, args.cpu_cycles)
-    if not args.no_extra:
-        log("patch workload")
-        line.setdefault("extra", {})["patches"] = patch_workload(ndgp, torch, 3, 2)
-        log("truncation workload")
-        line["extra"]["truncation"] = patch_workload(ndgp, torch, 3, 4)
-        log("particle workload")
-        line["extra"]["particles"] = particle_workload(ndgp, torch, 3)
-        log("512^3 workload")
-        line["extra"]["large"] = large_workload(ndgp, torch, 3)
-        if args.serve_requests > 0:
-            line["extra"]["serving"] = serving_workload(ndgp, torch, args.serve_requests,
-                                                        args.serve_rate, args.serve_saturation)
+    extras = set() if args.no_extra else {e for e in args.extra.split(",") if e}
+    unknown = extras - {"patches", "truncation", "particles", "large", "serving"}
+    if unknown:
+        raise SystemExit(f"unknown extra workloads: {sorted(unknown)}")
+    if extras:
+        out = line.setdefault("extra", {})
+        if "patches" in extras:
+            log("patch workload")
+            out["patches"] = patch_workload(ndgp, torch, 3, 2)
+        if "truncation" in extras:
+            log("truncation workload")
+            out["truncation"] = patch_workload(ndgp, torch, 3, 4)
+        if "particles" in extras:
+            log("particle workload")
+            out["particles"] = particle_workload(ndgp, torch, 3)
+        if "large" in extras:
+            log("512^3 workload")
+            out["large"] = large_workload(ndgp, torch, 3)
+        if "serving" in extras and args.serve_requests > 0:
+            out["serving"] = serving_workload(ndgp, torch, args.serve_requests,
+                                              args.serve_rate, args.serve_saturation)
     print(json.dumps(line), flush=True)
 
 
