@@ -402,8 +402,10 @@ ndgp_status ndgp_cic_force(const ndgp_grid *grid, const double *const force[1 + 
  * ndgp_plan_step    enqueues the next V-cycle (mixed precision: the next outer
  *                   iteration) and its residual norm if the last poll found
  *                   the plan waiting; otherwise does nothing.  Never blocks.
- * ndgp_plan_destroy releases the plan's host resources; the caller must not
- *                   free the device buffers before the plan's stream is idle.
+ * ndgp_plan_destroy releases the plan's host resources.  Called before poll
+ *                   has reported done, it blocks until the work the plan
+ *                   has enqueued is finished (the only call that blocks);
+ *                   the caller must not free the device buffers before.
  */
 typedef struct ndgp_plan ndgp_plan;
 ndgp_status ndgp_plan_create(const ndgp_grid *grid, const ndgp_params *params,

@@ -1165,8 +1165,10 @@ ndgp_status plan_create_impl(const ndgp_grid *grid, const ndgp_params *params,
                                st));
         plan_record(pl);
     } catch (...) {
+        // a copy into the slot may be in flight: the slot returns to the pool
+        // only once the stream is idle (else it is leaked, never reused)
         if (pl->ev) (void)hipEventDestroy(pl->ev);
-        if (pl->slot) pinned_slots().release(pl->slot);
+        if (pl->slot && hipStreamSynchronize(st) == hipSuccess) pinned_slots().release(pl->slot);
         delete pl;
         throw;
     }
@@ -1457,8 +1459,17 @@ ndgp_status ndgp_plan_step(ndgp_plan *plan) {
 
 void ndgp_plan_destroy(ndgp_plan *plan) {
     if (!plan) return;
-    if (plan->ev) (void)hipEventDestroy(plan->ev);
-    if (plan->slot) pinned_slots().release(plan->slot);
+    // Every enqueue of a plan ends with a copy into its pinned slot and a
+    // record of its event.  A plan destroyed before its work has finished
+    // waits for that event first: the slot goes back to the pool, and a
+    // later plan must not receive this one's late copy.  If the wait fails
+    // the slot is leaked rather than reused.
+    bool idle = true;
+    if (plan->ev) {
+        idle = hipEventSynchronize(plan->ev) == hipSuccess;
+        (void)hipEventDestroy(plan->ev);
+    }
+    if (plan->slot && idle) pinned_slots().release(plan->slot);
     delete plan;
 }
 

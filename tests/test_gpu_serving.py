@@ -52,6 +52,37 @@ def test_plan_equals_blocking_solve(precision):
     plan.close()
 
 
+def test_plan_destroyed_in_flight_leaves_later_plans_exact():
+    """Plans destroyed with work still enqueued (after create, after a step)
+    wait for it before their pinned norm slot is reused: the plans created
+    next, which take those slots, still give the blocking solve's bits."""
+    say("plan destroyed in flight")
+    n = 64
+    f = synth.make_field(n, 1.5, 78, n_tophats=3)
+    d = torch.from_numpy(f.delta).cuda()
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(64.0, n))
+    params = ndgp.Params(rc=1.0, tol=1e-10)
+    phi_a, rep_a = ndgp.solve(grid, params, [d])
+    side = torch.cuda.Stream()
+    for stepped in (False, True):
+        with torch.cuda.stream(side):
+            doomed = [ndgp.Plan(grid, params, [d], stream=side) for _ in range(3)]
+        for p in doomed:
+            if stepped:
+                side.synchronize()
+                assert not p.poll()   # the first norm is in: the plan waits for a step
+                p.step()              # one V-cycle and its norm enqueued
+            p.close()                 # with that work still in flight
+        plan = ndgp.Plan(grid, params, [d])
+        while not plan.poll():
+            plan.step()
+        torch.cuda.synchronize()
+        rep_b = plan.report
+        assert rep_b.status == 0 and rep_b.history == rep_a.history
+        assert torch.equal(plan.phi[0], phi_a[0])
+        plan.close()
+
+
 @pytest.mark.parametrize("precision", [ndgp.PREC_FP64, ndgp.PREC_MIXED])
 def test_plan_restart_safeguard_equals_blocking_solve(precision):
     """The divergent extreme request of the serving trace (sigma_ln 2.47,
