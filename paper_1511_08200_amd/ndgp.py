@@ -320,13 +320,21 @@ def workspace_bytes(grid: Grid, params: Params) -> int:
     return int(nb)
 
 
-def workspace(nbytes: int, device=None) -> torch.Tensor:
-    """A cached uint8 workspace of at least nbytes on the device."""
+def workspace(nbytes: int, device=None, stream=None) -> torch.Tensor:
+    """A cached uint8 workspace of at least nbytes for work enqueued on
+    `stream` (default: the device's current stream).  One cache entry per
+    device and stream, allocated on that stream: calls that enqueue on
+    different streams never share a workspace, and a replaced (smaller) one
+    is only reused by the allocator after the work queued before it on its
+    stream."""
     dev = torch.device(device if device is not None else "cuda")
-    key = (dev.type, dev.index if dev.index is not None else torch.cuda.current_device())
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    s = stream if stream is not None else torch.cuda.current_stream(idx)
+    key = (dev.type, idx, s.cuda_stream)
     ws = _ws_cache.get(key)
     if ws is None or ws.numel() < nbytes:
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        with torch.cuda.stream(s):
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         _ws_cache[key] = ws
     return ws
 
@@ -372,7 +380,7 @@ def solve(grid: Grid, params: Params, delta: Sequence[torch.Tensor], phi=None, w
         phi = alloc_phi(grid, device=delta[0].device)
     dptr, pptr = _solve_ptrs(grid, delta, phi)
     if ws is None:
-        ws = workspace(workspace_bytes(grid, params), delta[0].device)
+        ws = workspace(workspace_bytes(grid, params), delta[0].device, stream)
     rep = _Report()
     st = lib().ndgp_solve(ctypes.byref(g), ctypes.byref(p), _arr3(dptr), _arr3(pptr),
                           ws.data_ptr(), ws.numel(), _stream(stream), ctypes.byref(rep))
@@ -396,7 +404,7 @@ def solve_cellwise(grid: Grid, params: Params, delta: Sequence[torch.Tensor],
         shape = (grid.n,) * 3 if lvl == 0 else (grid.patches[lvl - 1].n + 2,) * 3
         sptr.append(_dev(t, shape, f"psi[{lvl}]") if t is not None else None)
     if ws is None:
-        ws = workspace(workspace_bytes(grid, params), delta[0].device)
+        ws = workspace(workspace_bytes(grid, params), delta[0].device, stream)
     rep = _Report()
     st = lib().ndgp_solve_cellwise(ctypes.byref(g), ctypes.byref(p), _arr3(dptr), _arr3(sptr),
                                    float(threshold), _arr3(pptr), ws.data_ptr(), ws.numel(),
@@ -416,7 +424,7 @@ def residual(grid: Grid, params: Params, delta: Sequence[torch.Tensor], phi: tor
     r = torch.empty((n,) * 3, dtype=torch.float64, device=phi.device) if want_r else None
     nb = workspace_bytes(grid, params)
     if ws is None:
-        ws = workspace(nb, phi.device)
+        ws = workspace(nb, phi.device, stream)
     rel = ctypes.c_double()
     _check(lib().ndgp_residual(ctypes.byref(g), ctypes.byref(p), level, _arr3(dptr),
                                _dev(phi, shape, "phi"), r.data_ptr() if r is not None else None,
@@ -471,7 +479,7 @@ def geff_stats(grid: Grid, phi: Sequence[torch.Tensor], psi: Sequence[torch.Tens
     nl = 1 + len(grid.patches)
     outs = (_GeffLevel * (1 + MAX_PATCHES))()
     hist = np.zeros((nl, e.size + 1), dtype=np.int64)
-    ws = workspace(GEFF_WORKSPACE, phi[0].device)
+    ws = workspace(GEFF_WORKSPACE, phi[0].device, stream)
     _check(lib().ndgp_geff_stats(ctypes.byref(g), _arr3(_level_ptrs(grid, phi, "phi")),
                                  _arr3(_level_ptrs(grid, psi, "psi")),
                                  e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), e.size, outs,
@@ -502,7 +510,7 @@ def cic_density(grid: Grid, pos: torch.Tensor, delta=None, ws=None, stream=None)
     if nb == 0:
         _check(NDGP_EINVAL)
     if ws is None:
-        ws = workspace(nb, pos.device)
+        ws = workspace(nb, pos.device, stream)
     _check(lib().ndgp_cic_density(ctypes.byref(g), _dev(pos, (3, npart), "pos"), npart,
                                   _arr3(dptr), ws.data_ptr(), ws.numel(), _stream(stream)))
     return delta
@@ -517,7 +525,7 @@ def refine_flags(grid: Grid, delta: Sequence[torch.Tensor], n_particles: int,
     flags = [torch.empty((grid.level_n(l),) * 3, dtype=torch.uint8, device=delta[0].device)
              for l in range(nl)]
     counts = (ctypes.c_int64 * (1 + MAX_PATCHES))()
-    ws = workspace(DIFF_NORMS_WORKSPACE, delta[0].device)
+    ws = workspace(DIFF_NORMS_WORKSPACE, delta[0].device, stream)
     dptr = [_dev(delta[l], (grid.level_n(l),) * 3, f"delta[{l}]") for l in range(nl)]
     _check(lib().ndgp_refine_flags(ctypes.byref(g), _arr3(dptr), int(n_particles), float(n_ref),
                                    _arr3([f.data_ptr() for f in flags]), counts, ws.data_ptr(),
@@ -570,7 +578,7 @@ def diff_norms(a: torch.Tensor, b: Optional[torch.Tensor] = None, stream=None):
     if b is not None and b.shape != a.shape:
         raise ValueError("a and b differ in shape")
     out = (ctypes.c_double * 3)()
-    ws = workspace(DIFF_NORMS_WORKSPACE, a.device)
+    ws = workspace(DIFF_NORMS_WORKSPACE, a.device, stream)
     _check(lib().ndgp_diff_norms(_dev(a, None, "a"), _dev(b, None, "b") if b is not None else None,
                                  a.numel(), out, ws.data_ptr(), ws.numel(), _stream(stream)))
     return out[0], out[1], out[2]
