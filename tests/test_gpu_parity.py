@@ -175,6 +175,7 @@ def test_fused_kernels_bitwise_equal_per_level_launches(n, levels):
                        [d])
     torch.cuda.synchronize()
     assert ra.cycles == rb.cycles and ra.history == rb.history
+    assert ra.fallbacks == rb.fallbacks
     assert not any(ra.damped_from)  # the safeguard stays off for ordinary fields
     assert torch.equal(a[0], b[0])
 

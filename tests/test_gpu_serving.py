@@ -106,6 +106,7 @@ def test_plan_restart_safeguard_equals_blocking_solve(precision):
     assert rep_b.status == 0 and rep_a.damped_from[0] > 0
     assert rep_b.damped_from == rep_a.damped_from and rep_b.cycles == rep_a.cycles
     assert rep_b.history == rep_a.history
+    assert rep_b.fallbacks == rep_a.fallbacks
     assert torch.equal(phi_a[0], plan.phi[0])
     plan.close()
 
