@@ -563,6 +563,53 @@ def test_full_size_residual_by_oracle(n, box, sigma, tophats, rc, seed, prec):
     assert relg <= 1e-10
 
 
+def test_full_size_patches_by_oracle():
+    """The benchmark's patch configuration at full size: 256^3 lognormal
+    sigma 2 + 50 top-hats, two nested 128^3 patches at 2x and 4x centred on
+    the largest top-hat.  Full mode: each patch's ghost shell is the oracle's
+    trilinear interpolation of its converged parent, and its residual (from
+    that shell) is the oracle's over the whole patch, below the tolerance.
+    Interpolated mode: each patch, interior and ghosts, is the oracle's
+    interpolation of its GPU parent."""
+    n, box, rc, m = 256, 256.0, 1.0, 128
+    say("full-size patches: generating")
+    f = synth.make_field(n, 2.0, 1513, n_tophats=50)
+    c = synth.densest_tophat_centre(f)
+    chain, deltas, patches = [], [f.delta], []
+    for q in range(2):
+        o = synth.patch_origin_centred(c, m // 2)
+        if q > 0:
+            o = tuple(min(max(v, 8), m - m // 2 - 8) for v in o)
+        chain.append(o)
+        deltas.append(synth.patch_delta(f, n, chain, m))
+        patches.append(ndgp.Patch(m, o))
+        c = tuple((c[a] - o[a]) * 2 for a in range(3))
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n), patches=patches)
+    beta = O.beta_lcdm(1.0, 0.3, rc)
+    al = O.alpha(rc, beta, 1.0)
+    _, mean = O.source(deltas[0], 0.3, 1.0, beta)
+    shell = np.ones((m + 2,) * 3, dtype=bool)
+    shell[1:-1, 1:-1, 1:-1] = False
+    for mode in (ndgp.MODE_FULL, ndgp.MODE_INTERPOLATED):
+        say(f"full-size patches: mode {mode}")
+        phig, rep = gpu_solve(deltas, grid, rc=rc, tol=1e-10, mode=mode)
+        assert rep.status == 0 and rep.rel_res[0] <= 1e-10
+        for lvl in (1, 2):
+            want = O.interpolate(phig[lvl - 1], lvl == 1, chain[lvl - 1], 0, m)
+            scale = np.abs(want).max()
+            if mode == ndgp.MODE_INTERPOLATED:
+                assert np.abs(phig[lvl] - want).max() <= 1e-14 * scale
+                continue
+            assert np.abs(phig[lvl][shell] - want[shell]).max() <= 1e-14 * scale
+            S = O.source_shift(deltas[lvl], mean, 0.3, 1.0, beta)
+            ro = S - O.operator_padded(phig[lvl], grid.level_h(lvl), al)
+            r, relg = ndgp.residual(grid, ndgp.Params(rc=rc), [dev(d) for d in deltas],
+                                    dev(phig[lvl]), level=lvl)
+            say(f"  level {lvl}: cycles={rep.cycles[lvl]} rel_res={relg:.2e}")
+            assert np.abs(r.cpu().numpy() - ro).max() <= 1e-12 * np.abs(S).max()
+            assert relg <= 1e-10 and rep.rel_res[lvl] <= 1e-10
+
+
 def test_largest_grid_sampled_residual():
     """n = 1024, the largest grid the library takes (about 35 GB of device
     memory with the workspace): lognormal sigma 2.5 drawn on the device, FP64
