@@ -17,6 +17,10 @@ fails at least one of them:
                 spherical Vainshtein solution, Eqs. (eomvarphi_sph)-(rv);
                 the unscreened force ratio 1/(3 beta), Eq. (forcelarge)
   background    Eq. (beta) on LCDM by finite differences of H(t)
+  sources       Eq. (eomvarphi)'s right-hand side in code units; a patch's
+                source measured against the domain mean (piecewise-constant
+                injection reproduces the parent's source bit for bit)
+  operator_at   the per-cell evaluation equals the whole-grid operator
   interpolation reproduces constants and linear fields, 27/64-9/64-3/64-1/64
   force         central differences on linear and sine fields
 """
@@ -173,6 +177,50 @@ def test_source_units(oracle_mod):
     S2, m2 = O.source(d + 0.25, om, a, beta)
     assert m2 == pytest.approx(0.25, rel=1e-12)
     np.testing.assert_allclose(S2, S, rtol=1e-12, atol=1e-14)
+
+
+def test_patch_source_uses_the_domain_mean(oracle_mod):
+    """A refinement sees the same density field at finer resolution (Sec. III.A),
+    so its contrast is measured against the domain's background: with the
+    lognormal part injected piecewise constant (no top-hats), every patch cell's
+    source equals its parent's domain source bit for bit.  Removing the patch's
+    own mean instead shifts every cell of a patch whose mean density differs
+    from the domain's."""
+    O = oracle_mod
+    n, nc = 16, 16
+    f = synth.make_field(n, 2.0, 41)
+    beta = O.beta_lcdm(1.0, 0.3, 1.0)
+    S0, mean = O.source(f.delta + 0.01, 0.3, 1.0, beta)  # a nonzero mean to remove
+    assert abs(mean - 0.01) < 1e-12
+    # patch over 8^3 parent cells at (3, 12, 5): wraps in y
+    origin = (3, 12, 5)
+    dp = synth.patch_delta(f, n, [origin], nc) + 0.01
+    Sp = O.source_shift(dp, mean, 0.3, 1.0, beta)
+    idx = [(origin[a] + np.arange(nc) // 2) % n for a in range(3)]
+    parent = S0[np.ix_(idx[2], idx[1], idx[0])]
+    assert np.array_equal(Sp, parent)
+    own = O.source_shift(dp, float(dp.mean()), 0.3, 1.0, beta)
+    assert abs(float(dp.mean()) - mean) > 1e-3
+    assert np.abs(own - parent).min() > 1e-5
+
+
+def test_operator_at_listed_cells_equals_whole_grid(oracle_mod):
+    """The per-cell evaluation that checks large GPU answers must be the same
+    operator as the whole-grid one, at every cell including those whose
+    stencil wraps around the periodic boundary (same arithmetic: equal bits)."""
+    O = oracle_mod
+    n = 16
+    rng = np.random.default_rng(77)
+    phi = rng.standard_normal((n, n, n)) * 1e-5
+    h, al = 1.0 / 2997.92458, 0.877
+    full = O.operator(phi, h, al)
+    kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    cells = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)
+    at = O.operator_at(phi, h, al, cells)
+    assert np.array_equal(at, full.ravel())
+    # the cell order of the list does not matter
+    perm = rng.permutation(len(cells))
+    assert np.array_equal(O.operator_at(phi, h, al, cells[perm]), full.ravel()[perm])
 
 
 # ---------------------------------------------------------------------------
