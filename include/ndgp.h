@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define NDGP_ABI_VERSION 2
+#define NDGP_ABI_VERSION 3
 #define NDGP_MAX_PATCHES 4
 #define NDGP_HIST_LEN 64
 
@@ -143,7 +143,8 @@ typedef struct {
     double removed_mean;   /* mean of delta projected out of the domain source         */
     double phi_mean;       /* mean of the domain phi removed at the end (gauge)        */
     int32_t fallbacks;     /* relaxation visits where the cell quadratic had no real
-                              root (moved to the vertex instead)                        */
+                              root (moved to its vertex instead, Eq. newton's
+                              linearisation is then stationary)                         */
     int32_t hist_len;      /* entries of res_hist used                                 */
     double res_hist[NDGP_HIST_LEN]; /* relative residual of the domain level per cycle */
     double t_total_ms;     /* wall time of the call                                    */
@@ -159,6 +160,9 @@ typedef struct {
                               that were relaxed (1 for relaxed levels, 0 for levels
                               filled by interpolation, in between with
                               ndgp_solve_cellwise)                                     */
+    int32_t holds;         /* relaxation visits of cells whose linearised operator was
+                              not elliptic there (dL/dphi of Eq. newton had the wrong
+                              sign): the cell kept its value for that visit             */
 } ndgp_report;
 
 /* Library ABI version (NDGP_ABI_VERSION of the build). */

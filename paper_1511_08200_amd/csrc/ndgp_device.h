@@ -135,19 +135,35 @@ __device__ __forceinline__ double fast_sqrt(double d) {
     return d > 0.0 ? s1 : 0.0;
 }
 
+// Relaxation events a thread counts in one unsigned: a visit with no real
+// root adds 1, a held non-elliptic cell adds kHoldEvent (a thread relaxes far
+// fewer than 2^16 cells per launch, so the halves never carry into each
+// other).  flush_events adds them to the launch's two counters:
+// counters[0] = no real root, counters[1] = non-elliptic holds.
+constexpr unsigned kHoldEvent = 1u << 16;
+
+__device__ __forceinline__ void flush_events(unsigned *counters, unsigned ev) {
+    if (ev & 0xffffu) atomicAdd(counters, ev & 0xffffu);
+    if (ev >> 16) atomicAdd(counters + 1, ev >> 16);
+}
+
 // New value of one cell: the root of its own quadratic with the neighbours
 // held, u + w * du.  w = 1 takes the root itself (w * r is then exactly r);
-// w < 1 damps the step, for the safeguarded iteration of the driver.
+// w < 1 damps the step, for the safeguarded iteration of the driver (the
+// vertex step of a cell without a real root is damped the same way).
 __device__ __forceinline__ double relax_cell(const double v[19], double s, double al, double w,
-                                             unsigned &fallbacks) {
+                                             unsigned &events) {
     const Terms t = stencil_terms(v);
     const double r = apply_L(t, al) - s;
     const double B = fma(al, fma(2.0, t.lap, 0.5 * t.see), 3.0);
-    if (!(B > 0.0)) return v[0];
+    if (!(B > 0.0)) {
+        events += kHoldEvent;
+        return v[0];
+    }
     const double D = fma(B, B, -18.0 * al * r);
     if (D < 0.0) {
-        ++fallbacks;
-        return v[0] + B / (18.0 * al);
+        ++events;
+        return fma(w, B / (18.0 * al), v[0]);
     }
     return fma(w * r, fast_rcp(B + fast_sqrt(D)), v[0]);
 }

@@ -55,7 +55,7 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
         write_owned_ghosts(pout, hat, ix, iu, j, k, un);
         write_owned_ghosts(pout, hat, ix, ic, j, k, uc);
     }
-    if (fb) atomicAdd(fallbacks, fb);
+    if (fb) flush_events(fallbacks, fb);
 }
 
 // One full red-black sweep of a periodic level in one launch, with the same
@@ -332,7 +332,7 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         step(k, true, ra, ba, rb, bb);
         step(k + 1, false, rb, bb, ra, ba);
     }
-    if (fb) atomicAdd(fallbacks, fb);
+    if (fb) flush_events(fallbacks, fb);
 }
 
 // FAS restriction with the residual on a large periodic level, through LDS:
@@ -889,7 +889,7 @@ k_coarsest(double *__restrict__ phi, const double *__restrict__ s, Ix<PER> ix, d
         }
     }
     for (int q = threadIdx.x; q < slots; q += blockDim.x) phi[q] = A[q];
-    if (fb) atomicAdd(fallbacks, fb);
+    if (fb) flush_events(fallbacks, fb);
 }
 
 // The bottom of a periodic V-cycle in one workgroup: every level from one of
@@ -1031,7 +1031,7 @@ k_bottom(double *__restrict__ phi, const double *__restrict__ s, int lg0, Bottom
         smooth(q, nu2);
     }
     for (int t = tid; t < cells0; t += kBottomThreads) phi[t] = PHI[t];
-    if (fb) atomicAdd(fallbacks, fb);
+    if (fb) flush_events(fallbacks, fb);
 }
 
 __global__ void __launch_bounds__(kBlock)

@@ -71,11 +71,14 @@ __device__ __forceinline__ float relax_corr_cell(const float vp[19], const float
     const double ad = (double)al;
     const double rT = (double)t.A - (double)r;
     const double B = fma(ad, fma(2.0, (double)t.lapw, 0.5 * (double)t.seew), 3.0);
-    if (!(B > 0.0)) return ve[0];
+    if (!(B > 0.0)) {
+        fallbacks += kHoldEvent;
+        return ve[0];
+    }
     const double D = fma(B, B, -18.0 * ad * rT);
     if (D < 0.0) {
         ++fallbacks;
-        return (float)((double)ve[0] + B / (18.0 * ad));
+        return (float)fma(w, B / (18.0 * ad), (double)ve[0]);
     }
     return (float)fma(w * rT, fast_rcp(B + fast_sqrt(D)), (double)ve[0]);
 }
@@ -167,7 +170,7 @@ k_corr_half(const float *__restrict__ ein, float *__restrict__ eout,
     const int me = ix(iu, j, k);
     eout[me] = relax_corr_cell(vp, ve, r[me], al, w, fb);
     eout[ix(ic, j, k)] = ein[ix(ic, j, k)];
-    if (fb) atomicAdd(fallbacks, fb);
+    if (fb) flush_events(fallbacks, fb);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -313,7 +316,7 @@ k_corr_coarsest(float *__restrict__ e, const float *__restrict__ phi, const floa
         }
     }
     if (active) e[t] = A[t];
-    if (fb) atomicAdd(fallbacks, fb);
+    if (fb) flush_events(fallbacks, fb);
 }
 
 // One full red-black sweep of the correction e on a large level in one
@@ -506,7 +509,7 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
         step(k, ra, ba, rb, bb);
         step(k + 1, rb, bb, ra, ba);
     }
-    if (fb) atomicAdd(fallbacks, fb);
+    if (fb) flush_events(fallbacks, fb);
 }
 
 // Restriction of the correction equation on a large level through LDS: phi

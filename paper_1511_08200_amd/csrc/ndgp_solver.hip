@@ -713,7 +713,7 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     Runner run{P, st, slot.p};
     run.timer = &timer;
     run.timed_s = P.base[0].s;
-    HIP_TRY(hipMemsetAsync(P.fallbacks, 0, sizeof(unsigned), st));
+    HIP_TRY(hipMemsetAsync(P.fallbacks, 0, 2 * sizeof(unsigned), st));
 
     // domain source: S = Omega_m (delta - mean) / (a beta), in cell units (x
     // h^2); its norm, the initial guess and the first residual norm are
@@ -814,15 +814,17 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         R.rel_res[q + 1] = rel;
         if (sq != NDGP_OK && status == NDGP_OK) status = sq;
     }
-    unsigned fb = 0;
+    unsigned fb[2] = {0, 0};
     HIP_TRY(hipGetLastError());
     if (psi && c.nrelax > 0) // iterated cells per masked patch, counted on the device
         HIP_TRY(hipMemcpyAsync(slot.p + 8, P.scal + 8, c.nrelax * sizeof(double),
                                hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(slot.p, P.fallbacks, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(slot.p, P.fallbacks, 2 * sizeof(unsigned), hipMemcpyDeviceToHost,
+                           st));
     HIP_TRY(hipStreamSynchronize(st));
-    std::memcpy(&fb, slot.p, sizeof(unsigned));
-    R.fallbacks = (int32_t)fb;
+    std::memcpy(fb, slot.p, 2 * sizeof(unsigned));
+    R.fallbacks = (int32_t)fb[0];
+    R.holds = (int32_t)fb[1];
     if (psi)
         for (int q = 0; q < c.nrelax; ++q)
             R.iterated_fraction[q + 1] = slot.p[8 + q] / ((double)c.pn[q] * c.pn[q] * c.pn[q]);
@@ -1079,7 +1081,8 @@ struct ndgp_plan {
     Plan P;
     hipStream_t st = nullptr;
     double *slot = nullptr; // pinned: [0] sum delta, [1] sum s^2, [2] sum r^2,
-                            //         [3] sum phi, [4] fallbacks (bits)
+                            //         [3] sum phi, [4] the two relaxation
+                            //         event counters (bits)
     hipEvent_t ev = nullptr;
     const double *delta[1 + NDGP_MAX_PATCHES] = {};
     double *phi[1 + NDGP_MAX_PATCHES] = {};
@@ -1114,7 +1117,7 @@ void plan_enqueue_tail(ndgp_plan *pl, bool zero_field) {
     }
     HIP_TRY(hipMemcpyAsync(pl->slot + 3, pl->P.scal + 3, sizeof(double), hipMemcpyDeviceToHost,
                            pl->st));
-    HIP_TRY(hipMemcpyAsync(pl->slot + 4, pl->P.fallbacks, sizeof(unsigned),
+    HIP_TRY(hipMemcpyAsync(pl->slot + 4, pl->P.fallbacks, 2 * sizeof(unsigned),
                            hipMemcpyDeviceToHost, pl->st));
     plan_record(pl);
     pl->state = ndgp_plan::FINISHING;
@@ -1154,7 +1157,7 @@ ndgp_status plan_create_impl(const ndgp_grid *grid, const ndgp_params *params,
         HIP_TRY(hipEventCreateWithFlags(&pl->ev, hipEventDisableTiming));
         Runner run = plan_runner(pl);
         const size_t cells0 = (size_t)c.n * c.n * c.n;
-        HIP_TRY(hipMemsetAsync(pl->P.fallbacks, 0, sizeof(unsigned), st));
+        HIP_TRY(hipMemsetAsync(pl->P.fallbacks, 0, 2 * sizeof(unsigned), st));
         run.enqueue_sum(delta[0], cells0, false, 0);
         launch_source(delta[0], cells0, pl->P.scal + 0, 1.0 / (double)cells0, c.fsrc * c.h * c.h,
                       pl->P.base[0].s, st);
@@ -1201,9 +1204,10 @@ ndgp_status plan_poll_impl(ndgp_plan *pl, int32_t *done, ndgp_report *rep) {
     const Cfg &c = pl->P.c;
     const size_t cells0 = (size_t)c.n * c.n * c.n;
     if (pl->state == ndgp_plan::FINISHING) {
-        unsigned fb = 0;
-        std::memcpy(&fb, pl->slot + 4, sizeof(unsigned));
-        pl->R.fallbacks = (int32_t)fb;
+        unsigned fb[2] = {0, 0};
+        std::memcpy(fb, pl->slot + 4, 2 * sizeof(unsigned));
+        pl->R.fallbacks = (int32_t)fb[0];
+        pl->R.holds = (int32_t)fb[1];
         pl->R.phi_mean = pl->slot[3] / (double)cells0;
         pl->R.t_total_ms = std::chrono::duration<double, std::milli>(
                                std::chrono::steady_clock::now() - pl->t0)

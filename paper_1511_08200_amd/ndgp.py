@@ -29,7 +29,7 @@ WARM_START = 1
 PROFILE = 2
 TWO_PASS = 4
 MAX_PATCHES = 4
-ABI_VERSION = 2
+ABI_VERSION = 3
 HIST_LEN = 64
 
 _STATUS = {NDGP_EINVAL: "EINVAL", NDGP_ENOMEM: "ENOMEM", NDGP_ENOCONV: "ENOCONV",
@@ -66,7 +66,8 @@ class _Report(ctypes.Structure):
                 ("t_smooth_ms", ctypes.c_double), ("smooth_launches", ctypes.c_int32),
                 ("smooth_cells_per_launch", ctypes.c_int32),
                 ("damped_from", ctypes.c_int32 * (1 + MAX_PATCHES)),
-                ("iterated_fraction", ctypes.c_double * (1 + MAX_PATCHES))]
+                ("iterated_fraction", ctypes.c_double * (1 + MAX_PATCHES)),
+                ("holds", ctypes.c_int32)]
 
 
 class _GeffLevel(ctypes.Structure):
@@ -279,6 +280,7 @@ class Report:
     status: int = NDGP_OK
     damped_from: list = dataclasses.field(default_factory=list)
     iterated_fraction: list = dataclasses.field(default_factory=list)
+    holds: int = 0
 
 
 def _report(r: _Report, status: int) -> Report:
@@ -288,7 +290,7 @@ def _report(r: _Report, status: int) -> Report:
                   t_smooth_ms=r.t_smooth_ms, smooth_launches=r.smooth_launches,
                   smooth_cells_per_launch=r.smooth_cells_per_launch, status=status,
                   damped_from=list(r.damped_from),
-                  iterated_fraction=list(r.iterated_fraction))
+                  iterated_fraction=list(r.iterated_fraction), holds=r.holds)
 
 
 # --------------------------------------------------------------------------

@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_version_and_beta(L):
-    assert L.ndgp_version() == 2
+    assert L.ndgp_version() == 3
     for rc in (0.5, 1.0, 2.0, 5.0):
         assert ndgp.beta_lcdm(1.0, 0.3, rc) == pytest.approx(1 + 1.7 * rc, rel=1e-14)
     # a < 1: against Eq. (beta) with a numerical Hdot

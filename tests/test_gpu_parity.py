@@ -671,3 +671,101 @@ def test_damped_step_safeguard_on_extreme_source(prec):
     S, _ = O.source(dn, 0.3, 1.0, beta)
     ro = S - O.operator(phi[0].cpu().numpy(), h, O.alpha(rc, beta, 1.0))
     assert np.linalg.norm(ro) / np.linalg.norm(S) <= 1.5e-10
+
+
+# --------------------------------------------------------------------------
+# the branches of the per-cell root (Sec. III.A, Eq. newton)
+
+@pytest.mark.parametrize("prec", [ndgp.PREC_FP64, ndgp.PREC_MIXED])
+def test_non_elliptic_cells_are_held_and_the_answer_matches_oracle(prec):
+    """A warm start far from the answer (white noise of 1.6e-8 on 1 Mpc/h
+    cells at r_cH0 = 5) makes the linearised operator non-elliptic at about
+    10% of the cells on the first visit (dL/dphi of the cell equation has the
+    wrong sign there); those cells keep their value until their neighbours
+    have moved.  The solve still reaches the unique elliptic solution, the
+    oracle's from its own nested start."""
+    n, rc = 32, 5.0
+    say(f"held cells precision={prec}")
+    f = synth.make_field(n, 2.0, 61, n_tophats=4)
+    h = ndgp.cell_size(32.0, n)
+    phio, _ = oracle_periodic(f.delta, h, rc)
+    rng = np.random.default_rng(7)
+    phi0 = dev(1.6e-8 * rng.standard_normal((n, n, n)))
+    grid = ndgp.Grid(n=n, h=h)
+    tol = 0.0 if prec == ndgp.PREC_FP64 else 1e-12
+    phi, rep = ndgp.solve(grid, ndgp.Params(rc=rc, tol=tol, max_cycles=200, precision=prec,
+                                            warm_start=True), [dev(f.delta)], phi=[phi0])
+    torch.cuda.synchronize()
+    say(f"  cycles={rep.cycles[0]} holds={rep.holds} fallbacks={rep.fallbacks} "
+        f"damped_from={rep.damped_from[0]} rel_res={rep.rel_res[0]:.2e}")
+    assert rep.status == 0
+    assert rep.holds > 0
+    e = rel(phi[0].cpu().numpy(), phio)
+    say(f"  rel err vs oracle {e:.2e}")
+    assert e <= (PHI_TOL if prec == ndgp.PREC_FP64 else MIXED_TOL)
+
+
+@pytest.mark.parametrize("prec", [ndgp.PREC_FP64, ndgp.PREC_MIXED])
+def test_no_real_root_on_an_unphysical_void(prec):
+    """The cell quadratic has no real root only where alpha S < -3/8, i.e.
+    delta far below -1 (an oracle pin shows this bound); there the
+    relaxation moves the cell to the vertex of its quadratic and counts the
+    event.  Three cells at delta = -40 (r_cH0 = 5): no elliptic solution exists
+    near them, the oracle fails too, and the solve ends with NDGP_ENOCONV after
+    counting the no-root visits instead of hanging or faulting."""
+    n, rc = 32, 5.0
+    say(f"unphysical void precision={prec}")
+    f = synth.make_field(n, 2.0, 61, n_tophats=4)
+    d = f.delta.copy()
+    for (i, j, k) in ((5, 6, 7), (20, 21, 3), (11, 27, 30)):
+        d[k, j, i] = -40.0
+    h = ndgp.cell_size(32.0, n)
+    beta = O.beta_lcdm(1.0, 0.3, rc)
+    S, _ = O.source(d, 0.3, 1.0, beta)
+    assert O.alpha(rc, beta, 1.0) * S.min() < -3 / 8
+    _, info = O.solve_periodic(S, h, O.alpha(rc, beta, 1.0), max_cycles=30)
+    assert info.status != 0
+    phi, rep = ndgp.solve(ndgp.Grid(n=n, h=h),
+                          ndgp.Params(rc=rc, tol=1e-10, max_cycles=20, precision=prec),
+                          [dev(d)], check=False)
+    torch.cuda.synchronize()
+    say(f"  status={rep.status} cycles={rep.cycles[0]} fallbacks={rep.fallbacks} "
+        f"holds={rep.holds}")
+    assert rep.status == ndgp.NDGP_ENOCONV
+    assert rep.fallbacks > 0
+
+
+# --------------------------------------------------------------------------
+# the norms behind the force-difference report (Sec. III.B, Eqs. errors, errors2)
+
+def test_diff_norms_against_numpy():
+    """ndgp_diff_norms: sum (a-b)^2, sum a^2, sum b^2 in the library's fixed-order
+    reduction, against exactly rounded sums (math.fsum), for counts that do not
+    fill the reduction grid, with b = NULL, on a force-sized array, and the
+    same bits on a second call."""
+    import math
+    rng = np.random.default_rng(5)
+    for count in (1, 7, 1000, 4096 * 256 + 17, 3 * 64**3, 5_000_003):
+        say(f"diff norms count={count}")
+        a = rng.standard_normal(count) * 1e-3
+        b = a + rng.standard_normal(count) * 1e-6
+        ta, tb = dev(a), dev(b)
+        d2, a2, b2 = ndgp.diff_norms(ta, tb)
+        assert d2 == pytest.approx(math.fsum((a - b) ** 2), rel=1e-12)
+        assert a2 == pytest.approx(math.fsum(a * a), rel=1e-12)
+        assert b2 == pytest.approx(math.fsum(b * b), rel=1e-12)
+        assert ndgp.diff_norms(ta, tb) == (d2, a2, b2)
+        n2, m2, z2 = ndgp.diff_norms(ta)
+        assert n2 == m2 == a2 and z2 == 0.0
+    # the force report itself: interpolated vs relaxed patch force, 64^3 + patches
+    f, deltas, grid = patch_problem()
+    full, _ = gpu_solve(deltas, grid, rc=1.0, tol=1e-10, mode=ndgp.MODE_FULL)
+    intp, _ = gpu_solve(deltas, grid, rc=1.0, tol=1e-10, mode=ndgp.MODE_INTERPOLATED)
+    Ff = ndgp.force(grid, [dev(p) for p in full])
+    Fi = ndgp.force(grid, [dev(p) for p in intp])
+    for lvl in (1, 2):
+        d2, i2, f2 = ndgp.diff_norms(Fi[lvl], Ff[lvl])
+        fi, ff = Fi[lvl].cpu().numpy().ravel(), Ff[lvl].cpu().numpy().ravel()
+        assert d2 == pytest.approx(math.fsum((fi - ff) ** 2), rel=1e-12)
+        assert f2 == pytest.approx(math.fsum(ff * ff), rel=1e-12)
+        say(f"  level {lvl}: |F_int - F_full| / |F_full| = {math.sqrt(d2 / f2):.3e}")

@@ -372,6 +372,81 @@ def test_cell_equation_quadratic_and_newton_derivative(oracle_mod):
     assert (phi[c[2], c[1], c[0]] - upd) == pytest.approx(T / slope, rel=1e-8)
 
 
+def _cell_discriminant(O, nb, h, al, S_c):
+    """Discriminant of the cell's own quadratic T(du) = L_h[phi + du e_c] - S_c
+    at the centre of a 3^3 neighbourhood ``nb`` (centre value 0), made
+    dimensionless: Delta h^4 / 4 (the quadratic's coefficients from three exact
+    evaluations of the oracle's operator)."""
+    d = 1e-2 * (np.abs(nb).max() + 1e-30)
+    vals = []
+    for t in (-1.0, 0.0, 1.0):
+        p = np.zeros((3, 3, 3))
+        p[...] = nb
+        p[1, 1, 1] += t * d
+        vals.append(O.operator_at(p, h, al, [(1, 1, 1)])[0] - S_c)
+    a2 = (vals[2] - 2 * vals[1] + vals[0]) / (2 * d * d)
+    a1 = (vals[2] - vals[0]) / (2 * d)
+    a0 = vals[1]
+    return (a1 * a1 - 4 * a2 * a0) * h**4 / 4
+
+
+def test_cell_equation_has_a_real_root_for_physical_sources(oracle_mod):
+    """Over every configuration of the 18 neighbours, the discriminant of a
+    cell's quadratic (Eq. newton's cell equation, made dimensionless) is at
+    least 27/4 + 18 alpha S_c, with equality reached.  So a cell without a real
+    root needs alpha S < -3/8, the same bound below which the spherical
+    solution of Eq. (eomvarphi_sph) has no real root (1 + 8 alpha S/3 < 0).
+    With delta >= -1, a = 1 and Omega_m = 0.3, alpha S >= -0.1 r_c^2/beta^2 >
+    -0.035 for every r_c: the no-root branch of the relaxation is reached only
+    by unphysical sources (or transiently on coarse multigrid levels)."""
+    O = oracle_mod
+    h = 1.0 / 2997.92458
+    al = 0.877
+    # the 3^3 box as a periodic 3^3 grid: operator_at reads exactly the 18
+    # neighbours and the centre of cell (1, 1, 1)
+    D0 = lambda nb: _cell_discriminant(O, nb, h, al, 0.0)
+    rng = np.random.default_rng(33)
+    scale = h * h / al
+    worst = np.inf
+    for _ in range(300):
+        nb = rng.standard_normal((3, 3, 3)) * scale * rng.uniform(0.01, 3.0)
+        for corner in ((0, 0, 0), (0, 0, 2), (0, 2, 0), (0, 2, 2), (2, 0, 0), (2, 0, 2),
+                       (2, 2, 0), (2, 2, 2)):
+            nb[corner] = 0.0  # not part of the 19-point stencil
+        nb[1, 1, 1] = 0.0
+        worst = min(worst, D0(nb))
+    assert worst >= 27 / 4 - 1e-9
+    # the minimum over the neighbours: D0 is quadratic in them; find its
+    # stationary point from probes and check the value 27/4 there
+    idx = [(k, j, i) for k in range(3) for j in range(3) for i in range(3)
+           if (abs(i - 1) + abs(j - 1) + abs(k - 1)) in (1, 2)]
+    assert len(idx) == 18
+
+    def f(x):
+        nb = np.zeros((3, 3, 3))
+        for v, c in zip(x, idx):
+            nb[c] = v * scale
+        return D0(nb)
+    E = np.eye(18)
+    c0 = f(np.zeros(18))
+    g = np.array([(f(E[q]) - f(-E[q])) / 2 for q in range(18)])
+    H = np.array([[(f(E[p] + E[q]) - f(E[p]) - f(E[q]) + c0) / 2 for q in range(18)]
+                  for p in range(18)])
+    assert c0 == pytest.approx(9.0, rel=1e-9)  # B = 3, r = 0 at a flat stencil
+    assert np.linalg.eigvalsh(H).min() >= -1e-6  # convex: the stationary point is the minimum
+    xm = -0.5 * np.linalg.lstsq(H, g, rcond=None)[0]
+    assert f(xm) == pytest.approx(27 / 4, abs=1e-6)
+    # the source enters linearly: 18 alpha S
+    nb = rng.standard_normal((3, 3, 3)) * scale
+    S_c = -0.2 / al
+    assert _cell_discriminant(O, nb, h, al, S_c) == pytest.approx(D0(nb) + 18 * al * S_c,
+                                                                  rel=1e-6)
+    # physical sources stay above the bound for every r_c at a = 1, Omega_m = 0.3
+    for rc in np.linspace(0.0, 1000.0, 2001):
+        beta = O.beta_lcdm(1.0, 0.3, rc)
+        assert O.alpha(rc, beta, 1.0) * 0.3 * (-1.0) / beta > -3 / 8 + 0.3
+
+
 # ---------------------------------------------------------------------------
 # solver
 
