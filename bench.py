@@ -3,17 +3,24 @@
 
 One step = one whole solve of the domain grid to ||S - L phi|| / ||S|| <= 1e-10
 (source preparation, nested start, FAS V-cycles, norms, gauge) followed by the
-fifth force, on a 256^3 periodic grid (box 256 Mpc/h, r_c H0 = 1, Omega_m = 0.3,
-lognormal delta with sigma_ln = 2 and P(k) ~ k^-2 plus 50 top-hats of
-delta = 200, radius 2-8 cells; seeded synthetic input resident in HBM).
+fifth force, on the 512^3 periodic grid of the mixed-precision configuration
+(box 512 Mpc/h, r_c H0 = 1, Omega_m = 0.3, lognormal delta with sigma_ln = 2.5
+and P(k) ~ k^-2, seeded synthetic input resident in HBM), in FP64.
+``--workload 256`` times the 256^3 grid with sigma_ln = 2 plus 50 top-hats
+instead.
 
-value = cell-updates/s = n^3 (nu1 + nu2) cycles / wall time per step.
+value = cell-updates/s = n^3 (nu1 + nu2) cycles / wall time per step.  The
+timed steps run without the library's profiling flag.
 
 The JSON line also carries:
-  roofline      the red-black relaxation kernel, timed with HIP events on its
-                launch stream during the timed steps; algorithmic bytes per
-                cell update = 24 (read phi and S, write phi; FP64);
-  cpu_baseline  the CPU oracle on a bounded sample of the same workload;
+  roofline      the red-black relaxation kernel of the finest level, timed
+                with HIP events on its launch stream in a separate profiled
+                pass after the timed steps; algorithmic bytes per cell update
+                = 24 (read phi and S, write phi; FP64); beside the 8 TB/s
+                peak, the measured copy ceiling: a plain stream that reads two
+                n^3 FP64 arrays and writes one (24 B per cell), timed here;
+  cpu_baseline  the CPU oracle's time to the same tolerance on the 32^3
+                configuration and on the timed input;
   extra         patches: 256^3 + two nested 128^3 patches, full vs interpolated
                 vs mixed + interpolated (time to tolerance, force difference);
                 truncation: 256^3 + four nested 128^3 patches at the truncation
@@ -21,10 +28,10 @@ The JSON line also carries:
                 G_eff per level; particles: one time step around the solver
                 (cloud-in-cell density, nDGP and Newtonian solves, total force,
                 cloud-in-cell force); large: 512^3 solves at three r_c, FP64
-                and mixed, with the relaxation roofline; serving: the request
+                and mixed; medium: the 256^3 solve; serving: the request
                 stream (Poisson arrivals) and saturation.
 
-    python bench.py [--steps K] [--warmup W] [--no-extra] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--workload 512|256] [--no-extra] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -106,7 +113,7 @@ def kernel_name(cells, n):
     return "k_smooth_half (one colour per launch, FP64)"
 
 
-def roofline(reps, n):
+def roofline(reps, n, copy_gbs=None):
     launches = sum(r.smooth_launches for r in reps)
     t_ms = sum(r.t_smooth_ms for r in reps)
     if not launches or t_ms <= 0:
@@ -116,26 +123,61 @@ def roofline(reps, n):
     alg_bytes = BYTES_PER_UPDATE_FP64 * cells
     achieved = alg_bytes / avg_s / 1e9
     tr = traffic_from_profiles(n)
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": tr, "kernel": kernel_name(cells, n),
-            "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
-            "cells_per_launch": cells, "alg_bytes_per_launch": alg_bytes,
-            "cell_updates_per_s": cells / avg_s}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": tr, "kernel": kernel_name(cells, n),
+           "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+           "cells_per_launch": cells, "alg_bytes_per_launch": alg_bytes,
+           "cell_updates_per_s": cells / avg_s}
+    if copy_gbs:
+        out["copy_ceiling_gbs"] = round(copy_gbs, 1)
+        out["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    return out
 
 
-def cpu_baseline(delta, h, rc, cycles):
+def copy_ceiling(torch, n, reps=5):
+    """Measured stream ceiling for the relaxation's access pattern: read two
+    n^3 FP64 arrays and write one (24 B per cell), as one elementwise kernel,
+    timed with events on torch's stream (where it runs)."""
+    a = torch.ones(n**3, dtype=torch.float64, device="cuda")
+    b = torch.full_like(a, 2.0)
+    c = torch.empty_like(a)
+    for _ in range(2):
+        torch.add(a, b, out=c)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        torch.add(a, b, out=c)
+    ev[1].record()
+    torch.cuda.synchronize()
+    s = ev[0].elapsed_time(ev[1]) / 1e3 / reps
+    del a, b, c
+    torch.cuda.empty_cache()
+    return 24.0 * n**3 / s / 1e9
+
+
+def cpu_baseline(cases):
+    """The oracle (plain FP64 C, OpenMP) on the host: nested start + V(2,2)
+    cycles to the same tolerance, on each (label, delta, h, rc) case."""
     from oracle import oracle as O
-    beta = O.beta_lcdm(1.0, 0.3, rc)
-    S, _ = O.source(delta, 0.3, 1.0, beta)
-    n = delta.shape[0]
-    t0 = time.perf_counter()
-    _, info = O.solve_periodic(S, h, O.alpha(rc, beta, 1.0), max_cycles=cycles, tol=1e-300)
-    dt = time.perf_counter() - t0
-    return {"value": n**3 * 4 * info.cycles / dt, "unit": "cell-updates/s",
+    rows = []
+    for label, delta, h, rc in cases:
+        beta = O.beta_lcdm(1.0, 0.3, rc)
+        S, _ = O.source(delta, 0.3, 1.0, beta)
+        n = delta.shape[0]
+        log(f"cpu baseline: oracle on {label}")
+        t0 = time.perf_counter()
+        _, info = O.solve_periodic(S, h, O.alpha(rc, beta, 1.0), tol=1e-10)
+        dt = time.perf_counter() - t0
+        rows.append({"case": label, "s_to_tol": round(dt, 3), "cycles": info.cycles,
+                     "rel_res": info.rel_res, "cell_updates_per_s": n**3 * 4 * info.cycles / dt})
+    head = rows[-1]
+    return {"value": head["cell_updates_per_s"], "unit": "cell-updates/s",
             "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{n}^3 same input: nested start + {info.cycles} V(2,2) cycles "
-                      f"(rel. residual {info.rel_res:.2e}) in {dt:.1f} s"}
+            "sample": "; ".join(f"{r['case']}: nested start + {r['cycles']} V(2,2) cycles to "
+                                f"rel. residual {r['rel_res']:.2e} in {r['s_to_tol']} s"
+                                for r in rows),
+            "time_to_tol_s": {r["case"]: r["s_to_tol"] for r in rows}}
 
 
 def patch_workload(ndgp, torch, steps, depth):
@@ -351,12 +393,12 @@ def large_workload(ndgp, torch, steps):
     grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
     out = {"workload": "512^3 periodic, lognormal sigma 2.5, tol 1e-10, FP64 and mixed"}
     for rc in (0.5, 1.0, 5.0):
-        params = ndgp.Params(rc=rc, tol=1e-10, profile=True)
+        params = ndgp.Params(rc=rc, tol=1e-10)
         dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, [f.delta], steps, 1,
                                         with_force=False)
         cyc = reps[-1].cycles[0]
         ent = {"fp64_ms_to_tol": round(dt * 1e3, 1), "fp64_cycles": cyc,
-               "fp64_cell_updates_per_s": n**3 * 4 * cyc / dt, "roofline": roofline(reps, n)}
+               "fp64_cell_updates_per_s": n**3 * 4 * cyc / dt}
         phi64 = phi[0].clone()
         del phi
         pm = ndgp.Params(rc=rc, tol=1e-10, precision=ndgp.PREC_MIXED)
@@ -371,6 +413,23 @@ def large_workload(ndgp, torch, steps):
         del phim, phi64, dd
         torch.cuda.empty_cache()
     return out
+
+
+def medium_workload(ndgp, torch, steps):
+    """The 256^3 configuration: lognormal sigma 2 + 50 top-hats, FP64 to 1e-10
+    plus the force, with its own profiled relaxation roofline."""
+    n, box, rc = 256, 256.0, 1.0
+    f = make_domain(n, box, 2.0, 50, 1513)
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
+    dt, reps, phi, dd = solve_steps(ndgp, torch, grid, ndgp.Params(rc=rc, tol=1e-10), [f.delta],
+                                    steps, 2)
+    _, preps, _, _ = solve_steps(ndgp, torch, grid, ndgp.Params(rc=rc, tol=1e-10, profile=True),
+                                 [f.delta], 2, 0)
+    cyc = reps[-1].cycles[0]
+    return {"workload": "256^3 periodic, lognormal sigma 2 + 50 top-hats, r_cH0=1, FP64, tol "
+                        "1e-10, + force",
+            "ms_to_tol": round(dt * 1e3, 2), "cycles": cyc,
+            "cell_updates_per_s": n**3 * 4 * cyc / dt, "roofline": roofline(preps, n)}
 
 
 def serving_workload(ndgp, torch, count, rate, sat_count):
@@ -397,14 +456,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=("256", "512"), default="256",
-                    help="timed workload: 256^3 lognormal+top-hats (default) or the 512^3 "
-                         "lognormal sigma 2.5 field (for profiling the HBM-bound regime)")
+    ap.add_argument("--workload", choices=("256", "512"), default="512",
+                    help="timed workload: the 512^3 lognormal sigma 2.5 field (default) or "
+                         "256^3 lognormal + top-hats")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extra", default="patches,truncation,particles,large,serving",
+    ap.add_argument("--extra", default="patches,truncation,particles,large,medium,serving",
                     help="comma-separated extra workloads to run after the timed one")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=4)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-saturation", type=int, default=400)
@@ -425,7 +483,8 @@ def main():
 
     if args.workload == "512":
         n, box, rc, sigma, tophats, seed = 512, 512.0, 1.0, 2.5, 0, 1515
-        wl = "ndgp-512^3-fp64-lognormal-sigma2.5, box 512 Mpc/h, r_cH0=1, tol 1e-10, V(2,2) 7 levels, + force"
+        wl = ("ndgp-512^3-fp64-lognormal-sigma2.5, box 512 Mpc/h, r_cH0=1, tol 1e-10, "
+              "V(2,2) 7 levels, + force")
     else:
         n, box, rc, sigma, tophats, seed = 256, 256.0, 1.0, 2.0, 50, 1513
         wl = ("ndgp-256^3-fp64-lognormal-sigma2+50tophats, box 256 Mpc/h, r_cH0=1, tol 1e-10, "
@@ -433,13 +492,22 @@ def main():
     log(f"generating {n}^3 input")
     f = make_domain(n, box, sigma, tophats, seed)
     grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
-    params = ndgp.Params(rc=rc, tol=1e-10, profile=True)
+    params = ndgp.Params(rc=rc, tol=1e-10)
     log("timing")
     dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, [f.delta], args.steps,
                                     args.warmup)
     cycles = reps[-1].cycles[0]
     assert all(r.cycles[0] == cycles for r in reps)
     value = n**3 * 4 * cycles / dt
+    del phi, dd
+    # the roofline from a separate pass with the relaxation launches timed
+    log("profiled pass (relaxation roofline)")
+    _, preps, phi, dd = solve_steps(ndgp, torch, grid, ndgp.Params(rc=rc, tol=1e-10, profile=True),
+                                    [f.delta], 3, 0)
+    del phi, dd
+    torch.cuda.empty_cache()
+    log("copy ceiling")
+    copy_gbs = copy_ceiling(torch, n)
     line = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
@@ -447,10 +515,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "n": n, "cycles": cycles, "rel_res": reps[-1].rel_res[0],
                    "solves_per_s": 1.0 / dt},
-        "roofline": roofline(reps, n),
+        "roofline": roofline(preps, n, copy_gbs),
     }
-    del phi, dd
-    torch.cuda.empty_cache()
     if args.calibrate_copy:
         a = torch.ones(n**3, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -460,10 +526,13 @@ def main():
         line["calibration_copy_bytes"] = {"read": a.numel() * 8, "write": b.numel() * 8}
         del a, b
     if not args.no_cpu:
-        log("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(f.delta, grid.h, rc, args.cpu_cycles)
+        from paper_1511_08200_amd import synth
+        f32 = synth.make_field(32, 1.0, 1512)
+        line["cpu_baseline"] = cpu_baseline(
+            [("32^3 sigma 1 (box 64 Mpc/h)", f32.delta, ndgp.cell_size(64.0, 32), 1.0),
+             (f"{n}^3 timed input", f.delta, grid.h, rc)])
     extras = set() if args.no_extra else {e for e in args.extra.split(",") if e}
-    unknown = extras - {"patches", "truncation", "particles", "large", "serving"}
+    unknown = extras - {"patches", "truncation", "particles", "large", "medium", "serving"}
     if unknown:
         raise SystemExit(f"unknown extra workloads: {sorted(unknown)}")
     if extras:
@@ -480,6 +549,9 @@ def main():
         if "large" in extras:
             log("512^3 workload")
             out["large"] = large_workload(ndgp, torch, 3)
+        if "medium" in extras:
+            log("256^3 workload")
+            out["medium"] = medium_workload(ndgp, torch, 5)
         if "serving" in extras and args.serve_requests > 0:
             out["serving"] = serving_workload(ndgp, torch, args.serve_requests,
                                               args.serve_rate, args.serve_saturation)
