@@ -160,9 +160,9 @@ typedef struct {
                               that were relaxed (1 for relaxed levels, 0 for levels
                               filled by interpolation, in between with
                               ndgp_solve_cellwise)                                     */
-    int32_t holds;         /* relaxation visits of cells whose linearised operator was
-                              not elliptic there (dL/dphi of Eq. newton had the wrong
-                              sign): the cell kept its value for that visit             */
+    int32_t holds;         /* relaxation visits of cells past the vertex of their own
+                              quadratic (dL/dphi of Eq. newton had the non-elliptic
+                              sign there): moved to the root on the elliptic side      */
 } ndgp_report;
 
 /* Library ABI version (NDGP_ABI_VERSION of the build). */
@@ -285,6 +285,31 @@ ndgp_status ndgp_residual(const ndgp_grid *grid, const ndgp_params *params, int3
                           const double *const delta[1 + NDGP_MAX_PATCHES], const double *phi,
                           double *r_out, double *rel_norm_out, void *workspace,
                           size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the residual
+ * of ndgp_residual without a workspace and without blocking.  Same arguments
+ * and the same kernels, with two differences:
+ *   norms_out     DEVICE, 3 doubles: sum r^2 and sum S^2 (both in the level's
+ *                 cell units, h^2 S) and the relative norm ||r|| / ||S||, the
+ *                 bits ndgp_residual returns in *rel_norm_out
+ *   (no checks)   the call only enqueues: a non-finite delta gives NaN norms
+ *                 instead of NDGP_EINVAL
+ * The scratch space is a static device array of the library, one per GPU
+ * (NDGP_NOALLOC_SCRATCH_BYTES, held until the process ends): a level of more
+ * than NDGP_NOALLOC_MAX_CELLS cells is rejected with NDGP_EINVAL.  Every call
+ * on a GPU uses that GPU's one array, whatever the stream: calls that overlap
+ * on one GPU race (serialise them, e.g. on one stream).  `stream` must belong
+ * to the current device.  The call never allocates device or pinned memory,
+ * never synchronises, and enqueues no memset.
+ */
+#define NDGP_NOALLOC_MAX_CELLS 2097152 /* 128^3 */
+#define NDGP_NOALLOC_SCRATCH_BYTES ((NDGP_NOALLOC_MAX_CELLS + 4096 + 32) * 8)
+ndgp_status ndgp_residual_noalloc(const ndgp_grid *grid, const ndgp_params *params,
+                                  int32_t level, const double *const delta[1 + NDGP_MAX_PATCHES],
+                                  const double *phi, double *r_out, double *norms_out,
+                                  hipStream_t stream);
 
 /*
  * Fifth force F = -grad(phi)/2 by central differences on every level

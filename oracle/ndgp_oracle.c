@@ -329,11 +329,18 @@ static void newton_gs_sweep(const hier_t *H, level_t *L)
                         double dL;
                         const double Lc = op_cell(L->phi, n, i, j, k, L->h, H->alpha, &dL);
                         const double T = Lc - L->S[c];
-                        /* dT/dphi >= 0 means the cell equation is past the
-                           vertex of its parabola (the linearised operator is
-                           not elliptic there): no Newton step, the cell waits
-                           for its neighbours to move. */
-                        if (!(dL < 0.0)) break;
+                        /* The cell equation is a parabola in phi[c] (leading
+                           coefficient 18 alpha / h^4).  dT/dphi >= 0 means the
+                           value is past its vertex, on the branch where the
+                           linearised operator is not elliptic: reflect it across
+                           the vertex (same T, slope of the elliptic sign), from
+                           where the Newton steps reach the elliptic root. */
+                        if (!(dL < 0.0)) {
+                            const double a2 = 18.0 * H->alpha / (L->h * L->h * L->h * L->h);
+                            if (!(dL > 0.0) || !(a2 > 0.0)) break;
+                            L->phi[c] -= dL / a2;
+                            continue;
+                        }
                         const double step = T / dL;
                         L->phi[c] -= step;
                         if (fabs(step) <= 1e-15 * fabs(L->phi[c])) break;

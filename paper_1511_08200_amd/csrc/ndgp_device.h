@@ -111,14 +111,17 @@ __device__ __forceinline__ double apply_L(const Terms &t, double al) {
     return fma(2.0 * al, t.nl, t.lap);
 }
 
-// New value of the centre cell: the root of its own equation T(u') = 0 that is
-// continuous with the linear case.  Moving u by du shifts every D_aa by -2 du
-// and every corner difference by +du, so with dt = 2 du
+// New value of the centre cell: the root of its own equation T(u') = 0 on the
+// elliptic branch.  Moving u by du shifts every D_aa by -2 du and every corner
+// difference by +du, so with dt = 2 du
 //     T(dt) = r - B dt + (9/2) alpha dt^2,   r = L - s,
 //     B = 3 + 4 alpha lap + 2 alpha M,  M = (1/4) sum C = see/4 - lap,
-// and the root is dt = 2 r / (B + sqrt(B^2 - 18 alpha r)) (no cancellation).
-// B <= 0: the linearised operator is not elliptic at this cell; it waits for
-// its neighbours.  No real root: move to the vertex dt = B / (9 alpha).
+// and B itself falls by 9 alpha dt: the linearised operator is elliptic at the
+// cell (dL/du < 0) left of the parabola's vertex dt = B / (9 alpha).  The root
+// there is dt = (B - sqrt(B^2 - 18 alpha r)) / (9 alpha), written as
+// 2 r / (B + sqrt(...)) when B > 0 (no cancellation; continuous with the
+// linear case) and as it stands when B <= 0 (the value was past the vertex).
+// No real root: move to the vertex.
 // Reciprocal and square root from the hardware estimates plus one Newton
 // step each (relative error near 1e-16).  The relaxation only needs them to
 // pick its step: the fixed point L[phi] = s does not depend on how they round.
@@ -136,11 +139,12 @@ __device__ __forceinline__ double fast_sqrt(double d) {
 }
 
 // Relaxation events a thread counts in one unsigned: a visit with no real
-// root adds 1, a held non-elliptic cell adds kHoldEvent (a thread relaxes far
-// fewer than 2^16 cells per launch, so the halves never carry into each
-// other).  flush_events adds them to the launch's two counters:
-// counters[0] = no real root, counters[1] = non-elliptic holds.
-constexpr unsigned kHoldEvent = 1u << 16;
+// root adds 1, a visit of a cell past its vertex (not elliptic there) adds
+// kPastVertexEvent (a thread relaxes far fewer than 2^16 cells per launch, so
+// the halves never carry into each other).  flush_events adds them to the
+// launch's two counters: counters[0] = no real root, counters[1] = past the
+// vertex.
+constexpr unsigned kPastVertexEvent = 1u << 16;
 
 __device__ __forceinline__ void flush_events(unsigned *counters, unsigned ev) {
     if (ev & 0xffffu) atomicAdd(counters, ev & 0xffffu);
@@ -149,23 +153,21 @@ __device__ __forceinline__ void flush_events(unsigned *counters, unsigned ev) {
 
 // New value of one cell: the root of its own quadratic with the neighbours
 // held, u + w * du.  w = 1 takes the root itself (w * r is then exactly r);
-// w < 1 damps the step, for the safeguarded iteration of the driver (the
-// vertex step of a cell without a real root is damped the same way).
+// w < 1 damps the step, for the safeguarded iteration of the driver (every
+// branch is damped the same way).
 __device__ __forceinline__ double relax_cell(const double v[19], double s, double al, double w,
                                              unsigned &events) {
     const Terms t = stencil_terms(v);
     const double r = apply_L(t, al) - s;
     const double B = fma(al, fma(2.0, t.lap, 0.5 * t.see), 3.0);
-    if (!(B > 0.0)) {
-        events += kHoldEvent;
-        return v[0];
-    }
     const double D = fma(B, B, -18.0 * al * r);
     if (D < 0.0) {
         ++events;
         return fma(w, B / (18.0 * al), v[0]);
     }
-    return fma(w * r, fast_rcp(B + fast_sqrt(D)), v[0]);
+    if (B > 0.0) return fma(w * r, fast_rcp(B + fast_sqrt(D)), v[0]);
+    events += kPastVertexEvent;
+    return fma(w, (B - fast_sqrt(D)) / (18.0 * al), v[0]);
 }
 
 // Coarse levels of a refinement: write the ghosts whose correction is taken

@@ -82,6 +82,9 @@ void launch_partial_sums(const double *a, size_t count, bool squares, double *pa
                          hipStream_t st);
 // out[0] = sum of the kReduceBlocks partials, in a fixed order.
 void launch_reduce_final(const double *partials, double *out, hipStream_t st);
+// out[0..3) = sum r^2, sum s^2 and the relative norm, from sums[1] = sum s^2
+// and sums[2] = sum r^2 (one thread).
+void launch_residual_norms(const double *sums, double *out, hipStream_t st);
 // FAS restriction: C.hat = mean of children of F.phi; C.s = 4 * mean of children residuals.
 // tiled: through LDS on periodic levels of n >= 128 (same bits).
 void launch_restrict_residual(const Level &F, const Level &C, bool tiled, hipStream_t st);

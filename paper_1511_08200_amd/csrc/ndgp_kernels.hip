@@ -637,6 +637,16 @@ k_reduce_final(const double *__restrict__ partials, double *__restrict__ out) {
     if (threadIdx.x == 0) out[0] = b;
 }
 
+// out = (sum r^2, sum s^2, relative norm) from sums[1] = sum s^2 and
+// sums[2] = sum r^2, the relative norm as the blocking residual computes it
+// on the host (IEEE division and square root: the same bits)
+__global__ void k_residual_norms(const double *__restrict__ sums, double *__restrict__ out) {
+    const double ss = sums[1], rr = sums[2];
+    out[0] = rr;
+    out[1] = ss;
+    out[2] = ss > 0.0 ? sqrt(rr / ss) : sqrt(rr);
+}
+
 // FAS restriction fused with the residual, for one coarse cell (I, J, K): the
 // mean of its 8 children's phi and 4 x the mean of their residuals s - L[phi],
 // from the 4x4x4 block of fine values around the children (the 8 block
@@ -1291,6 +1301,10 @@ void launch_diff_partials(const double *a, const double *b, size_t count, double
 
 void launch_reduce_final(const double *partials, double *out, hipStream_t st) {
     k_reduce_final<<<1, kBlock, 0, st>>>(partials, out);
+}
+
+void launch_residual_norms(const double *sums, double *out, hipStream_t st) {
+    k_residual_norms<<<1, 1, 0, st>>>(sums, out);
 }
 
 void launch_restrict_residual(const Level &F, const Level &C, bool tiled, hipStream_t st) {

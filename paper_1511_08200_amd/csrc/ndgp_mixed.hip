@@ -71,16 +71,14 @@ __device__ __forceinline__ float relax_corr_cell(const float vp[19], const float
     const double ad = (double)al;
     const double rT = (double)t.A - (double)r;
     const double B = fma(ad, fma(2.0, (double)t.lapw, 0.5 * (double)t.seew), 3.0);
-    if (!(B > 0.0)) {
-        fallbacks += kHoldEvent;
-        return ve[0];
-    }
     const double D = fma(B, B, -18.0 * ad * rT);
     if (D < 0.0) {
         ++fallbacks;
         return (float)fma(w, B / (18.0 * ad), (double)ve[0]);
     }
-    return (float)fma(w * rT, fast_rcp(B + fast_sqrt(D)), (double)ve[0]);
+    if (B > 0.0) return (float)fma(w * rT, fast_rcp(B + fast_sqrt(D)), (double)ve[0]);
+    fallbacks += kPastVertexEvent;
+    return (float)fma(w, (B - fast_sqrt(D)) / (18.0 * ad), (double)ve[0]);
 }
 
 using IxP = Ix<true>;

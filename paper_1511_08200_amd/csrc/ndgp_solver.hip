@@ -22,6 +22,12 @@
 
 using namespace ndgp;
 
+// Device scratch of ndgp_residual_noalloc, one copy per GPU, held until the
+// process ends: the level's source (at most NDGP_NOALLOC_MAX_CELLS doubles),
+// then kReduceBlocks reduction partials, then a few sums.
+static __device__ __align__(256) double scratch[NDGP_NOALLOC_MAX_CELLS + kReduceBlocks + 32];
+static_assert(sizeof(scratch) == NDGP_NOALLOC_SCRATCH_BYTES, "scratch size as documented");
+
 namespace {
 
 thread_local std::string g_err;
@@ -876,6 +882,73 @@ ndgp_status residual_impl(const ndgp_grid *grid, const ndgp_params *params, int3
     return NDGP_OK;
 }
 
+// ------------------------------------------------------------------------
+// ndgp_residual_noalloc: the residual with the library's own scratch array
+// instead of a caller workspace.  `scratch` is a host-side stand-in for the
+// device array in host code: host code only ever uses the address that
+// hipGetSymbolAddress returns for the current device (each GPU holds its own
+// copy of the array, at its own address).
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxScratchDevices] = {};
+
+double *scratch_for_current_device() {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        throw HipFailure{hipErrorInvalidDevice, "device id above the scratch table"};
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+ndgp_status residual_noalloc_impl(const ndgp_grid *grid, const ndgp_params *params, int32_t level,
+                                  const double *const delta[], const double *phi, double *r_out,
+                                  double *norms_out, hipStream_t st) {
+    Cfg c;
+    std::string why;
+    if (!resolve(grid, params, c, why)) return fail(NDGP_EINVAL, why);
+    if (level < 0 || level > c.np) return fail(NDGP_EINVAL, "level out of range");
+    if (!delta || !delta[0] || !delta[level] || !phi || !norms_out)
+        return fail(NDGP_EINVAL, "delta[0], delta[level], phi and norms_out must not be NULL");
+    const int nlv = c.nlev(level);
+    Level L;
+    L.n = nlv;
+    L.lg = ilog2(nlv);
+    L.periodic = level == 0;
+    if (L.cells() > (size_t)NDGP_NOALLOC_MAX_CELLS)
+        return fail(NDGP_EINVAL, "level " + std::to_string(level) + " has " +
+                                     std::to_string(L.cells()) +
+                                     " cells, more than NDGP_NOALLOC_MAX_CELLS = " +
+                                     std::to_string(NDGP_NOALLOC_MAX_CELLS) +
+                                     " (use ndgp_residual with a workspace)");
+    double *base = scratch_for_current_device();
+    const double hl = c.hl(level);
+    L.alpha = c.alpha / (hl * hl);
+    L.phi = const_cast<double *>(phi);
+    L.s = base;                                      // the level's source, cell units
+    double *partials = base + NDGP_NOALLOC_MAX_CELLS; // one per reduction block
+    double *sums = partials + kReduceBlocks;          // [0] sum delta, [1] sum s^2, [2] sum r^2
+    const size_t cells0 = (size_t)c.n * c.n * c.n;
+    // every scratch value is written before it is read: nothing to clear
+    launch_partial_sums(delta[0], cells0, false, partials, st);
+    launch_reduce_final(partials, sums + 0, st);
+    launch_source(delta[level], L.cells(), sums + 0, 1.0 / (double)cells0, c.fsrc * hl * hl, L.s,
+                  st);
+    launch_partial_sums(L.s, L.cells(), true, partials, st);
+    launch_reduce_final(partials, sums + 1, st);
+    launch_residual_sumsq(L, partials, r_out, 1.0 / (hl * hl), st);
+    launch_reduce_final(partials, sums + 2, st);
+    launch_residual_norms(sums, norms_out, st);
+    HIP_TRY(hipGetLastError());
+    return NDGP_OK;
+}
+
 ndgp_status force_impl(const ndgp_grid *grid, const double *const phi[], double *const force[],
                        hipStream_t st) {
     if (!grid) return fail(NDGP_EINVAL, "grid must not be NULL");
@@ -1435,6 +1508,15 @@ ndgp_status ndgp_residual(const ndgp_grid *grid, const ndgp_params *params, int3
     return guarded([&] {
         return residual_impl(grid, params, level, delta, phi, r_out, rel_norm_out, workspace,
                              workspace_bytes, stream);
+    });
+}
+
+ndgp_status ndgp_residual_noalloc(const ndgp_grid *grid, const ndgp_params *params,
+                                  int32_t level, const double *const delta[1 + NDGP_MAX_PATCHES],
+                                  const double *phi, double *r_out, double *norms_out,
+                                  hipStream_t stream) {
+    return guarded([&] {
+        return residual_noalloc_impl(grid, params, level, delta, phi, r_out, norms_out, stream);
     });
 }
 

@@ -137,6 +137,9 @@ def lib():
         L.ndgp_residual.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int32,
                                     arr3, vp, vp, ctypes.POINTER(ctypes.c_double), vp,
                                     ctypes.c_size_t, vp]
+        L.ndgp_residual_noalloc.restype = ctypes.c_int
+        L.ndgp_residual_noalloc.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params),
+                                            ctypes.c_int32, arr3, vp, vp, vp, vp]
         L.ndgp_force.restype = ctypes.c_int
         L.ndgp_force.argtypes = [ctypes.POINTER(_Grid), arr3, arr3, vp]
         L.ndgp_plan_create.restype = ctypes.c_int
@@ -432,6 +435,32 @@ def residual(grid: Grid, params: Params, delta: Sequence[torch.Tensor], phi: tor
                                _dev(phi, shape, "phi"), r.data_ptr() if r is not None else None,
                                ctypes.byref(rel), ws.data_ptr(), ws.numel(), _stream(stream)))
     return r, rel.value
+
+
+NOALLOC_MAX_CELLS = 128**3
+
+
+def residual_noalloc(grid: Grid, params: Params, delta: Sequence[torch.Tensor], phi: torch.Tensor,
+                     level: int = 0, r_out: Optional[torch.Tensor] = None,
+                     norms: Optional[torch.Tensor] = None, stream=None):
+    """As ``residual`` without a workspace and without blocking: the library's
+    static device scratch holds the source and the reduction partials.
+    ``norms`` (3 float64 on the device) receives sum r^2, sum S^2 (cell units)
+    and the relative norm.  Returns (r_out, norms); allocates nothing itself
+    when both are given."""
+    g, p = grid._c(), params._c()
+    n = grid.level_n(level)
+    shape = (n,) * 3 if level == 0 else (n + 2,) * 3
+    dptr = [_dev(delta[0], (grid.n,) * 3, "delta[0]")] + [None] * MAX_PATCHES
+    if level:
+        dptr[level] = _dev(delta[level], (n,) * 3, f"delta[{level}]")
+    if norms is None:
+        norms = torch.empty(3, dtype=torch.float64, device=phi.device)
+    _check(lib().ndgp_residual_noalloc(ctypes.byref(g), ctypes.byref(p), level, _arr3(dptr),
+                                       _dev(phi, shape, "phi"),
+                                       _dev(r_out, (n,) * 3, "r_out") if r_out is not None
+                                       else None, _dev(norms, (3,), "norms"), _stream(stream)))
+    return r_out, norms
 
 
 def force(grid: Grid, phi: Sequence[torch.Tensor], stream=None) -> list:

@@ -677,15 +677,15 @@ def test_damped_step_safeguard_on_extreme_source(prec):
 # the branches of the per-cell root (Sec. III.A, Eq. newton)
 
 @pytest.mark.parametrize("prec", [ndgp.PREC_FP64, ndgp.PREC_MIXED])
-def test_non_elliptic_cells_are_held_and_the_answer_matches_oracle(prec):
+def test_cells_past_their_vertex_take_the_elliptic_root_and_match_oracle(prec):
     """A warm start far from the answer (white noise of 1.6e-8 on 1 Mpc/h
-    cells at r_cH0 = 5) makes the linearised operator non-elliptic at about
-    10% of the cells on the first visit (dL/dphi of the cell equation has the
-    wrong sign there); those cells keep their value until their neighbours
-    have moved.  The solve still reaches the unique elliptic solution, the
-    oracle's from its own nested start."""
+    cells at r_cH0 = 5) puts about 10% of the cells past the vertex of their
+    own quadratic on the first visit (dL/dphi of the cell equation has the
+    non-elliptic sign there); those cells move to the root on the elliptic
+    side.  The solve reaches the unique elliptic solution, the oracle's from
+    its own nested start."""
     n, rc = 32, 5.0
-    say(f"held cells precision={prec}")
+    say(f"past-vertex cells precision={prec}")
     f = synth.make_field(n, 2.0, 61, n_tophats=4)
     h = ndgp.cell_size(32.0, n)
     phio, _ = oracle_periodic(f.delta, h, rc)

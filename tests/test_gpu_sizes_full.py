@@ -13,8 +13,8 @@ the benchmark times:
     every level relaxed to stagnation): <= 1e-11 per level;
   * 128^3, mixed precision at 1e-10 (the FP32 one-launch sweep, tiled
     restriction and block prolongation sizes): <= 1e-8;
-  * 512^3 lognormal sigma 2.5, r_cH0 = 5, mixed precision at 1e-10: <= 1e-8,
-    and FP64 at 1e-10: <= 1e-8 as well.
+  * 512^3 lognormal sigma 2.5 (delta up to ~1e5), mixed precision at 1e-10
+    for r_cH0 = 1 and 5, and FP64 at 1e-10 for r_cH0 = 1: <= 1e-8.
 """
 from __future__ import annotations
 
@@ -160,13 +160,16 @@ def test_256_with_two_patches_full_mode_matches_oracle():
         assert e <= PHI_TOL
 
 
-@pytest.mark.parametrize("prec", [ndgp.PREC_MIXED, ndgp.PREC_FP64])
-def test_512_rc5_at_configured_tolerance_matches_oracle(prec):
-    n, box, rc = 512, 512.0, 5.0
+@pytest.mark.parametrize("rc,prec", [(1.0, ndgp.PREC_MIXED), (1.0, ndgp.PREC_FP64),
+                                     (5.0, ndgp.PREC_MIXED)])
+def test_512_at_configured_tolerance_matches_oracle(rc, prec):
+    n, box = 512, 512.0
+    if ("phi", n, box, 2.5, 1515, 0, 1.0, 1e-12) in _cache and rc != 1.0:
+        del _cache[("phi", n, box, 2.5, 1515, 0, 1.0, 1e-12)]  # one 512^3 answer held at a time
     phio = oracle_phi(n, box, 2.5, 1515, 0, rc, tol=1e-12)
     f = field(n, 2.5, 1515, 0)
     phig, rep = gpu_phi(n, box, f, rc, tol=1e-10, precision=prec)
     e = rel(phig, phio)
-    say(f"512^3 rc=5 precision={prec} at 1e-10: cycles={rep.cycles[0]} "
+    say(f"512^3 rc={rc} precision={prec} at 1e-10: cycles={rep.cycles[0]} "
         f"t={rep.t_total_ms:.1f} ms rel err {e:.2e}")
     assert rep.status == 0 and rep.rel_res[0] <= 1e-10 and e <= MIXED_TOL
