@@ -58,7 +58,7 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("ndgp_kernels.hip", "ndgp_internal.h"):
+    for f in ("ndgp_kernels.hip", "ndgp_internal.h", "ndgp_device.h"):
         with open(os.path.join(ROOT, "paper_1511_08200_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -104,6 +104,9 @@ typedef enum {
                               LDS-tiled restriction on large levels and no
                               one-workgroup bottom of the V-cycle on levels of
                               at most 16^3 cells; same results, bit for bit */
+#define NDGP_DAMPED 8u     /* relax every level with the damped step u + 0.8 du from
+                              the start (the mode the divergence safeguard restarts
+                              in; ndgp_report.damped_from = 1 on relaxed levels) */
 
 typedef struct {
     int32_t n;             /* domain cells per side: power of two, 8..1024              */
@@ -131,7 +134,7 @@ typedef struct {
     int32_t n_levels;  /* multigrid levels of the domain grid (0 = down to 8^3)         */
     int32_t mode;      /* ndgp_mode                                                    */
     int32_t precision; /* ndgp_precision                                               */
-    uint32_t flags;    /* NDGP_WARM_START | NDGP_PROFILE | NDGP_TWO_PASS               */
+    uint32_t flags;    /* NDGP_WARM_START | NDGP_PROFILE | NDGP_TWO_PASS | NDGP_DAMPED */
     int32_t trunc_level; /* NDGP_MODE_TRUNCATED: first interpolated refinement level,
                             1..n_patch+1; ignored by the other modes                    */
 } ndgp_params;

@@ -188,7 +188,7 @@ bool resolve(const ndgp_grid *g, const ndgp_params *p, Cfg &c, std::string &why)
         why = "unknown precision";
         return false;
     }
-    if (p->flags & ~(NDGP_WARM_START | NDGP_PROFILE | NDGP_TWO_PASS)) {
+    if (p->flags & ~(NDGP_WARM_START | NDGP_PROFILE | NDGP_TWO_PASS | NDGP_DAMPED)) {
         why = "unknown flag bits";
         return false;
     }
@@ -729,6 +729,10 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     launch_source(delta[0], cells0, P.scal + 0, 1.0 / (double)cells0, c.fsrc * c.h * c.h,
                   P.base[0].s, st);
     run.enqueue_sum(P.base[0].s, cells0, true, 1);
+    if (c.flags & NDGP_DAMPED) { // the damped step from the start
+        set_step(P.base, c.prec == NDGP_PREC_MIXED ? P.base32 : nullptr, c.nl, kDampedStep);
+        R.damped_from[0] = 1;
+    }
     if (!(c.flags & NDGP_WARM_START)) run.nested_start(P.base, c.nl);
     run.enqueue_residual(P.base, P.base32);
     run.read_scalars(P.scal, 3);
@@ -809,6 +813,10 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         if (sn2 == 0.0) sn2 = std::max(run.residual_sumsq(H[0]), 1e-300);
         double rel = 0.0;
         bool restart = false;
+        if (c.flags & NDGP_DAMPED) {
+            set_step(H, nullptr, c.pnl[q], kDampedStep);
+            R.damped_from[q + 1] = 1;
+        }
         ndgp_status sq = run.drive(H, c.pnl[q], sn2, R.cycles[q + 1], rel, nullptr, nullptr,
                                    &restart);
         if (restart) { // the safeguard: from the interpolated guess again, damped
@@ -1235,6 +1243,11 @@ ndgp_status plan_create_impl(const ndgp_grid *grid, const ndgp_params *params,
         launch_source(delta[0], cells0, pl->P.scal + 0, 1.0 / (double)cells0, c.fsrc * c.h * c.h,
                       pl->P.base[0].s, st);
         run.enqueue_sum(pl->P.base[0].s, cells0, true, 1);
+        if (c.flags & NDGP_DAMPED) {
+            set_step(pl->P.base, c.prec == NDGP_PREC_MIXED ? pl->P.base32 : nullptr, c.nl,
+                     kDampedStep);
+            pl->R.damped_from[0] = 1;
+        }
         if (!(c.flags & NDGP_WARM_START)) run.nested_start(pl->P.base, c.nl);
         run.enqueue_residual(pl->P.base, pl->P.base32);
         HIP_TRY(hipMemcpyAsync(pl->slot, pl->P.scal, 3 * sizeof(double), hipMemcpyDeviceToHost,
@@ -1305,6 +1318,7 @@ ndgp_status plan_poll_impl(ndgp_plan *pl, int32_t *done, ndgp_report *rep) {
             return NDGP_OK;
         }
         pl->mon = CycleMonitor{c.tol, c.maxc};
+        pl->mon.damped = (c.flags & NDGP_DAMPED) != 0;
         pl->mon.start(std::sqrt(pl->slot[2] / pl->snorm2));
     } else if (pl->restarting) { // the damped nested start has completed
         pl->restarting = false;

@@ -28,6 +28,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 WARM_START = 1
 PROFILE = 2
 TWO_PASS = 4
+DAMPED = 8
 MAX_PATCHES = 4
 ABI_VERSION = 3
 HIST_LEN = 64
@@ -256,6 +257,7 @@ class Params:
     warm_start: bool = False
     profile: bool = False
     two_pass: bool = False
+    damped: bool = False
 
     def _c(self) -> _Params:
         p = _Params()
@@ -264,7 +266,7 @@ class Params:
         p.max_cycles, p.nu1, p.nu2, p.n_levels = self.max_cycles, self.nu1, self.nu2, self.n_levels
         p.mode, p.precision, p.trunc_level = self.mode, self.precision, self.trunc_level
         p.flags = ((WARM_START if self.warm_start else 0) | (PROFILE if self.profile else 0)
-                   | (TWO_PASS if self.two_pass else 0))
+                   | (TWO_PASS if self.two_pass else 0) | (DAMPED if self.damped else 0))
         return p
 
 

@@ -114,9 +114,9 @@ def test_workspace_bytes_and_validation(L):
     g, p = _args(max_cycles=5000)
     assert L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) == 0
     # every documented flag is accepted, any other bit refused
-    g, p = _args(flags=ndgp.WARM_START | ndgp.PROFILE | ndgp.TWO_PASS)
+    g, p = _args(flags=ndgp.WARM_START | ndgp.PROFILE | ndgp.TWO_PASS | ndgp.DAMPED)
     assert L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) > 0
-    g, p = _args(flags=8)
+    g, p = _args(flags=16)
     assert L.ndgp_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) == 0
     assert b"flag" in L.ndgp_last_error()
     # patch 2 must sit inside patch 1 with margin

@@ -83,31 +83,56 @@ def test_plan_destroyed_in_flight_leaves_later_plans_exact():
         plan.close()
 
 
-@pytest.mark.parametrize("precision", [ndgp.PREC_FP64, ndgp.PREC_MIXED])
-def test_plan_restart_safeguard_equals_blocking_solve(precision):
-    """The divergent extreme request of the serving trace (sigma_ln 2.47,
-    r_cH0 = 5, 1 Mpc/h cells): a plan restarts with the damped step at the
-    same cycle as the blocking solve and gives the same bits."""
-    say(f"plan restart precision={precision}")
-    n, rc, sigma, seed = 256, 5.0, 2.4694042826895837, 100881
-    d = synth.lognormal_delta_torch(n, sigma, seed, device="cuda")
-    grid = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n))
-    params = ndgp.Params(rc=rc, tol=1e-10, precision=precision, max_cycles=60)
-    phi_a, rep_a = ndgp.solve(grid, params, [d])
-    plan = ndgp.Plan(grid, params, [d])
+def _plan_to_end(grid, params, delta):
+    plan = ndgp.Plan(grid, params, delta)
     steps = 0
     while not plan.poll():
         plan.step()
         steps += 1
         assert steps < 10**7
     torch.cuda.synchronize()
+    return plan
+
+
+@pytest.mark.parametrize("precision", [ndgp.PREC_FP64, ndgp.PREC_MIXED])
+def test_plan_damped_and_safeguard_equal_blocking_solve(precision):
+    """Plans follow the blocking solve bit for bit through the damped step:
+    (a) NDGP_DAMPED on the extreme request of the serving trace (sigma_ln 2.47,
+    r_cH0 = 5, 1 Mpc/h cells); (b) the divergence safeguard on a source with
+    unphysical voids (delta = -40 in three cells, no elliptic solution near
+    them), where the residual grows and the solve restarts with the damped step
+    before giving up: same status, cycles, restart cycle, history and field."""
+    say(f"plan damped precision={precision}")
+    n, rc, sigma, seed = 256, 5.0, 2.4694042826895837, 100881
+    d = synth.lognormal_delta_torch(n, sigma, seed, device="cuda")
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n))
+    params = ndgp.Params(rc=rc, tol=1e-10, precision=precision, max_cycles=60, damped=True)
+    phi_a, rep_a = ndgp.solve(grid, params, [d])
+    plan = _plan_to_end(grid, params, [d])
     rep_b = plan.report
-    say(f"  cycles={rep_b.cycles[0]} damped_from={rep_b.damped_from[0]}")
-    assert rep_b.status == 0 and rep_a.damped_from[0] > 0
-    assert rep_b.damped_from == rep_a.damped_from and rep_b.cycles == rep_a.cycles
-    assert rep_b.history == rep_a.history
-    assert rep_b.fallbacks == rep_a.fallbacks
+    say(f"  damped: cycles={rep_b.cycles[0]} damped_from={rep_b.damped_from[0]}")
+    assert rep_b.status == 0 and rep_a.damped_from[0] == 1 == rep_b.damped_from[0]
+    assert rep_b.cycles == rep_a.cycles and rep_b.history == rep_a.history
     assert torch.equal(phi_a[0], plan.phi[0])
+    plan.close()
+    # (b) the safeguard restart
+    m = 32
+    v = synth.make_field(m, 2.0, 61, n_tophats=4).delta.copy()
+    for (i, j, k) in ((5, 6, 7), (20, 21, 3), (11, 27, 30)):
+        v[k, j, i] = -40.0
+    dv = torch.from_numpy(v).to("cuda")
+    gv = ndgp.Grid(n=m, h=ndgp.cell_size(float(m), m))
+    pv = ndgp.Params(rc=rc, tol=1e-10, precision=precision, max_cycles=40)
+    phi_a, rep_a = ndgp.solve(gv, pv, [dv], check=False)
+    plan = _plan_to_end(gv, pv, [dv])
+    rep_b = plan.report
+    say(f"  void: status={rep_a.status} cycles={rep_a.cycles[0]} "
+        f"damped_from={rep_a.damped_from[0]} fallbacks={rep_a.fallbacks}")
+    assert rep_a.status == ndgp.NDGP_ENOCONV == rep_b.status
+    assert rep_a.damped_from[0] > 0
+    assert rep_b.damped_from == rep_a.damped_from and rep_b.cycles == rep_a.cycles
+    assert np.array_equal(np.array(rep_b.history), np.array(rep_a.history), equal_nan=True)
+    assert np.array_equal(plan.phi[0].cpu().numpy(), phi_a[0].cpu().numpy(), equal_nan=True)
     plan.close()
 
 
