@@ -449,6 +449,82 @@ ndgp_status ndgp_plan_step(ndgp_plan *plan);
 void ndgp_plan_destroy(ndgp_plan *plan);
 
 /*
+ * Adaptive refinement (Sec. IV.A: a cell is refined when it holds more than
+ * N_ref particles; the refinements form a tree of patches, several per level).
+ *
+ * ndgp_box            one cubic refinement patch of a tree: its parent (-1 =
+ *                     the domain, else the index of an earlier box), cells per
+ *                     side (power of two, 8..512, at most twice its parent's)
+ *                     and lower corner in parent cells.  Children of the
+ *                     domain may wrap around it; a child of a box must lie
+ *                     inside it with room for the interpolation stencils of
+ *                     every multigrid level of the child (the rule of
+ *                     ndgp_grid's nested patches).  Children of one parent
+ *                     must not overlap (they may touch).
+ * ndgp_refine_boxes   clusters the refinement flags of one level into cubic
+ *                     patches by the point-clustering algorithm of Berger &
+ *                     Rigoutsos (IEEE Trans. Syst. Man Cybern. 21, 1991):
+ *                     bounding box of the flagged cells, accepted when at least
+ *                     `efficiency` of its cells are flagged, otherwise split at
+ *                     a hole of the flag signatures, else at the strongest sign
+ *                     change of their second difference, else in the middle of
+ *                     its longest side; a periodic level is cut open along the
+ *                     widest empty slab of each axis first.  Each cluster then
+ *                     becomes the smallest power-of-two cube of child cells
+ *                     (refinement ratio 2, at least 8 cells) centred on it;
+ *                     cubes that overlap are merged into one around both
+ *                     clusters until none do.  On a patch parent the cubes are
+ *                     kept inside it with the stencil room above: flagged cells
+ *                     closer to its boundary than that stay unrefined.
+ *   flags             the level's flags (natural n^3 bytes, nonzero = refine),
+ *                     DEVICE memory if flags_on_device, else HOST memory (the
+ *                     clustering itself runs on the host)
+ *   n, periodic       the level: the domain (periodic) or a patch
+ *   parent_index      written into every box's parent field
+ *   efficiency        in (0, 1]; min_width >= 1: clusters no wider than this
+ *                     (parent cells) are not split further
+ *   boxes, max_boxes  HOST output; NDGP_ENOMEM if more boxes are needed
+ *   n_boxes           HOST output: boxes written (0 if nothing is flagged)
+ * ndgp_solve_amr      the domain level as ndgp_solve with n_patch = 0, then
+ *                     every box in list order from its solved (or interpolated)
+ *                     parent: ghost shell and initial guess interpolated, then
+ *                     relaxed with its own FAS multigrid (NDGP_MODE_FULL), or
+ *                     kept at the interpolated field (NDGP_MODE_INTERPOLATED;
+ *                     NDGP_MODE_TRUNCATED interpolates the boxes of tree depth
+ *                     trunc_level and deeper).  Mixed precision applies to the
+ *                     domain level.  delta[1 + b] is box b's density contrast
+ *                     (n^3, measured against the domain's mean density as for
+ *                     ndgp_solve; may be NULL for interpolated boxes) and
+ *                     phi[1 + b] its padded solution ((n+2)^3).  box_report
+ *                     (HOST, n_boxes entries, optional) receives each box's
+ *                     tree depth, V-cycles, restart cycle and relative residual
+ *                     (-1 if interpolated).  Workspace: ndgp_amr_workspace_bytes.
+ */
+#define NDGP_AMR_MAX_BOXES 256
+typedef struct {
+    int32_t parent;
+    int32_t n;
+    int32_t origin[3];
+} ndgp_box;
+typedef struct {
+    int32_t depth;
+    int32_t cycles;
+    int32_t damped_from;
+    double rel_res;
+} ndgp_box_report;
+ndgp_status ndgp_refine_boxes(const unsigned char *flags, int32_t flags_on_device, int32_t n,
+                              int32_t periodic, int32_t parent_index, double efficiency,
+                              int32_t min_width, ndgp_box *boxes, int32_t max_boxes,
+                              int32_t *n_boxes, hipStream_t stream);
+size_t ndgp_amr_workspace_bytes(const ndgp_grid *grid, const ndgp_params *params,
+                                const ndgp_box *boxes, int32_t n_boxes);
+ndgp_status ndgp_solve_amr(const ndgp_grid *grid, const ndgp_params *params,
+                           const ndgp_box *boxes, int32_t n_boxes, const double *const *delta,
+                           double *const *phi, void *workspace, size_t workspace_bytes,
+                           hipStream_t stream, ndgp_report *report,
+                           ndgp_box_report *box_report);
+
+/*
  * Norms for comparing two fields, e.g. the force of the interpolated mode with
  * the fully relaxed one (the error of Sec. III.B, Eqs. errors-errors2):
  *   out[0] = sum (a - b)^2,  out[1] = sum a^2,  out[2] = sum b^2

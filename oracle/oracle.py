@@ -327,3 +327,31 @@ def solve_problem(p: Problem, interpolated: bool = False, tol: float = 0.0,
     if cellwise is not None:
         return phis, infos, masks
     return phis, infos
+
+
+def solve_tree(delta, h: float, rc: float, beta: float, boxes, a: float = 1.0,
+               omega_m: float = 0.3, interpolated: bool = False, trunc_depth=None,
+               tol: float = 0.0, max_cycles: int = 200):
+    """Sec. III.A's order on a tree of refinements (several per level, Sec.
+    IV.A): the periodic domain, then every box from its own parent, in list
+    order.  ``boxes``: (parent, n, origin) per box, parent -1 for the domain,
+    origin in parent cells; ``delta``: [domain, box 0, ...].  A box of tree
+    depth d has cells h / 2^d.  Boxes are interpolated (Sec. III.B) when
+    ``interpolated`` or their depth is at least ``trunc_depth``.  Returns
+    (phis, infos): phis[0] natural zero-mean, phis[1:] padded."""
+    al = alpha(rc, beta, a)
+    S0, mean = source(delta[0], omega_m, a, beta)
+    phi0, info0 = solve_periodic(S0, h, al, tol=tol, max_cycles=max_cycles)
+    phis, infos, depth = [phi0], [info0], []
+    for b, (parent, n, origin) in enumerate(boxes):
+        d = 1 if parent < 0 else depth[parent] + 1
+        depth.append(d)
+        interp = interpolated or (trunc_depth is not None and d >= trunc_depth)
+        S = (np.zeros((n, n, n)) if interp
+             else source_shift(delta[1 + b], mean, omega_m, a, beta))
+        par = phis[0] if parent < 0 else phis[1 + parent]
+        ph, inf = solve_patch(S, h / 2**d, al, par, parent < 0, origin, interp_only=interp,
+                              tol=tol, max_cycles=max_cycles)
+        phis.append(ph)
+        infos.append(inf)
+    return phis, infos

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libndgp.so")
-SOURCES = ["ndgp_kernels.hip", "ndgp_mixed.hip", "ndgp_solver.hip", "ndgp_screening.hip",
+SOURCES = ["ndgp_kernels.hip", "ndgp_mixed.hip", "ndgp_solver.hip", "ndgp_screening.hip", "ndgp_amr.hip",
            "ndgp_stats.hip", "ndgp_particles.hip"]
 ARCH = os.environ.get("NDGP_OFFLOAD_ARCH", "gfx950")
 

@@ -2,6 +2,8 @@
 // translation units (kernels, host driver).  Not part of the public ABI.
 #pragma once
 
+#include <cmath>
+
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -44,6 +46,28 @@ struct Level {
         return periodic ? cells() : (size_t)(n + 2) * (n + 2) * (n + 2);
     }
 };
+
+// levels of a hierarchy that coarsens by 2 down to <= 8 cells per side
+inline int default_levels(int n) {
+    int l = 1;
+    while ((n >> (l - 1)) > kCoarsestMax) ++l;
+    return l;
+}
+
+// Can every multigrid level (nlev of them) of a Dirichlet child of nc cells
+// with its lower corner at `origin` parent cells (along one axis) interpolate
+// its ghost shell (and, on the finest level, its interior) from a padded
+// parent of np cells?  Level m's cells are 2^m / 2 parent cells wide.
+inline bool child_fits_axis(int np, int origin, int nc, int nlev) {
+    for (int m = 0; m < nlev; ++m) {
+        const int nm = nc >> m;
+        const double q = std::ldexp(1.0, m - 1);
+        const double xmin = origin + (-1 + 0.5) * q - 0.5;
+        const double xmax = origin + (nm + 0.5) * q - 0.5;
+        if (std::floor(xmin) < -1.0 || std::floor(xmax) + 1.0 > (double)np) return false;
+    }
+    return true;
+}
 
 // Where a child box sits in its parent: lower corner in parent cells and a
 // cell size of 2^m / 2 parent cells.

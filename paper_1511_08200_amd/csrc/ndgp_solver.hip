@@ -120,25 +120,9 @@ struct Cfg {
     int nlev(int level) const { return level == 0 ? n : pn[level - 1]; }
 };
 
-// levels of a hierarchy that coarsens by 2 down to <= 8 cells per side
-int default_levels(int n) {
-    int l = 1;
-    while ((n >> (l - 1)) > kCoarsestMax) ++l;
-    return l;
-}
-
-// Can every multigrid level of a Dirichlet child interpolate its ghost shell
-// (and, for m = 0, its interior) from a padded parent of np cells?
 bool child_fits(int np, const int origin[3], int nc, int nlev) {
-    for (int m = 0; m < nlev; ++m) {
-        const int nm = nc >> m;
-        const double q = std::ldexp(1.0, m - 1);
-        for (int a = 0; a < 3; ++a) {
-            const double xmin = origin[a] + (-1 + 0.5) * q - 0.5;
-            const double xmax = origin[a] + (nm + 0.5) * q - 0.5;
-            if (std::floor(xmin) < -1.0 || std::floor(xmax) + 1.0 > (double)np) return false;
-        }
-    }
+    for (int a = 0; a < 3; ++a)
+        if (!child_fits_axis(np, origin[a], nc, nlev)) return false;
     return true;
 }
 
@@ -667,6 +651,57 @@ struct Runner {
     }
 };
 
+// One refinement relaxed from its solved parent (Sec. III.A).  The caller has
+// interpolated the parent into the patch's field (H[0].phi, interior and ghost
+// shell) and set any cell masks; here the ghost shells of the other arrays of
+// every level of the patch's own hierarchy are interpolated too, the source
+// S = Omega_m (delta - mean)/(a beta) is formed against the domain's mean
+// (whose sum sits in P.scal[0]), and FAS V-cycles run to the tolerance, with
+// the divergence safeguard.
+struct PatchOutcome {
+    int cycles = 0;
+    double rel = 0.0;
+    int damped_from = 0;
+    ndgp_status status = NDGP_OK;
+};
+
+PatchOutcome relax_patch(Runner &run, Level *H, int nlev, const double *parent, int npar,
+                         bool parent_periodic, const int origin[3], int m, double hq,
+                         const double *delta, double inv_cells0) {
+    const Cfg &c = run.P.c;
+    hipStream_t st = run.st;
+    PatchOutcome out;
+    ChildBox b0{{origin[0], origin[1], origin[2]}, 0, m};
+    launch_interpolate(parent, npar, parent_periodic, b0, H[0].alt, true, st);
+    for (int l = 1; l < nlev; ++l) {
+        ChildBox bm{{origin[0], origin[1], origin[2]}, l, m >> l};
+        launch_interpolate(parent, npar, parent_periodic, bm, H[l].phi, true, st);
+        launch_interpolate(parent, npar, parent_periodic, bm, H[l].alt, true, st);
+        launch_interpolate(parent, npar, parent_periodic, bm, H[l].hat, true, st);
+    }
+    const size_t cq = (size_t)m * m * m;
+    launch_source(delta, cq, run.P.scal + 0, inv_cells0, c.fsrc * hq * hq, H[0].s, st);
+    double sn2 = run.sum(H[0].s, cq, true, 1);
+    if (!std::isfinite(sn2)) {
+        out.status = fail(NDGP_EINVAL, "a patch density has non-finite values");
+        return out;
+    }
+    if (sn2 == 0.0) sn2 = std::max(run.residual_sumsq(H[0]), 1e-300);
+    bool restart = false;
+    if (c.flags & NDGP_DAMPED) {
+        set_step(H, nullptr, nlev, kDampedStep);
+        out.damped_from = 1;
+    }
+    out.status = run.drive(H, nlev, sn2, out.cycles, out.rel, nullptr, nullptr, &restart);
+    if (restart) { // the safeguard: from the interpolated guess again, damped
+        set_step(H, nullptr, nlev, kDampedStep);
+        out.damped_from = out.cycles + 1;
+        launch_interpolate(parent, npar, parent_periodic, b0, H[0].phi, false, st);
+        out.status = run.drive(H, nlev, sn2, out.cycles, out.rel, nullptr, nullptr, nullptr);
+    }
+    return out;
+}
+
 ndgp_status check_arrays(const Cfg &c, const double *const *delta, double *const *phi) {
     if (!delta || !phi || !delta[0] || !phi[0])
         return fail(NDGP_EINVAL, "delta[0] and phi[0] must not be NULL");
@@ -779,6 +814,13 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     R.phi_mean = psum / (double)cells0;
     launch_shift_by_mean(phi[0], cells0, P.scal + 3, st);
 
+    if (psi) // the Newtonian potentials of the parents must be finite everywhere
+        for (int q = 0; q < c.nrelax; ++q) {
+            const size_t np3 = q == 0 ? cells0 : (size_t)(c.pn[q - 1] + 2) * (c.pn[q - 1] + 2) *
+                                                     (c.pn[q - 1] + 2);
+            if (!std::isfinite(run.sum(psi[q], np3, false, 5)))
+                return fail(NDGP_EINVAL, "psi[" + std::to_string(q) + "] has non-finite values");
+        }
     for (int q = 0; q < c.np; ++q) {
         const bool parent_periodic = q == 0;
         const double *parent = phi[q];
@@ -798,33 +840,14 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
                 H[m].mask = P.mask[q][m];
             }
         }
-        launch_interpolate(parent, npar, parent_periodic, b0, H[0].alt, true, st);
-        for (int m = 1; m < c.pnl[q]; ++m) {
-            ChildBox bm{{c.po[q][0], c.po[q][1], c.po[q][2]}, m, c.pn[q] >> m};
-            launch_interpolate(parent, npar, parent_periodic, bm, H[m].phi, true, st);
-            launch_interpolate(parent, npar, parent_periodic, bm, H[m].alt, true, st);
-            launch_interpolate(parent, npar, parent_periodic, bm, H[m].hat, true, st);
-        }
-        const size_t cq = (size_t)c.pn[q] * c.pn[q] * c.pn[q];
-        const double hq = c.hl(q + 1);
-        launch_source(delta[q + 1], cq, P.scal + 0, 1.0 / (double)cells0, c.fsrc * hq * hq,
-                      H[0].s, st);
-        double sn2 = run.sum(H[0].s, cq, true, 1);
-        if (sn2 == 0.0) sn2 = std::max(run.residual_sumsq(H[0]), 1e-300);
-        double rel = 0.0;
-        bool restart = false;
-        if (c.flags & NDGP_DAMPED) {
-            set_step(H, nullptr, c.pnl[q], kDampedStep);
-            R.damped_from[q + 1] = 1;
-        }
-        ndgp_status sq = run.drive(H, c.pnl[q], sn2, R.cycles[q + 1], rel, nullptr, nullptr,
-                                   &restart);
-        if (restart) { // the safeguard: from the interpolated guess again, damped
-            set_step(H, nullptr, c.pnl[q], kDampedStep);
-            R.damped_from[q + 1] = R.cycles[q + 1] + 1;
-            launch_interpolate(parent, npar, parent_periodic, b0, phi[q + 1], false, st);
-            sq = run.drive(H, c.pnl[q], sn2, R.cycles[q + 1], rel, nullptr, nullptr, nullptr);
-        }
+        const PatchOutcome po = relax_patch(run, H, c.pnl[q], parent, npar, parent_periodic,
+                                            c.po[q], c.pn[q], c.hl(q + 1), delta[q + 1],
+                                            1.0 / (double)cells0);
+        if (po.status == NDGP_EINVAL) return po.status;
+        const double rel = po.rel;
+        const ndgp_status sq = po.status;
+        R.cycles[q + 1] = po.cycles;
+        R.damped_from[q + 1] = po.damped_from;
         R.rel_res[q + 1] = rel;
         if (sq != NDGP_OK && status == NDGP_OK) status = sq;
     }
@@ -846,6 +869,234 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (rep) *rep = R;
     return status;
+}
+
+// ------------------------------------------------------------------------
+// adaptive refinement: a tree of cubic boxes, several per level (Sec. IV.A)
+
+struct AmrTree {
+    int nb = 0;
+    int parent[NDGP_AMR_MAX_BOXES] = {};
+    int n[NDGP_AMR_MAX_BOXES] = {};
+    int depth[NDGP_AMR_MAX_BOXES] = {};
+    int nlev[NDGP_AMR_MAX_BOXES] = {};
+    int origin[NDGP_AMR_MAX_BOXES][3] = {};
+    bool relaxed[NDGP_AMR_MAX_BOXES] = {};
+    int max_relaxed_n = 0; // largest relaxed box (0: none)
+};
+
+// [o1, o1 + w1) and [o2, o2 + w2) intersect, on a ring of `period` cells if
+// period > 0
+bool spans_overlap(int o1, int w1, int o2, int w2, int period) {
+    if (period <= 0) return o1 < o2 + w2 && o2 < o1 + w1;
+    const int d12 = ((o2 - o1) % period + period) % period;
+    const int d21 = ((o1 - o2) % period + period) % period;
+    return d12 < w1 || d21 < w2;
+}
+
+bool resolve_tree(const ndgp_grid *grid, const ndgp_params *params, const ndgp_box *boxes,
+                  int nb, Cfg &c, AmrTree &T, std::string &why) {
+    if (!grid || !params) {
+        why = "grid and params must not be NULL";
+        return false;
+    }
+    if (grid->n_patch != 0) {
+        why = "the tree's boxes replace ndgp_grid's nested patches: n_patch must be 0";
+        return false;
+    }
+    ndgp_params p0 = *params; // the domain level's own checks
+    p0.mode = NDGP_MODE_FULL;
+    p0.trunc_level = 0;
+    if (!resolve(grid, &p0, c, why)) return false;
+    c.mode = params->mode;
+    if (c.mode == NDGP_MODE_TRUNCATED && params->trunc_level < 1) {
+        why = "trunc_level must be >= 1";
+        return false;
+    }
+    if (nb < 0 || nb > NDGP_AMR_MAX_BOXES || (nb > 0 && !boxes)) {
+        why = "n_boxes must be in [0, NDGP_AMR_MAX_BOXES] with a box list";
+        return false;
+    }
+    T.nb = nb;
+    for (int b = 0; b < nb; ++b) {
+        const ndgp_box &x = boxes[b];
+        if (x.parent < -1 || x.parent >= b) {
+            why = "box " + std::to_string(b) + ": parent must be -1 or an earlier box";
+            return false;
+        }
+        const int pn = x.parent < 0 ? c.n : T.n[x.parent];
+        if (!pow2(x.n) || x.n < 8 || x.n > 512 || x.n > 2 * pn) {
+            why = "box " + std::to_string(b) +
+                  ": n must be a power of two in [8, 512] covering at most its parent";
+            return false;
+        }
+        T.parent[b] = x.parent;
+        T.n[b] = x.n;
+        T.depth[b] = x.parent < 0 ? 1 : T.depth[x.parent] + 1;
+        T.nlev[b] = default_levels(x.n);
+        T.relaxed[b] = c.mode == NDGP_MODE_FULL ||
+                       (c.mode == NDGP_MODE_TRUNCATED && T.depth[b] < params->trunc_level);
+        if (T.depth[b] > 20) {
+            why = "tree deeper than 20 levels";
+            return false;
+        }
+        for (int a = 0; a < 3; ++a) {
+            T.origin[b][a] = x.origin[a];
+            if (x.origin[a] < -4 * pn || x.origin[a] > 4 * pn) {
+                why = "box " + std::to_string(b) + ": origin out of range";
+                return false;
+            }
+        }
+        if (x.parent >= 0 && !child_fits(pn, x.origin, x.n, T.relaxed[b] ? T.nlev[b] : 1)) {
+            why = "box " + std::to_string(b) + " must lie inside its parent box with room for "
+                  "the interpolation stencils of its " +
+                  (T.relaxed[b] ? "multigrid levels" : "cells");
+            return false;
+        }
+        for (int q = 0; q < b; ++q) {
+            if (T.parent[q] != x.parent) continue;
+            const int period = x.parent < 0 ? c.n : 0;
+            bool all = true;
+            for (int a = 0; a < 3; ++a)
+                all = all && spans_overlap(T.origin[q][a], T.n[q] / 2, x.origin[a], x.n / 2, period);
+            if (all) {
+                why = "boxes " + std::to_string(q) + " and " + std::to_string(b) +
+                      " (same parent) overlap";
+                return false;
+            }
+        }
+        if (T.relaxed[b]) T.max_relaxed_n = std::max(T.max_relaxed_n, x.n);
+    }
+    return true;
+}
+
+// the arrays the boxes' relaxation shares (one box at a time): reduction
+// scratch, event counters and a hierarchy sized for the largest relaxed box
+struct AmrScratch {
+    double *phi[kMaxLevels] = {}, *alt[kMaxLevels] = {}, *s[kMaxLevels] = {},
+           *hat[kMaxLevels] = {};
+    double *partials = nullptr, *scal = nullptr;
+    unsigned *fallbacks = nullptr;
+};
+
+size_t carve_amr(AmrScratch &A, char *base, int maxn) {
+    Carver cv{base};
+    if (maxn > 0) {
+        const int nl = default_levels(maxn);
+        for (int l = 0; l < nl; ++l) {
+            const size_t m = (size_t)(maxn >> l);
+            const size_t slots = (m + 2) * (m + 2) * (m + 2);
+            A.phi[l] = l ? cv.take<double>(slots) : nullptr;
+            A.alt[l] = cv.take<double>(slots);
+            A.s[l] = cv.take<double>(m * m * m);
+            A.hat[l] = l ? cv.take<double>(slots) : nullptr;
+        }
+    }
+    A.partials = cv.take<double>(kReduceBlocks);
+    A.scal = cv.take<double>(16);
+    A.fallbacks = cv.take<unsigned>(16);
+    return cv.off;
+}
+
+size_t amr_bytes(const Cfg &c, const AmrTree &T) {
+    AmrScratch A;
+    return total_bytes(c) + carve_amr(A, nullptr, T.max_relaxed_n) + 256;
+}
+
+ndgp_status solve_amr_impl(const ndgp_grid *grid, const ndgp_params *params,
+                           const ndgp_box *boxes, int32_t nb, const double *const *delta,
+                           double *const *phi, void *ws, size_t ws_bytes, hipStream_t st,
+                           ndgp_report *rep, ndgp_box_report *brep) {
+    const auto t0 = std::chrono::steady_clock::now();
+    Cfg c;
+    AmrTree T;
+    std::string why;
+    if (!resolve_tree(grid, params, boxes, nb, c, T, why)) return fail(NDGP_EINVAL, why);
+    if (!delta || !phi || !delta[0] || !phi[0])
+        return fail(NDGP_EINVAL, "delta[0] and phi[0] must not be NULL");
+    for (int b = 0; b < nb; ++b) {
+        if (!phi[1 + b]) return fail(NDGP_EINVAL, "phi of every box must not be NULL");
+        if (T.relaxed[b] && !delta[1 + b])
+            return fail(NDGP_EINVAL, "delta of every relaxed box must not be NULL");
+    }
+    const size_t need = amr_bytes(c, T);
+    if (!ws || ws_bytes < need)
+        return fail(NDGP_ENOMEM, "workspace smaller than ndgp_amr_workspace_bytes() = " +
+                                     std::to_string(need));
+    // the domain level: ndgp_solve's path with no patches, in the front of the workspace
+    const size_t dom = total_bytes(c);
+    ndgp_grid g0 = *grid;
+    ndgp_params p0 = *params;
+    p0.mode = NDGP_MODE_FULL;
+    p0.trunc_level = 0;
+    const double *d0[1 + NDGP_MAX_PATCHES] = {delta[0]};
+    double *f0[1 + NDGP_MAX_PATCHES] = {phi[0]};
+    ndgp_report R;
+    std::memset(&R, 0, sizeof(R));
+    ndgp_status status = solve_impl(&g0, &p0, d0, f0, ws, dom, st, &R);
+    if (status != NDGP_OK && status != NDGP_ENOCONV) return status;
+
+    AmrScratch A;
+    carve_amr(A, aligned_base(static_cast<char *>(ws) + dom), T.max_relaxed_n);
+    Plan P;
+    P.c = c;
+    P.partials = A.partials;
+    P.scal = A.scal;
+    P.fallbacks = A.fallbacks;
+    SlotGuard slot;
+    Runner run{P, st, slot.p};
+    const size_t cells0 = (size_t)c.n * c.n * c.n;
+    HIP_TRY(hipMemsetAsync(P.fallbacks, 0, 2 * sizeof(unsigned), st));
+    run.enqueue_sum(delta[0], cells0, false, 0); // the domain's mean for the box sources
+    for (int b = 0; b < nb; ++b) {
+        const int pb = T.parent[b];
+        const bool parent_periodic = pb < 0;
+        const double *parent = pb < 0 ? phi[0] : phi[1 + pb];
+        const int npar = pb < 0 ? c.n : T.n[pb];
+        ChildBox b0{{T.origin[b][0], T.origin[b][1], T.origin[b][2]}, 0, T.n[b]};
+        launch_interpolate(parent, npar, parent_periodic, b0, phi[1 + b], false, st);
+        ndgp_box_report br{T.depth[b], 0, 0, -1.0};
+        if (T.relaxed[b]) {
+            Level H[kMaxLevels];
+            const double hb = c.h / (double)(1 << T.depth[b]);
+            for (int l = 0; l < T.nlev[b]; ++l) {
+                Level &L = H[l];
+                L.n = T.n[b] >> l;
+                L.lg = ilog2(L.n);
+                L.periodic = false;
+                const double hm = hb * (double)(1 << l);
+                L.alpha = c.alpha / (hm * hm);
+                L.phi = l ? A.phi[l] : phi[1 + b];
+                L.alt = A.alt[l];
+                L.s = A.s[l];
+                L.hat = l ? A.hat[l] : nullptr;
+                L.dyn_bc = l > 0;
+            }
+            const PatchOutcome po = relax_patch(run, H, T.nlev[b], parent, npar, parent_periodic,
+                                                T.origin[b], T.n[b], hb, delta[1 + b],
+                                                1.0 / (double)cells0);
+            if (po.status == NDGP_EINVAL) return po.status;
+            if (po.status != NDGP_OK && status == NDGP_OK) status = po.status;
+            br.cycles = po.cycles;
+            br.damped_from = po.damped_from;
+            br.rel_res = po.rel;
+        }
+        if (brep) brep[b] = br;
+    }
+    unsigned fb[2] = {0, 0};
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(slot.p, P.fallbacks, 2 * sizeof(unsigned), hipMemcpyDeviceToHost,
+                           st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::memcpy(fb, slot.p, 2 * sizeof(unsigned));
+    R.fallbacks += (int32_t)fb[0];
+    R.holds += (int32_t)fb[1];
+    R.t_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = R;
+    if (status != NDGP_OK && status != NDGP_ENOCONV) return status;
+    if (status == NDGP_ENOCONV) return fail(NDGP_ENOCONV, "a level did not reach the tolerance");
+    return NDGP_OK;
 }
 
 ndgp_status residual_impl(const ndgp_grid *grid, const ndgp_params *params, int32_t level,
@@ -1522,6 +1773,29 @@ ndgp_status ndgp_residual(const ndgp_grid *grid, const ndgp_params *params, int3
     return guarded([&] {
         return residual_impl(grid, params, level, delta, phi, r_out, rel_norm_out, workspace,
                              workspace_bytes, stream);
+    });
+}
+
+size_t ndgp_amr_workspace_bytes(const ndgp_grid *grid, const ndgp_params *params,
+                                const ndgp_box *boxes, int32_t n_boxes) {
+    Cfg c;
+    AmrTree T;
+    std::string why;
+    if (!resolve_tree(grid, params, boxes, n_boxes, c, T, why)) {
+        g_err = why;
+        return 0;
+    }
+    return amr_bytes(c, T);
+}
+
+ndgp_status ndgp_solve_amr(const ndgp_grid *grid, const ndgp_params *params,
+                           const ndgp_box *boxes, int32_t n_boxes, const double *const *delta,
+                           double *const *phi, void *workspace, size_t workspace_bytes,
+                           hipStream_t stream, ndgp_report *report,
+                           ndgp_box_report *box_report) {
+    return guarded([&] {
+        return solve_amr_impl(grid, params, boxes, n_boxes, delta, phi, workspace,
+                              workspace_bytes, stream, report, box_report);
     });
 }
 

@@ -138,6 +138,17 @@ def lib():
         L.ndgp_residual.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), ctypes.c_int32,
                                     arr3, vp, vp, ctypes.POINTER(ctypes.c_double), vp,
                                     ctypes.c_size_t, vp]
+        L.ndgp_refine_boxes.restype = ctypes.c_int
+        L.ndgp_refine_boxes.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_double, ctypes.c_int32, vp,
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp]
+        L.ndgp_amr_workspace_bytes.restype = ctypes.c_size_t
+        L.ndgp_amr_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params),
+                                               vp, ctypes.c_int32]
+        L.ndgp_solve_amr.restype = ctypes.c_int
+        L.ndgp_solve_amr.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), vp,
+                                     ctypes.c_int32, vp, vp, vp, ctypes.c_size_t, vp,
+                                     ctypes.POINTER(_Report), vp]
         L.ndgp_residual_noalloc.restype = ctypes.c_int
         L.ndgp_residual_noalloc.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params),
                                             ctypes.c_int32, arr3, vp, vp, vp, vp]
@@ -566,25 +577,103 @@ def refine_flags(grid: Grid, delta: Sequence[torch.Tensor], n_particles: int,
     return flags, [int(counts[l]) for l in range(nl)]
 
 
-def suggest_patch_origin(flags_parent: "np.ndarray", m: int, periodic: bool = True):
-    """Integer lower corner (x, y, z) in parent cells of the m-cell patch
-    (m/2 parent cells wide) covering the most flagged parent cells: a static
-    stand-in for refining where the criterion asks (host helper, summed-area
-    table over the flags, with periodic wrap on the domain)."""
+@dataclasses.dataclass
+class Box:
+    """One cubic refinement of a tree (ndgp_box): parent -1 is the domain."""
+    parent: int
+    n: int
+    origin: tuple
+
+
+class _Box(ctypes.Structure):
+    _fields_ = [("parent", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("origin", ctypes.c_int32 * 3)]
+
+
+class _BoxReport(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("damped_from", ctypes.c_int32), ("rel_res", ctypes.c_double)]
+
+
+AMR_MAX_BOXES = 256
+
+
+def refine_boxes(flags, n: int, periodic: bool, parent_index: int = -1,
+                 efficiency: float = 0.7, min_width: int = 4, max_boxes: int = AMR_MAX_BOXES,
+                 stream=None) -> list:
+    """Cubic refinement boxes covering the flagged cells of one level
+    (ndgp_refine_boxes: Berger-Rigoutsos clustering in the library).  ``flags``
+    is a uint8 device tensor or a host array (natural n^3)."""
     import numpy as np
-    f = np.asarray(flags_parent, dtype=np.int64)
-    w = m // 2
-    n = f.shape[0]
-    if periodic:
-        f = np.pad(f, ((0, w), (0, w), (0, w)), mode="wrap")
-    s = f.cumsum(0).cumsum(1).cumsum(2)
-    s = np.pad(s, ((1, 0), (1, 0), (1, 0)))
-    lim = n if periodic else n - w + 1
-    k, j, i = np.meshgrid(np.arange(lim), np.arange(lim), np.arange(lim), indexing="ij")
-    box = (s[k + w, j + w, i + w] - s[k, j + w, i + w] - s[k + w, j, i + w] - s[k + w, j + w, i]
-           + s[k, j, i + w] + s[k, j + w, i] + s[k + w, j, i] - s[k, j, i])
-    kk, jj, ii = np.unravel_index(int(np.argmax(box)), box.shape)
-    return (int(ii), int(jj), int(kk))
+    if isinstance(flags, torch.Tensor) and flags.is_cuda:
+        if flags.dtype != torch.uint8 or not flags.is_contiguous() or flags.numel() != n**3:
+            raise ValueError("flags must be a contiguous uint8 tensor of n^3 cells")
+        ptr, on_dev, keep = flags.data_ptr(), 1, flags
+    else:
+        keep = np.ascontiguousarray(flags, dtype=np.uint8)
+        if keep.size != n**3:
+            raise ValueError("flags must hold n^3 cells")
+        ptr, on_dev = keep.ctypes.data, 0
+    out = (_Box * max(max_boxes, 1))()
+    nb = ctypes.c_int32()
+    st = _stream(stream) if on_dev else None  # host flags need no device
+    _check(lib().ndgp_refine_boxes(ptr, on_dev, n, 1 if periodic else 0, parent_index,
+                                   float(efficiency), int(min_width), out, max_boxes,
+                                   ctypes.byref(nb), st))
+    del keep
+    return [Box(out[b].parent, out[b].n, tuple(out[b].origin)) for b in range(nb.value)]
+
+
+def _boxes_c(boxes):
+    arr = (_Box * max(len(boxes), 1))()
+    for b, x in enumerate(boxes):
+        arr[b].parent, arr[b].n = int(x.parent), int(x.n)
+        for a in range(3):
+            arr[b].origin[a] = int(x.origin[a])
+    return arr
+
+
+def amr_workspace_bytes(grid: Grid, params: Params, boxes) -> int:
+    g, p = grid._c(), params._c()
+    nb = lib().ndgp_amr_workspace_bytes(ctypes.byref(g), ctypes.byref(p), _boxes_c(boxes),
+                                        len(boxes))
+    if nb == 0:
+        raise NdgpError(NDGP_EINVAL, lib().ndgp_last_error().decode())
+    return int(nb)
+
+
+def solve_amr(grid: Grid, params: Params, boxes, delta: Sequence[Optional[torch.Tensor]],
+              phi=None, ws=None, stream=None, check: bool = True):
+    """ndgp_solve_amr: the domain, then every box of the tree from its parent.
+    ``delta``: [domain (n^3), box 0 (n_b^3), ...]; returns (phi list with the
+    padded boxes, Report of the domain level, list of per-box dicts)."""
+    if grid.patches:
+        raise ValueError("the tree's boxes replace the grid's nested patches")
+    g, p = grid._c(), params._c()
+    dev = delta[0].device
+    if phi is None:
+        phi = [torch.zeros((grid.n,) * 3, dtype=torch.float64, device=dev)] + \
+              [torch.zeros((b.n + 2,) * 3, dtype=torch.float64, device=dev) for b in boxes]
+    nb = len(boxes)
+    dptr = (ctypes.c_void_p * (1 + nb))()
+    pptr = (ctypes.c_void_p * (1 + nb))()
+    dptr[0] = _dev(delta[0], (grid.n,) * 3, "delta[0]")
+    pptr[0] = _dev(phi[0], (grid.n,) * 3, "phi[0]")
+    for b, x in enumerate(boxes):
+        d = delta[1 + b] if 1 + b < len(delta) else None
+        dptr[1 + b] = _dev(d, (x.n,) * 3, f"delta[{1 + b}]") if d is not None else None
+        pptr[1 + b] = _dev(phi[1 + b], (x.n + 2,) * 3, f"phi[{1 + b}]")
+    if ws is None:
+        ws = workspace(amr_workspace_bytes(grid, params, boxes), dev, stream)
+    rep = _Report()
+    brep = (_BoxReport * max(nb, 1))()
+    st = lib().ndgp_solve_amr(ctypes.byref(g), ctypes.byref(p), _boxes_c(boxes), nb, dptr, pptr,
+                              ws.data_ptr(), ws.numel(), _stream(stream), ctypes.byref(rep), brep)
+    report = _finish(st, rep, check)
+    per_box = [{"depth": brep[b].depth, "cycles": brep[b].cycles,
+                "damped_from": brep[b].damped_from, "rel_res": brep[b].rel_res}
+               for b in range(nb)]
+    return phi, report, per_box
 
 
 def cic_force(grid: Grid, force: Sequence[torch.Tensor], pos: torch.Tensor, out=None,

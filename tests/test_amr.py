@@ -1,0 +1,132 @@
+"""Placement of refinement boxes (Sec. IV.A: refine the cells holding more than
+N_ref particles), by the library's Berger-Rigoutsos clustering, checked on the
+CPU against brute force: every flagged cell lies in a box (on a patch parent:
+every flagged cell outside the stencil margin the solver needs), boxes are
+powers of two of at least 8 cells, children of one parent never overlap
+(periodic wrap included), and the placement is deterministic."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_1511_08200_amd import ndgp, synth
+
+
+def covered(boxes, n, periodic):
+    """Mask of the parent cells inside any box (child cell = half a parent cell)."""
+    cov = np.zeros((n, n, n), dtype=bool)
+    for b in boxes:
+        w = b.n // 2
+        idx = [np.arange(b.origin[a], b.origin[a] + w) for a in range(3)]
+        if periodic:
+            idx = [i % n for i in idx]
+        else:
+            assert all(0 <= i.min() and i.max() < n for i in idx)
+        cov[np.ix_(idx[2], idx[1], idx[0])] = True
+    return cov
+
+
+def overlap_cells(boxes, n, periodic):
+    cnt = np.zeros((n, n, n), dtype=np.int32)
+    for b in boxes:
+        w = b.n // 2
+        idx = [np.arange(b.origin[a], b.origin[a] + w) for a in range(3)]
+        if periodic:
+            idx = [i % n for i in idx]
+        cnt[np.ix_(idx[2], idx[1], idx[0])] += 1
+    return int((cnt > 1).sum())
+
+
+def nref_flags(delta, n_particles, n_ref):
+    """The refinement criterion of Sec. IV.A by its definition: particles in a
+    cell = (delta + 1) times the mean count per cell, refined above n_ref."""
+    cells = delta.size
+    return ((delta + 1.0) * n_particles / cells > n_ref).astype(np.uint8)
+
+
+@pytest.mark.parametrize("n,seed,tophats", [(32, 5, 6), (64, 6, 12), (64, 7, 0)])
+@pytest.mark.parametrize("efficiency", [0.5, 0.8])
+def test_domain_boxes_cover_every_flag_and_do_not_overlap(n, seed, tophats, efficiency):
+    f = synth.make_field(n, 1.5, seed, n_tophats=tophats)
+    flags = nref_flags(f.delta, n_particles=n**3, n_ref=4.0)
+    assert flags.sum() > 0
+    boxes = ndgp.refine_boxes(flags, n, periodic=True, efficiency=efficiency)
+    assert boxes
+    for b in boxes:
+        assert b.parent == -1 and b.n >= 8 and (b.n & (b.n - 1)) == 0 and b.n <= 2 * n
+        assert all(0 <= o < n for o in b.origin)
+    assert np.all(covered(boxes, n, True)[flags.astype(bool)])
+    assert overlap_cells(boxes, n, True) == 0
+    again = ndgp.refine_boxes(flags, n, periodic=True, efficiency=efficiency)
+    assert again == boxes
+    vol = sum((b.n // 2) ** 3 for b in boxes)
+    print(f"n={n} flagged={int(flags.sum())} boxes={len(boxes)} covered parent cells={vol}")
+
+
+def test_cluster_across_the_periodic_edge_is_one_box():
+    n = 32
+    flags = np.zeros((n, n, n), dtype=np.uint8)
+    flags[10:13, 30:32, 0:2] = 1   # straddles y = 0 and x = 0
+    flags[10:13, 0:2, 30:32] = 1
+    flags[10:13, 0:2, 0:2] = 1
+    flags[10:13, 30:32, 30:32] = 1
+    boxes = ndgp.refine_boxes(flags, n, periodic=True, efficiency=0.7)
+    assert len(boxes) == 1 and boxes[0].n == 8
+    assert np.all(covered(boxes, n, True)[flags.astype(bool)])
+
+
+def test_separate_clusters_get_separate_boxes():
+    n = 64
+    flags = np.zeros((n, n, n), dtype=np.uint8)
+    flags[5:9, 5:9, 5:9] = 1
+    flags[40:46, 40:44, 20:30] = 1
+    boxes = ndgp.refine_boxes(flags, n, periodic=True, efficiency=0.7)
+    assert len(boxes) == 2
+    assert sorted(b.n for b in boxes) == [8, 32]
+    assert np.all(covered(boxes, n, True)[flags.astype(bool)])
+
+
+def test_patch_parent_boxes_fit_the_parent():
+    """Boxes inside a patch lie inside it with room for the interpolation
+    stencils of their multigrid levels (the solver's own check accepts the
+    tree), and flagged cells away from the patch boundary are all covered."""
+    n = 64
+    rng = np.random.default_rng(4)
+    flags = np.zeros((n, n, n), dtype=np.uint8)
+    inner = (slice(10, n - 10),) * 3
+    flags[inner] = (rng.random((n - 20,) * 3) < 0.002).astype(np.uint8)
+    flags[20:30, 24:34, 30:36] = 1  # a cluster
+    boxes = ndgp.refine_boxes(flags, n, periodic=False, parent_index=0, efficiency=0.7)
+    assert boxes and all(b.parent == 0 for b in boxes)
+    assert overlap_cells(boxes, n, False) == 0
+    assert np.all(covered(boxes, n, False)[flags.astype(bool)])
+    # a tree: domain 32^3, box 0 a 64-cell patch (32 parent cells), then these
+    grid = ndgp.Grid(n=32, h=ndgp.cell_size(32.0, 32))
+    tree = [ndgp.Box(-1, 64, (0, 0, 0))] + boxes
+    assert ndgp.amr_workspace_bytes(grid, ndgp.Params(rc=1.0), tree) > 0
+
+
+def test_tree_validation():
+    grid = ndgp.Grid(n=32, h=ndgp.cell_size(32.0, 32))
+    P = ndgp.Params(rc=1.0)
+    ok = [ndgp.Box(-1, 16, (2, 3, 4)), ndgp.Box(-1, 16, (10, 3, 4)), ndgp.Box(0, 8, (3, 3, 3))]
+    assert ndgp.amr_workspace_bytes(grid, P, ok) > 0
+    bad = [
+        [ndgp.Box(-1, 16, (2, 3, 4)), ndgp.Box(-1, 16, (9, 3, 4))],   # siblings overlap
+        [ndgp.Box(-1, 16, (30, 3, 4)), ndgp.Box(-1, 16, (2, 3, 4))],  # ... across the wrap
+        [ndgp.Box(0, 8, (0, 0, 0))],                                  # parent after child
+        [ndgp.Box(-1, 12, (0, 0, 0))],                                # not a power of two
+        [ndgp.Box(-1, 16, (2, 3, 4)), ndgp.Box(0, 16, (10, 0, 0))],   # child not inside
+    ]
+    for tree in bad:
+        with pytest.raises(ndgp.NdgpError):
+            ndgp.amr_workspace_bytes(grid, P, tree)
+
+
+def test_nothing_flagged_and_bad_arguments():
+    n = 16
+    assert ndgp.refine_boxes(np.zeros((n, n, n), np.uint8), n, periodic=True) == []
+    with pytest.raises(ndgp.NdgpError):
+        ndgp.refine_boxes(np.ones((n, n, n), np.uint8), n, periodic=True, efficiency=0.0)
+    with pytest.raises(ndgp.NdgpError):
+        ndgp.refine_boxes(np.ones((n, n, n), np.uint8), n, periodic=True, max_boxes=0)

@@ -105,24 +105,3 @@ def test_deposit_at_selected_cells_is_deposit():
     cells = rng.choice(16**3, size=200, replace=False)
     np.testing.assert_allclose(C.deposit_at(pos, 16, cells, chunk=7000), d.ravel()[cells],
                                rtol=0, atol=1e-12)
-
-
-def test_suggest_patch_origin_by_brute_force():
-    """The chosen window covers the most flagged cells of all windows
-    (periodic wrap on the domain), checked by counting every window."""
-    from paper_1511_08200_amd.ndgp import suggest_patch_origin
-    rng = np.random.default_rng(2)
-    n, m = 8, 6
-    flags = (rng.random((n, n, n)) < 0.3).astype(np.uint8)
-    flags[0:2, 6:8, 7] = 1   # a cluster across the periodic edge
-    w = m // 2
-
-    def window(o):
-        idx = [(o[a] + np.arange(w)) % n for a in range(3)]
-        return int(flags[np.ix_(idx[2], idx[1], idx[0])].sum())
-
-    best = max(window((i, j, k)) for i in range(n) for j in range(n) for k in range(n))
-    o = suggest_patch_origin(flags, m)
-    assert window(o) == best
-    o2 = suggest_patch_origin(flags, m, periodic=False)
-    assert all(0 <= v <= n - w for v in o2)

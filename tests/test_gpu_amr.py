@@ -1,0 +1,126 @@
+"""Adaptive refinement on the GPU (Sec. IV.A): refinement flags by the N_ref
+criterion, box placement by the library's Berger-Rigoutsos clustering, and the
+solve on the resulting tree of boxes (several per level, two levels deep),
+against the oracle's tree solve."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1511_08200_amd import ndgp, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-amr] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ndgp.lib()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def nref_flags(delta, n_particles, n_ref):
+    return ((delta + 1.0) * n_particles / delta.size > n_ref).astype(np.uint8)
+
+
+def build_tree(n=64, seed=31, n_particles=None, n_ref=4.0, max_level1=4):
+    """Flags on the domain -> level-1 boxes; flags on the largest level-1 box
+    -> level-2 boxes inside it.  Every flag array is the library's
+    (ndgp_refine_flags) and equals the criterion's definition exactly."""
+    f = synth.make_field(n, 1.5, seed, n_tophats=8)
+    N = n**3 if n_particles is None else n_particles
+    grid0 = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n))
+    flags, counts = ndgp.refine_flags(grid0, [dev(f.delta)], N, n_ref)
+    want = nref_flags(f.delta, N, n_ref)
+    assert np.array_equal(flags[0].cpu().numpy(), want) and counts[0] == int(want.sum())
+    boxes = ndgp.refine_boxes(flags[0], n, periodic=True)
+    assert boxes == ndgp.refine_boxes(want, n, periodic=True)  # device and host flags agree
+    boxes = sorted(boxes, key=lambda b: -b.n)[:max_level1]
+    chains = [[b.origin] for b in boxes]
+    deltas = [f.delta] + [synth.patch_delta(f, n, ch, b.n) for ch, b in zip(chains, boxes)]
+    # level 2 inside the largest level-1 box: the box's own density and flags
+    b0 = boxes[0]
+    g1 = ndgp.Grid(n=n, h=grid0.h, patches=[ndgp.Patch(b0.n, b0.origin)])
+    fl1, _ = ndgp.refine_flags(g1, [dev(deltas[0]), dev(deltas[1])], N, n_ref)
+    # a level-1 cell holds (delta + 1) N / (2n)^3 particles
+    want1 = ((deltas[1] + 1.0) * N / (2 * n) ** 3 > n_ref).astype(np.uint8)
+    assert np.array_equal(fl1[1].cpu().numpy(), want1)
+    kids = ndgp.refine_boxes(fl1[1], b0.n, periodic=False, parent_index=0)
+    kids = sorted(kids, key=lambda b: -b.n)[:3]
+    for k in kids:
+        boxes.append(k)
+        chains.append(chains[0] + [k.origin])
+        deltas.append(synth.patch_delta(f, n, chains[-1], k.n))
+    return f, grid0, boxes, deltas
+
+
+def test_amr_tree_solve_matches_oracle():
+    f, grid, boxes, deltas = build_tree()
+    say(f"tree: {[(b.parent, b.n, b.origin) for b in boxes]}")
+    assert len(boxes) >= 3 and any(b.parent >= 0 for b in boxes)
+    rc = 1.0
+    beta = O.beta_lcdm(1.0, 0.3, rc)
+    tree = [(b.parent, b.n, b.origin) for b in boxes]
+    phio, infos = O.solve_tree(deltas, grid.h, rc, beta, tree)
+    assert all(i.status == 0 for i in infos)
+    phig, rep, per_box = ndgp.solve_amr(grid, ndgp.Params(rc=rc, tol=0.0, max_cycles=200), boxes,
+                                        [dev(d) for d in deltas])
+    torch.cuda.synchronize()
+    say(f"domain cycles={rep.cycles[0]}; boxes {per_box}")
+    assert rep.status == 0
+    for lvl in range(len(phig)):
+        e = rel(phig[lvl].cpu().numpy(), phio[lvl])
+        say(f"  level {lvl}: rel err {e:.2e}")
+        assert e <= 1e-11
+    # interpolated mode: every box is the oracle's interpolation of its GPU parent
+    phii, rep_i, per_i = ndgp.solve_amr(grid, ndgp.Params(rc=rc, tol=1e-10,
+                                                          mode=ndgp.MODE_INTERPOLATED),
+                                        boxes, [dev(deltas[0])] + [None] * len(boxes))
+    torch.cuda.synchronize()
+    assert all(p["rel_res"] == -1.0 and p["cycles"] == 0 for p in per_i)
+    host = [x.cpu().numpy() for x in phii]
+    for b, x in enumerate(boxes):
+        par = host[0] if x.parent < 0 else host[1 + x.parent]
+        want = O.interpolate(par, x.parent < 0, x.origin, 0, x.n)
+        assert np.abs(host[1 + b] - want).max() <= 1e-14 * np.abs(want).max()
+    # truncated at depth 2: level-1 boxes relaxed (as in the full run), level 2 interpolated
+    phit, rep_t, per_t = ndgp.solve_amr(grid, ndgp.Params(rc=rc, tol=0.0, max_cycles=200,
+                                                          mode=ndgp.MODE_TRUNCATED,
+                                                          trunc_level=2),
+                                        boxes, [dev(d) for d in deltas])
+    torch.cuda.synchronize()
+    for b, x in enumerate(boxes):
+        if x.parent < 0:
+            assert torch.equal(phit[1 + b], phig[1 + b])
+        else:
+            assert per_t[b]["cycles"] == 0
+
+
+def test_amr_rejects_bad_trees_and_inputs():
+    f, grid, boxes, deltas = build_tree(max_level1=2)
+    bad = list(boxes) + [ndgp.Box(len(boxes) + 3, 8, (0, 0, 0))]
+    with pytest.raises(ndgp.NdgpError):
+        ndgp.solve_amr(grid, ndgp.Params(rc=1.0), bad, [dev(d) for d in deltas] + [None])
+    nan = [d.copy() for d in deltas]
+    nan[1][2, 3, 4] = np.nan
+    with pytest.raises(ndgp.NdgpError) as e:
+        ndgp.solve_amr(grid, ndgp.Params(rc=1.0), boxes, [dev(d) for d in nan])
+    assert e.value.status == ndgp.NDGP_EINVAL

@@ -1049,3 +1049,30 @@ def test_strong_screening_converges(oracle_mod):
     assert info.status == 0 and info.rel_res < 1e-13
     r = S - octant_operator(phi, h, O.alpha(5.0, beta, 1.0))
     assert np.linalg.norm(r) / np.linalg.norm(S) < 1e-12
+
+
+def test_tree_solve_on_a_chain_is_the_nested_solve(oracle_mod):
+    """The tree form of Sec. III.A's order (each box from its own parent)
+    reduces to the nested-patch solve when the tree is a chain, bit for bit;
+    two siblings of the domain are each the patch solve from the domain."""
+    O = oracle_mod
+    n = 16
+    f = synth.make_field(n, 1.5, 13, n_tophats=2)
+    beta = O.beta_lcdm(1.0, 0.3, 1.0)
+    h = 1.0 / 2997.92458
+    o1, o2 = (3, 4, 5), (4, 4, 4)
+    d1 = synth.patch_delta(f, n, [o1], 16)
+    d2 = synth.patch_delta(f, n, [o1, o2], 8)
+    chain, _ = O.solve_problem(O.Problem(delta=[f.delta, d1, d2], h=h, rc=1.0, beta=beta,
+                                         origins=(o1, o2)))
+    tree, _ = O.solve_tree([f.delta, d1, d2], h, 1.0, beta, [(-1, 16, o1), (0, 8, o2)])
+    for a, b in zip(chain, tree):
+        assert np.array_equal(a, b)
+    s1, s2 = (0, 0, 0), (9, 8, 8)
+    e1 = synth.patch_delta(f, n, [s1], 8)
+    e2 = synth.patch_delta(f, n, [s2], 8)
+    sib, _ = O.solve_tree([f.delta, e1, e2], h, 1.0, beta, [(-1, 8, s1), (-1, 8, s2)])
+    for o, d, got in ((s1, e1, sib[1]), (s2, e2, sib[2])):
+        one, _ = O.solve_problem(O.Problem(delta=[f.delta, d], h=h, rc=1.0, beta=beta,
+                                           origins=(o,)))
+        assert np.array_equal(one[1], got)
