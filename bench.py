@@ -459,6 +459,9 @@ def main():
     ap.add_argument("--workload", choices=("256", "512"), default="512",
                     help="timed workload: the 512^3 lognormal sigma 2.5 field (default) or "
                          "256^3 lognormal + top-hats")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="precision of the timed solve (mixed: FP32 multigrid on the correction "
+                         "inside the FP64 defect-correction loop; no relaxation roofline)")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--extra", default="patches,truncation,particles,large,medium,serving",
                     help="comma-separated extra workloads to run after the timed one")
@@ -492,7 +495,10 @@ def main():
     log(f"generating {n}^3 input")
     f = make_domain(n, box, sigma, tophats, seed)
     grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
-    params = ndgp.Params(rc=rc, tol=1e-10)
+    prec = ndgp.PREC_MIXED if args.precision == "mixed" else ndgp.PREC_FP64
+    if prec == ndgp.PREC_MIXED:
+        wl = wl.replace("-fp64-", "-mixed-")
+    params = ndgp.Params(rc=rc, tol=1e-10, precision=prec)
     log("timing")
     dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, [f.delta], args.steps,
                                     args.warmup)
@@ -502,7 +508,8 @@ def main():
     del phi, dd
     # the roofline from a separate pass with the relaxation launches timed
     log("profiled pass (relaxation roofline)")
-    _, preps, phi, dd = solve_steps(ndgp, torch, grid, ndgp.Params(rc=rc, tol=1e-10, profile=True),
+    _, preps, phi, dd = solve_steps(ndgp, torch, grid,
+                                    ndgp.Params(rc=rc, tol=1e-10, profile=True, precision=prec),
                                     [f.delta], 3, 0)
     del phi, dd
     torch.cuda.empty_cache()
@@ -511,7 +518,8 @@ def main():
     line = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == ndgp.PREC_FP64 else "f64+f32",
         "data": "synthetic",
         "config": {"workload": wl, "n": n, "cycles": cycles, "rel_res": reps[-1].rel_res[0],
                    "solves_per_s": 1.0 / dt},

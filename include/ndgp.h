@@ -500,7 +500,7 @@ void ndgp_plan_destroy(ndgp_plan *plan);
  *                     tree depth, V-cycles, restart cycle and relative residual
  *                     (-1 if interpolated).  Workspace: ndgp_amr_workspace_bytes.
  */
-#define NDGP_AMR_MAX_BOXES 256
+#define NDGP_AMR_MAX_BOXES 4096
 typedef struct {
     int32_t parent;
     int32_t n;

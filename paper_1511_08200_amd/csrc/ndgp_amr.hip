@@ -5,14 +5,16 @@
 // level are grouped into rectangular clusters by the point-clustering
 // algorithm of Berger & Rigoutsos ("An algorithm for point clustering and grid
 // generation", IEEE Trans. Syst. Man Cybern. 21, 1991), and each cluster is
-// turned into a cubic patch of 2^k cells at twice the resolution, the shape
-// the solver's per-patch multigrid needs.  Cubes that overlap are merged until
-// none do, so that sibling patches never hold two values for one place.
+// turned into cubic patches of 2^k cells at twice the resolution, the shape
+// the solver's per-patch multigrid needs.  The cubes sit on an octree lattice,
+// where two cubes either nest or lie apart: keeping the larger of any two that
+// meet leaves siblings that never hold two values for one place.
 
 #include "ndgp.h"
 #include "ndgp_internal.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -133,36 +135,6 @@ struct Cube {
     int o[3] = {}; // lower corner, cut-open parent coordinates
 };
 
-// the smallest cube of 2^k >= 8 child cells around c (refinement ratio 2), or
-// w = 0 when c needs a cube larger than the level allows
-Cube fit_cube(const Cluster &c, int n) {
-    Cube q;
-    q.c = c;
-    const int e = std::max({c.extent(0), c.extent(1), c.extent(2)});
-    int w = 8;
-    while (w < 2 * e) w *= 2;
-    if (w > 512 || w > 2 * n) return q;
-    q.w = w;
-    for (int a = 0; a < 3; ++a) q.o[a] = c.lo[a] - (w / 2 - c.extent(a)) / 2;
-    return q;
-}
-
-bool overlap(const Cube &x, const Cube &y, int period) {
-    for (int a = 0; a < 3; ++a) {
-        const int w1 = x.w / 2, w2 = y.w / 2;
-        bool ov;
-        if (period > 0) {
-            const int d12 = ((y.o[a] - x.o[a]) % period + period) % period;
-            const int d21 = ((x.o[a] - y.o[a]) % period + period) % period;
-            ov = d12 < w1 || d21 < w2;
-        } else {
-            ov = x.o[a] < y.o[a] + w2 && y.o[a] < x.o[a] + w1;
-        }
-        if (!ov) return false;
-    }
-    return true;
-}
-
 // the widest cube a level can hold: at most 512 cells and twice the level's
 // cells per side, and on a patch parent one that fits inside it
 int widest_cube(int n, bool periodic) {
@@ -179,111 +151,101 @@ int widest_cube(int n, bool periodic) {
     return w;
 }
 
-// Cubes for the clusters of a periodic level.  A cluster too wide for one
-// cube is covered by a grid of the widest cubes, aligned at its lower corner
-// (they only touch), leaving out those that hold no flags.
-void fit_all(const FlagView &F, const Cluster &c, int n, std::vector<Cube> &out) {
-    const int wmax = widest_cube(n, true);
-    Cube q = fit_cube(c, n);
-    if (q.w > 0 && q.w <= wmax) {
-        out.push_back(q);
-        return;
+bool overlap(const Cube &x, const Cube &y) {
+    for (int a = 0; a < 3; ++a)
+        if (!(x.o[a] < y.o[a] + y.w / 2 && y.o[a] < x.o[a] + x.w / 2)) return false;
+    return true;
+}
+
+int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Cubes on an octree lattice: a cube of w child cells (w/2 parent cells, a
+// power of two >= 8) sits at L0 + t w/2 along each axis.  Two lattice cubes
+// either nest or lie apart, so overlaps are removed by keeping the larger.
+// On a periodic level the lattice starts at the cut (L0 = 0 in cut-open
+// coordinates) and tiles it exactly; on a patch parent L0 is the lowest
+// corner at which the widest cube fits, and only cubes that fit the parent
+// with room for their stencils are used (flagged cells that none reaches,
+// next to the parent's boundary, stay unrefined).
+struct Lattice {
+    int n, L0, wmax;
+    bool periodic;
+    bool fits(const Cube &q) const {
+        if (periodic) return true;
+        for (int a = 0; a < 3; ++a)
+            if (!child_fits_axis(n, q.o[a], q.w, default_levels(q.w))) return false;
+        return true;
     }
-    const int span = wmax / 2;
-    for (int k = c.lo[2]; k < c.hi[2]; k += span)
-        for (int j = c.lo[1]; j < c.hi[1]; j += span)
-            for (int i = c.lo[0]; i < c.hi[0]; i += span) {
-                Cluster t{{i, j, k},
-                          {std::min(i + span, c.hi[0]), std::min(j + span, c.hi[1]),
-                           std::min(k + span, c.hi[2])}};
+};
+
+// lattice cubes of width w that meet the flags of c (each with the part of c
+// it holds), and whether they all fit
+bool lattice_tiles(const FlagView &F, const Lattice &L, const Cluster &c, int w,
+                   std::vector<Cube> &tiles) {
+    const int span = w / 2;
+    int t0[3], t1[3];
+    for (int a = 0; a < 3; ++a) {
+        t0[a] = floor_div(c.lo[a] - L.L0, span);
+        t1[a] = floor_div(c.hi[a] - 1 - L.L0, span);
+    }
+    bool all_fit = true;
+    for (int tk = t0[2]; tk <= t1[2]; ++tk)
+        for (int tj = t0[1]; tj <= t1[1]; ++tj)
+            for (int ti = t0[0]; ti <= t1[0]; ++ti) {
+                Cube g;
+                g.w = w;
+                g.o[0] = L.L0 + ti * span;
+                g.o[1] = L.L0 + tj * span;
+                g.o[2] = L.L0 + tk * span;
+                Cluster t;
+                for (int a = 0; a < 3; ++a) {
+                    t.lo[a] = std::max(c.lo[a], g.o[a]);
+                    t.hi[a] = std::min(c.hi[a], g.o[a] + span);
+                }
                 std::vector<int64_t> sig[3];
                 int64_t count = 0;
                 signatures(F, t, sig, count);
                 if (count == 0) continue;
-                Cube g;
                 g.c = t;
-                g.w = wmax;
-                g.o[0] = i;
-                g.o[1] = j;
-                g.o[2] = k;
-                out.push_back(g);
+                if (L.fits(g))
+                    tiles.push_back(g);
+                else
+                    all_fit = false;
             }
+    return all_fit;
 }
 
-// Cubes for the clusters of a patch level, on an octree lattice: a cube of w
-// child cells sits at L0 + t w/2 along each axis, L0 the lowest corner at
-// which the widest cube fits.  Two lattice cubes either nest or are apart,
-// so overlaps are removed by keeping the larger.  A cluster gets the smallest
-// lattice cube around it that fits the parent, else the widest lattice cubes
-// that meet its flags and fit; flagged cells that no fitting cube reaches
-// (next to the parent's boundary) stay unrefined.
-void fit_patch(const FlagView &F, const Cluster &c, int n, std::vector<Cube> &out) {
-    const int wmax = widest_cube(n, false);
-    if (wmax < 8) return;
-    int L0 = 1 << 30;
-    for (int o = -n; o <= n; ++o)
-        if (child_fits_axis(n, o, wmax, default_levels(wmax))) {
-            L0 = o;
-            break;
-        }
-    auto fits = [&](const Cube &q) {
-        for (int a = 0; a < 3; ++a)
-            if (!child_fits_axis(n, q.o[a], q.w, default_levels(q.w))) return false;
-        return true;
-    };
-    auto floor_div = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
-    for (int w = 8; w <= wmax; w *= 2) {
-        const int span = w / 2;
+// A cluster's cubes: of the lattice cubes just wide enough for it (as tiles)
+// and the smallest single lattice cube around it, the choice with the smaller
+// volume; narrower tiles where wide ones do not fit the parent.
+void fit_cluster(const FlagView &F, const Lattice &L, const Cluster &c, std::vector<Cube> &out) {
+    if (L.wmax < 8) return;
+    const int e = std::max({c.extent(0), c.extent(1), c.extent(2)});
+    int wc = 8;
+    while (wc < 2 * e && wc < L.wmax) wc *= 2;
+    Cube single;
+    for (int w = wc; w <= L.wmax && single.w == 0; w *= 2) {
         Cube q;
         q.c = c;
         q.w = w;
         bool ok = true;
         for (int a = 0; a < 3 && ok; ++a) {
-            q.o[a] = L0 + floor_div(c.lo[a] - L0, span) * span;
-            ok = q.o[a] + span >= c.hi[a];
+            q.o[a] = L.L0 + floor_div(c.lo[a] - L.L0, w / 2) * (w / 2);
+            ok = q.o[a] + w / 2 >= c.hi[a];
         }
-        if (ok && fits(q)) {
-            out.push_back(q);
-            return;
-        }
+        if (ok && L.fits(q)) single = q;
     }
-    // tiles of the widest lattice cubes that all fit, else narrower ones
-    for (int w = wmax; w >= 8; w /= 2) {
-        const int span = w / 2;
-        int t0[3], t1[3];
-        for (int a = 0; a < 3; ++a) {
-            t0[a] = floor_div(c.lo[a] - L0, span);
-            t1[a] = floor_div(c.hi[a] - 1 - L0, span);
-        }
+    for (int w = wc; w >= 8; w /= 2) {
         std::vector<Cube> tiles;
-        bool all_fit = true;
-        for (int tk = t0[2]; tk <= t1[2]; ++tk)
-            for (int tj = t0[1]; tj <= t1[1]; ++tj)
-                for (int ti = t0[0]; ti <= t1[0]; ++ti) {
-                    Cube g;
-                    g.w = w;
-                    g.o[0] = L0 + ti * span;
-                    g.o[1] = L0 + tj * span;
-                    g.o[2] = L0 + tk * span;
-                    Cluster t;
-                    for (int a = 0; a < 3; ++a) {
-                        t.lo[a] = std::max(c.lo[a], g.o[a]);
-                        t.hi[a] = std::min(c.hi[a], g.o[a] + span);
-                    }
-                    std::vector<int64_t> sig[3];
-                    int64_t count = 0;
-                    signatures(F, t, sig, count);
-                    if (count == 0) continue;
-                    g.c = t;
-                    if (fits(g))
-                        tiles.push_back(g);
-                    else
-                        all_fit = false;
-                }
-        if (all_fit || w == 8) {
+        const bool all_fit = lattice_tiles(F, L, c, w, tiles);
+        if (!all_fit && w > 8) continue;
+        const double vt = (double)tiles.size() * (w / 2) * (w / 2) * (w / 2);
+        const double vs = single.w ? std::pow(single.w / 2.0, 3) : 1e300;
+        if (single.w && vs <= vt)
+            out.push_back(single);
+        else
             out.insert(out.end(), tiles.begin(), tiles.end());
-            return;
-        }
+        return;
     }
 }
 
@@ -332,41 +294,27 @@ ndgp_status refine_boxes_impl(const unsigned char *flags, int on_device, int n, 
     }
     std::vector<Cluster> clusters;
     berger_rigoutsos(F, Cluster{{0, 0, 0}, {n, n, n}}, efficiency, min_width, clusters);
+    Lattice L{n, 0, widest_cube(n, periodic != 0), periodic != 0};
+    if (!periodic)
+        for (int o = -n; o <= n; ++o)
+            if (L.wmax >= 8 && child_fits_axis(n, o, L.wmax, default_levels(L.wmax))) {
+                L.L0 = o;
+                break;
+            }
     std::vector<Cube> cubes;
-    for (const Cluster &c : clusters) {
-        if (periodic)
-            fit_all(F, c, n, cubes);
-        else
-            fit_patch(F, c, n, cubes);
+    for (const Cluster &c : clusters) fit_cluster(F, L, c, cubes);
+    // lattice cubes nest or lie apart: drop every cube inside a larger (or an
+    // equal, earlier) one
+    std::vector<Cube> kept;
+    for (size_t x = 0; x < cubes.size(); ++x) {
+        bool inside = false;
+        for (size_t y = 0; y < cubes.size() && !inside; ++y)
+            if (y != x && overlap(cubes[x], cubes[y]) &&
+                (cubes[y].w > cubes[x].w || (cubes[y].w == cubes[x].w && y < x)))
+                inside = true;
+        if (!inside) kept.push_back(cubes[x]);
     }
-    const int period = periodic ? n : 0;
-    int rounds = 0;
-    for (bool merged = true; merged;) {
-        if (++rounds > 4096)
-            return fail(NDGP_ENOMEM, "the clusters' cubes could not be made disjoint; use a "
-                                     "higher efficiency or min_width");
-        merged = false;
-        for (size_t x = 0; x < cubes.size() && !merged; ++x)
-            for (size_t y = x + 1; y < cubes.size() && !merged; ++y)
-                if (overlap(cubes[x], cubes[y], period)) {
-                    if (!periodic) { // lattice cubes nest: keep the larger
-                        cubes.erase(cubes.begin() + (cubes[x].w >= cubes[y].w ? y : x));
-                        merged = true;
-                        break;
-                    }
-                    Cluster u = cubes[x].c;
-                    for (int a = 0; a < 3; ++a) {
-                        u.lo[a] = std::min(u.lo[a], cubes[y].c.lo[a]);
-                        u.hi[a] = std::max(u.hi[a], cubes[y].c.hi[a]);
-                    }
-                    cubes.erase(cubes.begin() + y);
-                    cubes.erase(cubes.begin() + x);
-                    std::vector<Cube> refit;
-                    fit_all(F, u, n, refit);
-                    cubes.insert(cubes.end(), refit.begin(), refit.end());
-                    merged = true;
-                }
-    }
+    cubes.swap(kept);
     if ((int)cubes.size() > max_boxes)
         return fail(NDGP_ENOMEM, "the flags need " + std::to_string(cubes.size()) +
                                      " boxes, more than max_boxes");

@@ -595,7 +595,7 @@ class _BoxReport(ctypes.Structure):
                 ("damped_from", ctypes.c_int32), ("rel_res", ctypes.c_double)]
 
 
-AMR_MAX_BOXES = 256
+AMR_MAX_BOXES = 4096
 
 
 def refine_boxes(flags, n: int, periodic: bool, parent_index: int = -1,

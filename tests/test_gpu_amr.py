@@ -41,11 +41,12 @@ def nref_flags(delta, n_particles, n_ref):
     return ((delta + 1.0) * n_particles / delta.size > n_ref).astype(np.uint8)
 
 
-def build_tree(n=64, seed=31, n_particles=None, n_ref=4.0, max_level1=4):
+def build_tree(n=64, seed=31, n_particles=None, n_ref=20.0, n_ref1=2.0, max_level1=4):
     """Flags on the domain -> level-1 boxes; flags on the largest level-1 box
-    -> level-2 boxes inside it.  Every flag array is the library's
-    (ndgp_refine_flags) and equals the criterion's definition exactly."""
-    f = synth.make_field(n, 1.5, seed, n_tophats=8)
+    (threshold n_ref1) -> level-2 boxes inside it.  Every flag array is the
+    library's (ndgp_refine_flags) and equals the criterion's definition
+    exactly."""
+    f = synth.make_field(n, 1.0, seed, n_tophats=6)
     N = n**3 if n_particles is None else n_particles
     grid0 = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n))
     flags, counts = ndgp.refine_flags(grid0, [dev(f.delta)], N, n_ref)
@@ -59,10 +60,10 @@ def build_tree(n=64, seed=31, n_particles=None, n_ref=4.0, max_level1=4):
     # level 2 inside the largest level-1 box: the box's own density and flags
     b0 = boxes[0]
     g1 = ndgp.Grid(n=n, h=grid0.h, patches=[ndgp.Patch(b0.n, b0.origin)])
-    fl1, _ = ndgp.refine_flags(g1, [dev(deltas[0]), dev(deltas[1])], N, n_ref)
+    fl1, _ = ndgp.refine_flags(g1, [dev(deltas[0]), dev(deltas[1])], N, n_ref1)
     # a level-1 cell holds (delta + 1) N / (2n)^3 particles
-    want1 = ((deltas[1] + 1.0) * N / (2 * n) ** 3 > n_ref).astype(np.uint8)
-    assert np.array_equal(fl1[1].cpu().numpy(), want1)
+    want1 = ((deltas[1] + 1.0) * N / (2 * n) ** 3 > n_ref1).astype(np.uint8)
+    assert np.array_equal(fl1[1].cpu().numpy(), want1) and want1.sum() > 0
     kids = ndgp.refine_boxes(fl1[1], b0.n, periodic=False, parent_index=0)
     kids = sorted(kids, key=lambda b: -b.n)[:3]
     for k in kids:
