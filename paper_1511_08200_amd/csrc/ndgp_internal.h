@@ -86,6 +86,7 @@ void launch_smooth_half(const Level &L, const double *pin, double *pout, int col
 // One full red-black sweep (both colours) in one launch through LDS tiles;
 // identical results to two launch_smooth_half calls.  Periodic levels with
 // n >= 128 only (fused_sweep_ok).
+bool fused_prolong_ok(const Level &L);
 bool fused_sweep_ok(const Level &L);
 void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
                         hipStream_t st);

@@ -81,7 +81,14 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
 // sees each old value and each source value once and each new value once:
 // 24 bytes per cell and sweep (PRO: + 2 x 8 bytes per coarse cell); tiles
 // are ordered per XCD so that their halo lines are shared in L2.
-template <int TX, int TY, int TZ, int NT, bool PRO>
+//
+// PER = false: the finest level of a refinement, in its padded layout with a
+// fixed ghost shell (no correction on load).  Cells of the halo that lie in
+// the shell keep their value instead of being relaxed, loads beyond the shell
+// (needed only to relax such cells) are clamped to it, and pairs are moved
+// as two 8-byte values (padded rows do not keep a pair 16-byte aligned); the
+// shell itself is never written (both ping-pong arrays hold it).
+template <int TX, int TY, int TZ, int NT, bool PRO, bool PER = true>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(4))) // two workgroups per CU: at most 128 VGPRs
 k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
@@ -97,6 +104,7 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     static_assert(TX % 2 == 0 && TY % 2 == 0 && TX * TY / 2 == NT, "one black cell per thread");
     static_assert(RED_CELLS <= 2 * NT, "at most two red cells per thread");
     static_assert(EX * EY <= NT, "one coarse value per thread");
+    static_assert(PER || !PRO, "refinements add the coarse correction in its own launch");
     __shared__ double PR[3][PY][HX];
     __shared__ double PB[5][PY][HX];
     __shared__ double R[3][PY][HX];
@@ -113,7 +121,29 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     const int tid = threadIdx.x;
     unsigned fb = 0;
 
-    auto zoff = [&](int z) { return (z & m) << (2 * lg); };
+    // padded layout (PER = false): row pitch n + 2, cell (x, y, z) at
+    // ((z + 1) pitch + y + 1) pitch + x + 1, every coordinate clamped to [-1, n]
+    const int pitch = n + 2;
+    auto cl = [&](int v) { return v < -1 ? -1 : (v > n ? n : v); };
+    auto zoff = [&](int z) {
+        if constexpr (PER) return (z & m) << (2 * lg);
+        else return (cl(z) + 1) * pitch * pitch;
+    };
+    // source index of (x, y, z), clamped inside the level where PER = false
+    auto sidx = [&](int x, int y, int z) {
+        if constexpr (PER) {
+            return (((z & m) << lg | (y & m)) << lg) | (x & m);
+        } else {
+            auto c0 = [&](int v) { return v < 0 ? 0 : (v > m ? m : v); };
+            return ((c0(z) << lg | c0(y)) << lg) | c0(x);
+        }
+    };
+    // a cell of the ghost shell: kept, not relaxed
+    auto ghost = [&](int x, int y, int z) {
+        if constexpr (PER) return false;
+        else return (unsigned)x >= (unsigned)n || (unsigned)y >= (unsigned)n ||
+                    (unsigned)z >= (unsigned)n;
+    };
     auto s5 = [](int z) { return (z + 5 * 4096) % 5; };
     auto s3 = [](int z) { return (z + 3 * 4096) % 3; };
 
@@ -123,12 +153,19 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     // their coarse cell in E with the step towards the neighbour row
     constexpr int PAIRS = PLANE / 2;
     constexpr int PRE2 = (PAIRS + NT - 1) / NT;
-    int pxy[PRE2], pidx[PRE2], ppar[PRE2], eat[PRE2], edy[PRE2];
+    int pxy[PRE2], pxy1[PRE2], pidx[PRE2], ppar[PRE2], eat[PRE2], edy[PRE2];
 #pragma unroll
     for (int e = 0; e < PRE2; ++e) {
         const int q = tid + e * NT;
         const int r = q / HX, j = q - r * HX;
-        pxy[e] = (((y0 - 2 + r) & m) << lg) | ((x0 - 2 + 2 * j) & m);
+        if constexpr (PER) {
+            pxy[e] = (((y0 - 2 + r) & m) << lg) | ((x0 - 2 + 2 * j) & m);
+            pxy1[e] = 0;
+        } else {
+            const int y = cl(y0 - 2 + r), x = x0 - 2 + 2 * j;
+            pxy[e] = (y + 1) * pitch + cl(x) + 1;
+            pxy1[e] = (y + 1) * pitch + cl(x + 1) + 1;
+        }
         pidx[e] = q < PAIRS ? r * HX + j : -1;
         ppar[e] = r & 1; // colour of column 2j = ppar ^ (z & 1)  (x0, y0 even)
         // fine x0-2+2j+i lies in coarse cell x0/2-1+j, E column j+1; the
@@ -141,7 +178,14 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         const int zo = zoff(z);
 #pragma unroll
         for (int e = 0; e < PRE2; ++e)
-            if (pidx[e] >= 0) pre[e] = *reinterpret_cast<const double2 *>(pin + (zo | pxy[e]));
+            if (pidx[e] >= 0) {
+                if constexpr (PER) {
+                    pre[e] = *reinterpret_cast<const double2 *>(pin + (zo | pxy[e]));
+                } else {
+                    pre[e].x = pin[zo + pxy[e]];
+                    pre[e].y = pin[zo + pxy1[e]];
+                }
+            }
     };
     auto commit = [&](int z) {
         double *red = &PR[s3(z)][0][0], *blk = &PB[s5(z)][0][0];
@@ -209,13 +253,12 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     }
     // the sources of plane z's red cells, loaded a step ahead of their use
     auto red_sources = [&](int z, double out[2]) {
-        const int zo = zoff(z);
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int rr = red_rr[e];
             const int p = (rr + z) & 1;
             const int gx = x0 - 2 + 2 * (red_jj[e] + 1 - p) + p, gy = y0 - 2 + rr;
-            out[e] = s[zo | ((gy & m) << lg) | (gx & m)]; // in bounds also when !red_on[e]
+            out[e] = s[sidx(gx, gy, z)]; // in bounds also when !red_on[e]
         }
     };
     // red cells of plane z over the tile + 1-cell halo -> R(z)
@@ -237,7 +280,12 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
                 c0[rr + 1][a], c0[rr - 1][a], c0[rr + 1][b], c0[rr - 1][b],
                 p0[rr][a], m0[rr][a], p0[rr][b], m0[rr][b],
                 p0[rr + 1][j], m0[rr + 1][j], p0[rr - 1][j], m0[rr - 1][j]};
-            rz[rr][j] = relax_cell(v, src[e], al, w, fb);
+            if constexpr (PER) {
+                rz[rr][j] = relax_cell(v, src[e], al, w, fb);
+            } else {
+                const int gx = x0 - 2 + 2 * j + p, gy = y0 - 2 + rr;
+                rz[rr][j] = ghost(gx, gy, z) ? v[0] : relax_cell(v, src[e], al, w, fb);
+            }
         }
     };
 
@@ -245,9 +293,11 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     const int rt = 2 + tid / (TX / 2), jt = 1 + tid % (TX / 2);
     const int yt = y0 - 2 + rt;
     const int xy_t = (yt << lg) | (x0 - 2 + 2 * jt);
+    const int pxy_t = (yt + 1) * pitch + x0 - 2 + 2 * jt + 1; // padded (PER = false)
     auto black_source = [&](int k) {
         const int pb = (1 + rt + k) & 1;
-        return s[zoff(k) | xy_t | pb];
+        if constexpr (PER) return s[zoff(k) | xy_t | pb];
+        else return s[((k < n ? k : m) << (2 * lg) | xy_t) + pb]; // plane n: loaded, unused
     };
     auto black_and_store = [&](int k, double sv) {
         const double(*rm)[HX] = R[s3(k - 1)], (*r0)[HX] = R[s3(k)], (*rp)[HX] = R[s3(k + 1)];
@@ -269,7 +319,13 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         pair_t o;
         o.x = pb ? vr : vb;
         o.y = pb ? vb : vr;
-        __builtin_nontemporal_store(o, reinterpret_cast<pair_t *>(pout + (zoff(k) | xy_t)));
+        if constexpr (PER) {
+            __builtin_nontemporal_store(o, reinterpret_cast<pair_t *>(pout + (zoff(k) | xy_t)));
+        } else {
+            double *q = pout + zoff(k) + pxy_t;
+            __builtin_nontemporal_store(o.x, q);
+            __builtin_nontemporal_store(o.y, q + 1);
+        }
     };
 
     // Planes needed: old z0-2 .. z0+TZ+1 (black) / z0-1 .. z0+TZ+1 (red), R
@@ -1226,23 +1282,37 @@ void launch_smooth_half(const Level &L, const double *pin, double *pout, int col
 
 // (on 32^3 and 64^3 the one-workgroup-per-tile pipeline is slower than two
 // short launches: its prologue latency is not amortised over enough planes)
-bool fused_sweep_ok(const Level &L) { return L.periodic && L.n >= 128; }
+// periodic levels, and the finest level of a refinement (fixed ghost shell,
+// every cell relaxed), from 128^3 on
+bool fused_sweep_ok(const Level &L) {
+    return L.n >= 128 && (L.periodic || (!L.dyn_bc && !L.mask));
+}
+bool fused_prolong_ok(const Level &L) { return L.periodic && L.n >= 128; }
 
-template <int TX, int TY, int TZ, int NT, bool PRO>
+template <int TX, int TY, int TZ, int NT, bool PRO, bool PER>
 void sweep_fused_tiles(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
                        const double *phi_c, const double *hat_c, hipStream_t st) {
     const int tiles = (L.n / TX) * (L.n / TY);
-    k_sweep_fused<TX, TY, TZ, NT, PRO><<<tiles * (L.n / TZ), NT, 0, st>>>(
+    k_sweep_fused<TX, TY, TZ, NT, PRO, PER><<<tiles * (L.n / TZ), NT, 0, st>>>(
         pin, pout, L.s, L.lg, L.alpha, L.omega, fallbacks, phi_c, hat_c);
+}
+
+template <bool PRO, bool PER>
+void sweep_fused_layout(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
+                        const double *phi_c, const double *hat_c, hipStream_t st) {
+    if (L.n >= 256) // long z-chunks: the halo planes are a small share
+        sweep_fused_tiles<64, 16, 32, 512, PRO, PER>(L, pin, pout, fallbacks, phi_c, hat_c, st);
+    else // 128^3: short chunks, two workgroups per CU (4 planes: 5% faster than 8)
+        sweep_fused_tiles<64, 16, 4, 512, PRO, PER>(L, pin, pout, fallbacks, phi_c, hat_c, st);
 }
 
 template <bool PRO>
 void sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
                  const double *phi_c, const double *hat_c, hipStream_t st) {
-    if (L.n >= 256) // long z-chunks: the halo planes are a small share
-        sweep_fused_tiles<64, 16, 32, 512, PRO>(L, pin, pout, fallbacks, phi_c, hat_c, st);
-    else // 128^3: short chunks, two workgroups per CU (4 planes: 5% faster than 8)
-        sweep_fused_tiles<64, 16, 4, 512, PRO>(L, pin, pout, fallbacks, phi_c, hat_c, st);
+    if (L.periodic)
+        sweep_fused_layout<PRO, true>(L, pin, pout, fallbacks, phi_c, hat_c, st);
+    else if constexpr (!PRO)
+        sweep_fused_layout<false, false>(L, pin, pout, fallbacks, phi_c, hat_c, st);
 }
 
 void launch_sweep_fused(const Level &L, const double *pin, double *pout, unsigned *fallbacks,

@@ -488,9 +488,10 @@ struct Runner {
     void smooth(Level &L, int sweeps, const Level *C = nullptr) {
         const bool fused = !(P.c.flags & NDGP_TWO_PASS) && fused_sweep_ok(L);
         const int nf = fused ? (sweeps & ~1) : 0;
+        const bool pro = nf > 0 && fused_prolong_ok(L); // the correction added on load
         int s = 0;
-        if (C && nf == 0) launch_prolong_correct(L, *C, st);
-        if (C && nf > 0) {
+        if (C && !pro) launch_prolong_correct(L, *C, st);
+        if (C && pro) {
             launch_sweep_fused_prolong(L, *C, L.phi, L.alt, P.fallbacks, st);
             std::swap(L.phi, L.alt);
             s = 1;

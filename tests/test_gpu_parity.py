@@ -180,6 +180,44 @@ def test_fused_kernels_bitwise_equal_per_level_launches(n, levels):
     assert torch.equal(a[0], b[0])
 
 
+@pytest.mark.parametrize("m,pn2,wrap", [(128, 128, False), (128, 64, True), (256, 128, False)])
+def test_patch_fused_sweep_bitwise_equal_per_colour_launches(m, pn2, wrap):
+    """The finest level of a refinement (fixed ghost shell) relaxed by the
+    one-launch LDS sweep gives the same bits as one launch per colour, for
+    every level of a full-mode solve (patch 1 wrapping the periodic domain in
+    one case), and the oracle's answer."""
+    say(f"patch fused sweep m={m} pn2={pn2} wrap={wrap}")
+    n = 64
+    f = synth.make_field(n, 2.0, 51, n_tophats=8)
+    c = synth.densest_tophat_centre(f)
+    o1 = synth.patch_origin_centred(c, m // 2)
+    if wrap:
+        o1 = (-m // 8, o1[1], o1[2])
+    c1 = tuple((c[a] - o1[a]) * 2 for a in range(3))
+    o2 = tuple(min(max(v, 8), m - pn2 // 2 - 8) for v in synth.patch_origin_centred(c1, pn2 // 2))
+    d1 = synth.patch_delta(f, n, [o1], m)
+    d2 = synth.patch_delta(f, n, [o1, o2], pn2)
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n),
+                     patches=[ndgp.Patch(m, o1), ndgp.Patch(pn2, o2)])
+    deltas = [dev(x) for x in (f.delta, d1, d2)]
+    p = dict(rc=1.0, tol=0.0, max_cycles=200)
+    a, ra = ndgp.solve(grid, ndgp.Params(**p), deltas)
+    b, rb = ndgp.solve(grid, ndgp.Params(two_pass=True, **p), deltas)
+    torch.cuda.synchronize()
+    say(f"  cycles={ra.cycles} rel_res={ra.rel_res}")
+    assert ra.status == 0 and ra.cycles == rb.cycles
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    if m == 128 and not wrap:
+        beta = O.beta_lcdm(1.0, 0.3, 1.0)
+        prob = O.Problem(delta=[f.delta, d1, d2], h=grid.h, rc=1.0, beta=beta, origins=(o1, o2))
+        phio, infos = O.solve_problem(prob)
+        for lvl in range(3):
+            e = rel(a[lvl].cpu().numpy(), phio[lvl])
+            say(f"  level {lvl}: rel err {e:.2e}")
+            assert e <= PHI_TOL
+
+
 @pytest.mark.parametrize("nu1,nu2", [(1, 1), (3, 1), (1, 3)])
 def test_odd_sweep_counts(nu1, nu2):
     """Odd numbers of pre/post sweeps: the fused one-launch sweeps take the
