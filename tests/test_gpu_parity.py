@@ -187,7 +187,7 @@ def test_patch_fused_sweep_bitwise_equal_per_colour_launches(m, pn2, wrap):
     every level of a full-mode solve (patch 1 wrapping the periodic domain in
     one case), and the oracle's answer."""
     say(f"patch fused sweep m={m} pn2={pn2} wrap={wrap}")
-    n = 64
+    n = max(64, m // 2)
     f = synth.make_field(n, 2.0, 51, n_tophats=8)
     c = synth.densest_tophat_centre(f)
     o1 = synth.patch_origin_centred(c, m // 2)
