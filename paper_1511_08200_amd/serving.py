@@ -72,19 +72,27 @@ def make_trace(count: int = 2000, rate: float = 50.0, seed: int = 1516,
                     float(sg[i]), 100000 + i) for i in range(count)]
 
 
-def request_problem(req: Request, device, precision=ndgp.PREC_MIXED, tol: float = 1e-10,
-                    box_per_cell: float = 1.0):
-    """Density, grid and parameters of one request (density made on the
-    current stream of `device`)."""
+def request_grid(req: Request, flat: int, precision=ndgp.PREC_MIXED, tol: float = 1e-10,
+                 box_per_cell: float = 1.0):
+    """Grid and parameters of one request whose densest cell has the flat
+    index `flat`: one (n/2)^3 patch at twice the resolution centred there."""
     n = req.n
-    delta = synth.lognormal_delta_torch(n, req.sigma, req.seed, device=device)
-    flat = int(torch.argmax(delta).item())
     k, j, i = flat // (n * n), (flat // n) % n, flat % n
     cover = n // 4  # the (n/2)^3 patch at twice the resolution covers (n/4)^3 cells
     origin = (i - cover // 2, j - cover // 2, k - cover // 2)
     grid = ndgp.Grid(n=n, h=ndgp.cell_size(box_per_cell * n, n),
                      patches=[ndgp.Patch(n // 2, origin)])
     params = ndgp.Params(rc=req.rc, tol=tol, mode=ndgp.MODE_INTERPOLATED, precision=precision)
+    return grid, params
+
+
+def request_problem(req: Request, device, precision=ndgp.PREC_MIXED, tol: float = 1e-10,
+                    box_per_cell: float = 1.0):
+    """Density, grid and parameters of one request (density made on the
+    current stream of `device`; waits for its densest cell)."""
+    delta = synth.lognormal_delta_torch(req.n, req.sigma, req.seed, device=device)
+    grid, params = request_grid(req, int(torch.argmax(delta).item()), precision, tol,
+                                box_per_cell)
     return delta, grid, params
 
 
@@ -106,7 +114,8 @@ def request_bytes(grid: ndgp.Grid, params: ndgp.Params) -> int:
 
 
 class _Active:
-    __slots__ = ("req", "plan", "stream", "admitted", "bytes", "delta", "grid", "params")
+    __slots__ = ("req", "plan", "stream", "admitted", "bytes", "delta", "grid", "params",
+                 "where", "placed")
 
 
 def warm_up(trace: list, precision=ndgp.PREC_MIXED, tol: float = 1e-10, device="cuda"):
@@ -151,11 +160,16 @@ def serve(trace: list, budget_bytes: float = 64e9, max_active: int = 16,
             pending.popleft()
             si = free_streams.popleft()
             with torch.cuda.stream(streams[si]):
-                delta, grid, params = request_problem(req, device, precision, tol)
+                # the density and its densest cell, copied back without waiting:
+                # the plan is created once the copy has landed
                 a = _Active()
                 a.req, a.stream, a.admitted, a.bytes = req, si, now(), need
-                a.delta, a.grid, a.params = delta, grid, params
-                a.plan = ndgp.Plan(grid, params, [delta], stream=streams[si])
+                a.delta = synth.lognormal_delta_torch(req.n, req.sigma, req.seed, device=device)
+                a.where = torch.empty(1, dtype=torch.int64, pin_memory=True)
+                a.where.copy_(torch.argmax(a.delta).reshape(1), non_blocking=True)
+                a.placed = torch.cuda.Event()
+                a.placed.record(streams[si])
+                a.plan = None
             used += need
             peak_used = max(peak_used, used)
             active.append(a)
@@ -163,6 +177,13 @@ def serve(trace: list, budget_bytes: float = 64e9, max_active: int = 16,
         # progress: poll every plan, step the waiting ones, retire the finished
         still = []
         for a in active:
+            if a.plan is None:  # waiting for its densest cell
+                if a.placed.query():
+                    a.grid, a.params = request_grid(a.req, int(a.where[0]), precision, tol)
+                    with torch.cuda.stream(streams[a.stream]):
+                        a.plan = ndgp.Plan(a.grid, a.params, [a.delta], stream=streams[a.stream])
+                still.append(a)
+                continue
             if a.plan.poll():
                 rep = a.plan.report
                 results.append(Result(a.req.idx, a.req.n, a.req.arrival, a.admitted, now(),
