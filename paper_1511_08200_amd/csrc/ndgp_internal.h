@@ -40,6 +40,10 @@ struct Level {
     // Cell-wise truncation: natural n^3, 0 = the cell is held at its value
     // (no relaxation, no residual, no coarse-grid correction); null = none held.
     const unsigned char *mask = nullptr;
+    // With a mask on a level with fixed ghosts: per colour and block of the
+    // half-sweep launch, 1 if the block relaxes any cell; blocks of held cells
+    // are skipped (both ping-pong arrays must then hold the held values).
+    const unsigned char *active = nullptr;
 
     size_t cells() const { return (size_t)n * n * n; }
     size_t slots() const {
@@ -163,6 +167,10 @@ void launch_cell_mask(const double *phi_parent, const double *psi_parent, int np
                       bool parent_periodic, const ChildBox &b, double threshold,
                       unsigned char *mask, double *partials, hipStream_t st);
 // mask_c (nc^3) = 1 where all eight children in mask_f ((2 nc)^3) are 1
+// Block activity of a masked level for the half sweeps (2 x blocks bytes).
+size_t block_activity_bytes(int n);
+void launch_block_activity(const unsigned char *mask, int n, unsigned char *active,
+                           hipStream_t st);
 void launch_mask_restrict(const unsigned char *mask_f, int nc, unsigned char *mask_c,
                           hipStream_t st);
 

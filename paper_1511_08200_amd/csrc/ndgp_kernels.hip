@@ -27,7 +27,11 @@ __global__ void __launch_bounds__(kBlock)
 k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
               const double *__restrict__ s, Ix<PER> ix, double al, double w, int colour,
               unsigned *__restrict__ fallbacks, const double *__restrict__ hat, int dyn_bc,
-              const unsigned char *__restrict__ mask) {
+              const unsigned char *__restrict__ mask,
+              const unsigned char *__restrict__ active) {
+    // a block whose cells of this colour are all held has nothing to do: both
+    // ping-pong arrays already hold their (fixed) values
+    if (active && !active[colour * gridDim.x + blockIdx.x]) return;
     const int n = ix.n, lg = ix.lg;
     const int half = n >> 1;
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -1242,10 +1246,36 @@ k_mask_restrict(const unsigned char *__restrict__ mf, int lgc, unsigned char *__
     mc[t] = all ? 1 : 0;
 }
 
+// Block activity of a masked level for k_smooth_half: active[c * blocks + b]
+// = 1 if block b of the colour-c launch relaxes any cell (same cell order).
+__global__ void __launch_bounds__(kBlock)
+k_block_activity(const unsigned char *__restrict__ mask, int lg,
+                 unsigned char *__restrict__ active) {
+    const int n = 1 << lg, half = n >> 1, colour = blockIdx.y;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    bool it = false;
+    if (t < (half << (2 * lg))) {
+        const int m = t & (half - 1), row = t >> (lg - 1);
+        const int j = row & (n - 1), k = row >> lg;
+        const int iu = 2 * m + ((colour ^ j ^ k) & 1);
+        it = mask[((k << lg) + j) * n + iu] != 0;
+    }
+    const int any = __syncthreads_or(it ? 1 : 0);
+    if (threadIdx.x == 0) active[colour * gridDim.x + blockIdx.x] = any ? 1 : 0;
+}
+
 } // namespace
 
 // ------------------------------------------------------------------------
 // launchers
+
+size_t block_activity_bytes(int n) { return 2 * (size_t)blocks_for((size_t)n * n * n / 2); }
+
+void launch_block_activity(const unsigned char *mask, int n, unsigned char *active,
+                           hipStream_t st) {
+    const dim3 grid(blocks_for((size_t)n * n * n / 2), 2);
+    k_block_activity<<<grid, kBlock, 0, st>>>(mask, log2i(n), active);
+}
 
 void launch_cell_mask(const double *phi_parent, const double *psi_parent, int np,
                       bool parent_periodic, const ChildBox &b, double threshold,
@@ -1273,11 +1303,12 @@ void launch_smooth_half(const Level &L, const double *pin, double *pout, int col
     if (L.periodic)
         k_smooth_half<true><<<nb, kBlock, 0, st>>>(pin, pout, L.s, make_ix<true>(L.n, L.lg),
                                                    L.alpha, L.omega, colour, fallbacks, nullptr,
-                                                   0, nullptr);
+                                                   0, nullptr, nullptr);
     else
         k_smooth_half<false><<<nb, kBlock, 0, st>>>(pin, pout, L.s, make_ix<false>(L.n, L.lg),
                                                     L.alpha, L.omega, colour, fallbacks, L.hat,
-                                                    L.dyn_bc ? 1 : 0, L.mask);
+                                                    L.dyn_bc ? 1 : 0, L.mask,
+                                                    L.dyn_bc ? nullptr : L.active);
 }
 
 // (on 32^3 and 64^3 the one-workgroup-per-tile pipeline is slower than two

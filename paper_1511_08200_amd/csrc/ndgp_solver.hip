@@ -251,6 +251,7 @@ struct Plan {
     Level32 base32[kMaxLevels]; // mixed precision only
     Level patch[NDGP_MAX_PATCHES][kMaxLevels];
     unsigned char *mask[NDGP_MAX_PATCHES][kMaxLevels] = {}; // cell-wise truncation
+    unsigned char *active[NDGP_MAX_PATCHES] = {}; // block activity of each patch's finest mask
     double *partials = nullptr;
     double *scal = nullptr; // [0] sum delta, [1] sum s^2, [2] sum r^2, [3] sum phi
     unsigned *fallbacks = nullptr;
@@ -303,6 +304,7 @@ size_t carve(Plan &P, char *base) {
                 L.dyn_bc = m > 0;
                 P.mask[q][m] = cv.take<unsigned char>(L.cells());
             }
+            P.active[q] = cv.take<unsigned char>(block_activity_bytes(c.pn[q]));
         }
     }
     P.partials = cv.take<double>(kReduceBlocks);
@@ -673,7 +675,9 @@ PatchOutcome relax_patch(Runner &run, Level *H, int nlev, const double *parent, 
     hipStream_t st = run.st;
     PatchOutcome out;
     ChildBox b0{{origin[0], origin[1], origin[2]}, 0, m};
-    launch_interpolate(parent, npar, parent_periodic, b0, H[0].alt, true, st);
+    // with held cells the partner array holds their values too (blocks of held
+    // cells are never written again)
+    launch_interpolate(parent, npar, parent_periodic, b0, H[0].alt, H[0].active == nullptr, st);
     for (int l = 1; l < nlev; ++l) {
         ChildBox bm{{origin[0], origin[1], origin[2]}, l, m >> l};
         launch_interpolate(parent, npar, parent_periodic, bm, H[l].phi, true, st);
@@ -836,6 +840,8 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
                              P.partials, st);
             launch_reduce_final(P.partials, P.scal + 8 + q, st); // read after the last patch
             H[0].mask = P.mask[q][0];
+            launch_block_activity(P.mask[q][0], c.pn[q], P.active[q], st);
+            H[0].active = P.active[q];
             for (int m = 1; m < c.pnl[q]; ++m) {
                 launch_mask_restrict(P.mask[q][m - 1], H[m].n, P.mask[q][m], st);
                 H[m].mask = P.mask[q][m];
