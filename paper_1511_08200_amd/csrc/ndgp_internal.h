@@ -167,6 +167,11 @@ void launch_cell_mask(const double *phi_parent, const double *psi_parent, int np
                       bool parent_periodic, const ChildBox &b, double threshold,
                       unsigned char *mask, double *partials, hipStream_t st);
 // mask_c (nc^3) = 1 where all eight children in mask_f ((2 nc)^3) are 1
+// Guard bands of the workspace (words <= 64): fill with `word`; count the
+// words that differ into *bad.
+void launch_guard_fill(void *band, int words, uint64_t word, hipStream_t st);
+void launch_guard_check(const void *band, int words, uint64_t word, unsigned *bad,
+                        hipStream_t st);
 // Block activity of a masked level for the half sweeps (2 x blocks bytes).
 size_t block_activity_bytes(int n);
 void launch_block_activity(const unsigned char *mask, int n, unsigned char *active,

@@ -1264,10 +1264,29 @@ k_block_activity(const unsigned char *__restrict__ mask, int lg,
     if (threadIdx.x == 0) active[colour * gridDim.x + blockIdx.x] = any ? 1 : 0;
 }
 
+// guard bands of the workspace (debugging aid): fill, then count changed words
+__global__ void k_guard_fill(uint64_t *__restrict__ g, int words, uint64_t w) {
+    if ((int)threadIdx.x < words) g[threadIdx.x] = w;
+}
+
+__global__ void k_guard_check(const uint64_t *__restrict__ g, int words, uint64_t w,
+                              unsigned *__restrict__ bad) {
+    if ((int)threadIdx.x < words && g[threadIdx.x] != w) atomicAdd(bad, 1u);
+}
+
 } // namespace
 
 // ------------------------------------------------------------------------
 // launchers
+
+void launch_guard_fill(void *band, int words, uint64_t word, hipStream_t st) {
+    k_guard_fill<<<1, 64, 0, st>>>(static_cast<uint64_t *>(band), words, word);
+}
+
+void launch_guard_check(const void *band, int words, uint64_t word, unsigned *bad,
+                        hipStream_t st) {
+    k_guard_check<<<1, 64, 0, st>>>(static_cast<const uint64_t *>(band), words, word, bad);
+}
 
 size_t block_activity_bytes(int n) { return 2 * (size_t)blocks_for((size_t)n * n * n / 2); }
 

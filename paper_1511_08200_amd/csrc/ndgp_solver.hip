@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -230,14 +231,36 @@ bool resolve(const ndgp_grid *g, const ndgp_params *p, Cfg &c, std::string &why)
 // ------------------------------------------------------------------------
 // workspace
 
+// Debugging aid: with the environment variable NDGP_GUARD_BANDS=1 (read once
+// per process) every sub-buffer of the solve's workspace is followed by a
+// guard band of kGuardWords words holding kGuardWord, written after the
+// carve and checked when the solve ends; an overwritten band fails the call
+// with NDGP_EDEVICE.  The workspace sizes grow to match.
+constexpr size_t kGuardWords = 32;
+constexpr uint64_t kGuardWord = 0x7ff4dead5eedbeefull; // a signalling-NaN payload
+
+bool guard_bands_on() {
+    static const bool on = [] {
+        const char *v = std::getenv("NDGP_GUARD_BANDS");
+        return v && v[0] && v[0] != '0';
+    }();
+    return on;
+}
+
 struct Carver {
     char *base;
     size_t off = 0;
+    std::vector<size_t> *guards = nullptr; // offsets of the guard bands laid out
     template <class T>
     T *take(size_t count) {
         off = (off + 255) & ~(size_t)255;
         T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
         off += count * sizeof(T);
+        if (guard_bands_on()) {
+            off = (off + 255) & ~(size_t)255;
+            if (guards) guards->push_back(off);
+            off += kGuardWords * sizeof(uint64_t);
+        }
         return p;
     }
 };
@@ -256,11 +279,16 @@ struct Plan {
     double *scal = nullptr; // [0] sum delta, [1] sum s^2, [2] sum r^2, [3] sum phi
     unsigned *fallbacks = nullptr;
     bool phi32_fresh = false; // base32[0].phi holds (float) base[0].phi
+    char *ws = nullptr;               // the carved workspace (guard bands on)
+    std::vector<size_t> guards;       // their offsets in it
 };
 
 // Lays out every array in `base` (or only counts bytes when base == nullptr).
 size_t carve(Plan &P, char *base) {
     Carver cv{base};
+    P.guards.clear();
+    P.ws = base;
+    if (base) cv.guards = &P.guards;
     const Cfg &c = P.c;
     for (int l = 0; l < c.nl; ++l) {
         Level &L = P.base[l];
@@ -311,6 +339,17 @@ size_t carve(Plan &P, char *base) {
     P.scal = cv.take<double>(16);
     P.fallbacks = cv.take<unsigned>(16);
     return cv.off;
+}
+
+void arm_guards(const Plan &P, hipStream_t st) {
+    for (size_t off : P.guards)
+        launch_guard_fill(P.ws + off, (int)kGuardWords, kGuardWord, st);
+}
+
+// counts overwritten guard words into P.fallbacks[2]
+void check_guards(const Plan &P, hipStream_t st) {
+    for (size_t off : P.guards)
+        launch_guard_check(P.ws + off, (int)kGuardWords, kGuardWord, P.fallbacks + 2, st);
 }
 
 // workspace of ndgp_residual on the largest level
@@ -748,6 +787,7 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
                                      std::to_string(need));
     carve(P, aligned_base(ws));
     P.base[0].phi = phi[0];
+    arm_guards(P, st);
 
     ndgp_report R;
     std::memset(&R, 0, sizeof(R));
@@ -759,7 +799,7 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
     Runner run{P, st, slot.p};
     run.timer = &timer;
     run.timed_s = P.base[0].s;
-    HIP_TRY(hipMemsetAsync(P.fallbacks, 0, 2 * sizeof(unsigned), st));
+    HIP_TRY(hipMemsetAsync(P.fallbacks, 0, 3 * sizeof(unsigned), st));
 
     // domain source: S = Omega_m (delta - mean) / (a beta), in cell units (x
     // h^2); its norm, the initial guess and the first residual norm are
@@ -858,15 +898,18 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         R.rel_res[q + 1] = rel;
         if (sq != NDGP_OK && status == NDGP_OK) status = sq;
     }
-    unsigned fb[2] = {0, 0};
+    unsigned fb[3] = {0, 0, 0};
+    check_guards(P, st);
     HIP_TRY(hipGetLastError());
     if (psi && c.nrelax > 0) // iterated cells per masked patch, counted on the device
         HIP_TRY(hipMemcpyAsync(slot.p + 8, P.scal + 8, c.nrelax * sizeof(double),
                                hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(slot.p, P.fallbacks, 2 * sizeof(unsigned), hipMemcpyDeviceToHost,
+    HIP_TRY(hipMemcpyAsync(slot.p, P.fallbacks, 3 * sizeof(unsigned), hipMemcpyDeviceToHost,
                            st));
     HIP_TRY(hipStreamSynchronize(st));
-    std::memcpy(fb, slot.p, 2 * sizeof(unsigned));
+    std::memcpy(fb, slot.p, 3 * sizeof(unsigned));
+    if (fb[2]) return fail(NDGP_EDEVICE, std::to_string(fb[2]) + " workspace guard-band words "
+                                         "were overwritten");
     R.fallbacks = (int32_t)fb[0];
     R.holds = (int32_t)fb[1];
     if (psi)
@@ -1420,8 +1463,9 @@ struct ndgp_plan {
     Plan P;
     hipStream_t st = nullptr;
     double *slot = nullptr; // pinned: [0] sum delta, [1] sum s^2, [2] sum r^2,
-                            //         [3] sum phi, [4] the two relaxation
-                            //         event counters (bits)
+                            //         [3] sum phi, [4..5] the two relaxation
+                            //         event counters and the guard-band count
+                            //         (bits)
     hipEvent_t ev = nullptr;
     const double *delta[1 + NDGP_MAX_PATCHES] = {};
     double *phi[1 + NDGP_MAX_PATCHES] = {};
@@ -1456,7 +1500,8 @@ void plan_enqueue_tail(ndgp_plan *pl, bool zero_field) {
     }
     HIP_TRY(hipMemcpyAsync(pl->slot + 3, pl->P.scal + 3, sizeof(double), hipMemcpyDeviceToHost,
                            pl->st));
-    HIP_TRY(hipMemcpyAsync(pl->slot + 4, pl->P.fallbacks, 2 * sizeof(unsigned),
+    check_guards(pl->P, pl->st);
+    HIP_TRY(hipMemcpyAsync(pl->slot + 4, pl->P.fallbacks, 3 * sizeof(unsigned),
                            hipMemcpyDeviceToHost, pl->st));
     plan_record(pl);
     pl->state = ndgp_plan::FINISHING;
@@ -1496,7 +1541,8 @@ ndgp_status plan_create_impl(const ndgp_grid *grid, const ndgp_params *params,
         HIP_TRY(hipEventCreateWithFlags(&pl->ev, hipEventDisableTiming));
         Runner run = plan_runner(pl);
         const size_t cells0 = (size_t)c.n * c.n * c.n;
-        HIP_TRY(hipMemsetAsync(pl->P.fallbacks, 0, 2 * sizeof(unsigned), st));
+        arm_guards(pl->P, st);
+        HIP_TRY(hipMemsetAsync(pl->P.fallbacks, 0, 3 * sizeof(unsigned), st));
         run.enqueue_sum(delta[0], cells0, false, 0);
         launch_source(delta[0], cells0, pl->P.scal + 0, 1.0 / (double)cells0, c.fsrc * c.h * c.h,
                       pl->P.base[0].s, st);
@@ -1548,10 +1594,12 @@ ndgp_status plan_poll_impl(ndgp_plan *pl, int32_t *done, ndgp_report *rep) {
     const Cfg &c = pl->P.c;
     const size_t cells0 = (size_t)c.n * c.n * c.n;
     if (pl->state == ndgp_plan::FINISHING) {
-        unsigned fb[2] = {0, 0};
-        std::memcpy(fb, pl->slot + 4, 2 * sizeof(unsigned));
+        unsigned fb[3] = {0, 0, 0};
+        std::memcpy(fb, pl->slot + 4, 3 * sizeof(unsigned));
         pl->R.fallbacks = (int32_t)fb[0];
         pl->R.holds = (int32_t)fb[1];
+        if (fb[2])
+            plan_fail(pl, NDGP_EDEVICE, "workspace guard-band words were overwritten");
         pl->R.phi_mean = pl->slot[3] / (double)cells0;
         pl->R.t_total_ms = std::chrono::duration<double, std::milli>(
                                std::chrono::steady_clock::now() - pl->t0)
