@@ -448,6 +448,10 @@ def serving_workload(ndgp, torch, count, rate, sat_count):
     log(f"serving {sat_count} requests arriving at once")
     res2, summ2 = serving.serve(trace2, budget_bytes=64e9, max_active=16, realtime=False, log=log)
     out["saturation"] = summ2
+    log(f"the same {sat_count} requests one at a time")
+    seq = serving.serve_one_at_a_time(trace2)
+    out["one_at_a_time"] = seq
+    out["saturation_speedup_vs_one_at_a_time"] = round(summ2["solves_per_s"] / seq["solves_per_s"], 3)
     return out
 
 

@@ -170,12 +170,49 @@ __device__ __forceinline__ double relax_cell(const double v[19], double s, doubl
     return fma(w, (B - fast_sqrt(D)) / (18.0 * al), v[0]);
 }
 
-// Coarse levels of a refinement: write the ghosts whose correction is taken
-// from interior cell (i,j,k), now holding `val`.  The correction phi - hat is
-// extrapolated linearly through zero at the fine boundary position (half a
-// fine cell outside), which puts -1/3 of it on the coarse ghost per axis
-// along which the ghost lies outside.  Every ghost has exactly one such
-// interior cell, so each is written by one thread.
+// Coarse levels of a refinement: the ghosts whose correction is taken from
+// interior cell (i,j,k).  The correction phi - hat is extrapolated linearly
+// through zero at the fine boundary position (half a fine cell outside), which
+// puts -1/3 of it on the coarse ghost per axis along which the ghost lies
+// outside.  Every ghost has exactly one such interior cell, so each is
+// written by one thread.
+//
+// ghost_slots: q[0] the cell itself, q[m] (m = 1..7, bit 0 x, bit 1 y, bit 2
+// z) the ghost reached by leaving the grid along the axes of m; an axis along
+// which the cell is not on the boundary keeps the cell's own index (always in
+// range).  Returns the bit set of the slots that are ghosts of this cell.
+template <bool PER>
+__device__ __forceinline__ unsigned ghost_slots(const Ix<PER> &ix, int i, int j, int k, int q[8]) {
+    const int n = ix.n;
+    const bool bx = i == 0 || i == n - 1, by = j == 0 || j == n - 1, bz = k == 0 || k == n - 1;
+    const int gx = bx ? (i == 0 ? -1 : n) : i, gy = by ? (j == 0 ? -1 : n) : j,
+              gz = bz ? (k == 0 ? -1 : n) : k;
+    unsigned own = 0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        q[m] = ix(m & 1 ? gx : i, m & 2 ? gy : j, m & 4 ? gz : k);
+        const bool ok = m != 0 && !((m & 1) && !bx) && !((m & 2) && !by) && !((m & 4) && !bz);
+        own |= ok ? 1u << m : 0u;
+    }
+    return own;
+}
+
+// ghost value from the cell's new value, with h[m] = hat[q[m]] of ghost_slots
+__device__ __forceinline__ void store_owned_ghosts(double *__restrict__ out, const int q[8],
+                                                   const double h[8], unsigned own, double val) {
+    const double e = val - h[0];
+#pragma unroll
+    for (int m = 1; m < 8; ++m) {
+        if (!(own >> m & 1u)) continue;
+        const int d = (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1);
+        const double f = d == 1 ? -1.0 / 3.0 : (d == 2 ? 1.0 / 9.0 : -1.0 / 27.0);
+        out[q[m]] = h[m] + f * e;
+    }
+}
+
+// Write the ghosts of cell (i,j,k) now holding `val`.  Every hat value is
+// loaded before the first store, so that a boundary cell waits for memory
+// once, not once per ghost.
 template <bool PER>
 __device__ __forceinline__ void write_owned_ghosts(double *__restrict__ out,
                                                    const double *__restrict__ hat,
@@ -183,22 +220,13 @@ __device__ __forceinline__ void write_owned_ghosts(double *__restrict__ out,
                                                    double val) {
     if constexpr (!PER) {
         const int n = ix.n;
-        const bool bx = i == 0 || i == n - 1, by = j == 0 || j == n - 1, bz = k == 0 || k == n - 1;
-        if (!(bx || by || bz)) return;
-        const int gx = i == 0 ? -1 : n, gy = j == 0 ? -1 : n, gz = k == 0 ? -1 : n;
-        const double e = val - hat[ix(i, j, k)];
+        if (!(i == 0 || i == n - 1 || j == 0 || j == n - 1 || k == 0 || k == n - 1)) return;
+        int q[8];
+        double h[8];
+        const unsigned own = ghost_slots(ix, i, j, k, q);
 #pragma unroll
-        for (int mz = 0; mz < 2; ++mz)
-#pragma unroll
-            for (int my = 0; my < 2; ++my)
-#pragma unroll
-                for (int mx = 0; mx < 2; ++mx) {
-                    if ((mx && !bx) || (my && !by) || (mz && !bz) || (mx + my + mz) == 0) continue;
-                    const int d = mx + my + mz;
-                    const double f = d == 1 ? -1.0 / 3.0 : (d == 2 ? 1.0 / 9.0 : -1.0 / 27.0);
-                    const int q = ix(mx ? gx : i, my ? gy : j, mz ? gz : k);
-                    out[q] = hat[q] + f * e;
-                }
+        for (int m = 0; m < 8; ++m) h[m] = hat[q[m]];
+        store_owned_ghosts(out, q, h, own, val);
     }
 }
 

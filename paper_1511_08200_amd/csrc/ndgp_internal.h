@@ -44,6 +44,8 @@ struct Level {
     // half-sweep launch, 1 if the block relaxes any cell; blocks of held cells
     // are skipped (both ping-pong arrays must then hold the held values).
     const unsigned char *active = nullptr;
+    // The same per workgroup of the fused sweep (1 if it writes any relaxed cell).
+    const unsigned char *tile_on = nullptr;
 
     size_t cells() const { return (size_t)n * n * n; }
     size_t slots() const {
@@ -139,6 +141,22 @@ struct BottomLevels {
 bool bottom_ok(const Level *H, int l, int nl);
 void launch_bottom(const Level *H, int l, int nl, int nu1, int nu2, int csweeps,
                    unsigned *fallbacks, hipStream_t st);
+// The same for the coarse levels of a refinement (padded, ghost shells that
+// follow the interior, held cells): level l (n <= 16) and every coarser level.
+struct BottomDirLevels {
+    int levels;                                 // l .. nl-1
+    int lg0;                                    // log2(n) of level l
+    double alpha[kBottomMaxLevels];
+    double omega;
+    double *phi0;                               // level l: in/out, padded
+    const double *s0;                           // level l: natural
+    const double *hat[kBottomMaxLevels];        // padded (ghost shells; interiors of
+                                                // the coarser levels are recomputed)
+    const unsigned char *mask[kBottomMaxLevels]; // natural, or null (none held)
+};
+bool bottom_dir_ok(const Level *H, int l, int nl);
+void launch_bottom_dir(const Level *H, int l, int nl, int nu1, int nu2, int csweeps,
+                       unsigned *fallbacks, hipStream_t st);
 // s = f * (delta - sum[0] * inv_count_mean)     (sum: device scalar)
 void launch_source(const double *delta, size_t count, const double *sum, double inv_count_mean,
                    double f, double *s, hipStream_t st);
@@ -172,8 +190,10 @@ void launch_cell_mask(const double *phi_parent, const double *psi_parent, int np
 void launch_guard_fill(void *band, int words, uint64_t word, hipStream_t st);
 void launch_guard_check(const void *band, int words, uint64_t word, unsigned *bad,
                         hipStream_t st);
-// Block activity of a masked level for the half sweeps (2 x blocks bytes).
+// Block activity of a masked level: per block of the half sweeps of both
+// colours, then per workgroup of the fused sweep (tile_activity points there).
 size_t block_activity_bytes(int n);
+const unsigned char *tile_activity(const unsigned char *active, int n);
 void launch_block_activity(const unsigned char *mask, int n, unsigned char *active,
                            hipStream_t st);
 void launch_mask_restrict(const unsigned char *mask_f, int nc, unsigned char *mask_c,

@@ -91,14 +91,18 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
 // the shell keep their value instead of being relaxed, loads beyond the shell
 // (needed only to relax such cells) are clamped to it, and pairs are moved
 // as two 8-byte values (padded rows do not keep a pair 16-byte aligned); the
-// shell itself is never written (both ping-pong arrays hold it).
+// shell itself is never written (both ping-pong arrays hold it).  With a
+// mask (cell-wise truncation) a held cell keeps its value like a shell cell,
+// and a workgroup whose own cells are all held (tile_on 0) returns at once:
+// both ping-pong arrays hold the held values, so there is nothing to write.
 template <int TX, int TY, int TZ, int NT, bool PRO, bool PER = true>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(4))) // two workgroups per CU: at most 128 VGPRs
 k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
               const double *__restrict__ s, int lg, double al, double w,
               unsigned *__restrict__ fallbacks, const double *__restrict__ phi_c,
-              const double *__restrict__ hat_c) {
+              const double *__restrict__ hat_c, const unsigned char *__restrict__ mask,
+              const unsigned char *__restrict__ tile_on) {
     constexpr int PX = TX + 4, PY = TY + 4;   // plane with halo 2
     constexpr int HX = PX / 2;                // cells of one colour per row
     constexpr int PLANE = PX * PY;
@@ -124,6 +128,8 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     const int z0 = (logical / tiles) * TZ;
     const int tid = threadIdx.x;
     unsigned fb = 0;
+    if constexpr (!PER)
+        if (tile_on && !tile_on[logical]) return;
 
     // padded layout (PER = false): row pitch n + 2, cell (x, y, z) at
     // ((z + 1) pitch + y + 1) pitch + x + 1, every coordinate clamped to [-1, n]
@@ -147,6 +153,11 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         if constexpr (PER) return false;
         else return (unsigned)x >= (unsigned)n || (unsigned)y >= (unsigned)n ||
                     (unsigned)z >= (unsigned)n;
+    };
+    // a held cell (mask 0, loaded with its source a step ahead): kept
+    auto held_at = [&](int at) {
+        if constexpr (PER) return false;
+        else return mask != nullptr && mask[at] == 0;
     };
     auto s5 = [](int z) { return (z + 5 * 4096) % 5; };
     auto s3 = [](int z) { return (z + 3 * 4096) % 3; };
@@ -256,17 +267,19 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         red_jj[e] = q - (red_rr[e] - 1) * RED_ROW;
     }
     // the sources of plane z's red cells, loaded a step ahead of their use
-    auto red_sources = [&](int z, double out[2]) {
+    auto red_sources = [&](int z, double out[2], bool hold[2]) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int rr = red_rr[e];
             const int p = (rr + z) & 1;
             const int gx = x0 - 2 + 2 * (red_jj[e] + 1 - p) + p, gy = y0 - 2 + rr;
-            out[e] = s[sidx(gx, gy, z)]; // in bounds also when !red_on[e]
+            const int at = sidx(gx, gy, z); // in bounds also when !red_on[e]
+            out[e] = s[at];
+            hold[e] = held_at(at);
         }
     };
     // red cells of plane z over the tile + 1-cell halo -> R(z)
-    auto red_plane = [&](int z, const double src[2]) {
+    auto red_plane = [&](int z, const double src[2], const bool hold[2]) {
         const double(*m0)[HX] = PR[s3(z - 1)], (*m1)[HX] = PB[s5(z - 1)];
         const double(*c0)[HX] = PR[s3(z)], (*c1)[HX] = PB[s5(z)];
         const double(*p0)[HX] = PR[s3(z + 1)], (*p1)[HX] = PB[s5(z + 1)];
@@ -288,7 +301,7 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
                 rz[rr][j] = relax_cell(v, src[e], al, w, fb);
             } else {
                 const int gx = x0 - 2 + 2 * j + p, gy = y0 - 2 + rr;
-                rz[rr][j] = ghost(gx, gy, z) ? v[0] : relax_cell(v, src[e], al, w, fb);
+                rz[rr][j] = ghost(gx, gy, z) || hold[e] ? v[0] : relax_cell(v, src[e], al, w, fb);
             }
         }
     };
@@ -298,12 +311,18 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     const int yt = y0 - 2 + rt;
     const int xy_t = (yt << lg) | (x0 - 2 + 2 * jt);
     const int pxy_t = (yt + 1) * pitch + x0 - 2 + 2 * jt + 1; // padded (PER = false)
-    auto black_source = [&](int k) {
+    auto black_source = [&](int k, bool &hold) {
         const int pb = (1 + rt + k) & 1;
-        if constexpr (PER) return s[zoff(k) | xy_t | pb];
-        else return s[((k < n ? k : m) << (2 * lg) | xy_t) + pb]; // plane n: loaded, unused
+        if constexpr (PER) {
+            hold = false;
+            return s[zoff(k) | xy_t | pb];
+        } else {
+            const int at = ((k < n ? k : m) << (2 * lg) | xy_t) + pb; // plane n: loaded, unused
+            hold = held_at(at);
+            return s[at];
+        }
     };
-    auto black_and_store = [&](int k, double sv) {
+    auto black_and_store = [&](int k, double sv, bool hold) {
         const double(*rm)[HX] = R[s3(k - 1)], (*r0)[HX] = R[s3(k)], (*rp)[HX] = R[s3(k + 1)];
         const double(*m1)[HX] = PB[s5(k - 1)], (*c1)[HX] = PB[s5(k)], (*p1)[HX] = PB[s5(k + 1)];
         const int pb = (1 + rt + k) & 1; // black cell at column 2jt + pb
@@ -314,7 +333,7 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
             c1[rr + 1][a], c1[rr - 1][a], c1[rr + 1][b], c1[rr - 1][b],
             p1[rr][a], m1[rr][a], p1[rr][b], m1[rr][b],
             p1[rr + 1][j], m1[rr + 1][j], p1[rr - 1][j], m1[rr - 1][j]};
-        const double vb = relax_cell(v, sv, al, w, fb);
+        const double vb = hold ? v[0] : relax_cell(v, sv, al, w, fb);
         const double vr = r0[rr][j]; // the red cell of the pair, column 2jt + 1 - pb
         // the pair as one 16-byte non-temporal store: the new field is not
         // read again in this sweep, so it need not displace the halo lines
@@ -350,47 +369,49 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     fetch(z0);
     commit(z0);
     double ra[2], rb[2], ba, bb;
-    red_sources(z0 - 1, ra);
+    bool ha[2], hb[2], hba, hbb;
+    red_sources(z0 - 1, ra, ha);
     fetch(z0 + 1);
     if constexpr (PRO) e_load(c0 + 1);
     __syncthreads();
-    red_plane(z0 - 1, ra);
+    red_plane(z0 - 1, ra, ha);
     __syncthreads(); // red(z0-1) has read the red slot that plane z0+1 takes
     if constexpr (PRO) {
         e_store(c0 + 1); // the slot of coarse plane c0-2, last used by plane z0-2
         __syncthreads();
     }
     commit(z0 + 1);
-    red_sources(z0, ra);
+    red_sources(z0, ra, ha);
     fetch(z0 + 2);
     __syncthreads();
-    red_plane(z0, ra);
+    red_plane(z0, ra, ha);
     __syncthreads(); // red(z0) has read the red slot that plane z0+2 takes
-    red_sources(z0 + 1, ra);
-    ba = black_source(z0);
+    red_sources(z0 + 1, ra, ha);
+    ba = black_source(z0, hba);
     if constexpr (PRO) e_load(c0 + 2);
     // one step: red(k+1), black(k); loads the sources of red(k+2), black(k+1)
     // and the field of plane k+3 (on the last step one plane past the ones
     // used: in bounds, never committed).  With PRO an even step stores
     // coarse plane k/2+2 (first needed by plane k+3, in the slot of plane
     // k/2-1, last needed by plane k) and an odd step loads the next one.
-    auto step = [&](int k, bool even, const double (&use_r)[2], double use_b,
-                    double (&next_r)[2], double &next_b) {
+    auto step = [&](int k, bool even, const double (&use_r)[2], const bool (&use_rh)[2],
+                    double use_b, bool use_bh, double (&next_r)[2], bool (&next_rh)[2],
+                    double &next_b, bool &next_bh) {
         commit(k + 2); // red slot of plane k-1 (last read by red(k)), black of k-3
-        red_sources(k + 2, next_r);
-        next_b = black_source(k + 1);
+        red_sources(k + 2, next_r, next_rh);
+        next_b = black_source(k + 1, next_bh);
         if (PRO && !even) e_load((k + 1) / 2 + 2);
         fetch(k + 3);
         __syncthreads();
         if (PRO && even) e_store(k / 2 + 2);
-        red_plane(k + 1, use_r); // writes the R slot of plane k-2, last read by black(k-1)
+        red_plane(k + 1, use_r, use_rh); // writes the R slot of plane k-2, last read by black(k-1)
         __syncthreads();
-        black_and_store(k, use_b);
+        black_and_store(k, use_b, use_bh);
     };
     static_assert(TZ % 2 == 0, "the z loop is unrolled by two");
     for (int k = z0; k < z0 + TZ; k += 2) {
-        step(k, true, ra, ba, rb, bb);
-        step(k + 1, false, rb, bb, ra, ba);
+        step(k, true, ra, ha, ba, hba, rb, hb, bb, hbb);
+        step(k + 1, false, rb, hb, bb, hbb, ra, ha, ba, hba);
     }
     if (fb) flush_events(fallbacks, fb);
 }
@@ -557,11 +578,11 @@ k_coarse_source_tiled(const double *__restrict__ hat, double *__restrict__ phi,
 // one-cell halo; each phi and S value is read from HBM about once.  One
 // partial sum per workgroup (fixed order), optional r_out = r * scale (FP64,
 // or rounded to FP32 for the mixed-precision loop).
-template <int TX, int TY, class OutT>
+template <int TX, int TY, class OutT, bool PER = true>
 __global__ void __launch_bounds__(kBlock)
 k_residual_tiled(const double *__restrict__ phi, const double *__restrict__ s, int lg, int tz,
                  double al, double *__restrict__ partials, OutT *__restrict__ r_out,
-                 double r_scale) {
+                 double r_scale, const unsigned char *__restrict__ mask = nullptr) {
     constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
     constexpr int PRE = (PLANE + kBlock - 1) / kBlock;
     constexpr int CELLS = TX * TY / kBlock; // output cells per thread per plane
@@ -580,14 +601,17 @@ k_residual_tiled(const double *__restrict__ phi, const double *__restrict__ s, i
         const int q = tid + e * kBlock;
         pq[e] = q < PLANE ? q : -1;
         const int yy = q / PX, xx = q - yy * PX;
-        pxy[e] = (((y0 - 1 + yy) & m) << lg) | ((x0 - 1 + xx) & m);
+        // periodic: wrapped natural index; Dirichlet: padded (n+2)^3, whose
+        // ghost shell holds the halo beyond the level's faces
+        pxy[e] = PER ? (((y0 - 1 + yy) & m) << lg) | ((x0 - 1 + xx) & m)
+                     : (y0 + yy) * (n + 2) + (x0 + xx);
     }
     double pre[PRE];
     auto fetch = [&](int z) {
-        const int zo = (z & m) << (2 * lg);
+        const int zo = PER ? (z & m) << (2 * lg) : (z + 1) * (n + 2) * (n + 2);
 #pragma unroll
         for (int e = 0; e < PRE; ++e)
-            if (pq[e] >= 0) pre[e] = phi[zo | pxy[e]];
+            if (pq[e] >= 0) pre[e] = phi[zo + pxy[e]];
     };
     auto commit = [&](int z) {
         double *dst = P[z & 3];
@@ -620,7 +644,8 @@ k_residual_tiled(const double *__restrict__ phi, const double *__restrict__ s, i
                 pp[rr][c + 1], pm[rr][c + 1], pp[rr][c - 1], pm[rr][c - 1],
                 pp[rr + 1][c], pm[rr + 1][c], pp[rr - 1][c], pm[rr - 1][c]};
             const int g = ((k << lg | (y0 + yt)) << lg) | (x0 + xt);
-            const double r = s[g] - apply_L(stencil_terms(v), al);
+            // a held cell (cell-wise truncation) is not part of the equations
+            const double r = !PER && mask && !mask[g] ? 0.0 : s[g] - apply_L(stencil_terms(v), al);
             acc = fma(r, r, acc);
             if (r_out) r_out[g] = (OutT)(r * r_scale);
         }
@@ -841,6 +866,32 @@ k_prolong8(double *__restrict__ phi_f, Ix<PER> ixf, const double *__restrict__ p
                 const int q = ixc(I + di - 1, J + dj - 1, K + dk - 1);
                 cv[dk][dj][di] = CORRECT ? phi_c[q] - hat_c[q] : phi_c[q];
             }
+    // Dirichlet levels: the children's masks and old values are loaded with
+    // the coarse values, before any store (one wait for memory, not one per
+    // child)
+    unsigned char it[2][2][2];
+    double old8[2][2][2] = {};
+    if constexpr (!PER) {
+#pragma unroll
+        for (int ck = 0; ck < 2; ++ck)
+#pragma unroll
+            for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+                for (int ci = 0; ci < 2; ++ci) {
+                    it[ck][cj][ci] = 1;
+                    if (CORRECT) old8[ck][cj][ci] = phi_f[ixf(2 * I + ci, 2 * J + cj, 2 * K + ck)];
+                }
+        if (mask_f)
+#pragma unroll
+            for (int ck = 0; ck < 2; ++ck)
+#pragma unroll
+                for (int cj = 0; cj < 2; ++cj) {
+                    const size_t row = ((size_t)(2 * K + ck) * ixf.n + 2 * J + cj) * ixf.n + 2 * I;
+                    it[ck][cj][0] = mask_f[row];
+                    it[ck][cj][1] = mask_f[row + 1];
+                }
+    }
+    double val8[2][2][2];
 #pragma unroll
     for (int ck = 0; ck < 2; ++ck)
 #pragma unroll
@@ -877,15 +928,39 @@ k_prolong8(double *__restrict__ phi_f, Ix<PER> ixf, const double *__restrict__ p
             } else {
 #pragma unroll
                 for (int ci = 0; ci < 2; ++ci) {
-                    // a held cell keeps its value: no correction
-                    if (mask_f && !mask_f[((size_t)k * ixf.n + j) * ixf.n + i + ci]) continue;
-                    const int q = ixf(i + ci, j, k);
-                    const double val = CORRECT ? phi_f[q] + out[ci] : out[ci];
-                    phi_f[q] = val;
-                    if (dyn_bc_f) write_owned_ghosts(phi_f, hat_f, ixf, i + ci, j, k, val);
+                    const double val = CORRECT ? old8[ck][cj][ci] + out[ci] : out[ci];
+                    val8[ck][cj][ci] = val;
+                    if (it[ck][cj][ci]) phi_f[ixf(i + ci, j, k)] = val; // else held: kept
                 }
             }
         }
+    // the ghosts of the children on the boundary of a coarse level of a
+    // refinement, four children at a time: their hat values first, then the
+    // stores
+    if constexpr (!PER) {
+        if (!dyn_bc_f || !(I == 0 || I == nc - 1 || J == 0 || J == nc - 1 || K == 0 || K == nc - 1))
+            return;
+#pragma unroll
+        for (int ck = 0; ck < 2; ++ck) {
+            int q[2][2][8];
+            double h[2][2][8];
+            unsigned own[2][2];
+#pragma unroll
+            for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+                for (int ci = 0; ci < 2; ++ci) {
+                    own[cj][ci] = ghost_slots(ixf, 2 * I + ci, 2 * J + cj, 2 * K + ck, q[cj][ci]);
+                    if (!it[ck][cj][ci]) own[cj][ci] = 0; // a held cell writes nothing
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) h[cj][ci][m] = hat_f[q[cj][ci][m]];
+                }
+#pragma unroll
+            for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+                for (int ci = 0; ci < 2; ++ci)
+                    store_owned_ghosts(phi_f, q[cj][ci], h[cj][ci], own[cj][ci], val8[ck][cj][ci]);
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -1104,6 +1179,186 @@ k_bottom(double *__restrict__ phi, const double *__restrict__ s, int lg0, Bottom
     if (fb) flush_events(fallbacks, fb);
 }
 
+// The bottom of a refinement's V-cycle in one workgroup: its coarse levels
+// from one of at most 16^3 cells down to the coarsest, padded with their
+// ghost shells, all arrays in LDS.  Each step has the arithmetic, in the same
+// order, of the per-level kernels of those levels (k_smooth_half,
+// k_restrict_residual, k_coarse_source, k_coarsest, k_prolong8), so the result
+// is bit for bit theirs.  Those kernels rewrite the ghosts of every cell they
+// write from its new value (write_owned_ghosts); a ghost is thus always the
+// same function of its interior cell's current value, and the half sweeps
+// here, done in place (new values of one colour into registers, wait, store),
+// rewrite only the ghosts of the cells they change.  Held cells (mask 0) keep
+// their values, take no residual and no correction.
+constexpr int kBottomDirThreads = 1024;
+constexpr int kBottomDirPerThread = 2048 / kBottomDirThreads; // cells of one colour at 16^3
+constexpr int kBottomDirPad = 18 * 18 * 18 + 10 * 10 * 10 + 6 * 6 * 6 + 4 * 4 * 4;
+constexpr int kBottomDirCells = 4096 + 512 + 64 + 8;
+
+__global__ void __launch_bounds__(kBottomDirThreads)
+k_bottom_dir(BottomDirLevels bl, int nu1, int nu2, int csweeps, unsigned *__restrict__ fallbacks) {
+    __shared__ double PHI[kBottomDirPad];
+    __shared__ double HAT[kBottomDirPad];
+    __shared__ double SRC[kBottomDirCells];
+    __shared__ unsigned char MSK[kBottomDirCells];
+    const int tid = threadIdx.x;
+    const int nb = bl.levels, lg0 = bl.lg0;
+    auto pad = [&](int q) {
+        const int m = (1 << (lg0 - q)) + 2;
+        return m * m * m;
+    };
+    // level q starts at poff(q) in PHI and HAT, at coff(q) in SRC and MSK
+    auto poff = [&](int q) {
+        int o = 0;
+        for (int p = 0; p < q; ++p) o += pad(p);
+        return o;
+    };
+    auto coff = [&](int q) {
+        int o = 0;
+        for (int p = 0; p < q; ++p) o += 1 << (3 * (lg0 - p));
+        return o;
+    };
+    auto alpha = [&](int q) {
+        return q == 0 ? bl.alpha[0] : q == 1 ? bl.alpha[1] : q == 2 ? bl.alpha[2] : bl.alpha[3];
+    };
+    auto ixq = [&](int q) {
+        const int lg = lg0 - q;
+        return Ix<false>{1 << lg, lg, (1 << lg) + 2};
+    };
+    unsigned fb = 0;
+    for (int q = 0; q < nb; ++q) {
+        const double *hg = q == 0 ? bl.hat[0] : q == 1 ? bl.hat[1] : q == 2 ? bl.hat[2] : bl.hat[3];
+        const unsigned char *mg =
+            q == 0 ? bl.mask[0] : q == 1 ? bl.mask[1] : q == 2 ? bl.mask[2] : bl.mask[3];
+        double *hl = HAT + poff(q);
+        for (int t = tid; t < pad(q); t += kBottomDirThreads) hl[t] = hg[t];
+        unsigned char *ml = MSK + coff(q);
+        for (int t = tid; t < (1 << (3 * (lg0 - q))); t += kBottomDirThreads)
+            ml[t] = mg ? mg[t] : (unsigned char)1;
+    }
+    for (int t = tid; t < pad(0); t += kBottomDirThreads) PHI[t] = bl.phi0[t];
+    for (int t = tid; t < (1 << (3 * lg0)); t += kBottomDirThreads) SRC[t] = bl.s0[t];
+    __syncthreads();
+
+    auto smooth = [&](int q, int sweeps) {
+        const Ix<false> ix = ixq(q);
+        const int lg = ix.lg, n = ix.n, half = n >> 1;
+        double *ph = PHI + poff(q);
+        const double *hh = HAT + poff(q);
+        const double *sr = SRC + coff(q);
+        const unsigned char *mk = MSK + coff(q);
+        const double al = alpha(q);
+        const int ncol = (n * n * n) >> 1; // cells of one colour
+        for (int sw = 0; sw < sweeps; ++sw)
+            for (int col = 0; col < 2; ++col) {
+                double v[kBottomDirPerThread];
+                int cell[kBottomDirPerThread]; // natural index, or -1: nothing to store
+#pragma unroll
+                for (int c = 0; c < kBottomDirPerThread; ++c) {
+                    v[c] = 0.0;
+                    cell[c] = -1;
+                    const int t = tid + c * kBottomDirThreads;
+                    if (t < ncol) {
+                        const int m = t & (half - 1);
+                        const int row = t >> (lg - 1);
+                        const int j = row & (n - 1), k = row >> lg;
+                        const int i = 2 * m + ((col ^ j ^ k) & 1);
+                        const int nat = ((k << lg) + j) * n + i;
+                        if (mk[nat]) { // a held cell keeps its value (and its ghosts)
+                            double g[19];
+                            gather(ph, ix, i, j, k, g);
+                            v[c] = relax_cell(g, sr[nat], al, bl.omega, fb);
+                            cell[c] = nat;
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0); // one cell at a time: no spills
+                }
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < kBottomDirPerThread; ++c)
+                    if (cell[c] >= 0) {
+                        const int i = cell[c] & (n - 1), j = (cell[c] >> lg) & (n - 1),
+                                  k = cell[c] >> (2 * lg);
+                        ph[ix(i, j, k)] = v[c];
+                        write_owned_ghosts(ph, hh, ix, i, j, k, v[c]);
+                    }
+                __syncthreads();
+            }
+    };
+
+    for (int q = 0; q + 1 < nb; ++q) {
+        smooth(q, nu1);
+        const Ix<false> ixf = ixq(q), ixc = ixq(q + 1);
+        const int nc = ixc.n, lgc = ixc.lg;
+        double *pc = PHI + poff(q + 1), *hc = HAT + poff(q + 1), *sc = SRC + coff(q + 1);
+        for (int t = tid; t < nc * nc * nc; t += kBottomDirThreads) {
+            const int I = t & (nc - 1), J = (t >> lgc) & (nc - 1), K = t >> (2 * lgc);
+            // restrict_cell's sums (children in its order), each child's
+            // stencil gathered on its own
+            const double *pf = PHI + poff(q), *sf = SRC + coff(q);
+            const unsigned char *mf = MSK + coff(q);
+            const int nf = ixf.n;
+            double sphi = 0.0, sr = 0.0;
+#pragma unroll 1
+            for (int ch = 0; ch < 8; ++ch) {
+                const int fi = 2 * I + (ch & 1), fj = 2 * J + ((ch >> 1) & 1), fk = 2 * K + (ch >> 2);
+                double v[19];
+                gather(pf, ixf, fi, fj, fk, v);
+                const int fc = (fk * nf + fj) * nf + fi;
+                const double r = !mf[fc] ? 0.0 : sf[fc] - apply_L(stencil_terms(v), alpha(q));
+                sphi += v[0];
+                sr += r;
+            }
+            hc[ixc(I, J, K)] = sphi * 0.125;
+            sc[t] = sr * 0.5;
+        }
+        __syncthreads();
+        for (int t = tid; t < nc * nc * nc; t += kBottomDirThreads) {
+            const int i = t & (nc - 1), j = (t >> lgc) & (nc - 1), k = t >> (2 * lgc);
+            double v[19];
+            gather(hc, ixc, i, j, k, v);
+            sc[t] = apply_L(stencil_terms(v), alpha(q + 1)) + sc[t];
+            pc[ixc(i, j, k)] = v[0];
+            write_owned_ghosts(pc, hc, ixc, i, j, k, v[0]); // zero correction
+        }
+        __syncthreads();
+    }
+    smooth(nb - 1, csweeps);
+    for (int q = nb - 2; q >= 0; --q) {
+        const Ix<false> ixf = ixq(q), ixc = ixq(q + 1);
+        const int nf = ixf.n, lgf = ixf.lg;
+        const double *pc = PHI + poff(q + 1), *hc = HAT + poff(q + 1);
+        double *pf = PHI + poff(q);
+        const double *hf = HAT + poff(q);
+        const unsigned char *mk = MSK + coff(q);
+        for (int t = tid; t < nf * nf * nf; t += kBottomDirThreads) {
+            if (!mk[t]) continue; // held: no correction
+            const int i = t & (nf - 1), j = (t >> lgf) & (nf - 1), k = t >> (2 * lgf);
+            const int I = i >> 1, J = j >> 1, K = k >> 1;
+            const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (c ? 0.25 : 0.75);
+                        const int qq = ixc(I + a * si, J + b * sj, K + c * sk);
+                        acc = fma(w, pc[qq] - hc[qq], acc);
+                    }
+            const int me = ixf(i, j, k);
+            const double val = pf[me] + acc;
+            pf[me] = val;
+            write_owned_ghosts(pf, hf, ixf, i, j, k, val);
+        }
+        __syncthreads();
+        smooth(q, nu2);
+    }
+    for (int t = tid; t < pad(0); t += kBottomDirThreads) bl.phi0[t] = PHI[t];
+    if (fb) flush_events(fallbacks, fb);
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_source(const double *__restrict__ delta, size_t count, const double *__restrict__ sum,
          double inv_count_mean, double f, double *__restrict__ s) {
@@ -1246,6 +1501,24 @@ k_mask_restrict(const unsigned char *__restrict__ mf, int lgc, unsigned char *__
     mc[t] = all ? 1 : 0;
 }
 
+// Tile activity of a masked level for the fused sweep: on[b] = 1 if the
+// cells that workgroup b of the sweep writes (a 64 x 16 column of tz planes,
+// numbered as the sweep numbers them) include any relaxed cell.
+__global__ void __launch_bounds__(kBlock)
+k_tile_activity(const unsigned char *__restrict__ mask, int lg, int tz,
+                unsigned char *__restrict__ on) {
+    const int n = 1 << lg, ntx = n / 64, tiles = ntx * (n / 16);
+    const int b = blockIdx.x, tile = b % tiles;
+    const int x0 = (tile % ntx) * 64, y0 = (tile / ntx) * 16, z0 = (b / tiles) * tz;
+    bool it = false;
+    for (int q = threadIdx.x; q < 64 * 16 * tz; q += kBlock) {
+        const int x = q & 63, y = (q >> 6) & 15, z = q >> 10;
+        it = it || mask[((size_t)((z0 + z) << lg) + y0 + y) * n + x0 + x] != 0;
+    }
+    const int any = __syncthreads_or(it ? 1 : 0);
+    if (threadIdx.x == 0) on[b] = any ? 1 : 0;
+}
+
 // Block activity of a masked level for k_smooth_half: active[c * blocks + b]
 // = 1 if block b of the colour-c launch relaxes any cell (same cell order).
 __global__ void __launch_bounds__(kBlock)
@@ -1288,12 +1561,29 @@ void launch_guard_check(const void *band, int words, uint64_t word, unsigned *ba
     k_guard_check<<<1, 64, 0, st>>>(static_cast<const uint64_t *>(band), words, word, bad);
 }
 
-size_t block_activity_bytes(int n) { return 2 * (size_t)blocks_for((size_t)n * n * n / 2); }
+// planes per workgroup of the fused sweep on a level of n cells per side
+// (tiles of 64 x 16 cells), and its number of workgroups
+int fused_tz(int n) { return n >= 256 ? 32 : 4; }
+size_t fused_tiles(int n) {
+    return n >= 128 ? (size_t)(n / 64) * (n / 16) * (n / fused_tz(n)) : 0;
+}
+
+// the half-sweep blocks of both colours, then the fused sweep's workgroups
+size_t block_activity_bytes(int n) {
+    return 2 * (size_t)blocks_for((size_t)n * n * n / 2) + fused_tiles(n);
+}
+
+const unsigned char *tile_activity(const unsigned char *active, int n) {
+    return active + 2 * (size_t)blocks_for((size_t)n * n * n / 2);
+}
 
 void launch_block_activity(const unsigned char *mask, int n, unsigned char *active,
                            hipStream_t st) {
-    const dim3 grid(blocks_for((size_t)n * n * n / 2), 2);
-    k_block_activity<<<grid, kBlock, 0, st>>>(mask, log2i(n), active);
+    const unsigned nb = blocks_for((size_t)n * n * n / 2);
+    k_block_activity<<<dim3(nb, 2), kBlock, 0, st>>>(mask, log2i(n), active);
+    if (fused_tiles(n))
+        k_tile_activity<<<(unsigned)fused_tiles(n), kBlock, 0, st>>>(mask, log2i(n), fused_tz(n),
+                                                                    active + 2 * (size_t)nb);
 }
 
 void launch_cell_mask(const double *phi_parent, const double *psi_parent, int np,
@@ -1333,10 +1623,8 @@ void launch_smooth_half(const Level &L, const double *pin, double *pout, int col
 // (on 32^3 and 64^3 the one-workgroup-per-tile pipeline is slower than two
 // short launches: its prologue latency is not amortised over enough planes)
 // periodic levels, and the finest level of a refinement (fixed ghost shell,
-// every cell relaxed), from 128^3 on
-bool fused_sweep_ok(const Level &L) {
-    return L.n >= 128 && (L.periodic || (!L.dyn_bc && !L.mask));
-}
+// held cells of the cell-wise mode kept), from 128^3 on
+bool fused_sweep_ok(const Level &L) { return L.n >= 128 && (L.periodic || !L.dyn_bc); }
 bool fused_prolong_ok(const Level &L) { return L.periodic && L.n >= 128; }
 
 template <int TX, int TY, int TZ, int NT, bool PRO, bool PER>
@@ -1344,13 +1632,14 @@ void sweep_fused_tiles(const Level &L, const double *pin, double *pout, unsigned
                        const double *phi_c, const double *hat_c, hipStream_t st) {
     const int tiles = (L.n / TX) * (L.n / TY);
     k_sweep_fused<TX, TY, TZ, NT, PRO, PER><<<tiles * (L.n / TZ), NT, 0, st>>>(
-        pin, pout, L.s, L.lg, L.alpha, L.omega, fallbacks, phi_c, hat_c);
+        pin, pout, L.s, L.lg, L.alpha, L.omega, fallbacks, phi_c, hat_c,
+        PER ? nullptr : L.mask, PER ? nullptr : L.tile_on);
 }
 
 template <bool PRO, bool PER>
 void sweep_fused_layout(const Level &L, const double *pin, double *pout, unsigned *fallbacks,
                         const double *phi_c, const double *hat_c, hipStream_t st) {
-    if (L.n >= 256) // long z-chunks: the halo planes are a small share
+    if (fused_tz(L.n) == 32) // n >= 256: long z-chunks, the halo planes are a small share
         sweep_fused_tiles<64, 16, 32, 512, PRO, PER>(L, pin, pout, fallbacks, phi_c, hat_c, st);
     else // 128^3: short chunks, two workgroups per CU (4 planes: 5% faster than 8)
         sweep_fused_tiles<64, 16, 4, 512, PRO, PER>(L, pin, pout, fallbacks, phi_c, hat_c, st);
@@ -1380,18 +1669,24 @@ void residual_tiled(const Level &L, double *partials, OutT *r_out, double r_scal
                     hipStream_t st) {
     constexpr int TX = 64, TY = 16;
     const int tiles = (L.n / TX) * (L.n / TY);
-    int chunks = L.n / 8; // z-chunks of 8 planes, at most kReduceBlocks workgroups
+    // z-chunks of 8 planes (4 at 128^3: enough workgroups to fill the chip), at
+    // most kReduceBlocks workgroups
+    int chunks = L.n >= 256 ? L.n / 8 : L.n / 4;
     while (tiles * chunks > kReduceBlocks) chunks /= 2;
     // blocks beyond the grid contribute zeros to the fixed-size final sum
     const size_t unused = (size_t)(kReduceBlocks - tiles * chunks);
     if (unused) k_fill<<<blocks_for(unused), kBlock, 0, st>>>(partials + tiles * chunks, unused, 0.0);
-    k_residual_tiled<TX, TY, OutT><<<tiles * chunks, kBlock, 0, st>>>(
-        L.phi, L.s, L.lg, L.n / chunks, L.alpha, partials, r_out, r_scale);
+    if (L.periodic)
+        k_residual_tiled<TX, TY, OutT, true><<<tiles * chunks, kBlock, 0, st>>>(
+            L.phi, L.s, L.lg, L.n / chunks, L.alpha, partials, r_out, r_scale, nullptr);
+    else
+        k_residual_tiled<TX, TY, OutT, false><<<tiles * chunks, kBlock, 0, st>>>(
+            L.phi, L.s, L.lg, L.n / chunks, L.alpha, partials, r_out, r_scale, L.mask);
 }
 
 void launch_residual_sumsq(const Level &L, double *partials, double *r_out, double r_scale,
                            hipStream_t st) {
-    if (L.periodic && L.n >= 128) {
+    if (L.n >= 128) { // periodic levels and the finest levels of refinements
         residual_tiled<double>(L, partials, r_out, r_scale, st);
         return;
     }
@@ -1516,6 +1811,29 @@ void launch_bottom(const Level *H, int l, int nl, int nu1, int nu2, int csweeps,
     bl.omega = H[l].omega;
     k_bottom<<<1, kBottomThreads, 0, st>>>(H[l].phi, H[l].s, H[l].lg, bl, nu1, nu2, csweeps,
                                            fallbacks);
+}
+
+bool bottom_dir_ok(const Level *H, int l, int nl) {
+    if (l + 1 >= nl || nl - l > kBottomMaxLevels) return false;
+    for (int q = l; q < nl; ++q)
+        if (H[q].periodic || !H[q].dyn_bc) return false;
+    return H[l].n <= 16 && H[nl - 1].n >= 2;
+}
+
+void launch_bottom_dir(const Level *H, int l, int nl, int nu1, int nu2, int csweeps,
+                       unsigned *fallbacks, hipStream_t st) {
+    BottomDirLevels bl{};
+    bl.levels = nl - l;
+    bl.lg0 = H[l].lg;
+    bl.omega = H[l].omega;
+    bl.phi0 = H[l].phi;
+    bl.s0 = H[l].s;
+    for (int q = 0; q < bl.levels; ++q) {
+        bl.alpha[q] = H[l + q].alpha;
+        bl.hat[q] = H[l + q].hat;
+        bl.mask[q] = H[l + q].mask;
+    }
+    k_bottom_dir<<<1, kBottomDirThreads, 0, st>>>(bl, nu1, nu2, csweeps, fallbacks);
 }
 
 void launch_source(const double *delta, size_t count, const double *sum, double inv_count_mean,

@@ -566,6 +566,10 @@ struct Runner {
             launch_bottom(H, l, nl, P.c.nu1, P.c.nu2, kCoarsestSweeps, P.fallbacks, st);
             return;
         }
+        if (!(P.c.flags & NDGP_TWO_PASS) && bottom_dir_ok(H, l, nl)) {
+            launch_bottom_dir(H, l, nl, P.c.nu1, P.c.nu2, kCoarsestSweeps, P.fallbacks, st);
+            return;
+        }
         smooth(L, P.c.nu1);
         Level &C = H[l + 1];
         launch_restrict_residual(L, C, !(P.c.flags & NDGP_TWO_PASS), st);
@@ -882,6 +886,7 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
             H[0].mask = P.mask[q][0];
             launch_block_activity(P.mask[q][0], c.pn[q], P.active[q], st);
             H[0].active = P.active[q];
+            H[0].tile_on = tile_activity(P.active[q], c.pn[q]);
             for (int m = 1; m < c.pnl[q]; ++m) {
                 launch_mask_restrict(P.mask[q][m - 1], H[m].n, P.mask[q][m], st);
                 H[m].mask = P.mask[q][m];

@@ -215,6 +215,26 @@ def serve(trace: list, budget_bytes: float = 64e9, max_active: int = 16,
     return results, summary
 
 
+def serve_one_at_a_time(trace: list, precision=ndgp.PREC_MIXED, tol: float = 1e-10,
+                        device="cuda", warm: bool = True) -> dict:
+    """The same requests solved one after the other with the blocking solve
+    (density, densest cell, solve, next request): the baseline that the
+    continuous-batching loop is measured against."""
+    if warm:
+        warm_up(trace, precision, tol, device)
+    torch.cuda.synchronize(device)
+    t0 = time.perf_counter()
+    failed = 0
+    for req in sorted(trace, key=lambda r: (r.arrival, r.idx)):
+        delta, grid, params = request_problem(req, device, precision, tol)
+        _, rep = ndgp.solve(grid, params, [delta], check=False)
+        failed += rep.status != ndgp.NDGP_OK
+    torch.cuda.synchronize(device)
+    dt = time.perf_counter() - t0
+    return {"completed": len(trace), "failed": int(failed), "solves_per_s": len(trace) / dt,
+            "makespan_s": dt}
+
+
 def summarize(results: list) -> dict:
     if not results:
         return {"completed": 0}

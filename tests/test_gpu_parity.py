@@ -218,6 +218,42 @@ def test_patch_fused_sweep_bitwise_equal_per_colour_launches(m, pn2, wrap):
             assert e <= PHI_TOL
 
 
+@pytest.mark.parametrize("m,depth,cellwise", [(32, 2, False), (64, 2, False), (16, 2, False),
+                                               (32, 2, True), (64, 1, True), (128, 1, True)])
+def test_patch_bottom_bitwise_equal_per_level_launches(m, depth, cellwise):
+    """The coarse levels of a refinement from 16^3 down (ghost shells that
+    follow the interior, held cells of the cell-wise mode) solved in one
+    workgroup, and a 128^3 refinement with held cells relaxed by the one-launch
+    LDS sweep (held cells kept, workgroups of held cells skipped), give the
+    same bits, cycle counts and event counts as one launch per colour, per
+    transfer and per level (patches of 16^3 have no such levels: both paths
+    are the per-level launches)."""
+    say(f"patch bottom m={m} depth={depth} cellwise={cellwise}")
+    f, deltas, grid = deep_patch_problem(n=max(32, m), m=m, depth=depth, seed=14)
+    dd = [dev(d) for d in deltas]
+    p = dict(rc=1.0, tol=0.0, max_cycles=200)
+    if not cellwise:
+        a, ra = ndgp.solve(grid, ndgp.Params(**p), dd)
+        b, rb = ndgp.solve(grid, ndgp.Params(two_pass=True, **p), dd)
+    else:
+        beta = ndgp.beta_lcdm(1.0, 0.3, 1.0)
+        psi = ndgp.solve(grid, ndgp.Params(rc=0.0, beta=beta, tol=0.0, max_cycles=200), dd)[0]
+        psi = [1.5 * beta * x for x in psi]
+        for thr in (0.12, 0.11, 0.13, 0.1, 0.14, 0.09, 0.15, 0.08, 0.06):
+            a, ra = ndgp.solve_cellwise(grid, ndgp.Params(**p), dd, psi, thr)
+            if 0.05 < ra.iterated_fraction[1] < 0.95:
+                break
+        say(f"  threshold {thr}: iterated {ra.iterated_fraction[:depth + 1]}")
+        assert 0.05 < ra.iterated_fraction[1] < 0.95
+        b, rb = ndgp.solve_cellwise(grid, ndgp.Params(two_pass=True, **p), dd, psi, thr)
+    torch.cuda.synchronize()
+    say(f"  cycles={ra.cycles} rel_res={ra.rel_res}")
+    assert ra.status == 0 and rb.status == 0
+    assert ra.cycles == rb.cycles and ra.fallbacks == rb.fallbacks and ra.holds == rb.holds
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
 @pytest.mark.parametrize("nu1,nu2", [(1, 1), (3, 1), (1, 3)])
 def test_odd_sweep_counts(nu1, nu2):
     """Odd numbers of pre/post sweeps: the fused one-launch sweeps take the

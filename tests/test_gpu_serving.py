@@ -174,3 +174,9 @@ def test_budget_limits_admission():
     one = serving.request_bytes(*serving._shape_only(trace[0], ndgp.PREC_MIXED, 1e-10))
     results, summary = serving.serve(trace, budget_bytes=1.5 * one, max_active=4)
     assert summary["completed"] == 6 and summary["peak_active"] == 1
+
+
+def test_one_at_a_time_baseline():
+    trace = serving.make_trace(count=6, seed=5, sizes=(32, 64), all_at_once=True)
+    out = serving.serve_one_at_a_time(trace)
+    assert out["completed"] == 6 and out["failed"] == 0 and out["solves_per_s"] > 0
