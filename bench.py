@@ -78,9 +78,10 @@ def traffic_from_profiles(n: int):
     return d.get("bytes_per_launch", {}).get(str(n))
 
 
-def make_domain(n, box, sigma, tophats, seed):
-    from paper_1511_08200_amd import synth
-    return synth.make_field(n, sigma, seed, n_tophats=tophats)
+def workload(name, **kw):
+    """A named workload of the package's presets (grid, parameters, seeded input)."""
+    from paper_1511_08200_amd import presets
+    return presets.load(name, **kw)
 
 
 def solve_steps(ndgp, torch, grid, params, deltas, steps, warmup, with_force=True):
@@ -187,20 +188,11 @@ def patch_workload(ndgp, torch, steps, depth):
     difference.  depth 4: every truncation level (the paper's l_trunc = l_d + 1,
     2, 4 and the full run, Table I), cell-wise truncation, and G_eff per
     level; force differences of each truncated run against the full one."""
-    from paper_1511_08200_amd import synth
-    n, box, rc, m = 256, 256.0, 1.0, 128
-    f = make_domain(n, box, 2.0, 50, 1513)
-    c = synth.densest_tophat_centre(f)
-    chain, deltas, patches = [], [f.delta], []
-    for q in range(depth):
-        o = synth.patch_origin_centred(c, m // 2)
-        if q > 0:
-            o = tuple(min(max(v, 8), m - m // 2 - 8) for v in o)
-        chain.append(o)
-        deltas.append(synth.patch_delta(f, n, chain, m))
-        patches.append(ndgp.Patch(m, o))
-        c = tuple((c[a] - o[a]) * 2 for a in range(3))
-    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n), patches=patches)
+    rc = 1.0
+    w = workload("nested-256" if depth == 2 else "nested-256-deep")
+    assert len(w.grid.patches) == depth
+    grid, deltas = w.grid, w.deltas()
+    chain = [p.origin for p in grid.patches]
     if depth == 2:
         out = {"workload": "256^3 + 2 nested 128^3 patches (2x, 4x), lognormal sigma 2 + 50 "
                            "top-hats, r_cH0=1, tol 1e-10; FP64 full, FP64 interpolated, mixed "
@@ -315,10 +307,9 @@ def particle_workload(ndgp, torch, steps):
     Newtonian potential (r_c = 0 solve), the total force and its
     cloud-in-cell interpolation back to the particles."""
     from paper_1511_08200_amd import synth
-    n, box, rc = 256, 256.0, 1.0
-    f = make_domain(n, box, 2.0, 50, 1513)
+    w = workload("periodic-256")
+    n, rc, f, grid = w.grid.n, 1.0, w.field, w.grid
     pos = torch.from_numpy(synth.make_particles(f, n**3, 7)).to("cuda")
-    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
     beta = ndgp.beta_lcdm(1.0, 0.3, rc)
     p5 = ndgp.Params(rc=rc, tol=1e-10)
     pn = ndgp.Params(rc=0.0, beta=beta, tol=1e-10)
@@ -387,10 +378,9 @@ def particle_workload(ndgp, torch, steps):
 
 def large_workload(ndgp, torch, steps):
     """512^3 periodic, sigma_ln = 2.5, FP64, r_c H0 in {0.5, 1, 5}."""
-    n, box = 512, 512.0
     log("generating 512^3 input")
-    f = make_domain(n, box, 2.5, 0, 1515)
-    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
+    w = workload("periodic-512")
+    n, f, grid = w.grid.n, w.field, w.grid
     out = {"workload": "512^3 periodic, lognormal sigma 2.5, tol 1e-10, FP64 and mixed"}
     for rc in (0.5, 1.0, 5.0):
         params = ndgp.Params(rc=rc, tol=1e-10)
@@ -418,11 +408,9 @@ def large_workload(ndgp, torch, steps):
 def medium_workload(ndgp, torch, steps):
     """The 256^3 configuration: lognormal sigma 2 + 50 top-hats, FP64 to 1e-10
     plus the force, with its own profiled relaxation roofline."""
-    n, box, rc = 256, 256.0, 1.0
-    f = make_domain(n, box, 2.0, 50, 1513)
-    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
-    dt, reps, phi, dd = solve_steps(ndgp, torch, grid, ndgp.Params(rc=rc, tol=1e-10), [f.delta],
-                                    steps, 2)
+    w = workload("periodic-256")
+    n, rc, f, grid = w.grid.n, 1.0, w.field, w.grid
+    dt, reps, phi, dd = solve_steps(ndgp, torch, grid, w.params, [f.delta], steps, 2)
     _, preps, _, _ = solve_steps(ndgp, torch, grid, ndgp.Params(rc=rc, tol=1e-10, profile=True),
                                  [f.delta], 2, 0)
     cyc = reps[-1].cycles[0]
@@ -438,15 +426,18 @@ def serving_workload(ndgp, torch, count, rate, sat_count):
     2x patch each, 64 GB device budget; then the same kind of requests all
     arriving at once (throughput at saturation)."""
     from paper_1511_08200_amd import serving
-    trace = serving.make_trace(count=count, rate=rate)
+    sw = workload("serving")
+    trace = serving.make_trace(count=count, rate=rate)  # the preset's stream at these sizes
     log(f"serving {count} requests at {rate}/s")
-    res, summ = serving.serve(trace, budget_bytes=64e9, max_active=16, log=log)
+    res, summ = serving.serve(trace, budget_bytes=sw.budget_bytes, max_active=sw.max_active,
+                              log=log)
     out = {"workload": f"{count} requests, Poisson {rate}/s, n in 32..256, r_cH0 in "
                        "{0.5,1,2,5}, mixed + interpolated patch, 64 GB budget",
            "poisson": summ}
     trace2 = serving.make_trace(count=sat_count, seed=1517, all_at_once=True)
     log(f"serving {sat_count} requests arriving at once")
-    res2, summ2 = serving.serve(trace2, budget_bytes=64e9, max_active=16, realtime=False, log=log)
+    res2, summ2 = serving.serve(trace2, budget_bytes=sw.budget_bytes, max_active=sw.max_active,
+                                realtime=False, log=log)
     out["saturation"] = summ2
     log(f"the same {sat_count} requests one at a time")
     seq = serving.serve_one_at_a_time(trace2)
@@ -488,21 +479,21 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     ndgp.lib()
 
+    rc = 1.0
+    prec = ndgp.PREC_MIXED if args.precision == "mixed" else ndgp.PREC_FP64
     if args.workload == "512":
-        n, box, rc, sigma, tophats, seed = 512, 512.0, 1.0, 2.5, 0, 1515
+        w = workload("periodic-512", rc=rc, precision=prec)
         wl = ("ndgp-512^3-fp64-lognormal-sigma2.5, box 512 Mpc/h, r_cH0=1, tol 1e-10, "
               "V(2,2) 7 levels, + force")
     else:
-        n, box, rc, sigma, tophats, seed = 256, 256.0, 1.0, 2.0, 50, 1513
+        w = workload("periodic-256", rc=rc, precision=prec)
         wl = ("ndgp-256^3-fp64-lognormal-sigma2+50tophats, box 256 Mpc/h, r_cH0=1, tol 1e-10, "
               "V(2,2) 6 levels, + force")
+    n, grid, params = w.grid.n, w.grid, w.params
     log(f"generating {n}^3 input")
-    f = make_domain(n, box, sigma, tophats, seed)
-    grid = ndgp.Grid(n=n, h=ndgp.cell_size(box, n))
-    prec = ndgp.PREC_MIXED if args.precision == "mixed" else ndgp.PREC_FP64
+    f = w.field
     if prec == ndgp.PREC_MIXED:
         wl = wl.replace("-fp64-", "-mixed-")
-    params = ndgp.Params(rc=rc, tol=1e-10, precision=prec)
     log("timing")
     dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, [f.delta], args.steps,
                                     args.warmup)
@@ -538,10 +529,9 @@ def main():
         line["calibration_copy_bytes"] = {"read": a.numel() * 8, "write": b.numel() * 8}
         del a, b
     if not args.no_cpu:
-        from paper_1511_08200_amd import synth
-        f32 = synth.make_field(32, 1.0, 1512)
+        w32 = workload("periodic-32")
         line["cpu_baseline"] = cpu_baseline(
-            [("32^3 sigma 1 (box 64 Mpc/h)", f32.delta, ndgp.cell_size(64.0, 32), 1.0),
+            [("32^3 sigma 1 (box 64 Mpc/h)", w32.field.delta, w32.grid.h, 1.0),
              (f"{n}^3 timed input", f.delta, grid.h, rc)])
     extras = set() if args.no_extra else {e for e in args.extra.split(",") if e}
     unknown = extras - {"patches", "truncation", "particles", "large", "medium", "serving"}

@@ -17,6 +17,7 @@ LIB = os.path.join(HERE, "libndgp.so")
 SOURCES = ["ndgp_kernels.hip", "ndgp_mixed.hip", "ndgp_solver.hip", "ndgp_screening.hip", "ndgp_amr.hip",
            "ndgp_stats.hip", "ndgp_particles.hip"]
 ARCH = os.environ.get("NDGP_OFFLOAD_ARCH", "gfx950")
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 
 
 def hipcc() -> str:
@@ -36,7 +37,9 @@ def build(verbose: bool = False) -> str:
            # way in every kernel it is inlined into (fma() is written out)
            "-ffp-contract=off",
            "-Wall", "-Wno-unused-function",
-           "-I", INCLUDE, "-I", CSRC, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+           "-I", INCLUDE, "-I", CSRC, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES] + [
+           # host ranges for rocprofv3 --marker-trace
+           f"-L{ROCM_LIB}", f"-Wl,-rpath,{ROCM_LIB}", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

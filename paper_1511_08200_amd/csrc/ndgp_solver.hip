@@ -12,6 +12,8 @@
 #include "ndgp.h"
 #include "ndgp_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -32,6 +34,16 @@ static_assert(sizeof(scratch) == NDGP_NOALLOC_SCRATCH_BYTES, "scratch size as do
 namespace {
 
 thread_local std::string g_err;
+
+// A named range on the host timeline (rocprofv3 --marker-trace): a solve, its
+// domain V-cycles, each refinement or box, each plan step.  Without a tool
+// attached a push or pop is one call that returns at once.
+struct Range {
+    explicit Range(const char *what) { roctxRangePushA(what); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 ndgp_status fail(ndgp_status st, std::string msg) {
     g_err = std::move(msg);
@@ -830,6 +842,7 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
         R.rel_res[0] = 0.0;
     } else {
         double rel = 0.0;
+        Range domain("ndgp domain V-cycles");
         for (bool first = true;; first = false) {
             if (!first) run.nested_start(P.base, c.nl); // the first start is enqueued above
             timer.on = (c.flags & NDGP_PROFILE) != 0; // the V-cycles only, not the start
@@ -892,6 +905,7 @@ ndgp_status solve_impl(const ndgp_grid *grid, const ndgp_params *params,
                 H[m].mask = P.mask[q][m];
             }
         }
+        Range patch_range("ndgp refinement");
         const PatchOutcome po = relax_patch(run, H, c.pnl[q], parent, npar, parent_periodic,
                                             c.po[q], c.pn[q], c.hl(q + 1), delta[q + 1],
                                             1.0 / (double)cells0);
@@ -1127,6 +1141,7 @@ ndgp_status solve_amr_impl(const ndgp_grid *grid, const ndgp_params *params,
                 L.hat = l ? A.hat[l] : nullptr;
                 L.dyn_bc = l > 0;
             }
+            Range box_range("ndgp box");
             const PatchOutcome po = relax_patch(run, H, T.nlev[b], parent, npar, parent_periodic,
                                                 T.origin[b], T.n[b], hb, delta[1 + b],
                                                 1.0 / (double)cells0);
@@ -1757,6 +1772,7 @@ ndgp_status ndgp_solve(const ndgp_grid *grid, const ndgp_params *params,
                        double *const phi[1 + NDGP_MAX_PATCHES], void *workspace,
                        size_t workspace_bytes, hipStream_t stream, ndgp_report *report) {
     return guarded([&] {
+        Range r("ndgp_solve");
         return solve_impl(grid, params, delta, phi, workspace, workspace_bytes, stream, report);
     });
 }
@@ -1821,6 +1837,7 @@ ndgp_status ndgp_solve_cellwise(const ndgp_grid *grid, const ndgp_params *params
                                 ndgp_report *report) {
     return guarded([&] {
         if (!psi) return fail(NDGP_EINVAL, "psi must not be NULL");
+        Range r("ndgp_solve_cellwise");
         return solve_impl(grid, params, delta, phi, workspace, workspace_bytes, stream, report,
                           psi, threshold);
     });
@@ -1854,6 +1871,7 @@ ndgp_status ndgp_solve_amr(const ndgp_grid *grid, const ndgp_params *params,
                            hipStream_t stream, ndgp_report *report,
                            ndgp_box_report *box_report) {
     return guarded([&] {
+        Range r("ndgp_solve_amr");
         return solve_amr_impl(grid, params, boxes, n_boxes, delta, phi, workspace,
                               workspace_bytes, stream, report, box_report);
     });
@@ -1888,7 +1906,10 @@ ndgp_status ndgp_plan_poll(ndgp_plan *plan, int32_t *done, ndgp_report *report) 
 }
 
 ndgp_status ndgp_plan_step(ndgp_plan *plan) {
-    return guarded([&] { return plan_step_impl(plan); });
+    return guarded([&] {
+        Range r("ndgp_plan_step");
+        return plan_step_impl(plan);
+    });
 }
 
 void ndgp_plan_destroy(ndgp_plan *plan) {

@@ -219,12 +219,14 @@ def test_patch_fused_sweep_bitwise_equal_per_colour_launches(m, pn2, wrap):
 
 
 @pytest.mark.parametrize("m,depth,cellwise", [(32, 2, False), (64, 2, False), (16, 2, False),
-                                               (32, 2, True), (64, 1, True), (128, 1, True)])
+                                               (32, 2, True), (64, 1, True), (128, 1, True),
+                                               (256, 1, True)])
 def test_patch_bottom_bitwise_equal_per_level_launches(m, depth, cellwise):
     """The coarse levels of a refinement from 16^3 down (ghost shells that
     follow the interior, held cells of the cell-wise mode) solved in one
-    workgroup, and a 128^3 refinement with held cells relaxed by the one-launch
-    LDS sweep (held cells kept, workgroups of held cells skipped), give the
+    workgroup, and 128^3 and 256^3 refinements with held cells relaxed by the
+    one-launch LDS sweep (held cells kept, workgroups of held cells skipped;
+    chunks of 4 and of 32 planes), give the
     same bits, cycle counts and event counts as one launch per colour, per
     transfer and per level (patches of 16^3 have no such levels: both paths
     are the per-level launches)."""
