@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libndgp.so")
 SOURCES = ["ndgp_kernels.hip", "ndgp_mixed.hip", "ndgp_solver.hip", "ndgp_screening.hip", "ndgp_amr.hip",
-           "ndgp_stats.hip", "ndgp_particles.hip"]
+           "ndgp_boxes.hip", "ndgp_stats.hip", "ndgp_particles.hip"]
 ARCH = os.environ.get("NDGP_OFFLOAD_ARCH", "gfx950")
 ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 

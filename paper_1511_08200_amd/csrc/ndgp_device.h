@@ -230,6 +230,46 @@ __device__ __forceinline__ void write_owned_ghosts(double *__restrict__ out,
     }
 }
 
+// Cell-centred trilinear interpolation of a parent level at the padded slot
+// (ii, jj, kk) of a child box (bx: lower corner in parent cells, the box's
+// cells 2^(m-1) parent cells wide, nc cells per side; slot 0 and nc+1 are
+// the ghost shell).  Parent: natural and periodic (PPER) or padded.
+template <bool PPER>
+__device__ __forceinline__ double interpolate_slot(const double *__restrict__ parent, int np,
+                                                   int lgp, const ChildBox &bx, int ii, int jj,
+                                                   int kk) {
+    const int ijk[3] = {ii - 1, jj - 1, kk - 1};
+    const double q = ldexp(1.0, bx.m - 1);
+    int i0[3];
+    double w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double X = bx.origin[a] + (ijk[a] + 0.5) * q - 0.5;
+        const double f = floor(X);
+        i0[a] = (int)f;
+        w[a] = X - f;
+    }
+    const int msk = np - 1, pp = np + 2;
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const double wt = (a ? w[0] : 1.0 - w[0]) * (b ? w[1] : 1.0 - w[1]) *
+                                  (c ? w[2] : 1.0 - w[2]);
+                const int x = i0[0] + a, y = i0[1] + b, z = i0[2] + c;
+                int q2;
+                if (PPER)
+                    q2 = (((z & msk) << lgp | (y & msk)) << lgp) | (x & msk);
+                else
+                    q2 = ((z + 1) * pp + (y + 1)) * pp + (x + 1);
+                v += wt * parent[q2];
+            }
+    return v;
+}
+
 // Workgroups of a launch are dealt to the 8 XCDs of the chip round robin
 // (workgroup id modulo 8), and each XCD has its own L2.  Renumber so that XCD
 // x runs a contiguous run of logical tiles: spatial neighbours then share the

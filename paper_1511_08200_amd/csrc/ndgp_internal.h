@@ -53,6 +53,94 @@ struct Level {
     }
 };
 
+// The bookkeeping of the cycle loop on one level, shared by the blocking
+// drivers, the plans and the one-workgroup box solves (host and device):
+// stopping test, divergence, and the safeguard.  The red-black sweep updates
+// same-colour edge neighbours simultaneously (Jacobi within a colour); where
+// the nonlinear coupling through those edges is strong (extreme densities
+// with large r_c) that iteration can amplify an error mode, and the cycles
+// diverge after first converging.  Damping the step from the middle of such
+// a run does not recover it (the iterate has left the basin), but a run
+// damped from its start converges.  So once the residual has grown to
+// kRiseFactor times the smallest one seen (well above rounding level) with
+// the plain step, the level is solved again from its initial guess with the
+// damped step u + kDampedStep du everywhere.  Plateaus with small ups and
+// downs, common before the screened regions settle, do not trigger it; runs
+// that never grow keep the plain root, bit for bit.
+constexpr double kDampedStep = 0.8;
+constexpr double kRiseFactor = 2.0;
+constexpr double kDampAbove = 1e-9; // rel. residual; below it a rise is rounding noise
+constexpr int kTolNotReached = 1, kStagnated = 2; // verdict codes (0: reached)
+
+struct CycleMonitor {
+    double tol = 0.0;
+    int maxc = 0;
+    double rel0 = 0.0, prev = 0.0, rel = 0.0, best = 0.0;
+    int slow = 0;
+    bool damped = false;
+
+    __host__ __device__ void start(double r) { rel = rel0 = prev = best = r; }
+    // a zero residual is exact (e.g. a patch whose every cell is held)
+    __host__ __device__ bool converged() const { return rel == 0.0 || (tol > 0.0 && rel <= tol); }
+    __host__ __device__ bool diverged() const {
+        return !__builtin_isfinite(rel) || rel > 1e6 * (rel0 < 1.0 ? 1.0 : rel0);
+    }
+    // after a cycle: true when the level is to be solved again with the damped step
+    __host__ __device__ bool record(double r) {
+        rel = r;
+        bool damp = false;
+        if (!damped && rel > kRiseFactor * best && rel > kDampAbove) {
+            damped = damp = true;
+            slow = 0;
+        } else if (tol == 0.0) {
+            slow = rel > 0.7 * prev ? slow + 1 : 0;
+        }
+        best = rel < best ? rel : best;
+        prev = rel;
+        return damp;
+    }
+    __host__ __device__ bool stalled() const { return tol == 0.0 && slow >= 2; }
+    // once the loop has stopped (not diverged): 0, kTolNotReached or kStagnated
+    __host__ __device__ int verdict_code() const {
+        if (tol > 0.0 && rel > tol) return kTolNotReached;
+        if (tol == 0.0 && rel > 1e-11) return kStagnated;
+        return 0;
+    }
+};
+
+// ---- the small boxes of an adaptive tree, one workgroup each (ndgp_boxes.hip)
+// Relaxed boxes of at most kBoxBatchMaxN cells per side are solved by one
+// launch per tree level.  A box's status: 0, kTolNotReached, kStagnated,
+// kBoxDiverged, or kBoxBadSource (non-finite density).
+constexpr int kBoxBatchMaxN = 32;
+constexpr int kBoxDiverged = 8, kBoxBadSource = 9;
+struct BoxJob {
+    const double *parent;  // the parent's solution: natural n^3 (domain) or padded
+    int np, parent_periodic;
+    int origin[3];         // lower corner in parent cells
+    int n, nl;             // cells per side (8, 16 or 32) and levels (n = 8 -> 1)
+    double *phi;           // out: padded (n+2)^3
+    double *alt, *s0;      // n = 32: partner and source of the finest level (scratch)
+    double *phi1, *alt1, *hat1, *s1; // n = 32: its 16^3 level (scratch; padded, natural s)
+    const double *delta;   // natural n^3
+    double f;              // source factor Omega_m / (a beta) h^2 of the box
+    double alpha[3];       // per level, cell units
+};
+struct BoxResult {
+    int cycles, damped_from, status;
+    double rel;
+};
+struct BoxRun {
+    const double *dsum;    // device: the domain's delta sum
+    double inv_cells0;     // 1 / cells of the domain
+    int nu1, nu2, csweeps, maxc;
+    double tol;
+    int damped_start;
+    unsigned *fallbacks;   // event counters (no real root, past the vertex)
+};
+void launch_solve_boxes(const BoxJob *jobs, BoxResult *results, int count, const BoxRun &run,
+                        hipStream_t st);
+
 // levels of a hierarchy that coarsens by 2 down to <= 8 cells per side
 inline int default_levels(int n) {
     int l = 1;

@@ -1399,39 +1399,10 @@ k_interpolate(const double *__restrict__ parent, int np, int lgp, ChildBox bx,
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= pc * pc * pc) return;
     const int ii = t % pc, jj = (t / pc) % pc, kk = t / (pc * pc);
-    const int ijk[3] = {ii - 1, jj - 1, kk - 1};
-    const bool interior = ijk[0] >= 0 && ijk[0] < bx.nc && ijk[1] >= 0 && ijk[1] < bx.nc &&
-                          ijk[2] >= 0 && ijk[2] < bx.nc;
+    const bool interior = ii >= 1 && ii <= bx.nc && jj >= 1 && jj <= bx.nc && kk >= 1 &&
+                          kk <= bx.nc;
     if (ghosts_only && interior) return;
-    const double q = ldexp(1.0, bx.m - 1);
-    int i0[3];
-    double w[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double X = bx.origin[a] + (ijk[a] + 0.5) * q - 0.5;
-        const double f = floor(X);
-        i0[a] = (int)f;
-        w[a] = X - f;
-    }
-    const int msk = np - 1, pp = np + 2;
-    double v = 0.0;
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const double wt = (a ? w[0] : 1.0 - w[0]) * (b ? w[1] : 1.0 - w[1]) *
-                                  (c ? w[2] : 1.0 - w[2]);
-                const int x = i0[0] + a, y = i0[1] + b, z = i0[2] + c;
-                int q2;
-                if (PPER)
-                    q2 = (((z & msk) << lgp | (y & msk)) << lgp) | (x & msk);
-                else
-                    q2 = ((z + 1) * pp + (y + 1)) * pp + (x + 1);
-                v += wt * parent[q2];
-            }
-    child[t] = v;
+    child[t] = interpolate_slot<PPER>(parent, np, lgp, bx, ii, jj, kk);
 }
 
 template <bool PER>

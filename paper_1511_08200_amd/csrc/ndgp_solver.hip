@@ -416,56 +416,15 @@ struct SmoothTimer {
     }
 };
 
-// The bookkeeping of the cycle loop on one level, shared by the blocking
-// drivers and the plans: stopping test, divergence, and the safeguard.  The
-// red-black sweep updates same-colour edge neighbours simultaneously (Jacobi
-// within a colour); where the nonlinear coupling through those edges is
-// strong (extreme densities with large r_c) that iteration can amplify an
-// error mode, and the cycles diverge after first converging.  Damping the
-// step from the middle of such a run does not recover it (the iterate has
-// left the basin), but a run damped from its start converges.  So once the
-// residual has grown to kRiseFactor times the smallest one seen (well above
-// rounding level) with the plain step, the level is solved again from its
-// initial guess with the damped step u + kDampedStep du everywhere.  Plateaus
-// with small ups and downs, common before the screened regions settle, do
-// not trigger it; runs that never grow keep the plain root, bit for bit.
-constexpr double kDampedStep = 0.8;
-constexpr double kRiseFactor = 2.0;
-constexpr double kDampAbove = 1e-9; // rel. residual; below it a rise is rounding noise
-
-struct CycleMonitor {
-    double tol = 0.0;
-    int maxc = 0;
-    double rel0 = 0.0, prev = 0.0, rel = 0.0, best = 0.0;
-    int slow = 0;
-    bool damped = false;
-
-    void start(double r) { rel = rel0 = prev = best = r; }
-    // a zero residual is exact (e.g. a patch whose every cell is held)
-    bool converged() const { return rel == 0.0 || (tol > 0.0 && rel <= tol); }
-    bool diverged() const { return !std::isfinite(rel) || rel > 1e6 * std::max(rel0, 1.0); }
-    // after a cycle: true when the level is to be solved again with the damped step
-    bool record(double r) {
-        rel = r;
-        bool damp = false;
-        if (!damped && rel > kRiseFactor * best && rel > kDampAbove) {
-            damped = damp = true;
-            slow = 0;
-        } else if (tol == 0.0) {
-            slow = rel > 0.7 * prev ? slow + 1 : 0;
-        }
-        best = std::min(best, rel);
-        prev = rel;
-        return damp;
+// The monitor of a level's cycles (CycleMonitor, ndgp_internal.h), with the
+// status of its end as an error message.
+ndgp_status verdict(const CycleMonitor &m) {
+    switch (m.verdict_code()) {
+    case kTolNotReached: return fail(NDGP_ENOCONV, "tolerance not reached within max_cycles");
+    case kStagnated: return fail(NDGP_ENOCONV, "stagnated above rounding level");
+    default: return NDGP_OK;
     }
-    bool stalled() const { return tol == 0.0 && slow >= 2; }
-    // the status once the loop has stopped (not diverged)
-    ndgp_status verdict() const {
-        if (tol > 0.0 && rel > tol) return fail(NDGP_ENOCONV, "tolerance not reached within max_cycles");
-        if (tol == 0.0 && rel > 1e-11) return fail(NDGP_ENOCONV, "stagnated above rounding level");
-        return NDGP_OK;
-    }
-};
+}
 
 inline void set_step(Level *H, Level32 *H32, int nl, double w) {
     for (int l = 0; l < nl; ++l) {
@@ -677,7 +636,7 @@ struct Runner {
             if (m.diverged()) return fail(NDGP_ENOCONV, "mixed-precision iteration diverged");
             if (m.stalled()) break;
         }
-        return m.verdict();
+        return verdict(m);
     }
 
     // V-cycles on H[0] until ||r|| <= tol ||s|| (tol > 0) or until the
@@ -705,7 +664,7 @@ struct Runner {
             if (m.diverged()) return fail(NDGP_ENOCONV, "multigrid diverged");
             if (m.stalled()) break;
         }
-        return m.verdict();
+        return verdict(m);
     }
 };
 
@@ -1046,10 +1005,23 @@ struct AmrScratch {
            *hat[kMaxLevels] = {};
     double *partials = nullptr, *scal = nullptr;
     unsigned *fallbacks = nullptr;
+    // the boxes solved one workgroup each: descriptors, results, and the
+    // global levels of each 32^3 one
+    BoxJob *jobs = nullptr;
+    BoxResult *results = nullptr;
+    double *box32 = nullptr;
 };
 
-size_t carve_amr(AmrScratch &A, char *base, int maxn) {
+// scratch doubles of one 32^3 box solved by one workgroup: the finest level's
+// partner (padded) and source, its 16^3 level's phi, partner and hat (padded)
+// and source
+constexpr size_t kBox32Doubles = 34 * 34 * 34 + 32 * 32 * 32 + 3 * 18 * 18 * 18 + 16 * 16 * 16;
+
+size_t carve_amr(AmrScratch &A, char *base, int maxn, int nb = 0, int n32 = 0) {
     Carver cv{base};
+    A.jobs = cv.take<BoxJob>((size_t)nb);
+    A.results = cv.take<BoxResult>((size_t)nb);
+    A.box32 = cv.take<double>((size_t)n32 * kBox32Doubles);
     if (maxn > 0) {
         const int nl = default_levels(maxn);
         for (int l = 0; l < nl; ++l) {
@@ -1067,9 +1039,23 @@ size_t carve_amr(AmrScratch &A, char *base, int maxn) {
     return cv.off;
 }
 
+// relaxed boxes that one workgroup each solves, and how many of them are 32^3
+int batched_boxes(const Cfg &c, const AmrTree &T, int *n32) {
+    int k = 0, k32 = 0;
+    for (int b = 0; b < T.nb; ++b)
+        if (T.relaxed[b] && T.n[b] <= kBoxBatchMaxN && !(c.flags & NDGP_TWO_PASS)) {
+            ++k;
+            k32 += T.n[b] == 32;
+        }
+    if (n32) *n32 = k32;
+    return k;
+}
+
 size_t amr_bytes(const Cfg &c, const AmrTree &T) {
     AmrScratch A;
-    return total_bytes(c) + carve_amr(A, nullptr, T.max_relaxed_n) + 256;
+    int n32 = 0;
+    const int k = batched_boxes(c, T, &n32);
+    return total_bytes(c) + carve_amr(A, nullptr, T.max_relaxed_n, k, n32) + 256;
 }
 
 ndgp_status solve_amr_impl(const ndgp_grid *grid, const ndgp_params *params,
@@ -1106,7 +1092,9 @@ ndgp_status solve_amr_impl(const ndgp_grid *grid, const ndgp_params *params,
     if (status != NDGP_OK && status != NDGP_ENOCONV) return status;
 
     AmrScratch A;
-    carve_amr(A, aligned_base(static_cast<char *>(ws) + dom), T.max_relaxed_n);
+    int n32 = 0;
+    const int nbatch = batched_boxes(c, T, &n32);
+    carve_amr(A, aligned_base(static_cast<char *>(ws) + dom), T.max_relaxed_n, nbatch, n32);
     Plan P;
     P.c = c;
     P.partials = A.partials;
@@ -1117,41 +1105,111 @@ ndgp_status solve_amr_impl(const ndgp_grid *grid, const ndgp_params *params,
     const size_t cells0 = (size_t)c.n * c.n * c.n;
     HIP_TRY(hipMemsetAsync(P.fallbacks, 0, 2 * sizeof(unsigned), st));
     run.enqueue_sum(delta[0], cells0, false, 0); // the domain's mean for the box sources
-    for (int b = 0; b < nb; ++b) {
-        const int pb = T.parent[b];
-        const bool parent_periodic = pb < 0;
-        const double *parent = pb < 0 ? phi[0] : phi[1 + pb];
-        const int npar = pb < 0 ? c.n : T.n[pb];
-        ChildBox b0{{T.origin[b][0], T.origin[b][1], T.origin[b][2]}, 0, T.n[b]};
-        launch_interpolate(parent, npar, parent_periodic, b0, phi[1 + b], false, st);
-        ndgp_box_report br{T.depth[b], 0, 0, -1.0};
-        if (T.relaxed[b]) {
-            Level H[kMaxLevels];
+    // Level by level of the tree (a box after its parent): relaxed boxes of at
+    // most kBoxBatchMaxN cells per side all in one launch, one workgroup each
+    // (the same bits as relax_patch); the others one after the other.
+    const BoxRun brun{P.scal + 0, 1.0 / (double)cells0, c.nu1, c.nu2, kCoarsestSweeps, c.maxc,
+                      c.tol, (c.flags & NDGP_DAMPED) ? 1 : 0, P.fallbacks};
+    std::vector<BoxJob> jobs;
+    std::vector<int> job_box;
+    jobs.reserve((size_t)nbatch); // no reallocation: copies read from these elements
+    int max_depth = 0, k32 = 0;
+    for (int b = 0; b < nb; ++b) max_depth = std::max(max_depth, T.depth[b]);
+    for (int d = 1; d <= max_depth; ++d) {
+        const size_t first = jobs.size();
+        for (int b = 0; b < nb; ++b) {
+            if (T.depth[b] != d) continue;
+            const int pb = T.parent[b];
+            const bool parent_periodic = pb < 0;
+            const double *parent = pb < 0 ? phi[0] : phi[1 + pb];
+            const int npar = pb < 0 ? c.n : T.n[pb];
             const double hb = c.h / (double)(1 << T.depth[b]);
-            for (int l = 0; l < T.nlev[b]; ++l) {
-                Level &L = H[l];
-                L.n = T.n[b] >> l;
-                L.lg = ilog2(L.n);
-                L.periodic = false;
-                const double hm = hb * (double)(1 << l);
-                L.alpha = c.alpha / (hm * hm);
-                L.phi = l ? A.phi[l] : phi[1 + b];
-                L.alt = A.alt[l];
-                L.s = A.s[l];
-                L.hat = l ? A.hat[l] : nullptr;
-                L.dyn_bc = l > 0;
+            if (T.relaxed[b] && T.n[b] <= kBoxBatchMaxN && !(c.flags & NDGP_TWO_PASS)) {
+                BoxJob J{};
+                J.parent = parent;
+                J.np = npar;
+                J.parent_periodic = parent_periodic ? 1 : 0;
+                for (int a = 0; a < 3; ++a) J.origin[a] = T.origin[b][a];
+                J.n = T.n[b];
+                J.nl = T.nlev[b];
+                J.phi = phi[1 + b];
+                J.delta = delta[1 + b];
+                J.f = c.fsrc * hb * hb;
+                for (int l = 0; l < 3; ++l) {
+                    const double hm = hb * (double)(1 << l);
+                    J.alpha[l] = c.alpha / (hm * hm);
+                }
+                if (J.n == 32) {
+                    J.alt = A.box32 + (size_t)(k32++) * kBox32Doubles;
+                    J.s0 = J.alt + 34 * 34 * 34;
+                    J.phi1 = J.s0 + 32 * 32 * 32;
+                    J.alt1 = J.phi1 + 18 * 18 * 18;
+                    J.hat1 = J.alt1 + 18 * 18 * 18;
+                    J.s1 = J.hat1 + 18 * 18 * 18;
+                }
+                jobs.push_back(J);
+                job_box.push_back(b);
+                continue;
             }
-            Range box_range("ndgp box");
-            const PatchOutcome po = relax_patch(run, H, T.nlev[b], parent, npar, parent_periodic,
-                                                T.origin[b], T.n[b], hb, delta[1 + b],
-                                                1.0 / (double)cells0);
-            if (po.status == NDGP_EINVAL) return po.status;
-            if (po.status != NDGP_OK && status == NDGP_OK) status = po.status;
-            br.cycles = po.cycles;
-            br.damped_from = po.damped_from;
-            br.rel_res = po.rel;
+            ChildBox b0{{T.origin[b][0], T.origin[b][1], T.origin[b][2]}, 0, T.n[b]};
+            launch_interpolate(parent, npar, parent_periodic, b0, phi[1 + b], false, st);
+            ndgp_box_report br{T.depth[b], 0, 0, -1.0};
+            if (T.relaxed[b]) {
+                Level H[kMaxLevels];
+                for (int l = 0; l < T.nlev[b]; ++l) {
+                    Level &L = H[l];
+                    L.n = T.n[b] >> l;
+                    L.lg = ilog2(L.n);
+                    L.periodic = false;
+                    const double hm = hb * (double)(1 << l);
+                    L.alpha = c.alpha / (hm * hm);
+                    L.phi = l ? A.phi[l] : phi[1 + b];
+                    L.alt = A.alt[l];
+                    L.s = A.s[l];
+                    L.hat = l ? A.hat[l] : nullptr;
+                    L.dyn_bc = l > 0;
+                }
+                Range box_range("ndgp box");
+                const PatchOutcome po = relax_patch(run, H, T.nlev[b], parent, npar,
+                                                    parent_periodic, T.origin[b], T.n[b], hb,
+                                                    delta[1 + b], 1.0 / (double)cells0);
+                if (po.status == NDGP_EINVAL) return po.status;
+                if (po.status != NDGP_OK && status == NDGP_OK) status = po.status;
+                br.cycles = po.cycles;
+                br.damped_from = po.damped_from;
+                br.rel_res = po.rel;
+            }
+            if (brep) brep[b] = br;
         }
-        if (brep) brep[b] = br;
+        const int count = (int)(jobs.size() - first);
+        if (count > 0) {
+            Range boxes_range("ndgp small boxes, one workgroup each");
+            HIP_TRY(hipMemcpyAsync(A.jobs + first, jobs.data() + first, count * sizeof(BoxJob),
+                                   hipMemcpyHostToDevice, st));
+            launch_solve_boxes(A.jobs + first, A.results + first, count, brun, st);
+        }
+    }
+    if (!jobs.empty()) {
+        std::vector<BoxResult> res(jobs.size());
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(res.data(), A.results, res.size() * sizeof(BoxResult),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (size_t q = 0; q < jobs.size(); ++q) {
+            const BoxResult &r = res[q];
+            const int b = job_box[q];
+            if (r.status == kBoxBadSource)
+                return fail(NDGP_EINVAL, "a patch density has non-finite values");
+            CycleMonitor m{c.tol, c.maxc};
+            m.rel = r.rel;
+            ndgp_status sq = NDGP_OK;
+            if (r.status == kBoxDiverged)
+                sq = fail(NDGP_ENOCONV, "multigrid diverged");
+            else if (r.status)
+                sq = verdict(m);
+            if (sq != NDGP_OK && status == NDGP_OK) status = sq;
+            if (brep) brep[b] = ndgp_box_report{T.depth[b], r.cycles, r.damped_from, r.rel};
+        }
     }
     unsigned fb[2] = {0, 0};
     HIP_TRY(hipGetLastError());
@@ -1680,7 +1738,7 @@ ndgp_status plan_poll_impl(ndgp_plan *pl, int32_t *done, ndgp_report *rep) {
     }
     pl->R.rel_res[0] = pl->mon.rel;
     if (pl->mon.converged() || pl->mon.stalled() || pl->R.cycles[0] >= c.maxc) {
-        const ndgp_status v = pl->mon.verdict();
+        const ndgp_status v = verdict(pl->mon);
         if (v != NDGP_OK) plan_fail(pl, v, g_err.c_str());
         plan_enqueue_tail(pl, false);
         return NDGP_OK;

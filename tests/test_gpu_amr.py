@@ -125,3 +125,67 @@ def test_amr_rejects_bad_trees_and_inputs():
     with pytest.raises(ndgp.NdgpError) as e:
         ndgp.solve_amr(grid, ndgp.Params(rc=1.0), boxes, [dev(d) for d in nan])
     assert e.value.status == ndgp.NDGP_EINVAL
+
+
+def many_box_tree(n=128, seed=41, n_ref=12.0, n_ref1=2.0, deep=3):
+    """A tree the way N_ref flags make it on a mildly clustered field (sigma_ln
+    0.8, 12 top-hats; clustering efficiency 0.3): 74 boxes of 8^3 to 32^3
+    (solved one workgroup each) and one of 64^3 (solved level by level), and
+    inside the largest boxes the boxes their own flags ask for (a level-1 cell
+    holds (delta + 1) N / (2n)^3 particles)."""
+    f = synth.make_field(n, 0.8, seed, n_tophats=12)
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n))
+    flags = nref_flags(f.delta, n**3, n_ref)
+    boxes = ndgp.refine_boxes(flags, n, periodic=True, efficiency=0.3)
+    chains = [[b.origin] for b in boxes]
+    deltas = [f.delta] + [synth.patch_delta(f, n, ch, b.n) for ch, b in zip(chains, boxes)]
+    parents = sorted(range(len(boxes)), key=lambda b: -boxes[b].n)[:deep]
+    for p in parents:
+        bp = boxes[p]
+        fl = ((deltas[1 + p] + 1.0) * n**3 / (2 * n) ** 3 > n_ref1).astype(np.uint8)
+        kids = ndgp.refine_boxes(fl, bp.n, periodic=False, parent_index=p, efficiency=0.7)
+        for k in sorted(kids, key=lambda b: -b.n)[:4]:
+            boxes.append(k)
+            chains.append(chains[p] + [k.origin])
+            deltas.append(synth.patch_delta(f, n, chains[-1], k.n))
+    return f, grid, boxes, deltas
+
+
+@pytest.mark.parametrize("case", ["tol", "stagnation", "damped"])
+def test_small_boxes_in_one_launch_equal_box_by_box(case):
+    """Boxes of at most 32^3 cells solved one workgroup each (all of a tree
+    level in one launch) give the same bits, cycles, restart cycles, residuals
+    and event counts as relaxing them one after the other (NDGP_TWO_PASS), on
+    a tree with boxes of 8^3 to 64^3 at two depths."""
+    f, grid, boxes, deltas = many_box_tree()
+    sizes = sorted({b.n for b in boxes})
+    say(f"{case}: {len(boxes)} boxes of sizes {sizes}, depths "
+        f"{sorted({0 if b.parent < 0 else 1 for b in boxes})}")
+    assert {8, 16, 32, 64} <= set(sizes) and any(b.parent >= 0 for b in boxes)
+    kw = dict(rc=1.0, tol=1e-10)
+    if case == "stagnation":
+        kw = dict(rc=1.0, tol=0.0, max_cycles=200)
+    if case == "damped":
+        kw = dict(rc=5.0, tol=1e-10, damped=True)
+    dd = [dev(d) for d in deltas]
+    a, ra, pa = ndgp.solve_amr(grid, ndgp.Params(**kw), boxes, dd)
+    b, rb, pb = ndgp.solve_amr(grid, ndgp.Params(two_pass=True, **kw), boxes, dd)
+    torch.cuda.synchronize()
+    say(f"  cycles {sorted({p['cycles'] for p in pa})}, domain {ra.cycles[0]}")
+    assert ra.status == rb.status == 0
+    assert pa == pb
+    assert ra.fallbacks == rb.fallbacks and ra.holds == rb.holds
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    if case == "damped":
+        assert all(p["damped_from"] == 1 for p in pa)
+
+
+def test_small_boxes_reject_bad_density():
+    f, grid, boxes, deltas = many_box_tree(deep=0)
+    small = next(q for q, b in enumerate(boxes) if b.n <= 32)
+    bad = [d.copy() for d in deltas]
+    bad[1 + small][1, 2, 3] = np.inf
+    with pytest.raises(ndgp.NdgpError) as e:
+        ndgp.solve_amr(grid, ndgp.Params(rc=1.0), boxes, [dev(d) for d in bad])
+    assert e.value.status == ndgp.NDGP_EINVAL
