@@ -27,9 +27,12 @@ The JSON line also carries:
                 levels l_d+1, l_d+2, l_d+4 and full, cell-wise truncation,
                 G_eff per level; particles: one time step around the solver
                 (cloud-in-cell density, nDGP and Newtonian solves, total force,
-                cloud-in-cell force); large: 512^3 solves at three r_c, FP64
-                and mixed; medium: the 256^3 solve; serving: the request
-                stream (Poisson arrivals) and saturation.
+                cloud-in-cell force); amr: boxes placed on N_ref flags and
+                solved as a tree (small boxes one workgroup each, in one
+                launch per tree level) against box by box; large: 512^3
+                solves at three r_c, FP64 and mixed; medium: the 256^3 solve;
+                serving: the request stream (Poisson arrivals) and saturation,
+                against the same requests solved one at a time.
 
     python bench.py [--steps K] [--warmup W] [--workload 512|256] [--no-extra] [--no-cpu]
 """
@@ -376,6 +379,57 @@ def particle_workload(ndgp, torch, steps):
             "max_delta": float(delta[0].max())}
 
 
+def amr_workload(ndgp, torch, steps):
+    """Adaptive refinement (Sec. IV.A): a 256^3 field with small-scale
+    clustering (lognormal sigma_ln 0.8 + 50 top-hats, box 256 Mpc/h), the
+    cells holding more than N_ref = 16 of 256^3 particles flagged, cubic boxes
+    placed on the flags (Berger-Rigoutsos, efficiency 0.7), every box relaxed
+    to 1e-10 from its parent (full) or interpolated; the full solve also box
+    by box (NDGP_TWO_PASS) against the small boxes in one launch."""
+    from paper_1511_08200_amd import synth
+    n, rc, n_ref = 256, 1.0, 16.0
+    f = synth.make_field(n, 0.8, 1513, n_tophats=50)
+    grid = ndgp.Grid(n=n, h=ndgp.cell_size(float(n), n))
+    d0 = torch.from_numpy(f.delta).to("cuda")
+    flags, counts = ndgp.refine_flags(grid, [d0], n**3, n_ref)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    boxes = ndgp.refine_boxes(flags[0], n, periodic=True, efficiency=0.7)
+    t_cluster = time.perf_counter() - t0
+    sizes = {}
+    for b in boxes:
+        sizes[str(b.n)] = sizes.get(str(b.n), 0) + 1
+    dd = [d0] + [torch.from_numpy(synth.patch_delta(f, n, [b.origin], b.n)).to("cuda")
+                 for b in boxes]
+    out = {"workload": "256^3, lognormal sigma 0.8 + 50 top-hats, N_ref = 16 of 256^3 particles, "
+                       "boxes by Berger-Rigoutsos (efficiency 0.7), r_cH0=1, tol 1e-10",
+           "flagged_cells": int(counts[0]), "boxes": len(boxes), "box_sizes": sizes,
+           "clustering_ms": round(t_cluster * 1e3, 1)}
+    runs = (("full", ndgp.Params(rc=rc, tol=1e-10), steps),
+            ("interpolated", ndgp.Params(rc=rc, tol=1e-10, mode=ndgp.MODE_INTERPOLATED), steps),
+            ("full_box_by_box", ndgp.Params(rc=rc, tol=1e-10, two_pass=True), 1))
+    res = {}
+    for name, params, reps in runs:
+        ws = ndgp.workspace(ndgp.amr_workspace_bytes(grid, params, boxes))
+        phi, rep, per = ndgp.solve_amr(grid, params, boxes, dd, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            phi, rep, per = ndgp.solve_amr(grid, params, boxes, dd, phi=phi, ws=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        cyc = [p["cycles"] for p in per]
+        out[name] = {"ms_to_tol": round(dt * 1e3, 2), "domain_cycles": rep.cycles[0],
+                     "box_cycles_mean": round(float(np.mean(cyc)), 2), "box_cycles_max": max(cyc)}
+        res[name] = phi
+        del ws
+    out["small_boxes_in_one_launch_speedup"] = round(out["full_box_by_box"]["ms_to_tol"] /
+                                                     out["full"]["ms_to_tol"], 1)
+    out["bitwise_equal_to_box_by_box"] = all(torch.equal(a, b) for a, b in
+                                             zip(res["full"], res["full_box_by_box"]))
+    return out
+
+
 def large_workload(ndgp, torch, steps):
     """512^3 periodic, sigma_ln = 2.5, FP64, r_c H0 in {0.5, 1, 5}."""
     log("generating 512^3 input")
@@ -458,7 +512,7 @@ def main():
                     help="precision of the timed solve (mixed: FP32 multigrid on the correction "
                          "inside the FP64 defect-correction loop; no relaxation roofline)")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extra", default="patches,truncation,particles,large,medium,serving",
+    ap.add_argument("--extra", default="patches,truncation,particles,amr,large,medium,serving",
                     help="comma-separated extra workloads to run after the timed one")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -534,7 +588,7 @@ def main():
             [("32^3 sigma 1 (box 64 Mpc/h)", w32.field.delta, w32.grid.h, 1.0),
              (f"{n}^3 timed input", f.delta, grid.h, rc)])
     extras = set() if args.no_extra else {e for e in args.extra.split(",") if e}
-    unknown = extras - {"patches", "truncation", "particles", "large", "medium", "serving"}
+    unknown = extras - {"patches", "truncation", "particles", "amr", "large", "medium", "serving"}
     if unknown:
         raise SystemExit(f"unknown extra workloads: {sorted(unknown)}")
     if extras:
@@ -548,6 +602,9 @@ def main():
         if "particles" in extras:
             log("particle workload")
             out["particles"] = particle_workload(ndgp, torch, 3)
+        if "amr" in extras:
+            log("adaptive refinement workload")
+            out["amr"] = amr_workload(ndgp, torch, 3)
         if "large" in extras:
             log("512^3 workload")
             out["large"] = large_workload(ndgp, torch, 3)

@@ -1115,9 +1115,14 @@ ndgp_status solve_amr_impl(const ndgp_grid *grid, const ndgp_params *params,
     jobs.reserve((size_t)nbatch); // no reallocation: copies read from these elements
     int max_depth = 0, k32 = 0;
     for (int b = 0; b < nb; ++b) max_depth = std::max(max_depth, T.depth[b]);
+    // within a level the larger boxes first: their workgroups take longest, the
+    // small ones fill the compute units behind them
+    std::vector<int> order(nb);
+    for (int b = 0; b < nb; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return T.n[x] > T.n[y]; });
     for (int d = 1; d <= max_depth; ++d) {
         const size_t first = jobs.size();
-        for (int b = 0; b < nb; ++b) {
+        for (int b : order) {
             if (T.depth[b] != d) continue;
             const int pb = T.parent[b];
             const bool parent_periodic = pb < 0;
