@@ -87,7 +87,12 @@ def workload(name, **kw):
     return presets.load(name, **kw)
 
 
-def solve_steps(ndgp, torch, grid, params, deltas, steps, warmup, with_force=True):
+def solve_steps(ndgp, torch, grid, params, deltas, steps, warmup, with_force=True,
+                median=False):
+    """Time `steps` solves (+ force) after `warmup` untimed ones: the mean over
+    the steps between two synchronisations, or (median=True, for the extras)
+    the median of the steps each timed between synchronisations, which a
+    stray pause of the host does not move."""
     dd = [torch.from_numpy(d).to("cuda") if d is not None else None for d in deltas]
     phi = ndgp.alloc_phi(grid)
     ws = ndgp.workspace(ndgp.workspace_bytes(grid, params))
@@ -98,13 +103,20 @@ def solve_steps(ndgp, torch, grid, params, deltas, steps, warmup, with_force=Tru
             ndgp.force(grid, phi)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    each = []
     for _ in range(steps):
+        t1 = time.perf_counter()
         _, rep = ndgp.solve(grid, params, dd, phi=phi, ws=ws)
         if with_force:
             ndgp.force(grid, phi)
         reps.append(rep)
+        if median:
+            torch.cuda.synchronize()
+            each.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(steps, 1)
+    if median and each:
+        dt = float(np.median(each))
     return dt, reps, phi, dd
 
 
@@ -218,7 +230,7 @@ def patch_workload(ndgp, torch, steps, depth):
     res = {}
     for name, mode, k, prec in runs:
         params = ndgp.Params(rc=rc, tol=1e-10, mode=mode, trunc_level=k, precision=prec)
-        dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, deltas, steps, 1)
+        dt, reps, phi, dd = solve_steps(ndgp, torch, grid, params, deltas, steps, 1, median=True)
         res[name] = [p.clone() for p in phi]
         out[name] = {"ms_to_tol": round(dt * 1e3, 2), "cycles": reps[-1].cycles,
                      "rel_res": reps[-1].rel_res}
@@ -252,12 +264,14 @@ def patch_workload(ndgp, torch, steps, depth):
         phi_c = ndgp.alloc_phi(grid)
         ndgp.solve_cellwise(grid, full_params, dd, psi, thr, phi=phi_c, ws=ws)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
+        each = []
+        for _ in range(steps):  # the median step, as for the modes above
+            t0 = time.perf_counter()
             _, rep_c = ndgp.solve_cellwise(grid, full_params, dd, psi, thr, phi=phi_c, ws=ws)
             ndgp.force(grid, phi_c)
-        torch.cuda.synchronize()
-        dtc = (time.perf_counter() - t0) / steps
+            torch.cuda.synchronize()
+            each.append(time.perf_counter() - t0)
+        dtc = float(np.median(each))
         name = f"cellwise{thr:g}"
         res[name] = phi_c
         out["cellwise"][f"{thr:g}"] = {"ms_to_tol": round(dtc * 1e3, 2), "cycles": rep_c.cycles,
@@ -595,10 +609,10 @@ def main():
         out = line.setdefault("extra", {})
         if "patches" in extras:
             log("patch workload")
-            out["patches"] = patch_workload(ndgp, torch, 3, 2)
+            out["patches"] = patch_workload(ndgp, torch, 5, 2)
         if "truncation" in extras:
             log("truncation workload")
-            out["truncation"] = patch_workload(ndgp, torch, 3, 4)
+            out["truncation"] = patch_workload(ndgp, torch, 5, 4)
         if "particles" in extras:
             log("particle workload")
             out["particles"] = particle_workload(ndgp, torch, 3)
