@@ -109,9 +109,10 @@ struct CycleMonitor {
 };
 
 // ---- the small boxes of an adaptive tree, one workgroup each (ndgp_boxes.hip)
-// Relaxed boxes of at most kBoxBatchMaxN cells per side are solved by one
-// launch per tree level.  A box's status: 0, kTolNotReached, kStagnated,
-// kBoxDiverged, or kBoxBadSource (non-finite density).
+// Relaxed boxes of at most kBoxBatchMaxN cells per side (32^3 ones when
+// several share a tree level) are solved by one launch per tree level.  A
+// box's status: 0, kTolNotReached, kStagnated, kBoxDiverged, or kBoxBadSource
+// (non-finite density).
 constexpr int kBoxBatchMaxN = 32;
 constexpr int kBoxDiverged = 8, kBoxBadSource = 9;
 struct BoxJob {

@@ -1039,15 +1039,34 @@ size_t carve_amr(AmrScratch &A, char *base, int maxn, int nb = 0, int n32 = 0) {
     return cv.off;
 }
 
+// A relaxed box is solved by the one-workgroup kernel if it has at most 16^3
+// cells, or 32^3 when at least kBatch32Min boxes of that size share its tree
+// level: one workgroup relaxes a 32^3 box's two finer levels from L2, about
+// four times as slowly as the per-level launches do one box, so a few such
+// boxes go faster one after the other (measured: even at four).
+constexpr int kBatch32Min = 4;
+
+struct BatchPlan {
+    int n32_at_depth[22] = {}; // relaxed 32^3 boxes per tree level
+    bool batched(const Cfg &c, const AmrTree &T, int b) const {
+        if (!T.relaxed[b] || T.n[b] > kBoxBatchMaxN || (c.flags & NDGP_TWO_PASS)) return false;
+        return T.n[b] < 32 || n32_at_depth[T.depth[b]] >= kBatch32Min;
+    }
+};
+
 // relaxed boxes that one workgroup each solves, and how many of them are 32^3
-int batched_boxes(const Cfg &c, const AmrTree &T, int *n32) {
+int batched_boxes(const Cfg &c, const AmrTree &T, int *n32, BatchPlan *plan = nullptr) {
+    BatchPlan bp;
+    for (int b = 0; b < T.nb; ++b)
+        if (T.relaxed[b] && T.n[b] == 32) ++bp.n32_at_depth[T.depth[b]];
     int k = 0, k32 = 0;
     for (int b = 0; b < T.nb; ++b)
-        if (T.relaxed[b] && T.n[b] <= kBoxBatchMaxN && !(c.flags & NDGP_TWO_PASS)) {
+        if (bp.batched(c, T, b)) {
             ++k;
             k32 += T.n[b] == 32;
         }
     if (n32) *n32 = k32;
+    if (plan) *plan = bp;
     return k;
 }
 
@@ -1093,7 +1112,8 @@ ndgp_status solve_amr_impl(const ndgp_grid *grid, const ndgp_params *params,
 
     AmrScratch A;
     int n32 = 0;
-    const int nbatch = batched_boxes(c, T, &n32);
+    BatchPlan bplan;
+    const int nbatch = batched_boxes(c, T, &n32, &bplan);
     carve_amr(A, aligned_base(static_cast<char *>(ws) + dom), T.max_relaxed_n, nbatch, n32);
     Plan P;
     P.c = c;
@@ -1129,7 +1149,7 @@ ndgp_status solve_amr_impl(const ndgp_grid *grid, const ndgp_params *params,
             const double *parent = pb < 0 ? phi[0] : phi[1 + pb];
             const int npar = pb < 0 ? c.n : T.n[pb];
             const double hb = c.h / (double)(1 << T.depth[b]);
-            if (T.relaxed[b] && T.n[b] <= kBoxBatchMaxN && !(c.flags & NDGP_TWO_PASS)) {
+            if (bplan.batched(c, T, b)) {
                 BoxJob J{};
                 J.parent = parent;
                 J.np = npar;
