@@ -17,6 +17,7 @@ truncated mode of Sec. III.B), mixed precision by default.
 from __future__ import annotations
 
 import dataclasses
+import json
 import time
 from collections import deque
 
@@ -133,11 +134,16 @@ def warm_up(trace: list, precision=ndgp.PREC_MIXED, tol: float = 1e-10, device="
 
 def serve(trace: list, budget_bytes: float = 64e9, max_active: int = 16,
           precision=ndgp.PREC_MIXED, tol: float = 1e-10, device="cuda",
-          keep_results: bool = False, realtime: bool = True, log=None, warm: bool = True):
+          keep_results: bool = False, realtime: bool = True, log=None, warm: bool = True,
+          request_log: str = None):
     """Run the request stream; returns (results, summary[, kept]) where kept
-    maps request index -> (delta, phi list) when keep_results is set."""
+    maps request index -> (delta, phi list) when keep_results is set.
+    ``request_log``: a path; one JSON line per finished request is appended
+    (index, size, r_c, sigma, arrival / admission / completion times in
+    seconds from the start, latency, cycles, residual, status, bytes held)."""
     if warm:
         warm_up(trace, precision, tol, device)
+    log_fh = open(request_log, "a") if request_log else None
     streams = [torch.cuda.Stream(device=device) for _ in range(max_active)]
     free_streams = deque(range(max_active))
     pending = deque(sorted(trace, key=lambda r: (r.arrival, r.idx)))
@@ -189,6 +195,13 @@ def serve(trace: list, budget_bytes: float = 64e9, max_active: int = 16,
                 results.append(Result(a.req.idx, a.req.n, a.req.arrival, a.admitted, now(),
                                       rep.cycles[0], rep.rel_res[0], rep.status, a.bytes,
                                       a.req.rc, a.req.sigma))
+                if log_fh:
+                    r = results[-1]
+                    log_fh.write(json.dumps({
+                        "idx": r.idx, "n": r.n, "rc": r.rc, "sigma": r.sigma,
+                        "arrival_s": r.arrival, "admitted_s": r.admitted, "done_s": r.done,
+                        "latency_ms": r.latency * 1e3, "cycles": r.cycles, "rel_res": r.rel_res,
+                        "status": r.status, "bytes": r.bytes}) + "\n")
                 if keep_results:
                     kept[a.req.idx] = (a.delta, a.plan.phi, a.grid, a.params)
                 a.plan.close()
@@ -207,6 +220,8 @@ def serve(trace: list, budget_bytes: float = 64e9, max_active: int = 16,
             if wait > 0:
                 time.sleep(min(wait, 0.002))
     torch.cuda.synchronize(device)
+    if log_fh:
+        log_fh.close()
     summary = summarize(results)
     summary.update({"peak_active": peak_active, "peak_bytes": peak_used,
                     "budget_bytes": budget_bytes, "max_active": max_active})

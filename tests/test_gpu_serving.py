@@ -180,3 +180,19 @@ def test_one_at_a_time_baseline():
     trace = serving.make_trace(count=6, seed=5, sizes=(32, 64), all_at_once=True)
     out = serving.serve_one_at_a_time(trace)
     assert out["completed"] == 6 and out["failed"] == 0 and out["solves_per_s"] > 0
+
+
+def test_request_log(tmp_path):
+    """One JSON line per finished request, with its timings and outcome."""
+    import json
+    trace = serving.make_trace(count=5, rate=1e6, seed=4, sizes=(32,))
+    path = tmp_path / "requests.jsonl"
+    results, summary = serving.serve(trace, budget_bytes=4e9, max_active=2,
+                                     request_log=str(path))
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert summary["completed"] == 5 and len(lines) == 5
+    assert sorted(x["idx"] for x in lines) == [r.idx for r in trace]
+    for x in lines:
+        assert x["status"] == 0 and x["cycles"] > 0
+        assert x["arrival_s"] <= x["admitted_s"] <= x["done_s"]
+        assert abs(x["latency_ms"] - 1e3 * (x["done_s"] - x["arrival_s"])) < 1e-6
