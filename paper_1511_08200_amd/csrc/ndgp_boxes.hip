@@ -10,11 +10,12 @@
 // k_reduce_final, k_smooth_half, k_restrict_residual, k_coarse_source,
 // k_coarsest, k_prolong8, and the host's CycleMonitor), including the order
 // of every reduction, so a box's result, cycle count and event counts are
-// bit for bit those of relax_patch.  Levels of at most 16^3 cells live in
-// LDS and are relaxed in place (a half sweep computes its colour into
-// registers, waits, stores; ghosts of the coarse levels rewritten from their
-// interior cell as write_owned_ghosts does); a 32^3 finest level stays in
-// global memory (L2) and ping-pongs like k_smooth_half.
+// bit for bit those of relax_patch.  The finest level of a box of at most
+// 16^3 cells and every 8^3 level live in LDS and are relaxed in place (a half
+// sweep writes its colour's new values to an LDS buffer, waits, copies them
+// in; ghosts of the coarse levels rewritten from their interior cell as
+// write_owned_ghosts does); the 32^3 and 16^3 levels of a 32^3 box stay in
+// global memory (L2, the box's scratch) and ping-pong like k_smooth_half.
 #include "ndgp_device.h"
 
 namespace ndgp {
@@ -28,7 +29,7 @@ constexpr int kMaxWaveSums = 32768 / 64; // one per wave of cells at 32^3
 
 // one level of a box's hierarchy, as the workgroup sees it
 struct BoxLevel {
-    double *phi, *alt; // alt: the 32^3 level only (out-of-place half sweeps)
+    double *phi, *alt; // alt: levels in global memory only (out-of-place half sweeps)
     double *hat;       // levels >= 1
     double *s;
     Ix<false> ix;
@@ -43,11 +44,10 @@ __device__ __forceinline__ double wave_tree(double v) {
     return v;
 }
 
-// LDS of one workgroup: levels of 16^3 and 8^3 cells (phi and hat padded,
-// source natural) and the reduction scratch
 // LDS of one workgroup.  A 16^3 level lives here only as the finest level of
 // a 16^3 box (phi and source; no hat); the 8^3 level always does.  newv holds
-// the new values of one colour of an LDS level during a half sweep.
+// the new values of one colour of an LDS level during a half sweep; the rest
+// is the reduction scratch.
 struct BoxShared {
     double phi16[kPad16], src16[4096], newv[2048];
     double phi8[kPad8], hat8[kPad8], src8[512];

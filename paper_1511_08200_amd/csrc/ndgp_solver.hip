@@ -1017,8 +1017,10 @@ struct AmrScratch {
 // and source
 constexpr size_t kBox32Doubles = 34 * 34 * 34 + 32 * 32 * 32 + 3 * 18 * 18 * 18 + 16 * 16 * 16;
 
-size_t carve_amr(AmrScratch &A, char *base, int maxn, int nb = 0, int n32 = 0) {
+size_t carve_amr(AmrScratch &A, char *base, int maxn, int nb = 0, int n32 = 0,
+                 std::vector<size_t> *guards = nullptr) {
     Carver cv{base};
+    cv.guards = guards;
     A.jobs = cv.take<BoxJob>((size_t)nb);
     A.results = cv.take<BoxResult>((size_t)nb);
     A.box32 = cv.take<double>((size_t)n32 * kBox32Doubles);
@@ -1114,7 +1116,10 @@ ndgp_status solve_amr_impl(const ndgp_grid *grid, const ndgp_params *params,
     int n32 = 0;
     BatchPlan bplan;
     const int nbatch = batched_boxes(c, T, &n32, &bplan);
-    carve_amr(A, aligned_base(static_cast<char *>(ws) + dom), T.max_relaxed_n, nbatch, n32);
+    char *abase = aligned_base(static_cast<char *>(ws) + dom);
+    std::vector<size_t> guards;
+    carve_amr(A, abase, T.max_relaxed_n, nbatch, n32, &guards);
+    for (size_t off : guards) launch_guard_fill(abase + off, (int)kGuardWords, kGuardWord, st);
     Plan P;
     P.c = c;
     P.partials = A.partials;
@@ -1123,7 +1128,7 @@ ndgp_status solve_amr_impl(const ndgp_grid *grid, const ndgp_params *params,
     SlotGuard slot;
     Runner run{P, st, slot.p};
     const size_t cells0 = (size_t)c.n * c.n * c.n;
-    HIP_TRY(hipMemsetAsync(P.fallbacks, 0, 2 * sizeof(unsigned), st));
+    HIP_TRY(hipMemsetAsync(P.fallbacks, 0, 3 * sizeof(unsigned), st));
     run.enqueue_sum(delta[0], cells0, false, 0); // the domain's mean for the box sources
     // Level by level of the tree (a box after its parent): relaxed boxes of at
     // most kBoxBatchMaxN cells per side all in one launch, one workgroup each
@@ -1236,12 +1241,16 @@ ndgp_status solve_amr_impl(const ndgp_grid *grid, const ndgp_params *params,
             if (brep) brep[b] = ndgp_box_report{T.depth[b], r.cycles, r.damped_from, r.rel};
         }
     }
-    unsigned fb[2] = {0, 0};
+    unsigned fb[3] = {0, 0, 0};
+    for (size_t off : guards)
+        launch_guard_check(abase + off, (int)kGuardWords, kGuardWord, P.fallbacks + 2, st);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(slot.p, P.fallbacks, 2 * sizeof(unsigned), hipMemcpyDeviceToHost,
+    HIP_TRY(hipMemcpyAsync(slot.p, P.fallbacks, 3 * sizeof(unsigned), hipMemcpyDeviceToHost,
                            st));
     HIP_TRY(hipStreamSynchronize(st));
-    std::memcpy(fb, slot.p, 2 * sizeof(unsigned));
+    std::memcpy(fb, slot.p, 3 * sizeof(unsigned));
+    if (fb[2]) return fail(NDGP_EDEVICE, std::to_string(fb[2]) + " workspace guard-band words "
+                                         "were overwritten");
     R.fallbacks += (int32_t)fb[0];
     R.holds += (int32_t)fb[1];
     R.t_total_ms =
