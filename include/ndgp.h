@@ -486,9 +486,14 @@ void ndgp_plan_destroy(ndgp_plan *plan);
  *   boxes, max_boxes  HOST output; NDGP_ENOMEM if more boxes are needed
  *   n_boxes           HOST output: boxes written (0 if nothing is flagged)
  * ndgp_solve_amr      the domain level as ndgp_solve with n_patch = 0, then
- *                     every box in list order from its solved (or interpolated)
- *                     parent: ghost shell and initial guess interpolated, then
- *                     relaxed with its own FAS multigrid (NDGP_MODE_FULL), or
+ *                     every box from its solved (or interpolated) parent, tree
+ *                     depth by tree depth: ghost shell and initial guess
+ *                     interpolated, then relaxed with its own FAS multigrid
+ *                     (NDGP_MODE_FULL; boxes of at most 16^3 cells, and 32^3
+ *                     ones when four or more share a depth, all in one launch
+ *                     of one workgroup each; the result is bit for bit that of
+ *                     relaxing them one after the other, which NDGP_TWO_PASS
+ *                     forces), or
  *                     kept at the interpolated field (NDGP_MODE_INTERPOLATED;
  *                     NDGP_MODE_TRUNCATED interpolates the boxes of tree depth
  *                     trunc_level and deeper).  Mixed precision applies to the
