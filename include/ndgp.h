@@ -101,9 +101,10 @@ typedef enum {
                               events on `stream` (ndgp_report.t_smooth_ms) */
 #define NDGP_TWO_PASS 4u   /* one launch per colour, per transfer and per level,
                               one thread per cell: no fused one-launch sweep or
-                              LDS-tiled restriction on large levels and no
+                              LDS-tiled restriction on large levels, no
                               one-workgroup bottom of the V-cycle on levels of
-                              at most 16^3 cells; same results, bit for bit */
+                              at most 16^3 cells, and the boxes of a tree solved
+                              one after the other; same results, bit for bit */
 #define NDGP_DAMPED 8u     /* relax every level with the damped step u + 0.8 du from
                               the start (the mode the divergence safeguard restarts
                               in; ndgp_report.damped_from = 1 on relaxed levels) */
