@@ -189,3 +189,16 @@ def test_small_boxes_reject_bad_density():
     with pytest.raises(ndgp.NdgpError) as e:
         ndgp.solve_amr(grid, ndgp.Params(rc=1.0), boxes, [dev(d) for d in bad])
     assert e.value.status == ndgp.NDGP_EINVAL
+
+
+def test_empty_tree_is_the_plain_solve():
+    """A tree with no boxes is ndgp_solve of the domain, bit for bit."""
+    f = synth.make_field(32, 1.0, 5, n_tophats=2)
+    grid = ndgp.Grid(n=32, h=ndgp.cell_size(64.0, 32))
+    params = ndgp.Params(rc=1.0, tol=1e-10)
+    d = dev(f.delta)
+    a, ra, pa = ndgp.solve_amr(grid, params, [], [d])
+    b, rb = ndgp.solve(grid, params, [d])
+    torch.cuda.synchronize()
+    assert pa == [] and ra.cycles[0] == rb.cycles[0] and ra.rel_res[0] == rb.rel_res[0]
+    assert torch.equal(a[0], b[0])
