@@ -62,6 +62,34 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
     if (fb) flush_events(fallbacks, fb);
 }
 
+// A plane of a fused sweep's z-chunk named by its offset from the chunk's first
+// plane, as a type: LDS ring slots derived from it are compile-time constants,
+// so every LDS access is the thread's base address plus an immediate offset.
+template <int D>
+struct Plane {
+    static constexpr int d = D;
+};
+constexpr int ring_slot(int a, int p) { return ((a % p) + p) % p; }
+constexpr int floor_half(int a) { return a >= 0 ? a / 2 : -((1 - a) / 2); }
+
+// The same per-thread value, opaque to the optimiser at this point: addresses
+// derived from it are formed here, one instruction each, instead of being
+// hoisted out of the z loop and held in registers the stencil needs.
+__device__ __forceinline__ int fresh(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Cell i of one z-plane, the plane's address uniform across the workgroup (in
+// scalar registers) and i a 32-bit offset inside it (a padded 1024^2 plane is
+// 8.4 MB): one vector register per address instead of two.
+__device__ __forceinline__ const double *plane_at(const double *plane, unsigned i) {
+    return reinterpret_cast<const double *>(reinterpret_cast<const char *>(plane) + i * 8u);
+}
+__device__ __forceinline__ double *plane_at(double *plane, unsigned i) {
+    return reinterpret_cast<double *>(reinterpret_cast<char *>(plane) + i * 8u);
+}
+
 // One full red-black sweep of a periodic level in one launch, with the same
 // semantics as two k_smooth_half launches (colour 0 from pin, then colour 1
 // from that result; same-colour neighbours always at their pass-start
@@ -75,9 +103,12 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
 // working on consecutive cells of one colour touch consecutive words (no
 // bank conflicts):
 //   PR, PB: the old field's red and black cells, tile + 2-cell halo, red on
-//           planes k .. k+2, black on planes k-2 .. k+2;
-//   R:  red cells after the red pass, planes k-1 .. k+1;
+//           planes k .. k+2 (3 slots), black on planes k-2 .. k+2 (6 slots);
+//   R:  red cells after the red pass, planes k-1 .. k+1 (3 slots);
 //   E:  (PRO) the coarse correction under the tile, three coarse planes.
+// A plane's slot is its offset from the chunk's first plane modulo the ring
+// size; the z loop is unrolled by 6 (a multiple of every ring), so the slots
+// are constants and LDS addresses need no arithmetic per step.
 // Step k relaxes the red cells of plane k+1 over the tile plus a 1-cell halo
 // (the black cells at the tile's edge need them), then the black cells of
 // plane k over the tile (red neighbours from R, black ones from PB), and
@@ -114,7 +145,7 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     static_assert(EX * EY <= NT, "one coarse value per thread");
     static_assert(PER || !PRO, "refinements add the coarse correction in its own launch");
     __shared__ double PR[3][PY][HX];
-    __shared__ double PB[5][PY][HX];
+    __shared__ double PB[6][PY][HX];
     __shared__ double R[3][PY][HX];
     __shared__ double E[PRO ? 3 : 1][EY * EX];
 
@@ -136,17 +167,19 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     const int pitch = n + 2;
     auto cl = [&](int v) { return v < -1 ? -1 : (v > n ? n : v); };
     auto zoff = [&](int z) {
-        if constexpr (PER) return (z & m) << (2 * lg);
-        else return (cl(z) + 1) * pitch * pitch;
+        if constexpr (PER) return (size_t)(z & m) << (2 * lg);
+        else return (size_t)(cl(z) + 1) * pitch * pitch;
     };
-    // source index of (x, y, z), clamped inside the level where PER = false
-    auto sidx = [&](int x, int y, int z) {
-        if constexpr (PER) {
-            return (((z & m) << lg | (y & m)) << lg) | (x & m);
-        } else {
-            auto c0 = [&](int v) { return v < 0 ? 0 : (v > m ? m : v); };
-            return ((c0(z) << lg | c0(y)) << lg) | c0(x);
-        }
+    // sources (and mask): plane of z and the offset of (x, y) in it, clamped
+    // inside the level where PER = false
+    auto inside = [&](int v) { return v < 0 ? 0 : (v > m ? m : v); };
+    auto splane = [&](int z) {
+        if constexpr (PER) return (size_t)(z & m) << (2 * lg);
+        else return (size_t)inside(z) << (2 * lg);
+    };
+    auto sxy = [&](int x, int y) {
+        if constexpr (PER) return (unsigned)(((y & m) << lg) | (x & m));
+        else return (unsigned)((inside(y) << lg) | inside(x));
     };
     // a cell of the ghost shell: kept, not relaxed
     auto ghost = [&](int x, int y, int z) {
@@ -155,12 +188,10 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
                     (unsigned)z >= (unsigned)n;
     };
     // a held cell (mask 0, loaded with its source a step ahead): kept
-    auto held_at = [&](int at) {
+    auto held_at = [&](size_t plane, unsigned at) {
         if constexpr (PER) return false;
-        else return mask != nullptr && mask[at] == 0;
+        else return mask != nullptr && mask[plane + at] == 0;
     };
-    auto s5 = [](int z) { return (z + 5 * 4096) % 5; };
-    auto s3 = [](int z) { return (z + 3 * 4096) % 3; };
 
     // this thread's share of a plane, in 16-byte pairs of cells (columns 2j,
     // 2j+1 of a row: one red, one black, both at split index j): global x-y
@@ -190,32 +221,36 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     }
     double2 pre[PRE2];
     auto fetch = [&](int z) {
-        const int zo = zoff(z);
+        const double *plane = pin + zoff(z);
 #pragma unroll
         for (int e = 0; e < PRE2; ++e)
             if (pidx[e] >= 0) {
                 if constexpr (PER) {
-                    pre[e] = *reinterpret_cast<const double2 *>(pin + (zo | pxy[e]));
+                    pre[e] = *reinterpret_cast<const double2 *>(plane_at(plane, pxy[e]));
                 } else {
-                    pre[e].x = pin[zo + pxy[e]];
-                    pre[e].y = pin[zo + pxy1[e]];
+                    pre[e].x = *plane_at(plane, pxy[e]);
+                    pre[e].y = *plane_at(plane, pxy1[e]);
                 }
             }
     };
-    auto commit = [&](int z) {
-        double *red = &PR[s3(z)][0][0], *blk = &PB[s5(z)][0][0];
-        const int zp = z & 1;
+    auto commit = [&](int z, auto pl) {
+        constexpr int d = decltype(pl)::d; // z = z0 + d, z0 even
+        double *red = &PR[ring_slot(d, 3)][0][0], *blk = &PB[ring_slot(d, 6)][0][0];
+        constexpr int zp = ring_slot(d, 2);
         const double *e0 = nullptr, *e1 = nullptr;
         if constexpr (PRO) {
-            const int K = z >> 1, sk = (z & 1) ? 1 : -1; // parent plane, neighbour side
-            e0 = E[s3(K)];
-            e1 = E[s3(K + sk)];
+            // parent plane (offset from z0 / 2) and the neighbour side
+            constexpr int K = floor_half(d), sk = zp ? 1 : -1;
+            e0 = E[ring_slot(K, 3)];
+            e1 = E[ring_slot(K + sk, 3)];
         }
 #pragma unroll
         for (int e = 0; e < PRE2; ++e)
             if (pidx[e] >= 0) {
                 double v[2] = {pre[e].x, pre[e].y};
                 if constexpr (PRO) {
+                    // the own and the neighbour coarse row, one column to the left
+                    const int er[2] = {fresh(eat[e] - 1), fresh(eat[e] + edy[e] - 1)};
 #pragma unroll
                     for (int i = 0; i < 2; ++i) {
                         const int edx = i ? 1 : -1;
@@ -228,15 +263,16 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
 #pragma unroll
                                 for (int a = 0; a < 2; ++a) {
                                     const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (cz ? 0.25 : 0.75);
-                                    acc = fma(w, ep[eat[e] + b * edy[e] + a * edx], acc);
+                                    acc = fma(w, ep[er[b] + 1 + a * edx], acc);
                                 }
                         }
                         v[i] = v[i] + acc;
                     }
                 }
                 const bool first_black = (ppar[e] ^ zp) != 0;
-                red[pidx[e]] = first_black ? v[1] : v[0];
-                blk[pidx[e]] = first_black ? v[0] : v[1];
+                const int at = fresh(pidx[e]);
+                red[at] = first_black ? v[1] : v[0];
+                blk[at] = first_black ? v[0] : v[1];
             }
     };
     // (PRO) coarse plane K of the correction: loaded into registers, then
@@ -252,12 +288,14 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
             eb = hat_c[q];
         }
     };
-    auto e_store = [&](int K) {
-        if (eq >= 0) E[s3(K)][eq] = ea - eb;
+    auto e_store = [&](auto kpl) { // kpl: the coarse plane's offset from z0 / 2
+        if (eq >= 0) E[ring_slot(decltype(kpl)::d, 3)][eq] = ea - eb;
     };
 
     // red cells of the halo-1 region: thread slot e covers q = tid + e * NT
-    int red_rr[2], red_jj[2];
+    // (row rr, split index jj + 1 - p at plane parity p; red_low: row rr - 1
+    // at split index jj, the lowest LDS index its stencil reads)
+    int red_rr[2], red_jj[2], red_low[2];
     bool red_on[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -265,43 +303,47 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         red_on[e] = q < RED_CELLS;
         red_rr[e] = 1 + q / RED_ROW;
         red_jj[e] = q - (red_rr[e] - 1) * RED_ROW;
+        red_low[e] = (red_rr[e] - 1) * HX + red_jj[e];
     }
     // the sources of plane z's red cells, loaded a step ahead of their use
-    auto red_sources = [&](int z, double out[2], bool hold[2]) {
+    auto red_sources = [&](int z, auto pl, double out[2], bool hold[2]) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int rr = red_rr[e];
-            const int p = (rr + z) & 1;
+            const int p = (rr + ring_slot(decltype(pl)::d, 2)) & 1;
             const int gx = x0 - 2 + 2 * (red_jj[e] + 1 - p) + p, gy = y0 - 2 + rr;
-            const int at = sidx(gx, gy, z); // in bounds also when !red_on[e]
-            out[e] = s[at];
-            hold[e] = held_at(at);
+            const size_t plane = splane(z);
+            const unsigned at = sxy(gx, gy); // in bounds also when !red_on[e]
+            out[e] = *plane_at(s + plane, at);
+            hold[e] = held_at(plane, at);
         }
     };
     // red cells of plane z over the tile + 1-cell halo -> R(z)
-    auto red_plane = [&](int z, const double src[2], const bool hold[2]) {
-        const double(*m0)[HX] = PR[s3(z - 1)], (*m1)[HX] = PB[s5(z - 1)];
-        const double(*c0)[HX] = PR[s3(z)], (*c1)[HX] = PB[s5(z)];
-        const double(*p0)[HX] = PR[s3(z + 1)], (*p1)[HX] = PB[s5(z + 1)];
-        double(*rz)[HX] = R[s3(z)];
+    auto red_plane = [&](int z, auto pl, const double src[2], const bool hold[2]) {
+        constexpr int d = decltype(pl)::d;
+        const double *m0 = PR[ring_slot(d - 1, 3)][0], *m1 = PB[ring_slot(d - 1, 6)][0];
+        const double *c0 = PR[ring_slot(d, 3)][0], *c1 = PB[ring_slot(d, 6)][0];
+        const double *p0 = PR[ring_slot(d + 1, 3)][0], *p1 = PB[ring_slot(d + 1, 6)][0];
+        double *rz = R[ring_slot(d, 3)][0];
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             if (!red_on[e]) continue;
-            const int rr = red_rr[e];
-            const int p = (rr + z) & 1;         // red cell at column c = 2j + p
-            const int j = red_jj[e] + 1 - p;    // c in [1, PX-2]
-            const int a = j + p, b = j + p - 1; // split index of columns c+1, c-1
+            // red cell at column c = 2j + p, j = jj + 1 - p in [1, PX-2];
+            // columns c+1, c-1 at split indices a = jj + 1, b = jj
+            const int p = (red_rr[e] + ring_slot(d, 2)) & 1;
+            const int lo = fresh(red_low[e]); // row rr - 1, split index b
+            const int lj = lo + 1 - p;        // row rr - 1, split index j
             const double v[19] = {
-                c0[rr][j], c1[rr][a], c1[rr][b], c1[rr + 1][j], c1[rr - 1][j],
-                p1[rr][j], m1[rr][j],
-                c0[rr + 1][a], c0[rr - 1][a], c0[rr + 1][b], c0[rr - 1][b],
-                p0[rr][a], m0[rr][a], p0[rr][b], m0[rr][b],
-                p0[rr + 1][j], m0[rr + 1][j], p0[rr - 1][j], m0[rr - 1][j]};
+                c0[lj + HX], c1[lo + HX + 1], c1[lo + HX], c1[lj + 2 * HX], c1[lj],
+                p1[lj + HX], m1[lj + HX],
+                c0[lo + 2 * HX + 1], c0[lo + 1], c0[lo + 2 * HX], c0[lo],
+                p0[lo + HX + 1], m0[lo + HX + 1], p0[lo + HX], m0[lo + HX],
+                p0[lj + 2 * HX], m0[lj + 2 * HX], p0[lj], m0[lj]};
             if constexpr (PER) {
-                rz[rr][j] = relax_cell(v, src[e], al, w, fb);
+                rz[lj + HX] = relax_cell(v, src[e], al, w, fb);
             } else {
-                const int gx = x0 - 2 + 2 * j + p, gy = y0 - 2 + rr;
-                rz[rr][j] = ghost(gx, gy, z) || hold[e] ? v[0] : relax_cell(v, src[e], al, w, fb);
+                const int gx = x0 - 2 + 2 * (red_jj[e] + 1 - p) + p, gy = y0 - 2 + red_rr[e];
+                rz[lj + HX] = ghost(gx, gy, z) || hold[e] ? v[0] : relax_cell(v, src[e], al, w, fb);
             }
         }
     };
@@ -311,30 +353,37 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     const int yt = y0 - 2 + rt;
     const int xy_t = (yt << lg) | (x0 - 2 + 2 * jt);
     const int pxy_t = (yt + 1) * pitch + x0 - 2 + 2 * jt + 1; // padded (PER = false)
-    auto black_source = [&](int k, bool &hold) {
-        const int pb = (1 + rt + k) & 1;
+    const int black_low = (rt - 1) * HX + jt; // LDS index of row rt - 1, split index jt
+    auto black_source = [&](int k, auto pl, bool &hold) {
+        const int pb = (1 + rt + ring_slot(decltype(pl)::d, 2)) & 1;
         if constexpr (PER) {
             hold = false;
-            return s[zoff(k) | xy_t | pb];
+            return *plane_at(s + splane(k), (unsigned)(xy_t | pb));
         } else {
-            const int at = ((k < n ? k : m) << (2 * lg) | xy_t) + pb; // plane n: loaded, unused
-            hold = held_at(at);
-            return s[at];
+            const size_t plane = (size_t)(k < n ? k : m) << (2 * lg); // plane n: loaded, unused
+            const unsigned at = (unsigned)(xy_t + pb);
+            hold = held_at(plane, at);
+            return *plane_at(s + plane, at);
         }
     };
-    auto black_and_store = [&](int k, double sv, bool hold) {
-        const double(*rm)[HX] = R[s3(k - 1)], (*r0)[HX] = R[s3(k)], (*rp)[HX] = R[s3(k + 1)];
-        const double(*m1)[HX] = PB[s5(k - 1)], (*c1)[HX] = PB[s5(k)], (*p1)[HX] = PB[s5(k + 1)];
-        const int pb = (1 + rt + k) & 1; // black cell at column 2jt + pb
-        const int j = jt, rr = rt, a = j + pb, b = j + pb - 1;
+    auto black_and_store = [&](int k, auto pl, double sv, bool hold) {
+        constexpr int d = decltype(pl)::d;
+        const double *rm = R[ring_slot(d - 1, 3)][0], *r0 = R[ring_slot(d, 3)][0],
+                     *rp = R[ring_slot(d + 1, 3)][0];
+        const double *m1 = PB[ring_slot(d - 1, 6)][0], *c1 = PB[ring_slot(d, 6)][0],
+                     *p1 = PB[ring_slot(d + 1, 6)][0];
+        const int pb = (1 + rt + ring_slot(d, 2)) & 1; // black cell at column 2jt + pb
+        // columns 2jt + pb +- 1 at split indices a = jt + pb, b = jt + pb - 1
+        const int lo = fresh(black_low); // row rt - 1, split index jt
+        const int lb = lo + pb - 1;      // row rt - 1, split index b
         const double v[19] = {
-            c1[rr][j], r0[rr][a], r0[rr][b], r0[rr + 1][j], r0[rr - 1][j],
-            rp[rr][j], rm[rr][j],
-            c1[rr + 1][a], c1[rr - 1][a], c1[rr + 1][b], c1[rr - 1][b],
-            p1[rr][a], m1[rr][a], p1[rr][b], m1[rr][b],
-            p1[rr + 1][j], m1[rr + 1][j], p1[rr - 1][j], m1[rr - 1][j]};
+            c1[lo + HX], r0[lb + HX + 1], r0[lb + HX], r0[lo + 2 * HX], r0[lo],
+            rp[lo + HX], rm[lo + HX],
+            c1[lb + 2 * HX + 1], c1[lb + 1], c1[lb + 2 * HX], c1[lb],
+            p1[lb + HX + 1], m1[lb + HX + 1], p1[lb + HX], m1[lb + HX],
+            p1[lo + 2 * HX], m1[lo + 2 * HX], p1[lo], m1[lo]};
         const double vb = hold ? v[0] : relax_cell(v, sv, al, w, fb);
-        const double vr = r0[rr][j]; // the red cell of the pair, column 2jt + 1 - pb
+        const double vr = r0[lo + HX]; // the red cell of the pair, column 2jt + 1 - pb
         // the pair as one 16-byte non-temporal store: the new field is not
         // read again in this sweep, so it need not displace the halo lines
         // that neighbouring tiles read from L2 (3% faster at 256^3)
@@ -343,9 +392,10 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
         o.x = pb ? vr : vb;
         o.y = pb ? vb : vr;
         if constexpr (PER) {
-            __builtin_nontemporal_store(o, reinterpret_cast<pair_t *>(pout + (zoff(k) | xy_t)));
+            __builtin_nontemporal_store(o, reinterpret_cast<pair_t *>(plane_at(pout + zoff(k),
+                                                                                (unsigned)xy_t)));
         } else {
-            double *q = pout + zoff(k) + pxy_t;
+            double *q = plane_at(pout + zoff(k), (unsigned)pxy_t);
             __builtin_nontemporal_store(o.x, q);
             __builtin_nontemporal_store(o.y, q + 1);
         }
@@ -356,62 +406,81 @@ k_sweep_fused(const double *__restrict__ pin, double *__restrict__ pout,
     // plane z needs coarse planes z/2-1, z/2 (z even) or (z-1)/2, (z+1)/2.
     const int c0 = z0 >> 1;
     if constexpr (PRO) {
-        for (int K = c0 - 2; K <= c0; ++K) {
-            e_load(K);
-            e_store(K);
-        }
+        e_load(c0 - 2);
+        e_store(Plane<-2>{});
+        e_load(c0 - 1);
+        e_store(Plane<-1>{});
+        e_load(c0);
+        e_store(Plane<0>{});
         __syncthreads();
     }
     fetch(z0 - 2);
-    commit(z0 - 2);
+    commit(z0 - 2, Plane<-2>{});
     fetch(z0 - 1);
-    commit(z0 - 1);
+    commit(z0 - 1, Plane<-1>{});
     fetch(z0);
-    commit(z0);
+    commit(z0, Plane<0>{});
     double ra[2], rb[2], ba, bb;
     bool ha[2], hb[2], hba, hbb;
-    red_sources(z0 - 1, ra, ha);
+    red_sources(z0 - 1, Plane<-1>{}, ra, ha);
     fetch(z0 + 1);
     if constexpr (PRO) e_load(c0 + 1);
     __syncthreads();
-    red_plane(z0 - 1, ra, ha);
+    red_plane(z0 - 1, Plane<-1>{}, ra, ha);
     __syncthreads(); // red(z0-1) has read the red slot that plane z0+1 takes
     if constexpr (PRO) {
-        e_store(c0 + 1); // the slot of coarse plane c0-2, last used by plane z0-2
+        e_store(Plane<1>{}); // the slot of coarse plane c0-2, last used by plane z0-2
         __syncthreads();
     }
-    commit(z0 + 1);
-    red_sources(z0, ra, ha);
+    commit(z0 + 1, Plane<1>{});
+    red_sources(z0, Plane<0>{}, ra, ha);
     fetch(z0 + 2);
     __syncthreads();
-    red_plane(z0, ra, ha);
+    red_plane(z0, Plane<0>{}, ra, ha);
     __syncthreads(); // red(z0) has read the red slot that plane z0+2 takes
-    red_sources(z0 + 1, ra, ha);
-    ba = black_source(z0, hba);
+    red_sources(z0 + 1, Plane<1>{}, ra, ha);
+    ba = black_source(z0, Plane<0>{}, hba);
     if constexpr (PRO) e_load(c0 + 2);
     // one step: red(k+1), black(k); loads the sources of red(k+2), black(k+1)
     // and the field of plane k+3 (on the last step one plane past the ones
     // used: in bounds, never committed).  With PRO an even step stores
     // coarse plane k/2+2 (first needed by plane k+3, in the slot of plane
     // k/2-1, last needed by plane k) and an odd step loads the next one.
-    auto step = [&](int k, bool even, const double (&use_r)[2], const bool (&use_rh)[2],
+    auto step = [&](int k, auto pl, const double (&use_r)[2], const bool (&use_rh)[2],
                     double use_b, bool use_bh, double (&next_r)[2], bool (&next_rh)[2],
                     double &next_b, bool &next_bh) {
-        commit(k + 2); // red slot of plane k-1 (last read by red(k)), black of k-3
-        red_sources(k + 2, next_r, next_rh);
-        next_b = black_source(k + 1, next_bh);
-        if (PRO && !even) e_load((k + 1) / 2 + 2);
+        constexpr int d = decltype(pl)::d; // k = z0 + d modulo the ring period
+        commit(k + 2, Plane<d + 2>{}); // red slot of plane k-1 (last read by red(k)), black of k-4
+        red_sources(k + 2, Plane<d + 2>{}, next_r, next_rh);
+        next_b = black_source(k + 1, Plane<d + 1>{}, next_bh);
+        if constexpr (PRO && (d & 1)) e_load((k + 1) / 2 + 2);
         fetch(k + 3);
         __syncthreads();
-        if (PRO && even) e_store(k / 2 + 2);
-        red_plane(k + 1, use_r, use_rh); // writes the R slot of plane k-2, last read by black(k-1)
+        if constexpr (PRO && !(d & 1)) e_store(Plane<d / 2 + 2>{});
+        // writes the R slot of plane k-2, last read by black(k-1)
+        red_plane(k + 1, Plane<d + 1>{}, use_r, use_rh);
         __syncthreads();
-        black_and_store(k, use_b, use_bh);
+        black_and_store(k, Plane<d>{}, use_b, use_bh);
     };
-    static_assert(TZ % 2 == 0, "the z loop is unrolled by two");
-    for (int k = z0; k < z0 + TZ; k += 2) {
-        step(k, true, ra, ha, ba, hba, rb, hb, bb, hbb);
-        step(k + 1, false, rb, hb, bb, hbb, ra, ha, ba, hba);
+    static_assert(TZ % 2 == 0, "steps alternate between two register sets");
+    constexpr int G = 6; // ring period: a multiple of 3 and of 6 planes
+    int k = z0;
+    for (int g = 0; g < TZ / G; ++g, k += G) {
+        step(k, Plane<0>{}, ra, ha, ba, hba, rb, hb, bb, hbb);
+        step(k + 1, Plane<1>{}, rb, hb, bb, hbb, ra, ha, ba, hba);
+        step(k + 2, Plane<2>{}, ra, ha, ba, hba, rb, hb, bb, hbb);
+        step(k + 3, Plane<3>{}, rb, hb, bb, hbb, ra, ha, ba, hba);
+        step(k + 4, Plane<4>{}, ra, ha, ba, hba, rb, hb, bb, hbb);
+        step(k + 5, Plane<5>{}, rb, hb, bb, hbb, ra, ha, ba, hba);
+    }
+    // the last TZ mod 6 planes
+    if constexpr (TZ % G >= 2) {
+        step(k, Plane<0>{}, ra, ha, ba, hba, rb, hb, bb, hbb);
+        step(k + 1, Plane<1>{}, rb, hb, bb, hbb, ra, ha, ba, hba);
+    }
+    if constexpr (TZ % G >= 4) {
+        step(k + 2, Plane<2>{}, ra, ha, ba, hba, rb, hb, bb, hbb);
+        step(k + 3, Plane<3>{}, rb, hb, bb, hbb, ra, ha, ba, hba);
     }
     if (fb) flush_events(fallbacks, fb);
 }
