@@ -9,6 +9,44 @@ namespace ndgp {
 namespace dev {
 
 // ------------------------------------------------------------------------
+// z-streamed sweeps: ring slots, opaque per-thread values, plane addressing
+
+// A plane of a fused sweep's z-chunk named by its offset from the chunk's first
+// plane, as a type: LDS ring slots derived from it are compile-time constants,
+// so every LDS access is the thread's base address plus an immediate offset
+// (the LDS-streamed fused sweeps).
+template <int D>
+struct Plane {
+    static constexpr int d = D;
+};
+constexpr int ring_slot(int a, int p) { return ((a % p) + p) % p; }
+constexpr int floor_half(int a) { return a >= 0 ? a / 2 : -((1 - a) / 2); }
+
+// The same per-thread value, opaque to the optimiser at this point: addresses
+// derived from it are formed here, one instruction each, instead of being
+// hoisted out of the z loop and held in registers the stencil needs.
+__device__ __forceinline__ int fresh(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Cell i of one z-plane, the plane's address uniform across the workgroup (in
+// scalar registers) and i a 32-bit offset inside it (a padded 1024^2 plane is
+// 8.4 MB): one vector register per address instead of two.
+__device__ __forceinline__ const double *plane_at(const double *plane, unsigned i) {
+    return reinterpret_cast<const double *>(reinterpret_cast<const char *>(plane) + i * 8u);
+}
+__device__ __forceinline__ double *plane_at(double *plane, unsigned i) {
+    return reinterpret_cast<double *>(reinterpret_cast<char *>(plane) + i * 8u);
+}
+__device__ __forceinline__ const float *plane_at(const float *plane, unsigned i) {
+    return reinterpret_cast<const float *>(reinterpret_cast<const char *>(plane) + i * 4u);
+}
+__device__ __forceinline__ float *plane_at(float *plane, unsigned i) {
+    return reinterpret_cast<float *>(reinterpret_cast<char *>(plane) + i * 4u);
+}
+
+// ------------------------------------------------------------------------
 // indexing: periodic levels are natural n^3 with wrap-around (n a power of
 // two, so wrap is a mask); Dirichlet levels are padded (n+2)^3.
 

@@ -62,34 +62,6 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
     if (fb) flush_events(fallbacks, fb);
 }
 
-// A plane of a fused sweep's z-chunk named by its offset from the chunk's first
-// plane, as a type: LDS ring slots derived from it are compile-time constants,
-// so every LDS access is the thread's base address plus an immediate offset.
-template <int D>
-struct Plane {
-    static constexpr int d = D;
-};
-constexpr int ring_slot(int a, int p) { return ((a % p) + p) % p; }
-constexpr int floor_half(int a) { return a >= 0 ? a / 2 : -((1 - a) / 2); }
-
-// The same per-thread value, opaque to the optimiser at this point: addresses
-// derived from it are formed here, one instruction each, instead of being
-// hoisted out of the z loop and held in registers the stencil needs.
-__device__ __forceinline__ int fresh(int v) {
-    asm volatile("" : "+v"(v));
-    return v;
-}
-
-// Cell i of one z-plane, the plane's address uniform across the workgroup (in
-// scalar registers) and i a 32-bit offset inside it (a padded 1024^2 plane is
-// 8.4 MB): one vector register per address instead of two.
-__device__ __forceinline__ const double *plane_at(const double *plane, unsigned i) {
-    return reinterpret_cast<const double *>(reinterpret_cast<const char *>(plane) + i * 8u);
-}
-__device__ __forceinline__ double *plane_at(double *plane, unsigned i) {
-    return reinterpret_cast<double *>(reinterpret_cast<char *>(plane) + i * 8u);
-}
-
 // One full red-black sweep of a periodic level in one launch, with the same
 // semantics as two k_smooth_half launches (colour 0 from pin, then colour 1
 // from that result; same-colour neighbours always at their pass-start

@@ -37,29 +37,33 @@ __device__ __forceinline__ CorrTerms corr_terms(const float vp[19], const float 
     const float Dwx = Dpx + Dex, Dwy = Dpy + Dey, Dwz = Dpz + Dez;
     const float pair = fmaf(Dwx, Dey, Dex * Dpy) + fmaf(Dwx, Dez, Dex * Dpz) +
                        fmaf(Dwy, Dez, Dey * Dpz);
-    float cs = 0.f, see = 0.f;
-    auto corner = [&](int q, float pa, float pb, float ea, float eb) {
-        const float gp = vp[q] - up, ge = ve[q] - ue;
-        see += gp + ge;
-        const float Cp = gp - pa - pb, Ce = ge - ea - eb;
-        cs = fmaf(Cp + Cp + Ce, Ce, cs);
+    // corner (s, t) of plane a-b: C = (v_st - v_s) - (v_t - v_centre), the
+    // first difference exact for neighbouring values (Sterbenz), for phi and
+    // for e; the sum of the corner differences of w is the edge sum less
+    // 4 lap w (every face neighbour sits in four corners)
+    float cs = 0.f, sw = 0.f;
+    auto corner = [&](int q, int s_face, float pb, float eb) {
+        const float Cp = (vp[q] - vp[s_face]) - pb, Ce = (ve[q] - ve[s_face]) - eb;
+        const float Cw = Cp + Ce;
+        sw += Cw;
+        cs = fmaf(Cw + Cp, Ce, cs);
     };
-    corner(7, pxp, pyp, exp_, eyp);
-    corner(8, pxp, pym, exp_, eym);
-    corner(9, pxm, pyp, exm, eyp);
-    corner(10, pxm, pym, exm, eym);
-    corner(11, pxp, pzp, exp_, ezp);
-    corner(12, pxp, pzm, exp_, ezm);
-    corner(13, pxm, pzp, exm, ezp);
-    corner(14, pxm, pzm, exm, ezm);
-    corner(15, pyp, pzp, eyp, ezp);
-    corner(16, pyp, pzm, eyp, ezm);
-    corner(17, pym, pzp, eym, ezp);
-    corner(18, pym, pzm, eym, ezm);
+    corner(7, 1, pyp, eyp);
+    corner(8, 1, pym, eym);
+    corner(9, 2, pyp, eyp);
+    corner(10, 2, pym, eym);
+    corner(11, 1, pzp, ezp);
+    corner(12, 1, pzm, ezm);
+    corner(13, 2, pzp, ezp);
+    corner(14, 2, pzm, ezm);
+    corner(15, 3, pzp, ezp);
+    corner(16, 3, pzm, ezm);
+    corner(17, 4, pzp, ezp);
+    corner(18, 4, pzm, ezm);
     CorrTerms t;
     t.A = fmaf(2.f * al, pair - 0.25f * cs, (Dex + Dey) + Dez);
     t.lapw = (Dwx + Dwy) + Dwz;
-    t.seew = see;
+    t.seew = fmaf(4.f, t.lapw, sw);
     return t;
 }
 
@@ -321,7 +325,9 @@ k_corr_coarsest(float *__restrict__ e, const float *__restrict__ phi, const floa
 // launch: the LDS-streamed z pipeline of the FP64 k_sweep_fused with FP32
 // planes of phi (both colours, static during the sweep) and of e (old red on
 // 3 planes, old black on 5, red after the red pass on 3), and the cell update
-// of k_corr_half, so the result is bit for bit two k_corr_half launches.
+// of k_corr_half, so the result is bit for bit two k_corr_half launches.  As
+// in the FP64 sweep, the rings of 5 planes (phi, old black e) have 6 slots and
+// the z loop is unrolled by 6, so every LDS slot is a compile-time constant.
 template <int TX, int TY, int TZ, int NT>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(4))) // two workgroups per CU: at most 128 VGPRs
@@ -333,9 +339,9 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
     constexpr int RED_ROW = (TX + 2) / 2, RED_CELLS = RED_ROW * (TY + 2);
     static_assert(TX % 2 == 0 && TY % 2 == 0 && TX * TY / 2 == NT, "one black cell per thread");
     static_assert(RED_CELLS <= 2 * NT, "at most two red cells per thread");
-    __shared__ float F[5][2][PY][HX]; // phi, both colours, planes k-2 .. k+2
+    __shared__ float F[6][2][PY][HX]; // phi, both colours, planes k-2 .. k+2
     __shared__ float ER[3][PY][HX];   // old e, red cells
-    __shared__ float EB[5][PY][HX];   // old e, black cells
+    __shared__ float EB[6][PY][HX];   // old e, black cells, planes k-2 .. k+2
     __shared__ float R[3][PY][HX];    // e after the red pass, red cells
 
     const int n = 1 << lg, m = n - 1;
@@ -346,9 +352,7 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
     const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY, z0 = (logical / tiles) * TZ;
     const int tid = threadIdx.x;
     unsigned fb = 0;
-    auto zoff = [&](int z) { return (z & m) << (2 * lg); };
-    auto s5 = [](int z) { return (z + 5 * 4096) % 5; };
-    auto s3 = [](int z) { return (z + 3 * 4096) % 3; };
+    auto zoff = [&](int z) { return (size_t)(z & m) << (2 * lg); };
 
     // pairs of cells (columns 2j, 2j+1 of a row: one red, one black, split
     // index j), loaded 8 bytes at a time
@@ -363,30 +367,35 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
     }
     float2 pre_p[PRE], pre_e[PRE];
     auto fetch = [&](int z) {
-        const int zo = zoff(z);
+        const float *pp = phi + zoff(z), *pe = ein + zoff(z);
 #pragma unroll
         for (int e = 0; e < PRE; ++e)
             if (pidx[e] >= 0) {
-                pre_p[e] = *reinterpret_cast<const float2 *>(phi + (zo | pxy[e]));
-                pre_e[e] = *reinterpret_cast<const float2 *>(ein + (zo | pxy[e]));
+                pre_p[e] = *reinterpret_cast<const float2 *>(plane_at(pp, pxy[e]));
+                pre_e[e] = *reinterpret_cast<const float2 *>(plane_at(pe, pxy[e]));
             }
     };
-    auto commit = [&](int z) {
-        float *f0 = &F[s5(z)][0][0][0], *f1 = &F[s5(z)][1][0][0];
-        float *red = &ER[s3(z)][0][0], *blk = &EB[s5(z)][0][0];
-        const int zp = z & 1;
+    auto commit = [&](auto pl) {
+        constexpr int d = decltype(pl)::d; // the plane z0 + d, z0 even
+        float *f0 = &F[ring_slot(d, 6)][0][0][0], *f1 = &F[ring_slot(d, 6)][1][0][0];
+        float *red = &ER[ring_slot(d, 3)][0][0], *blk = &EB[ring_slot(d, 6)][0][0];
+        constexpr int zp = ring_slot(d, 2);
 #pragma unroll
         for (int e = 0; e < PRE; ++e)
             if (pidx[e] >= 0) {
                 const bool fb1 = (ppar[e] ^ zp) != 0; // column 2j black
-                f0[pidx[e]] = fb1 ? pre_p[e].y : pre_p[e].x;
-                f1[pidx[e]] = fb1 ? pre_p[e].x : pre_p[e].y;
-                red[pidx[e]] = fb1 ? pre_e[e].y : pre_e[e].x;
-                blk[pidx[e]] = fb1 ? pre_e[e].x : pre_e[e].y;
+                const int at = fresh(pidx[e]);
+                f0[at] = fb1 ? pre_p[e].y : pre_p[e].x;
+                f1[at] = fb1 ? pre_p[e].x : pre_p[e].y;
+                red[at] = fb1 ? pre_e[e].y : pre_e[e].x;
+                blk[at] = fb1 ? pre_e[e].x : pre_e[e].y;
             }
     };
 
-    int red_rr[2], red_jj[2];
+    // red cells of the halo-1 region (row rr, split index jj + 1 - p at plane
+    // parity p; red_low: row rr - 1 at split index jj, the lowest LDS index
+    // the stencil reads)
+    int red_rr[2], red_jj[2], red_low[2];
     bool red_on[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -394,118 +403,144 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
         red_on[e] = q < RED_CELLS;
         red_rr[e] = 1 + q / RED_ROW;
         red_jj[e] = q - (red_rr[e] - 1) * RED_ROW;
+        red_low[e] = (red_rr[e] - 1) * HX + red_jj[e];
     }
-    auto red_sources = [&](int z, float out[2]) {
-        const int zo = zoff(z);
+    auto red_sources = [&](int z, auto pl, float out[2]) {
+        const float *rp = rr_in + zoff(z);
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int rr = red_rr[e];
-            const int p = (rr + z) & 1;
+            const int p = (rr + ring_slot(decltype(pl)::d, 2)) & 1;
             const int gx = x0 - 2 + 2 * (red_jj[e] + 1 - p) + p, gy = y0 - 2 + rr;
-            out[e] = rr_in[zo | ((gy & m) << lg) | (gx & m)]; // in bounds also when !red_on[e]
+            // in bounds also when !red_on[e]
+            out[e] = *plane_at(rp, (unsigned)(((gy & m) << lg) | (gx & m)));
         }
     };
-    auto red_plane = [&](int z, const float src[2]) {
-        const float(*pm0)[HX] = F[s5(z - 1)][0], (*pm1)[HX] = F[s5(z - 1)][1];
-        const float(*pc0)[HX] = F[s5(z)][0], (*pc1)[HX] = F[s5(z)][1];
-        const float(*pp0)[HX] = F[s5(z + 1)][0], (*pp1)[HX] = F[s5(z + 1)][1];
-        const float(*m0)[HX] = ER[s3(z - 1)], (*m1)[HX] = EB[s5(z - 1)];
-        const float(*c0)[HX] = ER[s3(z)], (*c1)[HX] = EB[s5(z)];
-        const float(*p0)[HX] = ER[s3(z + 1)], (*p1)[HX] = EB[s5(z + 1)];
-        float(*rz)[HX] = R[s3(z)];
+    auto red_plane = [&](auto pl, const float src[2]) {
+        constexpr int d = decltype(pl)::d;
+        const float *pm0 = F[ring_slot(d - 1, 6)][0][0], *pm1 = F[ring_slot(d - 1, 6)][1][0];
+        const float *pc0 = F[ring_slot(d, 6)][0][0], *pc1 = F[ring_slot(d, 6)][1][0];
+        const float *pp0 = F[ring_slot(d + 1, 6)][0][0], *pp1 = F[ring_slot(d + 1, 6)][1][0];
+        const float *m0 = ER[ring_slot(d - 1, 3)][0], *m1 = EB[ring_slot(d - 1, 6)][0];
+        const float *c0 = ER[ring_slot(d, 3)][0], *c1 = EB[ring_slot(d, 6)][0];
+        const float *p0 = ER[ring_slot(d + 1, 3)][0], *p1 = EB[ring_slot(d + 1, 6)][0];
+        float *rz = R[ring_slot(d, 3)][0];
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             if (!red_on[e]) continue;
-            const int rr = red_rr[e];
-            const int p = (rr + z) & 1;
-            const int j = red_jj[e] + 1 - p;
-            const int a = j + p, b = j + p - 1;
+            // red cell at split index j = jj + 1 - p; its x neighbours at
+            // a = jj + 1 and b = jj
+            const int p = (red_rr[e] + ring_slot(d, 2)) & 1;
+            const int lo = fresh(red_low[e]); // row rr - 1, split index b
+            const int lj = lo + 1 - p;        // row rr - 1, split index j
             const float vp[19] = {
-                pc0[rr][j], pc1[rr][a], pc1[rr][b], pc1[rr + 1][j], pc1[rr - 1][j],
-                pp1[rr][j], pm1[rr][j],
-                pc0[rr + 1][a], pc0[rr - 1][a], pc0[rr + 1][b], pc0[rr - 1][b],
-                pp0[rr][a], pm0[rr][a], pp0[rr][b], pm0[rr][b],
-                pp0[rr + 1][j], pm0[rr + 1][j], pp0[rr - 1][j], pm0[rr - 1][j]};
+                pc0[lj + HX], pc1[lo + HX + 1], pc1[lo + HX], pc1[lj + 2 * HX], pc1[lj],
+                pp1[lj + HX], pm1[lj + HX],
+                pc0[lo + 2 * HX + 1], pc0[lo + 1], pc0[lo + 2 * HX], pc0[lo],
+                pp0[lo + HX + 1], pm0[lo + HX + 1], pp0[lo + HX], pm0[lo + HX],
+                pp0[lj + 2 * HX], pm0[lj + 2 * HX], pp0[lj], pm0[lj]};
             const float ve[19] = {
-                c0[rr][j], c1[rr][a], c1[rr][b], c1[rr + 1][j], c1[rr - 1][j],
-                p1[rr][j], m1[rr][j],
-                c0[rr + 1][a], c0[rr - 1][a], c0[rr + 1][b], c0[rr - 1][b],
-                p0[rr][a], m0[rr][a], p0[rr][b], m0[rr][b],
-                p0[rr + 1][j], m0[rr + 1][j], p0[rr - 1][j], m0[rr - 1][j]};
-            rz[rr][j] = relax_corr_cell(vp, ve, src[e], al, w, fb);
+                c0[lj + HX], c1[lo + HX + 1], c1[lo + HX], c1[lj + 2 * HX], c1[lj],
+                p1[lj + HX], m1[lj + HX],
+                c0[lo + 2 * HX + 1], c0[lo + 1], c0[lo + 2 * HX], c0[lo],
+                p0[lo + HX + 1], m0[lo + HX + 1], p0[lo + HX], m0[lo + HX],
+                p0[lj + 2 * HX], m0[lj + 2 * HX], p0[lj], m0[lj]};
+            rz[lj + HX] = relax_corr_cell(vp, ve, src[e], al, w, fb);
         }
     };
 
     const int rt = 2 + tid / (TX / 2), jt = 1 + tid % (TX / 2);
     const int yt = y0 - 2 + rt;
     const int xy_t = (yt << lg) | (x0 - 2 + 2 * jt);
-    auto black_source = [&](int k) {
-        const int pb = (1 + rt + k) & 1;
-        return rr_in[zoff(k) | xy_t | pb];
+    const int black_low = (rt - 1) * HX + jt; // LDS index of row rt - 1, split index jt
+    auto black_source = [&](int k, auto pl) {
+        const int pb = (1 + rt + ring_slot(decltype(pl)::d, 2)) & 1;
+        return *plane_at(rr_in + zoff(k), (unsigned)(xy_t | pb));
     };
-    auto black_and_store = [&](int k, float sv) {
-        const float(*pm0)[HX] = F[s5(k - 1)][0], (*pm1)[HX] = F[s5(k - 1)][1];
-        const float(*pc0)[HX] = F[s5(k)][0], (*pc1)[HX] = F[s5(k)][1];
-        const float(*pp0)[HX] = F[s5(k + 1)][0], (*pp1)[HX] = F[s5(k + 1)][1];
-        const float(*rm)[HX] = R[s3(k - 1)], (*r0)[HX] = R[s3(k)], (*rp)[HX] = R[s3(k + 1)];
-        const float(*m1)[HX] = EB[s5(k - 1)], (*c1)[HX] = EB[s5(k)], (*p1)[HX] = EB[s5(k + 1)];
-        const int pb = (1 + rt + k) & 1;
-        const int j = jt, rr = rt, a = j + pb, b = j + pb - 1;
+    auto black_and_store = [&](int k, auto pl, float sv) {
+        constexpr int d = decltype(pl)::d;
+        const float *pm0 = F[ring_slot(d - 1, 6)][0][0], *pm1 = F[ring_slot(d - 1, 6)][1][0];
+        const float *pc0 = F[ring_slot(d, 6)][0][0], *pc1 = F[ring_slot(d, 6)][1][0];
+        const float *pp0 = F[ring_slot(d + 1, 6)][0][0], *pp1 = F[ring_slot(d + 1, 6)][1][0];
+        const float *rm = R[ring_slot(d - 1, 3)][0], *r0 = R[ring_slot(d, 3)][0],
+                    *rp = R[ring_slot(d + 1, 3)][0];
+        const float *m1 = EB[ring_slot(d - 1, 6)][0], *c1 = EB[ring_slot(d, 6)][0],
+                    *p1 = EB[ring_slot(d + 1, 6)][0];
+        const int pb = (1 + rt + ring_slot(d, 2)) & 1; // black cell at column 2jt + pb
+        // its x neighbours at split indices a = jt + pb, b = jt + pb - 1
+        const int lo = fresh(black_low); // row rt - 1, split index jt
+        const int lb = lo + pb - 1;      // row rt - 1, split index b
         const float vp[19] = {
-            pc1[rr][j], pc0[rr][a], pc0[rr][b], pc0[rr + 1][j], pc0[rr - 1][j],
-            pp0[rr][j], pm0[rr][j],
-            pc1[rr + 1][a], pc1[rr - 1][a], pc1[rr + 1][b], pc1[rr - 1][b],
-            pp1[rr][a], pm1[rr][a], pp1[rr][b], pm1[rr][b],
-            pp1[rr + 1][j], pm1[rr + 1][j], pp1[rr - 1][j], pm1[rr - 1][j]};
+            pc1[lo + HX], pc0[lb + HX + 1], pc0[lb + HX], pc0[lo + 2 * HX], pc0[lo],
+            pp0[lo + HX], pm0[lo + HX],
+            pc1[lb + 2 * HX + 1], pc1[lb + 1], pc1[lb + 2 * HX], pc1[lb],
+            pp1[lb + HX + 1], pm1[lb + HX + 1], pp1[lb + HX], pm1[lb + HX],
+            pp1[lo + 2 * HX], pm1[lo + 2 * HX], pp1[lo], pm1[lo]};
         const float ve[19] = {
-            c1[rr][j], r0[rr][a], r0[rr][b], r0[rr + 1][j], r0[rr - 1][j],
-            rp[rr][j], rm[rr][j],
-            c1[rr + 1][a], c1[rr - 1][a], c1[rr + 1][b], c1[rr - 1][b],
-            p1[rr][a], m1[rr][a], p1[rr][b], m1[rr][b],
-            p1[rr + 1][j], m1[rr + 1][j], p1[rr - 1][j], m1[rr - 1][j]};
+            c1[lo + HX], r0[lb + HX + 1], r0[lb + HX], r0[lo + 2 * HX], r0[lo],
+            rp[lo + HX], rm[lo + HX],
+            c1[lb + 2 * HX + 1], c1[lb + 1], c1[lb + 2 * HX], c1[lb],
+            p1[lb + HX + 1], m1[lb + HX + 1], p1[lb + HX], m1[lb + HX],
+            p1[lo + 2 * HX], m1[lo + 2 * HX], p1[lo], m1[lo]};
         const float vb = relax_corr_cell(vp, ve, sv, al, w, fb);
-        const float vr = r0[rr][j];
-        float *dst = eout + (zoff(k) | xy_t);
+        const float vr = r0[lo + HX];
+        float *dst = plane_at(eout + zoff(k), (unsigned)xy_t);
         dst[0] = pb ? vr : vb;
         dst[1] = pb ? vb : vr;
     };
 
     // the FP64 kernel's schedule: phi and old e on planes z0-2 .. z0+TZ+1
     fetch(z0 - 2);
-    commit(z0 - 2);
+    commit(Plane<-2>{});
     fetch(z0 - 1);
-    commit(z0 - 1);
+    commit(Plane<-1>{});
     fetch(z0);
-    commit(z0);
+    commit(Plane<0>{});
     float ra[2], rb[2], ba, bb;
-    red_sources(z0 - 1, ra);
+    red_sources(z0 - 1, Plane<-1>{}, ra);
     fetch(z0 + 1);
     __syncthreads();
-    red_plane(z0 - 1, ra);
+    red_plane(Plane<-1>{}, ra);
     __syncthreads(); // red(z0-1) has read the red slot that plane z0+1 takes
-    commit(z0 + 1);
-    red_sources(z0, ra);
+    commit(Plane<1>{});
+    red_sources(z0, Plane<0>{}, ra);
     fetch(z0 + 2);
     __syncthreads();
-    red_plane(z0, ra);
+    red_plane(Plane<0>{}, ra);
     __syncthreads();
-    red_sources(z0 + 1, ra);
-    ba = black_source(z0);
-    auto step = [&](int k, const float (&use_r)[2], float use_b, float (&next_r)[2],
+    red_sources(z0 + 1, Plane<1>{}, ra);
+    ba = black_source(z0, Plane<0>{});
+    auto step = [&](int k, auto pl, const float (&use_r)[2], float use_b, float (&next_r)[2],
                     float &next_b) {
-        commit(k + 2); // red e slot of plane k-1, black e and phi slots of plane k-3
-        red_sources(k + 2, next_r);
-        next_b = black_source(k + 1);
+        constexpr int d = decltype(pl)::d; // k = z0 + d modulo the ring period
+        commit(Plane<d + 2>{}); // red e slot of plane k-1, black e and phi slots of plane k-4
+        red_sources(k + 2, Plane<d + 2>{}, next_r);
+        next_b = black_source(k + 1, Plane<d + 1>{});
         fetch(k + 3);
         __syncthreads();
-        red_plane(k + 1, use_r);
+        red_plane(Plane<d + 1>{}, use_r);
         __syncthreads();
-        black_and_store(k, use_b);
+        black_and_store(k, Plane<d>{}, use_b);
     };
-    static_assert(TZ % 2 == 0, "the z loop is unrolled by two");
-    for (int k = z0; k < z0 + TZ; k += 2) {
-        step(k, ra, ba, rb, bb);
-        step(k + 1, rb, bb, ra, ba);
+    static_assert(TZ % 2 == 0, "steps alternate between two register sets");
+    constexpr int G = 6; // ring period: a multiple of 3 and of 6 planes
+    int k = z0;
+    for (int g = 0; g < TZ / G; ++g, k += G) {
+        step(k, Plane<0>{}, ra, ba, rb, bb);
+        step(k + 1, Plane<1>{}, rb, bb, ra, ba);
+        step(k + 2, Plane<2>{}, ra, ba, rb, bb);
+        step(k + 3, Plane<3>{}, rb, bb, ra, ba);
+        step(k + 4, Plane<4>{}, ra, ba, rb, bb);
+        step(k + 5, Plane<5>{}, rb, bb, ra, ba);
+    }
+    // the last TZ mod 6 planes
+    if constexpr (TZ % G >= 2) {
+        step(k, Plane<0>{}, ra, ba, rb, bb);
+        step(k + 1, Plane<1>{}, rb, bb, ra, ba);
+    }
+    if constexpr (TZ % G >= 4) {
+        step(k + 2, Plane<2>{}, ra, ba, rb, bb);
+        step(k + 3, Plane<3>{}, rb, bb, ra, ba);
     }
     if (fb) flush_events(fallbacks, fb);
 }
