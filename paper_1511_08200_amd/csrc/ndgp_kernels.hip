@@ -1459,6 +1459,75 @@ k_force(const double *__restrict__ phi, Ix<PER> ix, double c4h, double *__restri
     f[2 * (size_t)cells + t] = -(phi[ix(i, j, k + 1)] - phi[ix(i, j, k - 1)]) * c4h;
 }
 
+// Force on a large periodic level through LDS: a workgroup streams a TX x TY
+// column along z over tz planes with a ring of four planes (one-cell halo in
+// x and y) as k_residual_tiled does, so phi is read from HBM about once
+// instead of once per difference direction; each component is k_force's
+// expression (same bits).
+template <int TX, int TY>
+__global__ void __launch_bounds__(kBlock)
+k_force_tiled(const double *__restrict__ phi, int lg, int tz, double c4h,
+              double *__restrict__ f) {
+    constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
+    constexpr int PRE = (PLANE + kBlock - 1) / kBlock;
+    constexpr int CELLS = TX * TY / kBlock; // output cells per thread per plane
+    static_assert(TX * TY % kBlock == 0, "tile");
+    __shared__ double P[4][PLANE];
+    const int n = 1 << lg, m = n - 1;
+    const size_t cells = (size_t)1 << (3 * lg);
+    const int ntx = n / TX;
+    const int tiles = ntx * (n / TY);
+    const int logical = xcd_local_id(blockIdx.x, gridDim.x);
+    const int tile = logical % tiles;
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY, z0 = (logical / tiles) * tz;
+    const int tid = threadIdx.x;
+    int pq[PRE], pxy[PRE];
+#pragma unroll
+    for (int e = 0; e < PRE; ++e) {
+        const int q = tid + e * kBlock;
+        pq[e] = q < PLANE ? q : -1;
+        const int yy = q / PX, xx = q - yy * PX;
+        pxy[e] = (((y0 - 1 + yy) & m) << lg) | ((x0 - 1 + xx) & m);
+    }
+    double pre[PRE];
+    auto fetch = [&](int z) {
+        const double *plane = phi + ((size_t)(z & m) << (2 * lg));
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pq[e] >= 0) pre[e] = *plane_at(plane, (unsigned)pxy[e]);
+    };
+    auto commit = [&](int z) {
+        double *dst = P[z & 3];
+#pragma unroll
+        for (int e = 0; e < PRE; ++e)
+            if (pq[e] >= 0) dst[pq[e]] = pre[e];
+    };
+    fetch(z0 - 1);
+    commit(z0 - 1);
+    fetch(z0);
+    commit(z0);
+    fetch(z0 + 1);
+    for (int k = z0; k < z0 + tz; ++k) {
+        commit(k + 1); // slot of plane k-3, last read at step k-2
+        if (k + 2 <= z0 + tz) fetch(k + 2);
+        __syncthreads();
+        const double(*pm)[PX] = reinterpret_cast<const double(*)[PX]>(P[(k - 1) & 3]);
+        const double(*p0)[PX] = reinterpret_cast<const double(*)[PX]>(P[k & 3]);
+        const double(*pp)[PX] = reinterpret_cast<const double(*)[PX]>(P[(k + 1) & 3]);
+        double *fx = f + ((size_t)k << (2 * lg));
+#pragma unroll
+        for (int e = 0; e < CELLS; ++e) {
+            const int q = tid + e * kBlock;
+            const int yt = q / TX, xt = q - yt * TX;
+            const int rr = yt + 1, c = xt + 1;
+            const unsigned g = (unsigned)(((y0 + yt) << lg) | (x0 + xt)); // in plane k
+            *plane_at(fx, g) = -(p0[rr][c + 1] - p0[rr][c - 1]) * c4h;
+            *plane_at(fx + cells, g) = -(p0[rr + 1][c] - p0[rr - 1][c]) * c4h;
+            *plane_at(fx + 2 * cells, g) = -(pp[rr][c] - pm[rr][c]) * c4h;
+        }
+    }
+}
+
 // Cell-wise truncation (the generalisation proposed in Sec. III.C): child
 // cell (i, j, k) of a ratio-2 box is iterated only if its parent cell P =
 // origin + (i, j, k) / 2 has |F_5th| >= threshold |F_GR|, F_5th = -grad(phi)/2
@@ -1879,6 +1948,13 @@ void launch_interpolate(const double *parent, int np, bool parent_periodic, cons
 
 void launch_force(const double *phi, int n, bool periodic, double h, double *f, hipStream_t st) {
     const int lg = log2i(n);
+    if (periodic && n >= 128) {
+        constexpr int TX = 64, TY = 16;
+        const int tz = n >= 256 ? 8 : 4; // 128^3: enough workgroups to fill the chip
+        const int tiles = (n / TX) * (n / TY);
+        k_force_tiled<TX, TY><<<tiles * (n / tz), kBlock, 0, st>>>(phi, lg, tz, 0.25 / h, f);
+        return;
+    }
     const unsigned nb = blocks_for((size_t)n * n * n);
     if (periodic)
         k_force<true><<<nb, kBlock, 0, st>>>(phi, make_ix<true>(n, lg), 0.25 / h, f);

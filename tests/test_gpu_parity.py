@@ -541,6 +541,22 @@ def test_cellwise_truncation_matches_oracle():
     assert r0.cycles == rf.cycles and r0.iterated_fraction[:3] == [1.0, 1.0, 1.0]
 
 
+@pytest.mark.parametrize("n", [64, 128, 256])
+def test_force_matches_oracle_on_periodic_levels(n):
+    """F5 on a periodic level (Sec. III.B): the z-streamed kernel (n >= 128)
+    and the per-cell kernel (64^3) against the oracle's central differences
+    of the same field, with the wrap-around cells of every face."""
+    rng = np.random.default_rng(900 + n)
+    phi = rng.standard_normal((n, n, n))
+    h = ndgp.cell_size(256.0, n)
+    grid = ndgp.Grid(n=n, h=h)
+    say(f"[force] n={n}")
+    fg = ndgp.force(grid, [dev(phi)])[0].cpu().numpy()
+    fo = O.force(phi, h, periodic=True)
+    assert fg.shape == fo.shape
+    assert np.abs(fg - fo).max() <= 1e-13 * np.abs(fo).max()
+
+
 def test_total_force_and_geff_stats_match_oracle():
     """ndgp_total_force and ndgp_geff_stats (Eq. modpoisson, Sec. III.B; the
     per-level G_eff of Fig. 3 over cells) on seeded fields: a 32^3 domain and
