@@ -80,7 +80,7 @@ k_smooth_half(const double *__restrict__ pin, double *__restrict__ pout,
 //   E:  (PRO) the coarse correction under the tile, three coarse planes.
 // A plane's slot is its offset from the chunk's first plane modulo the ring
 // size; the z loop is unrolled by 6 (a multiple of every ring), so the slots
-// are constants and LDS addresses need no arithmetic per step.
+// are constants: an LDS address is a per-thread base plus an immediate.
 // Step k relaxes the red cells of plane k+1 over the tile plus a 1-cell halo
 // (the black cells at the tile's edge need them), then the black cells of
 // plane k over the tile (red neighbours from R, black ones from PB), and
