@@ -390,6 +390,30 @@ def test_patches_match_oracle(interpolated, wrap):
         assert rel(fg[lvl], fo_or) <= 1e-10
 
 
+@pytest.mark.parametrize("interpolated", [False, True])
+def test_mixed_precision_with_patches_matches_oracle(interpolated):
+    """Mixed precision on the domain (FP32 correction multigrid) with two
+    nested refinements relaxed in FP64 from ghost shells of that domain
+    solution (full mode), or interpolated from it: every level within the
+    mixed-precision bar of the FP64 oracle."""
+    say(f"mixed + patches interpolated={interpolated}")
+    rc = 1.0
+    f, deltas, grid = patch_problem()
+    beta = O.beta_lcdm(1.0, 0.3, rc)
+    prob = O.Problem(delta=deltas, h=grid.h, rc=rc, beta=beta,
+                     origins=tuple(p.origin for p in grid.patches))
+    phio, infos = O.solve_problem(prob, interpolated=interpolated)
+    mode = ndgp.MODE_INTERPOLATED if interpolated else ndgp.MODE_FULL
+    phig, rep = gpu_solve(deltas, grid, rc=rc, tol=1e-12, max_cycles=200, mode=mode,
+                          precision=ndgp.PREC_MIXED)
+    say(f"  cycles={rep.cycles} rel_res={rep.rel_res}")
+    assert rep.status == 0
+    for lvl in range(3):
+        e = rel(phig[lvl], phio[lvl])
+        say(f"  level {lvl}: rel err {e:.2e}")
+        assert e <= MIXED_TOL
+
+
 def deep_patch_problem(n=32, m=32, depth=4, seed=12):
     """``depth`` nested patches of m cells (ratio 2 each), centred on the
     largest top-hat and kept 2 parent cells inside their parent."""
