@@ -11,7 +11,8 @@ the benchmark times:
     1e-10, within the mixed-precision bar 1e-8;
   * the same base plus two nested 128^3 patches at 2x and 4x (full mode,
     every level relaxed to stagnation): <= 1e-11 per level; and the same base
-    with one 256^3 patch at 2x: <= 1e-11 per level;
+    with one 256^3 patch at 2x: <= 1e-11 per level; the four-refinement
+    truncation workload at l_trunc = l_d + 2: <= 1e-11 per level;
   * 128^3, mixed precision at 1e-10 (the FP32 one-launch sweep, tiled
     restriction and block prolongation sizes): <= 1e-8;
   * 512^3 lognormal sigma 2.5 (delta up to ~1e5), mixed precision at 1e-10
@@ -183,6 +184,36 @@ def test_256_with_a_256_patch_full_mode_matches_oracle():
     torch.cuda.synchronize()
     assert rep.status == 0
     for lvl in range(2):
+        e = rel(phi[lvl].cpu().numpy(), phio[lvl])
+        say(f"  level {lvl}: cycles={rep.cycles[lvl]} rel err {e:.2e}")
+        assert e <= PHI_TOL
+
+
+def test_four_refinements_truncated_at_two_match_oracle():
+    """The truncation workload (256^3 + four nested 128^3 refinements at 2x to
+    16x, the `nested-256-deep` preset) at l_trunc = l_d + 2 (Sec. IV.A): the
+    domain and the first refinement relaxed to stagnation, the three finer ones
+    interpolated each from its parent; every level against the oracle's
+    truncated path."""
+    from paper_1511_08200_amd import presets
+    w = presets.load("nested-256-deep", mode=ndgp.MODE_TRUNCATED, trunc_level=2)
+    deltas = w.deltas()
+    grid = w.grid
+    beta = O.beta_lcdm(1.0, 0.3, w.params.rc)
+    prob = O.Problem(delta=deltas, h=grid.h, rc=w.params.rc, beta=beta,
+                     origins=tuple(p.origin for p in grid.patches))
+    t = time.time()
+    phio, infos = O.solve_problem(prob, trunc_level=2)
+    say(f"oracle 256^3 + 4 x 128^3 truncated at 2: cycles {[i.cycles for i in infos]}, "
+        f"{time.time() - t:.1f} s")
+    assert all(i.status == 0 for i in infos[:2])
+    phi, rep = ndgp.solve(grid, ndgp.Params(rc=w.params.rc, tol=0.0, max_cycles=200,
+                                            mode=ndgp.MODE_TRUNCATED, trunc_level=2),
+                          [dev(d) for d in deltas])
+    torch.cuda.synchronize()
+    assert rep.status == 0
+    assert rep.cycles[2:5] == [0, 0, 0]
+    for lvl in range(5):
         e = rel(phi[lvl].cpu().numpy(), phio[lvl])
         say(f"  level {lvl}: cycles={rep.cycles[lvl]} rel err {e:.2e}")
         assert e <= PHI_TOL
