@@ -328,21 +328,30 @@ k_corr_coarsest(float *__restrict__ e, const float *__restrict__ phi, const floa
 // of k_corr_half, so the result is bit for bit two k_corr_half launches.  As
 // in the FP64 sweep, the rings of 5 planes (phi, old black e) have 6 slots and
 // the z loop is unrolled by 6, so every LDS slot is a compile-time constant.
-template <int TX, int TY, int TZ, int NT>
+// With PRO the sweep starts from e plus the interpolated coarse-grid
+// correction P(e_c - ehat_c), added as each old e value is loaded, with the
+// arithmetic of k_corr_prolong_blocks (three coarse planes of e_c - ehat_c in
+// an LDS ring E): the same bits as that launch followed by the sweep.
+template <int TX, int TY, int TZ, int NT, bool PRO = false>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(4))) // two workgroups per CU: at most 128 VGPRs
 k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
                    const float *__restrict__ phi, const float *__restrict__ rr_in, int lg,
-                   float al, double w, unsigned *__restrict__ fallbacks) {
+                   float al, double w, unsigned *__restrict__ fallbacks,
+                   const float *__restrict__ e_c = nullptr,
+                   const float *__restrict__ ehat_c = nullptr) {
     constexpr int PX = TX + 4, PY = TY + 4, HX = PX / 2, PLANE = PX * PY;
     constexpr int PRE = (PLANE / 2 + NT - 1) / NT; // pairs of cells per thread
     constexpr int RED_ROW = (TX + 2) / 2, RED_CELLS = RED_ROW * (TY + 2);
+    constexpr int EX = TX / 2 + 4, EY = TY / 2 + 4; // coarse cells under the plane, +-1
     static_assert(TX % 2 == 0 && TY % 2 == 0 && TX * TY / 2 == NT, "one black cell per thread");
     static_assert(RED_CELLS <= 2 * NT, "at most two red cells per thread");
+    static_assert(EX * EY <= NT, "one coarse value per thread");
     __shared__ float F[6][2][PY][HX]; // phi, both colours, planes k-2 .. k+2
     __shared__ float ER[3][PY][HX];   // old e, red cells
     __shared__ float EB[6][PY][HX];   // old e, black cells, planes k-2 .. k+2
     __shared__ float R[3][PY][HX];    // e after the red pass, red cells
+    __shared__ float E[PRO ? 3 : 1][EY * EX]; // (PRO) e_c - ehat_c under the tile
 
     const int n = 1 << lg, m = n - 1;
     const int ntx = n / TX;
@@ -356,7 +365,7 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
 
     // pairs of cells (columns 2j, 2j+1 of a row: one red, one black, split
     // index j), loaded 8 bytes at a time
-    int pxy[PRE], pidx[PRE], ppar[PRE];
+    int pxy[PRE], pidx[PRE], ppar[PRE], eat[PRE], edy[PRE];
 #pragma unroll
     for (int e = 0; e < PRE; ++e) {
         const int q = tid + e * NT;
@@ -364,6 +373,11 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
         pxy[e] = (((y0 - 2 + r) & m) << lg) | ((x0 - 2 + 2 * j) & m);
         pidx[e] = q < PLANE / 2 ? r * HX + j : -1;
         ppar[e] = r & 1; // colour of column 2j = ppar ^ (z & 1)
+        // (PRO) fine x0-2+2j+i lies in coarse cell x0/2-1+j, E column j+1;
+        // the neighbour column is on the left for i = 0, on the right for
+        // i = 1, the neighbour row below for an even fine row
+        eat[e] = ((r >> 1) + 1) * EX + j + 1;
+        edy[e] = (r & 1) ? EX : -EX;
     }
     float2 pre_p[PRE], pre_e[PRE];
     auto fetch = [&](int z) {
@@ -380,16 +394,62 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
         float *f0 = &F[ring_slot(d, 6)][0][0][0], *f1 = &F[ring_slot(d, 6)][1][0][0];
         float *red = &ER[ring_slot(d, 3)][0][0], *blk = &EB[ring_slot(d, 6)][0][0];
         constexpr int zp = ring_slot(d, 2);
+        const float *e0 = nullptr, *e1 = nullptr;
+        if constexpr (PRO) {
+            // parent plane (offset from z0 / 2) and the neighbour side
+            constexpr int K = floor_half(d), sk = zp ? 1 : -1;
+            e0 = E[ring_slot(K, 3)];
+            e1 = E[ring_slot(K + sk, 3)];
+        }
 #pragma unroll
         for (int e = 0; e < PRE; ++e)
             if (pidx[e] >= 0) {
+                float ev[2] = {pre_e[e].x, pre_e[e].y};
+                if constexpr (PRO) {
+                    // the own and the neighbour coarse row, one column to the left
+                    const int er[2] = {fresh(eat[e] - 1), fresh(eat[e] + edy[e] - 1)};
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const int edx = i ? 1 : -1;
+                        float acc = 0.f;
+#pragma unroll
+                        for (int cz = 0; cz < 2; ++cz) {
+                            const float *ep = cz ? e1 : e0;
+#pragma unroll
+                            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                                for (int a = 0; a < 2; ++a) {
+                                    const float wt = (a ? 0.25f : 0.75f) * (b ? 0.25f : 0.75f) *
+                                                     (cz ? 0.25f : 0.75f);
+                                    acc = fmaf(wt, ep[er[b] + 1 + a * edx], acc);
+                                }
+                        }
+                        ev[i] += acc;
+                    }
+                }
                 const bool fb1 = (ppar[e] ^ zp) != 0; // column 2j black
                 const int at = fresh(pidx[e]);
                 f0[at] = fb1 ? pre_p[e].y : pre_p[e].x;
                 f1[at] = fb1 ? pre_p[e].x : pre_p[e].y;
-                red[at] = fb1 ? pre_e[e].y : pre_e[e].x;
-                blk[at] = fb1 ? pre_e[e].x : pre_e[e].y;
+                red[at] = fb1 ? ev[1] : ev[0];
+                blk[at] = fb1 ? ev[0] : ev[1];
             }
+    };
+    // (PRO) coarse plane K of the correction: loaded into registers, then
+    // stored into its E slot
+    const int mc = (n >> 1) - 1, lgc = lg - 1;
+    const int eq = PRO && tid < EX * EY ? tid : -1;
+    const int exy = (((y0 / 2 - 2 + tid / EX) & mc) << lgc) | ((x0 / 2 - 2 + tid % EX) & mc);
+    float ea = 0.f, eb = 0.f;
+    auto e_load = [&](int K) {
+        if (eq >= 0) {
+            const int q = ((K & mc) << (2 * lgc)) | exy;
+            ea = e_c[q];
+            eb = ehat_c[q];
+        }
+    };
+    auto e_store = [&](auto kpl) { // kpl: the coarse plane's offset from z0 / 2
+        if (eq >= 0) E[ring_slot(decltype(kpl)::d, 3)][eq] = ea - eb;
     };
 
     // red cells of the halo-1 region (row rr, split index jj + 1 - p at plane
@@ -489,7 +549,18 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
         dst[1] = pb ? vb : vr;
     };
 
-    // the FP64 kernel's schedule: phi and old e on planes z0-2 .. z0+TZ+1
+    // the FP64 kernel's schedule: phi and old e on planes z0-2 .. z0+TZ+1;
+    // with PRO the coarse planes z0/2-2 .. z0/2+TZ/2+1
+    const int c0 = z0 >> 1;
+    if constexpr (PRO) {
+        e_load(c0 - 2);
+        e_store(Plane<-2>{});
+        e_load(c0 - 1);
+        e_store(Plane<-1>{});
+        e_load(c0);
+        e_store(Plane<0>{});
+        __syncthreads();
+    }
     fetch(z0 - 2);
     commit(Plane<-2>{});
     fetch(z0 - 1);
@@ -499,9 +570,14 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
     float ra[2], rb[2], ba, bb;
     red_sources(z0 - 1, Plane<-1>{}, ra);
     fetch(z0 + 1);
+    if constexpr (PRO) e_load(c0 + 1);
     __syncthreads();
     red_plane(Plane<-1>{}, ra);
     __syncthreads(); // red(z0-1) has read the red slot that plane z0+1 takes
+    if constexpr (PRO) {
+        e_store(Plane<1>{}); // the slot of coarse plane c0-2, last used by plane z0-2
+        __syncthreads();
+    }
     commit(Plane<1>{});
     red_sources(z0, Plane<0>{}, ra);
     fetch(z0 + 2);
@@ -510,14 +586,20 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
     __syncthreads();
     red_sources(z0 + 1, Plane<1>{}, ra);
     ba = black_source(z0, Plane<0>{});
+    if constexpr (PRO) e_load(c0 + 2);
+    // (PRO) an even step stores coarse plane k/2+2 (first needed by plane
+    // k+3, in the slot of plane k/2-1, last needed by plane k) and an odd
+    // step loads the next one
     auto step = [&](int k, auto pl, const float (&use_r)[2], float use_b, float (&next_r)[2],
                     float &next_b) {
         constexpr int d = decltype(pl)::d; // k = z0 + d modulo the ring period
         commit(Plane<d + 2>{}); // red e slot of plane k-1, black e and phi slots of plane k-4
         red_sources(k + 2, Plane<d + 2>{}, next_r);
         next_b = black_source(k + 1, Plane<d + 1>{});
+        if constexpr (PRO && (d & 1)) e_load((k + 1) / 2 + 2);
         fetch(k + 3);
         __syncthreads();
+        if constexpr (PRO && !(d & 1)) e_store(Plane<d / 2 + 2>{});
         red_plane(Plane<d + 1>{}, use_r);
         __syncthreads();
         black_and_store(k, Plane<d>{}, use_b);
@@ -687,19 +769,30 @@ void launch_corr_half(const Level32 &L, const float *ein, float *eout, int colou
 
 bool corr_fused_ok(const Level32 &L) { return L.n >= 128; }
 
-void launch_corr_sweep_fused(const Level32 &L, const float *ein, float *eout,
-                             unsigned *fallbacks, hipStream_t st) {
+template <bool PRO>
+void corr_sweep_fused(const Level32 &L, const float *ein, float *eout, unsigned *fallbacks,
+                      const float *e_c, const float *ehat_c, hipStream_t st) {
     constexpr int TX = 64, TY = 16, NT = 512;
     const int tiles = (L.n / TX) * (L.n / TY);
     if (L.n >= 256) {
         constexpr int TZ = 32;
-        k_corr_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(
-            ein, eout, L.phi, L.r, L.lg, (float)L.alpha, L.omega, fallbacks);
+        k_corr_sweep_fused<TX, TY, TZ, NT, PRO><<<tiles * (L.n / TZ), NT, 0, st>>>(
+            ein, eout, L.phi, L.r, L.lg, (float)L.alpha, L.omega, fallbacks, e_c, ehat_c);
     } else {
         constexpr int TZ = 8;
-        k_corr_sweep_fused<TX, TY, TZ, NT><<<tiles * (L.n / TZ), NT, 0, st>>>(
-            ein, eout, L.phi, L.r, L.lg, (float)L.alpha, L.omega, fallbacks);
+        k_corr_sweep_fused<TX, TY, TZ, NT, PRO><<<tiles * (L.n / TZ), NT, 0, st>>>(
+            ein, eout, L.phi, L.r, L.lg, (float)L.alpha, L.omega, fallbacks, e_c, ehat_c);
     }
+}
+
+void launch_corr_sweep_fused(const Level32 &L, const float *ein, float *eout,
+                             unsigned *fallbacks, hipStream_t st) {
+    corr_sweep_fused<false>(L, ein, eout, fallbacks, nullptr, nullptr, st);
+}
+
+void launch_corr_sweep_fused_prolong(const Level32 &L, const Level32 &C, const float *ein,
+                                     float *eout, unsigned *fallbacks, hipStream_t st) {
+    corr_sweep_fused<true>(L, ein, eout, fallbacks, C.e, C.ehat, st);
 }
 
 void launch_corr_restrict(const Level32 &F, const Level32 &C, bool tiled, hipStream_t st) {

@@ -570,10 +570,19 @@ struct Runner {
     // as smooth(): fused sweeps on large levels, an odd last sweep in two
     // launches.  (Adding the coarse-grid correction on load, as the FP64
     // sweep does, spills registers here and is slower than its own launch.)
-    void corr_smooth(Level32 &L, int sweeps) {
+    // with C the coarse-grid correction from C is added first: on load in
+    // the first fused sweep, else by its own launch (same bits)
+    void corr_smooth(Level32 &L, int sweeps, const Level32 *C = nullptr) {
         const bool fused = !(P.c.flags & NDGP_TWO_PASS) && corr_fused_ok(L);
         const int nf = fused ? (sweeps & ~1) : 0;
-        for (int s = 0; s < nf; ++s) {
+        int s = 0;
+        if (C && nf == 0) launch_corr_prolong(L, *C, st);
+        if (C && nf > 0) {
+            launch_corr_sweep_fused_prolong(L, *C, L.e, L.ealt, P.fallbacks, st);
+            std::swap(L.e, L.ealt);
+            s = 1;
+        }
+        for (; s < nf; ++s) {
             launch_corr_sweep_fused(L, L.e, L.ealt, P.fallbacks, st);
             std::swap(L.e, L.ealt);
         }
@@ -595,8 +604,7 @@ struct Runner {
         launch_corr_restrict(L, C, !(P.c.flags & NDGP_TWO_PASS), st);
         launch_corr_coarse_source(C, st);
         corr_vcycle(H, nl, l + 1);
-        launch_corr_prolong(L, C, st);
-        corr_smooth(L, P.c.nu2);
+        corr_smooth(L, P.c.nu2, &C);
     }
 
     double residual_to32(const Level &L, float *r32) {
