@@ -168,12 +168,15 @@ __device__ __forceinline__ double fast_rcp(double q) {
     return fma(y, fma(-q, y, 1.0), y);
 }
 
+// fast_sqrt takes d >= 0 (the relaxation calls it only there): the estimate
+// of 1/sqrt(d) is capped at 2^511, its value at the smallest normal double,
+// so that d = 0 gives 0 (0 x 2^511) with no select, and every d >= 2^-1022 is
+// unchanged.
 __device__ __forceinline__ double fast_sqrt(double d) {
-    const double rs = __builtin_amdgcn_rsq(d);
+    const double rs = fmin(__builtin_amdgcn_rsq(d), 0x1p511);
     const double s0 = d * rs;
     const double e = fma(-s0, 0.5 * rs, 0.5);
-    const double s1 = fma(s0, e, s0);
-    return d > 0.0 ? s1 : 0.0;
+    return fma(s0, e, s0);
 }
 
 // Relaxation events a thread counts in one unsigned: a visit with no real
