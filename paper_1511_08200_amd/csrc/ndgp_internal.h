@@ -374,6 +374,10 @@ void launch_corr_half(const Level32 &L, const float *ein, float *eout, int colou
 bool corr_fused_ok(const Level32 &L);
 void launch_corr_sweep_fused(const Level32 &L, const float *ein, float *eout,
                              unsigned *fallbacks, hipStream_t st);
+// the same sweep starting from e = 0 (nothing read): bit for bit a zero fill
+// of the input followed by launch_corr_sweep_fused
+void launch_corr_sweep_fused_from_zero(const Level32 &L, float *eout, unsigned *fallbacks,
+                                       hipStream_t st);
 // the same sweep starting from ein + trilinear(C.e - C.ehat): bit for bit
 // launch_corr_prolong followed by launch_corr_sweep_fused
 void launch_corr_sweep_fused_prolong(const Level32 &L, const Level32 &C, const float *ein,

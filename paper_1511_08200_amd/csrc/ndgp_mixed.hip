@@ -331,8 +331,10 @@ k_corr_coarsest(float *__restrict__ e, const float *__restrict__ phi, const floa
 // With PRO the sweep starts from e plus the interpolated coarse-grid
 // correction P(e_c - ehat_c), added as each old e value is loaded, with the
 // arithmetic of k_corr_prolong_blocks (three coarse planes of e_c - ehat_c in
-// an LDS ring E): the same bits as that launch followed by the sweep.
-template <int TX, int TY, int TZ, int NT, bool PRO = false>
+// an LDS ring E): the same bits as that launch followed by the sweep.  With ZE
+// the old e is zero everywhere (the first sweep of an outer iteration) and is
+// not read: the same bits as zero-filling ein first.
+template <int TX, int TY, int TZ, int NT, bool PRO = false, bool ZE = false>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(4))) // two workgroups per CU: at most 128 VGPRs
 k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
@@ -347,6 +349,7 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
     static_assert(TX % 2 == 0 && TY % 2 == 0 && TX * TY / 2 == NT, "one black cell per thread");
     static_assert(RED_CELLS <= 2 * NT, "at most two red cells per thread");
     static_assert(EX * EY <= NT, "one coarse value per thread");
+    static_assert(!(PRO && ZE), "the correction is added after the first sweep");
     __shared__ float F[6][2][PY][HX]; // phi, both colours, planes k-2 .. k+2
     __shared__ float ER[3][PY][HX];   // old e, red cells
     __shared__ float EB[6][PY][HX];   // old e, black cells, planes k-2 .. k+2
@@ -386,7 +389,10 @@ k_corr_sweep_fused(const float *__restrict__ ein, float *__restrict__ eout,
         for (int e = 0; e < PRE; ++e)
             if (pidx[e] >= 0) {
                 pre_p[e] = *reinterpret_cast<const float2 *>(plane_at(pp, pxy[e]));
-                pre_e[e] = *reinterpret_cast<const float2 *>(plane_at(pe, pxy[e]));
+                if constexpr (ZE)
+                    pre_e[e] = make_float2(0.f, 0.f);
+                else
+                    pre_e[e] = *reinterpret_cast<const float2 *>(plane_at(pe, pxy[e]));
             }
     };
     auto commit = [&](auto pl) {
@@ -769,30 +775,35 @@ void launch_corr_half(const Level32 &L, const float *ein, float *eout, int colou
 
 bool corr_fused_ok(const Level32 &L) { return L.n >= 128; }
 
-template <bool PRO>
+template <bool PRO, bool ZE>
 void corr_sweep_fused(const Level32 &L, const float *ein, float *eout, unsigned *fallbacks,
                       const float *e_c, const float *ehat_c, hipStream_t st) {
     constexpr int TX = 64, TY = 16, NT = 512;
     const int tiles = (L.n / TX) * (L.n / TY);
     if (L.n >= 256) {
         constexpr int TZ = 32;
-        k_corr_sweep_fused<TX, TY, TZ, NT, PRO><<<tiles * (L.n / TZ), NT, 0, st>>>(
+        k_corr_sweep_fused<TX, TY, TZ, NT, PRO, ZE><<<tiles * (L.n / TZ), NT, 0, st>>>(
             ein, eout, L.phi, L.r, L.lg, (float)L.alpha, L.omega, fallbacks, e_c, ehat_c);
     } else {
         constexpr int TZ = 8;
-        k_corr_sweep_fused<TX, TY, TZ, NT, PRO><<<tiles * (L.n / TZ), NT, 0, st>>>(
+        k_corr_sweep_fused<TX, TY, TZ, NT, PRO, ZE><<<tiles * (L.n / TZ), NT, 0, st>>>(
             ein, eout, L.phi, L.r, L.lg, (float)L.alpha, L.omega, fallbacks, e_c, ehat_c);
     }
 }
 
 void launch_corr_sweep_fused(const Level32 &L, const float *ein, float *eout,
                              unsigned *fallbacks, hipStream_t st) {
-    corr_sweep_fused<false>(L, ein, eout, fallbacks, nullptr, nullptr, st);
+    corr_sweep_fused<false, false>(L, ein, eout, fallbacks, nullptr, nullptr, st);
+}
+
+void launch_corr_sweep_fused_from_zero(const Level32 &L, float *eout, unsigned *fallbacks,
+                                       hipStream_t st) {
+    corr_sweep_fused<false, true>(L, nullptr, eout, fallbacks, nullptr, nullptr, st);
 }
 
 void launch_corr_sweep_fused_prolong(const Level32 &L, const Level32 &C, const float *ein,
                                      float *eout, unsigned *fallbacks, hipStream_t st) {
-    corr_sweep_fused<true>(L, ein, eout, fallbacks, C.e, C.ehat, st);
+    corr_sweep_fused<true, false>(L, ein, eout, fallbacks, C.e, C.ehat, st);
 }
 
 void launch_corr_restrict(const Level32 &F, const Level32 &C, bool tiled, hipStream_t st) {

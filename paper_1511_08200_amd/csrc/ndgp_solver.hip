@@ -474,8 +474,11 @@ struct Runner {
         const size_t cells = H[0].cells();
         if (!P.phi32_fresh) launch_to32(H[0].phi, H32[0].phi, cells, st);
         for (int l = 1; l < nl; ++l) launch_avg32(H32[l - 1], H32[l], st);
-        launch_fill32(H32[0].e, cells, 0.f, st);
-        for (int q = 0; q < kMixedInner; ++q) corr_vcycle(H32, nl, 0);
+        // the correction starts from zero: the first fused sweep takes it as
+        // such without reading it, else it is filled
+        const bool from_zero = corr_first_sweep_from_zero(H32[0]);
+        if (!from_zero) launch_fill32(H32[0].e, cells, 0.f, st);
+        for (int q = 0; q < kMixedInner; ++q) corr_vcycle(H32, nl, 0, from_zero && q == 0);
         launch_add_to32(H[0].phi, H32[0].e, H32[0].phi, cells, st);
         P.phi32_fresh = true;
     }
@@ -570,12 +573,23 @@ struct Runner {
     // as smooth(): fused sweeps on large levels, an odd last sweep in two
     // launches.  (Adding the coarse-grid correction on load, as the FP64
     // sweep does, spills registers here and is slower than its own launch.)
+    bool corr_first_sweep_from_zero(const Level32 &L) const {
+        return !(P.c.flags & NDGP_TWO_PASS) && corr_fused_ok(L) && P.c.nu1 >= 2;
+    }
+
     // with C the coarse-grid correction from C is added first: on load in
-    // the first fused sweep, else by its own launch (same bits)
-    void corr_smooth(Level32 &L, int sweeps, const Level32 *C = nullptr) {
+    // the first fused sweep, else by its own launch (same bits); with
+    // from_zero the correction is zero and the first fused sweep does not
+    // read it (corr_first_sweep_from_zero(L) holds)
+    void corr_smooth(Level32 &L, int sweeps, const Level32 *C = nullptr, bool from_zero = false) {
         const bool fused = !(P.c.flags & NDGP_TWO_PASS) && corr_fused_ok(L);
         const int nf = fused ? (sweeps & ~1) : 0;
         int s = 0;
+        if (from_zero) {
+            launch_corr_sweep_fused_from_zero(L, L.ealt, P.fallbacks, st);
+            std::swap(L.e, L.ealt);
+            s = 1;
+        }
         if (C && nf == 0) launch_corr_prolong(L, *C, st);
         if (C && nf > 0) {
             launch_corr_sweep_fused_prolong(L, *C, L.e, L.ealt, P.fallbacks, st);
@@ -593,13 +607,13 @@ struct Runner {
             }
     }
 
-    void corr_vcycle(Level32 *H, int nl, int l) {
+    void corr_vcycle(Level32 *H, int nl, int l, bool from_zero = false) {
         Level32 &L = H[l];
         if (l == nl - 1) {
             launch_corr_coarsest(L, kCoarsestSweeps, P.fallbacks, st);
             return;
         }
-        corr_smooth(L, P.c.nu1);
+        corr_smooth(L, P.c.nu1, nullptr, from_zero);
         Level32 &C = H[l + 1];
         launch_corr_restrict(L, C, !(P.c.flags & NDGP_TWO_PASS), st);
         launch_corr_coarse_source(C, st);
